@@ -1,0 +1,555 @@
+"""Pins of the CPU oracle against things other than itself.
+
+Each test checks the oracle against the mathematics or an independent routine:
+brute-force enumeration with exact rationals, closed forms, a library
+(scikit-learn's CART, numpy's float16 conversion), published test vectors, or
+invariants that any correct split search satisfies.
+"""
+from __future__ import annotations
+
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from tests import bruteforce as BF
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def one_node(X, y, C, feats, weights, *, T=0, bins=256, idx=None, hist=False):
+    """Run the oracle on a single node holding all rows of X (or idx)."""
+    n_rows = X.shape[1]
+    idx = np.arange(n_rows, dtype=np.int32) if idx is None else np.asarray(idx, np.int32)
+    k = len(feats)
+    nz_off = np.zeros(k + 1, np.int32)
+    nz_off[1:] = np.cumsum([len(f) for f in feats])
+    nf = np.concatenate([np.asarray(f, np.int32) for f in feats])
+    nw = np.concatenate([np.asarray(w, np.int8) for w in weights])
+    sp, H = O.find_splits(X, y, C, np.array([0, len(idx)], np.int32), idx,
+                          np.array([0, k], np.int32), nz_off, nf, nw, bins=bins,
+                          sort_threshold=T, hist=hist)
+    return sp[0], H, (nz_off, nf, nw)
+
+
+def exact_values(Xi, feats, weights, idx):
+    """Projected values of integer-valued features, in exact integers."""
+    return [[sum(int(w) * int(Xi[f, r]) for f, w in zip(fs, ws)) for r in idx]
+            for fs, ws in zip(feats, weights)]
+
+
+def random_projs(rng, k, d, zmax):
+    feats, weights = [], []
+    for _ in range(k):
+        z = int(rng.integers(1, zmax + 1))
+        feats.append(sorted(rng.choice(d, size=z, replace=False).tolist()))
+        weights.append(rng.choice([-1, 1], size=z).tolist())
+    return feats, weights
+
+
+# --------------------------------------------------------------------------
+# storage, projection, sampler
+# --------------------------------------------------------------------------
+
+def test_half_to_float_matches_numpy_on_every_pattern():
+    bits = np.arange(1 << 16, dtype=np.uint32).astype(np.uint16)
+    ref = bits.view(np.float16).astype(np.float32)
+    got = np.array([O.half_to_float(int(b)) for b in bits], np.float32)
+    nan = np.isnan(ref)
+    assert np.array_equal(np.isnan(got), nan)
+    assert np.array_equal(got[~nan].view(np.uint32), ref[~nan].view(np.uint32))
+
+
+def test_projection_exact_on_integer_data():
+    rng = np.random.default_rng(11)
+    X = rng.integers(-1000, 1001, size=(12, 50)).astype(np.float32)
+    for _ in range(200):
+        z = int(rng.integers(1, 9))
+        f = np.sort(rng.choice(12, size=z, replace=False)).astype(np.int32)
+        w = rng.choice([-1, 1], size=z).astype(np.int8)
+        r = int(rng.integers(0, 50))
+        exact = sum(int(wj) * int(X[fj, r]) for fj, wj in zip(f, w))
+        got = O.project_value(X, f, w, r)
+        assert got == np.float32(exact)
+        assert not (got == 0 and math.copysign(1.0, got) < 0), "projection produced -0.0"
+
+
+def test_projection_error_within_z_ulp_of_fp64():
+    rng = np.random.default_rng(12)
+    X = (rng.standard_normal((16, 200)) * 10).astype(np.float32)
+    for _ in range(300):
+        z = int(rng.integers(1, 17))
+        f = np.sort(rng.choice(16, size=z, replace=False)).astype(np.int32)
+        w = rng.choice([-1, 1], size=z).astype(np.int8)
+        r = int(rng.integers(0, 200))
+        exact = sum(float(wj) * float(X[fj, r]) for fj, wj in zip(f, w))
+        got = float(O.project_value(X, f, w, r))
+        bound = z * max(abs(float(X[fj, r])) for fj in f) * 2.0 ** -23
+        assert abs(got - exact) <= bound
+
+
+def test_projection_sequential_csr_order():
+    # a + b - c where the order matters in float32: 1e8 + 1 - 1e8 = 0 (not 1)
+    X = np.array([[1e8], [1.0], [1e8]], np.float32)
+    got = O.project_value(X, np.array([0, 1, 2], np.int32), np.array([1, 1, -1], np.int8), 0)
+    assert got == np.float32(0.0)
+    got2 = O.project_value(X, np.array([0, 2, 1], np.int32), np.array([1, -1, 1], np.int8), 0)
+    assert got2 == np.float32(1.0)
+
+
+def test_fp16_grid_projections_are_exact():
+    # 1/256 grid, |x| <= 8: sums of <= 8 terms are exact in FP32 and FP16
+    rng = np.random.default_rng(13)
+    m = rng.integers(-2048, 2049, size=(10, 300))
+    X32 = (m / 256.0).astype(np.float32)
+    X16 = X32.astype(np.float16)
+    assert np.array_equal(X16.astype(np.float32), X32)
+    for _ in range(300):
+        z = int(rng.integers(1, 9))
+        f = np.sort(rng.choice(10, size=z, replace=False)).astype(np.int32)
+        w = rng.choice([-1, 1], size=z).astype(np.int8)
+        r = int(rng.integers(0, 300))
+        exact = Fraction(sum(int(wj) * int(m[fj, r]) for fj, wj in zip(f, w)), 256)
+        a, b = O.project_value(X32, f, w, r), O.project_value(X16, f, w, r)
+        assert Fraction(float(a)) == exact and a == b
+
+
+def test_splitmix64_published_vectors():
+    with open(os.path.join(GOLDEN, "splitmix64_seed0.txt")) as fh:
+        rows = [ln.split() for ln in fh if ln.strip() and not ln.startswith("#")]
+    for c, val in rows:
+        assert O.hash64(0, int(c)) == int(val, 16)
+
+
+def test_sampler_distinct_sorted_in_range_and_uniform():
+    rng_counts = {}
+    d, z = 5, 2
+    for pos in range(20000):
+        f, w = O.sample_projection(123, 0, 0, pos, 0, d, z)
+        assert len(set(f.tolist())) == z and np.all(np.diff(f) > 0)
+        assert f.min() >= 0 and f.max() < d
+        assert set(w.tolist()) <= {-1, 1}
+        rng_counts[tuple(f)] = rng_counts.get(tuple(f), 0) + 1
+    # every one of the C(5,2) = 10 subsets equally likely: chi-square, 9 dof
+    assert len(rng_counts) == 10
+    exp = 20000 / 10
+    chi2 = sum((v - exp) ** 2 / exp for v in rng_counts.values())
+    assert chi2 < 27.9  # p = 0.001
+
+
+def test_sampler_full_draw_and_determinism():
+    f, _ = O.sample_projection(7, 3, 2, 11, 5, 12, 12)
+    assert f.tolist() == list(range(12))
+    a = O.sample_projection(99, 1, 4, 17, 3, 1024, 3)
+    b = O.sample_projection(99, 1, 4, 17, 3, 1024, 3)
+    assert a[0].tolist() == b[0].tolist() and a[1].tolist() == b[1].tolist()
+    c = O.sample_projection(99, 2, 4, 17, 3, 1024, 3)
+    assert c[0].tolist() != a[0].tolist() or c[1].tolist() != a[1].tolist()
+
+
+def test_sampler_sign_balance():
+    neg = tot = 0
+    for pos in range(4000):
+        _, w = O.sample_projection(5, 0, 1, pos, 7, 64, 3)
+        neg += int((w < 0).sum())
+        tot += w.size
+    assert abs(neg / tot - 0.5) < 0.03
+
+
+# --------------------------------------------------------------------------
+# bins
+# --------------------------------------------------------------------------
+
+def test_bin_invariants_random():
+    rng = np.random.default_rng(21)
+    for _ in range(300):
+        B = int(rng.integers(2, 257))
+        v = (rng.standard_normal(64) * 10 ** rng.uniform(-3, 3)).astype(np.float32)
+        lo, hi = v.min(), v.max()
+        s = O.bin_scale(B, lo, hi)
+        b = np.array([O.bin_index(x, lo, s, B) for x in np.sort(v)])
+        assert b.min() >= 0 and b.max() <= B - 1
+        assert np.all(np.diff(b) >= 0)          # monotone in v
+        assert O.bin_index(lo, lo, s, B) == 0
+        assert O.bin_index(hi, lo, s, B) == B - 1
+
+
+def test_bins_equal_exact_floor_away_from_rounding():
+    rng = np.random.default_rng(22)
+    checked = 0
+    for _ in range(200):
+        B = int(rng.choice([2, 3, 7, 16, 100, 128, 255, 256]))
+        v = rng.integers(-500, 501, size=40).astype(np.float32)
+        lo, hi = v.min(), v.max()
+        if lo == hi:
+            continue
+        s = O.bin_scale(B, lo, hi)
+        for x in v:
+            e = Fraction(int(x) - int(lo)) * B / (int(hi) - int(lo))
+            if e >= B:
+                assert O.bin_index(x, lo, s, B) == B - 1
+                continue
+            if abs(e - round(e)) < Fraction(1, 10**5) * max(1, e):
+                continue        # too close to a boundary for the rounding to be decided
+            assert O.bin_index(x, lo, s, B) == math.floor(e)
+            checked += 1
+    assert checked > 1000
+
+
+def test_scale_overflow_guard():
+    lo = np.float32(1.0)
+    hi = np.nextafter(lo, np.float32(2.0))
+    # hi - lo = 2^-23: 256 / 2^-23 = 2^31, finite; a denormal width overflows
+    assert O.bin_scale(256, lo, hi) == np.float32(2.0 ** 31)
+    tiny = np.float32(1e-45)
+    assert O.bin_scale(256, np.float32(0), tiny) == np.finfo(np.float32).max
+    assert O.bin_scale(256, np.float32(3), np.float32(3)) == np.finfo(np.float32).max
+    assert O.bin_index(np.float32(3), np.float32(3), np.finfo(np.float32).max, 256) == 0
+
+
+def test_worked_example():
+    spec = {}
+    with open(os.path.join(GOLDEN, "worked_separable.txt")) as fh:
+        for ln in fh:
+            if ln.strip() and not ln.startswith("#"):
+                key, *vals = ln.split()
+                spec[key] = vals
+    v = np.array([float(t) for t in spec["values"]], np.float32)
+    y = np.array([int(t) for t in spec["labels"]], np.int32)
+    B = int(spec["bins"][0])
+    s = O.bin_scale(B, v.min(), v.max())
+    assert [O.bin_index(x, v.min(), s, B) for x in v] == [int(t) for t in spec["expect_bins"]]
+    sp, H, _ = one_node(v[None, :], y, 2, [[0]], [[1]], bins=B, hist=True)
+    assert sp["proj"] == 0 and sp["kind"] == 0
+    assert sp["bin"] == int(spec["expect_split_bin"][0])
+    assert sp["n_left"] == int(spec["expect_n_left"][0])
+    assert sp["gain"] == float(Fraction(int(spec["expect_gain_num"][0]), int(spec["expect_gain_den"][0])))
+    assert H[0].sum() == 4 and H[0, :, 0].sum() == 2
+
+
+# --------------------------------------------------------------------------
+# split search: brute force, closed forms, library, invariants
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", range(60))
+def test_sort_path_matches_bruteforce(seed):
+    rng = np.random.default_rng(1000 + seed)
+    n = int(rng.integers(2, 13))
+    C = int(rng.integers(2, 5))
+    d = 6
+    Xi = rng.integers(-3, 4, size=(d, n))
+    y = rng.integers(0, C, size=n).astype(np.int32)
+    k = int(rng.integers(1, 5))
+    feats, weights = random_projs(rng, k, d, 3)
+    vals = exact_values(Xi, feats, weights, range(n))
+    want = BF.best_threshold_split(vals, y.tolist(), C)
+    sp, _, _ = one_node(Xi.astype(np.float32), y, C, feats, weights, T=1 << 30)
+    assert sp["kind"] == 1
+    if want is None:
+        assert sp["proj"] == -1 and sp["gain"] == 0.0 and sp["n_left"] == n
+        return
+    g, p, t, n_left = want
+    assert sp["proj"] == p and sp["threshold"] == np.float32(t) and sp["n_left"] == n_left
+    assert sp["bin"] == n_left - 1 and sp["n_right"] == n - n_left
+    assert abs(Fraction(float(sp["gain"])) - g) <= g * Fraction(1, 2**50)
+
+
+@pytest.mark.parametrize("seed", range(120))
+def test_hist_path_matches_bruteforce(seed):
+    rng = np.random.default_rng(2000 + seed)
+    n = int(rng.integers(2, 13))
+    C = int(rng.integers(2, 5))
+    d = 5
+    amp = int(rng.choice([4, 1000]))
+    Xi = rng.integers(-amp, amp + 1, size=(d, n))
+    y = rng.integers(0, C, size=n).astype(np.int32)
+    k = int(rng.integers(1, 5))
+    B = int(rng.choice([2, 3, 4, 7, 8, 16, 100, 256]))
+    feats, weights = random_projs(rng, k, d, 3)
+    vals = exact_values(Xi, feats, weights, range(n))
+    bins = []
+    for vs in vals:
+        lo, hi = min(vs), max(vs)
+        row = []
+        # B/(hi-lo) exactly representable in binary32: then (v-lo)*scale is the
+        # exact rational e whenever e is an integer, and no edge is ambiguous
+        exact_scale = hi != lo and Fraction(float(np.float32(B) / np.float32(hi - lo))) == Fraction(B, hi - lo)
+        for v in vs:
+            if hi == lo:
+                row.append(0)
+                continue
+            e = Fraction(v - lo) * B / (hi - lo)
+            near = abs(e - round(e)) < Fraction(1, 10**5) * max(1, e)
+            if e < B and e != 0 and near and not (exact_scale and e.denominator == 1):
+                pytest.skip("a sample sits on a bin edge within rounding")
+            row.append(min(math.floor(e), B - 1))
+        bins.append(row)
+    want = BF.best_bin_split(bins, y.tolist(), C, B)
+    sp, H, _ = one_node(Xi.astype(np.float32), y, C, feats, weights, T=0, bins=B, hist=True)
+    assert sp["kind"] == 0
+    for p in range(k):
+        for b in range(B):
+            for c in range(C):
+                assert H[p, b, c] == sum(1 for kk, yy in zip(bins[p], y) if kk == b and yy == c)
+    if want is None:
+        assert sp["proj"] == -1 and sp["gain"] == 0.0
+        return
+    g, p, b, n_left = want
+    assert (sp["proj"], sp["bin"], sp["n_left"]) == (p, b, n_left)
+    assert abs(Fraction(float(sp["gain"])) - g) <= g * Fraction(1, 2**50)
+
+
+@pytest.mark.parametrize("seed", range(25))
+def test_hist_equals_sort_when_bins_hold_single_values(seed):
+    # small-integer projected values and B >= range + 1: each nonempty bin holds
+    # one distinct value, so both paths must pick the same partition
+    rng = np.random.default_rng(3000 + seed)
+    n = int(rng.integers(4, 200))
+    C = int(rng.integers(2, 5))
+    d = 8
+    X = rng.integers(0, 3, size=(d, n)).astype(np.float32)
+    y = rng.integers(0, C, size=n).astype(np.int32)
+    feats, weights = random_projs(rng, 6, d, 3)
+    sh, _, csr = one_node(X, y, C, feats, weights, T=0, bins=256)
+    ss, _, _ = one_node(X, y, C, feats, weights, T=1 << 30, bins=256)
+    assert sh["proj"] == ss["proj"]
+    assert sh["n_left"] == ss["n_left"] and sh["gain"] == ss["gain"]
+    if sh["proj"] >= 0:
+        no, si, po = np.array([0, n], np.int32), np.arange(n, dtype=np.int32), np.array([0, 6], np.int32)
+        a, _ = O.partition(X, no, si, po, *csr, sh[None], bins=256)
+        b, _ = O.partition(X, no, si, po, *csr, ss[None], bins=256)
+        assert np.array_equal(a, b)
+
+
+def test_closed_forms():
+    X = np.array([[0.0, 1.0, 2.0, 3.0]], np.float32)
+    y = np.array([0, 0, 1, 1], np.int32)
+    for T in (0, 1 << 30):
+        sp, _, _ = one_node(X, y, 2, [[0]], [[1]], T=T)
+        assert sp["gain"] == 0.5 and sp["n_left"] == 2          # separable: G = Gini(parent)
+    # three pure classes of sizes 2, 3, 5 separated by one threshold at best:
+    X3 = np.array([[0, 0, 1, 1, 1, 2, 2, 2, 2, 2]], np.float32)
+    y3 = np.array([0, 0, 1, 1, 1, 2, 2, 2, 2, 2], np.int32)
+    sp, _, _ = one_node(X3, y3, 3, [[0]], [[1]], T=1 << 30)
+    parent = 1 - Fraction(4 + 9 + 25, 100)
+    # split {0,1} | {2}: left Gini = 1 - (4+9)/25 = 12/25 with weight 1/2
+    g = parent - Fraction(1, 2) * Fraction(12, 25)
+    assert abs(Fraction(float(sp["gain"])) - g) < Fraction(1, 2**50)
+    # constant projection: no candidate
+    sp, _, _ = one_node(np.ones((1, 6), np.float32), np.array([0, 1] * 3, np.int32), 2, [[0]], [[1]])
+    assert sp["proj"] == -1 and sp["gain"] == 0.0
+    # pure node: no split
+    sp, _, _ = one_node(np.arange(6, dtype=np.float32)[None], np.zeros(6, np.int32), 2, [[0]], [[1]])
+    assert sp["proj"] == -1 and sp["n_left"] == 6
+
+
+def test_tie_rules():
+    rng = np.random.default_rng(5)
+    X = rng.standard_normal((4, 64)).astype(np.float32)
+    y = (X[1] > 0).astype(np.int32)
+    for T in (0, 1 << 30):
+        # the same projection at indices 0 and 1: the lower index wins
+        sp, _, _ = one_node(X, y, 2, [[1, 2], [1, 2]], [[1, -1], [1, -1]], T=T)
+        assert sp["proj"] == 0
+        # w and -w give mirrored splits with equal Gini: the lower index wins
+        sp, _, _ = one_node(X, y, 2, [[1], [1]], [[1], [-1]], T=T)
+        assert sp["proj"] == 0
+        sp, _, _ = one_node(X, y, 2, [[3], [1], [1]], [[1], [-1], [1]], T=T)
+        assert sp["proj"] == 1
+    # empty bins: the chosen bin is the last nonempty one on the left
+    Xe = np.array([[0.0, 0.0, 10.0, 10.0]], np.float32)
+    ye = np.array([0, 0, 1, 1], np.int32)
+    sp, H, _ = one_node(Xe, ye, 2, [[0]], [[1]], bins=256, hist=True)
+    assert sp["bin"] == 0 and H[0, 0].sum() == 2 and H[0, 255].sum() == 2
+    # symmetric counts (3,1 | 1,3) vs (1,3 | 3,1): equal Q, the lower index wins
+    Xs = np.array([[0, 0, 0, 1, 1, 1, 1, 0], [1, 1, 1, 0, 0, 0, 0, 1]], np.float32)
+    ys = np.array([0, 0, 0, 1, 1, 1, 0, 1], np.int32)
+    sp, _, _ = one_node(Xs, ys, 2, [[0], [1]], [[1], [1]], T=1 << 30)
+    assert sp["proj"] == 0
+
+
+def test_gain_matches_sklearn_cart():
+    sk = pytest.importorskip("sklearn.tree")
+    rng = np.random.default_rng(31)
+    for trial in range(20):
+        n = int(rng.integers(20, 400))
+        C = int(rng.integers(2, 5))
+        X = rng.standard_normal((3, n)).astype(np.float32)
+        y = rng.integers(0, C, size=n).astype(np.int32)
+        feats, weights = [[0, 2]], [[1, -1]]
+        sp, _, _ = one_node(X, y, C, feats, weights, T=1 << 30)
+        v = np.array([O.project_value(X, np.array([0, 2], np.int32), np.array([1, -1], np.int8), r)
+                      for r in range(n)], np.float32)
+        t = sk.DecisionTreeClassifier(max_depth=1, criterion="gini", random_state=0).fit(v[:, None], y)
+        if t.tree_.node_count == 1:
+            assert sp["proj"] == -1
+            continue
+        imp, cnt = t.tree_.impurity, t.tree_.n_node_samples
+        dec = imp[0] - cnt[1] / cnt[0] * imp[1] - cnt[2] / cnt[0] * imp[2]
+        assert sp["proj"] == 0
+        assert abs(sp["gain"] - dec) <= 1e-9 * max(dec, 1e-12)
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_invariants_random_frontier(seed):
+    from paper_2603_00326_amd import workloads as W
+    rng = np.random.default_rng(seed)
+    sizes = rng.integers(0, 300, size=12)
+    C = int(rng.integers(2, 8))
+    wl = W.random_frontier(4000 + seed, n_rows=2000, d=20, n_classes=C, sizes=sizes, k=8, z=3,
+                           bins=int(rng.choice([16, 128, 256])), sort_threshold=int(rng.integers(0, 200)))
+    sp, H = O.find_splits_w(wl, hist=True)
+    for v in range(wl.n_nodes):
+        a, b = wl.node_offsets[v], wl.node_offsets[v + 1]
+        yy = wl.y[wl.sample_idx[a:b]]
+        n = b - a
+        assert sp[v]["n_left"] + sp[v]["n_right"] == n
+        parent = [int((yy == c).sum()) for c in range(C)]
+        g_parent = 1 - sum(Fraction(p, n) ** 2 for p in parent) if n else 0
+        if sp[v]["proj"] >= 0:
+            assert 0 < sp[v]["gain"] <= float(g_parent) * (1 + 1e-12)
+            assert sp[v]["n_left"] >= 1 and sp[v]["n_right"] >= 1
+        else:
+            assert sp[v]["gain"] == 0
+        hist_node = n >= wl.sort_threshold
+        assert sp[v]["kind"] == (0 if hist_node else 1)
+        for q in range(wl.proj_offsets[v], wl.proj_offsets[v + 1]):
+            if hist_node:
+                assert H[q].sum() == n
+                assert H[q].sum(axis=0).tolist() == parent
+            else:
+                assert H[q].sum() == 0
+    # partition: a stable permutation with the split's left count
+    out, co = O.partition(wl.X, wl.node_offsets, wl.sample_idx, wl.proj_offsets, wl.nz_offsets,
+                          wl.nz_feature, wl.nz_weight, sp, bins=wl.bins)
+    for v in range(wl.n_nodes):
+        a, b = wl.node_offsets[v], wl.node_offsets[v + 1]
+        assert co[2 * v] == a and co[2 * v + 1] - a == sp[v]["n_left"]
+        assert sorted(out[a:b].tolist()) == sorted(wl.sample_idx[a:b].tolist())
+        src = wl.sample_idx[a:b].tolist()
+        left, right = out[a:co[2 * v + 1]].tolist(), out[co[2 * v + 1]:b].tolist()
+        pos = {}
+        for i, r in enumerate(src):
+            pos.setdefault(r, []).append(i)
+        # order preserved within each child (positions in the input increase)
+        for part in (left, right):
+            seen = {}
+            last = -1
+            for r in part:
+                i = pos[r][seen.get(r, 0)]
+                seen[r] = seen.get(r, 0) + 1
+                assert i > last
+                last = i
+    assert co[-1] == wl.node_offsets[-1]
+
+
+def test_partition_matches_list_comprehension_on_integer_data():
+    rng = np.random.default_rng(41)
+    d, n = 6, 300
+    Xi = rng.integers(-5, 6, size=(d, n))
+    X = Xi.astype(np.float32)
+    y = rng.integers(0, 3, size=n).astype(np.int32)
+    idx = rng.permutation(n)[:200].astype(np.int32)
+    feats, weights = random_projs(rng, 5, d, 3)
+    for T in (0, 1 << 30):
+        sp, _, csr = one_node(X, y, 3, feats, weights, T=T, idx=idx)
+        if sp["proj"] < 0:
+            continue
+        vals = exact_values(Xi, [feats[sp["proj"]]], [weights[sp["proj"]]], idx)[0]
+        if T:
+            goes = [v <= float(sp["threshold"]) for v in vals]
+        else:
+            lo, hi = min(vals), max(vals)
+            goes = [min(math.floor(Fraction(v - lo) * 256 / (hi - lo)), 255) <= sp["bin"] for v in vals]
+        want = [r for r, g in zip(idx, goes) if g] + [r for r, g in zip(idx, goes) if not g]
+        got, co = O.partition(X, np.array([0, len(idx)], np.int32), idx, np.array([0, 5], np.int32),
+                              *csr, sp[None], bins=256)
+        assert got.tolist() == [int(r) for r in want] and co[1] == sum(goes)
+
+
+def test_fp16_storage_equals_fp32_storage():
+    from paper_2603_00326_amd import workloads as W
+    X32 = W.grid_matrix(3, 5000, 16)
+    rng = np.random.default_rng(3)
+    y = rng.integers(0, 2, size=5000).astype(np.int32)
+    po, no, nf, nw = W.random_projections(rng, 1, 24, 16, (1, 8))
+    args = (np.array([0, 5000], np.int32), np.arange(5000, dtype=np.int32), po, no, nf, nw)
+    a, Ha = O.find_splits(X32, y, 2, *args, hist=True)
+    b, Hb = O.find_splits(X32.astype(np.float16), y, 2, *args, hist=True)
+    assert a.tobytes() == b.tobytes() and np.array_equal(Ha, Hb)
+
+
+# --------------------------------------------------------------------------
+# growth
+# --------------------------------------------------------------------------
+
+def _route(nodes, X, r, root):
+    i = root
+    while not nodes[i]["is_leaf"]:
+        nd = nodes[i]
+        z = nd["nnz"]
+        v = O.project_value(X, nd["feature"][:z], nd["weight"][:z], r)
+        if nd["kind"] == 0:
+            left = O.bin_index(v, nd["lo"], nd["scale"], nd["n_bins"]) <= nd["bin"]
+        else:
+            left = v <= nd["threshold"]
+        i = nd["left"] if left else nd["right"]
+    return i
+
+
+def test_growth_to_purity_small():
+    rng = np.random.default_rng(51)
+    d, n, C = 10, 400, 3
+    X = rng.standard_normal((d, n)).astype(np.float32)
+    y = rng.integers(0, C, size=n).astype(np.int32)
+    roots = [np.sort(np.random.default_rng(t).integers(0, n, n)).astype(np.int32) for t in range(3)]
+    ro = np.array([0, n, 2 * n, 3 * n], np.int64)
+    ri = np.concatenate(roots)
+    nodes, ln, lu = O.grow_forest(X, y, C, ro, ri, k=6, z=2, seed=9, bins=64, sort_threshold=50)
+    assert ln[0] == 3
+    for t in range(3):
+        for r in roots[t]:
+            leaf = _route(nodes, X, int(r), t)
+            assert nodes[leaf]["tree"] == t
+    leaves = nodes[nodes["is_leaf"] == 1]
+    internal = nodes[nodes["is_leaf"] == 0]
+    assert np.all(internal["gain"] > 0)
+    # every sample of each tree lands in exactly one leaf: leaf sizes sum to n
+    for t in range(3):
+        assert leaves[leaves["tree"] == t]["n_samples"].sum() == n
+    # children sizes add up
+    for nd in internal:
+        assert nodes[nd["left"]]["n_samples"] + nodes[nd["right"]]["n_samples"] == nd["n_samples"]
+    # training accuracy on the bootstrap rows is 100% (continuous features: no
+    # duplicate rows with different labels)
+    acc = np.mean([nodes[_route(nodes, X, int(r), t)]["label"] == y[r]
+                   for t in range(3) for r in roots[t]])
+    assert acc == 1.0
+
+
+def renumber_tree(nodes, t):
+    """Nodes of tree t with ids rewritten to the tree's own creation order."""
+    sel = np.nonzero(nodes["tree"] == t)[0]
+    remap = {int(g): i for i, g in enumerate(sel)}
+    out = nodes[sel].copy()
+    for f in ("parent", "left", "right"):
+        out[f] = [remap.get(int(g), -1) if g >= 0 else -1 for g in out[f]]
+    return out
+
+
+def test_growth_batched_equals_single_tree():
+    rng = np.random.default_rng(52)
+    d, n, C = 8, 300, 2
+    X = rng.standard_normal((d, n)).astype(np.float32)
+    y = rng.integers(0, C, size=n).astype(np.int32)
+    roots = [np.sort(np.random.default_rng(100 + t).integers(0, n, n)).astype(np.int32) for t in range(3)]
+    ro = np.array([0, n, 2 * n, 3 * n], np.int64)
+    nodes, _, _ = O.grow_forest(X, y, C, ro, np.concatenate(roots), k=5, z=2, seed=4, bins=32,
+                                sort_threshold=20)
+    for t in range(3):
+        single, _, _ = O.grow_forest(X, y, C, np.array([0, n], np.int64), roots[t], k=5, z=2, seed=4,
+                                     bins=32, sort_threshold=20, first_tree=t)
+        assert renumber_tree(nodes, t).tobytes() == single.tobytes()
