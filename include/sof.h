@@ -1,0 +1,254 @@
+/*
+ * sof.h -- split search for sparse oblique forests on AMD Instinct MI355X
+ * (gfx950).  C ABI: plain pointers and sizes, no C++ or framework types.
+ *
+ * The method is the per-node split search of "Vectorized Adaptive Histograms
+ * for Sparse Oblique Forests" (section 4, steps 1-3; section 4.1 for the
+ * switch between histograms and sorting; section 4.3 for the data resident on
+ * the device and a call that returns the best projection and its split).  For
+ * every node of a frontier and each of its sparse projections the library
+ *   1. forms the projected value of every active sample, a +/-1 weighted sum
+ *      of a few feature columns accumulated in FP32 in CSR order from +0.0f;
+ *   2. builds per-class counts over equal-width bins spanning the node's
+ *      [min, max] of that projection (histogram path), or sorts the projected
+ *      values when the node has fewer than the sort threshold samples;
+ *   3. scans the bin (or sorted-sample) boundaries for the largest Gini
+ *      impurity decrease, compared exactly in integers, and keeps the best over
+ *      projections (ties: lowest projection, then lowest bin or position);
+ * and then stably partitions each node's sample indices between its children.
+ *
+ * Conventions shared by every call:
+ *  - Array pointers inside sof_data / sof_frontier / sof_proj / sof_params and
+ *    every output pointer are DEVICE pointers owned by the caller; the library
+ *    never frees caller memory.  Host-side counts in those structs must match
+ *    the device arrays (checked on the device only when SOF_CHECK=1 is set in
+ *    the environment; otherwise a mismatch is undefined behaviour).
+ *  - Compute calls are asynchronous on `stream` (a hipStream_t passed as void*,
+ *    NULL = the default stream), allocate nothing and do not synchronise; they
+ *    can be captured in a HIP graph.  sof_create, sof_forest_create,
+ *    sof_forest_frontier_size, sof_forest_export and sof_autotune allocate
+ *    and/or synchronise.
+ *  - Every call returns a status; sof_last_error() gives a thread-local message
+ *    for the last failure.  Host-side argument checks run before any launch
+ *    and need no GPU.
+ *
+ * Data layout:
+ *  - features: x[f * ld + r] for feature f < n_features and row r < n_rows
+ *    (column store: each feature contiguous), FP32 or FP16;
+ *  - labels: int32 y[r] in [0, n_classes);
+ *  - frontier: node v owns sample_idx[node_offsets[v] .. node_offsets[v+1]);
+ *  - projections (CSR): node v owns projections proj_offsets[v] ..
+ *    proj_offsets[v+1]; projection q owns nonzeros nz_offsets[q] ..
+ *    nz_offsets[q+1] with feature ids nz_feature[] (distinct within a
+ *    projection) and weights nz_weight[] in {-1, +1}.
+ */
+#ifndef SOF_H
+#define SOF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define SOF_OK               0
+#define SOF_ERR_INVALID_ARG (-1)  /* a null pointer, a size out of range, inconsistent counts */
+#define SOF_ERR_UNSUPPORTED (-2)  /* dtype, class count, bin count or device not supported */
+#define SOF_ERR_WORKSPACE   (-3)  /* workspace missing, too small or misaligned */
+#define SOF_ERR_OVERFLOW    (-4)  /* a node above 2^24 samples, totals above 2^31-1 */
+#define SOF_ERR_HIP         (-5)  /* a HIP runtime call failed; the message names it */
+#define SOF_ERR_DEVICE      (-6)  /* a device-side content check failed (SOF_CHECK=1) */
+
+/* feature storage types */
+#define SOF_F32 0
+#define SOF_F16 1
+
+/* limits */
+#define SOF_MAX_BINS         256
+#define SOF_MIN_BINS         2
+#define SOF_MAX_CLASSES      16
+#define SOF_MAX_NNZ          16          /* nonzeros per projection */
+#define SOF_MAX_NODE_SAMPLES (1 << 24)   /* exact 128-bit comparisons need n <= 2^24 */
+#define SOF_SORT_LIMIT       8192        /* largest node that can take the sort path */
+#define SOF_WORKSPACE_ALIGN  256
+
+/* split kinds */
+#define SOF_SPLIT_HIST 0
+#define SOF_SPLIT_SORT 1
+
+typedef struct sof_ctx sof_ctx;
+typedef struct sof_forest sof_forest;
+
+typedef struct {
+    const void*    x;           /* device, x[f * ld + r] */
+    const int32_t* y;           /* device, n_rows labels */
+    int64_t        ld;          /* >= n_rows */
+    int32_t        n_rows;
+    int32_t        n_features;
+    int32_t        n_classes;   /* 2..SOF_MAX_CLASSES */
+    int32_t        dtype;       /* SOF_F32 or SOF_F16 */
+} sof_data;
+
+typedef struct {
+    const int32_t* node_offsets;  /* device, n_nodes + 1, non-decreasing, [0] = 0 */
+    const int32_t* sample_idx;    /* device, n_samples row ids (repeats allowed) */
+    int64_t        n_samples;     /* = node_offsets[n_nodes] */
+    int32_t        n_nodes;
+    int32_t        max_node_samples; /* >= every node's sample count (host-known bound) */
+} sof_frontier;
+
+typedef struct {
+    const int32_t* proj_offsets;  /* device, n_nodes + 1 */
+    const int32_t* nz_offsets;    /* device, n_proj + 1 */
+    const int32_t* nz_feature;    /* device, n_nz */
+    const int8_t*  nz_weight;     /* device, n_nz, each -1 or +1 */
+    int64_t        n_nz;          /* = nz_offsets[n_proj] */
+    int32_t        n_proj;        /* = proj_offsets[n_nodes] */
+    int32_t        max_proj_per_node; /* >= every node's projection count, <= 1024 */
+} sof_proj;
+
+typedef struct {
+    const int32_t* node_bins;     /* device, n_nodes bin counts in [2, bins], or NULL */
+    int32_t        bins;          /* 2..SOF_MAX_BINS: bin count when node_bins is NULL, else the maximum */
+    int32_t        sort_threshold;/* nodes with n < min(T, SOF_SORT_LIMIT + 1) sort; 0 = all histogram */
+} sof_params;
+
+/* Best split of one node (section 4.3: the projection and its split value). */
+typedef struct {
+    int32_t proj;       /* node-local index of the winning projection, -1 = no split */
+    int32_t kind;       /* SOF_SPLIT_HIST or SOF_SPLIT_SORT: the node's path (also without a split) */
+    int32_t bin;        /* hist: left iff bin(v) <= bin; sort: sorted position, left = first bin+1; -1 */
+    float   threshold;  /* sort: left iff v <= threshold; hist: lo + (bin+1)/scale, informational */
+    float   lo;         /* min projected value of the winner */
+    float   scale;      /* hist: bins / (hi - lo), FLT_MAX if that is not finite; sort: 0 */
+    int32_t n_left;     /* no split: n_left = n, n_right = 0 */
+    int32_t n_right;
+    int32_t flags;      /* bit 0: left child pure, bit 1: right child pure */
+    float   gain;       /* Gini(parent) - weighted Gini(children) in FP32; 0 without a split */
+} sof_split;
+
+/* Node of an exported tree.  Ids are positions in the forest's creation
+ * order: roots first, then level by level, children in frontier order, left
+ * before right. */
+typedef struct {
+    int32_t tree, depth, parent, left, right;   /* -1 where absent */
+    int32_t n_samples, label, is_leaf;          /* label: majority class, lowest id on ties */
+    int32_t kind, bin;                          /* split rule (kind -1 for leaves) */
+    float   threshold, lo, scale;
+    int32_t n_bins, nnz, pad;
+    int32_t feature[16];                        /* the winning projection */
+    int8_t  weight[16];
+    double  gain;
+} sof_tree_node;
+
+typedef struct {
+    const int64_t* root_offsets;  /* HOST, n_trees + 1: tree t owns root_idx[root_offsets[t] ..) */
+    const int32_t* root_idx;      /* device, root sample ids of every tree (e.g. a bootstrap) */
+    uint64_t       seed;          /* projection sampler seed */
+    int32_t        n_trees;
+    int32_t        first_tree;    /* tree ids first_tree .. first_tree+n_trees-1 key the sampler */
+    int32_t        k;             /* projections per node, 1..1024 */
+    int32_t        z;             /* nonzeros per projection, 1..15, <= n_features */
+    int32_t        bins;          /* 2..256 */
+    int32_t        sort_threshold;
+    int32_t        max_depth;     /* 0..64: nodes at this depth become leaves */
+    int32_t        pad;
+} sof_forest_desc;
+
+typedef struct {
+    int32_t sort_threshold;   /* chosen histogram/sort switch T */
+    int32_t bins_small;       /* bin count for nodes below bins_switch */
+    int32_t bins_switch;      /* nodes with n < bins_switch use bins_small, others the caller's bins */
+    int32_t n_points;         /* measured sizes */
+    float   sort_us[32];      /* per measured size: sort-path time per node-projection (us) */
+    float   hist_us[32];      /* per measured size: histogram-path time per node-projection (us) */
+    int32_t sizes[32];
+    float   elapsed_ms;       /* wall time of the whole tuning run */
+} sof_tune;
+
+/* ---------------------------------------------------------------------- */
+
+/* Library version string (static storage). */
+const char* sof_version(void);
+
+/* Message for the last failed call on this thread ("" if none). */
+const char* sof_last_error(void);
+
+/* Create a context on HIP device `device`: checks the architecture (gfx950),
+ * sizes the persistent launches from the device's compute-unit count and
+ * occupancy.  Allocates host memory only.  Errors: SOF_ERR_INVALID_ARG (null
+ * out), SOF_ERR_HIP, SOF_ERR_UNSUPPORTED (not gfx950). */
+int sof_create(int device, sof_ctx** out);
+int sof_destroy(sof_ctx* ctx);
+
+/* Bytes of device workspace that sof_project, sof_find_splits and
+ * sof_partition need for these sizes (the maximum over the three).  Pure host
+ * arithmetic; runs without a GPU when ctx is NULL.  Errors as the calls. */
+int sof_workspace_size(const sof_ctx* ctx, const sof_data* data, const sof_frontier* frontier,
+                       const sof_proj* proj, const sof_params* params, size_t* bytes);
+
+/* Step 1 alone (section 4, step 1): projected values of every (node,
+ * projection, sample), node blocks in node order, each block [projection]
+ * [sample] in frontier sample order.  out has sum_v k_v * n_v floats.
+ * ws: device workspace of at least sof_workspace_size bytes, 256-byte aligned. */
+int sof_project(sof_ctx* ctx, const sof_data* data, const sof_frontier* frontier,
+                const sof_proj* proj, float* out, void* ws, size_t ws_bytes, void* stream);
+
+/* Steps 1-3 for a whole frontier in one batched launch sequence: writes the
+ * best split of every node to out[n_nodes].  hist_out (optional, NULL to skip)
+ * receives int32 counts [n_proj][params->bins][n_classes] for histogram-path
+ * nodes (entries beyond a node's bin count and all entries of sort-path nodes
+ * are zero).  Errors: SOF_ERR_INVALID_ARG, SOF_ERR_UNSUPPORTED,
+ * SOF_ERR_WORKSPACE, SOF_ERR_OVERFLOW, SOF_ERR_HIP. */
+int sof_find_splits(sof_ctx* ctx, const sof_data* data, const sof_frontier* frontier,
+                    const sof_proj* proj, const sof_params* params, sof_split* out,
+                    int32_t* hist_out, void* ws, size_t ws_bytes, void* stream);
+
+/* Stable partition (section 4: each node splits its samples between its
+ * children): out_idx (same size as sample_idx, must not alias it) receives,
+ * per node, the samples going left in input order then those going right in
+ * input order, re-evaluating the split rule on recomputed projected values.
+ * child_offsets[2N+1]: [2v] = node start, [2v+1] = start of the right block,
+ * [2N] = n_samples.  A node without a split keeps all samples on the left.
+ * The left count is measured, not taken from splits[v].n_left. */
+int sof_partition(sof_ctx* ctx, const sof_data* data, const sof_frontier* frontier,
+                  const sof_proj* proj, const sof_params* params, const sof_split* splits,
+                  int32_t* out_idx, int32_t* child_offsets, void* ws, size_t ws_bytes,
+                  void* stream);
+
+/* Forest growth to purity, level by level (sections 2 and 4.1: trees trained
+ * to purity; section 6: several nodes and trees batched into single launches).
+ * sof_forest_create allocates the forest's device state (frontier buffers,
+ * node table, workspace) for the trees in desc; data must stay valid. */
+int sof_forest_create(sof_ctx* ctx, const sof_data* data, const sof_forest_desc* desc,
+                      sof_forest** out);
+int sof_forest_destroy(sof_forest* forest);
+
+/* One level for every tree: sample k projections per frontier node on the
+ * device (counter-based SplitMix64 hash, Floyd's distinct sampling), find the
+ * splits, partition, record nodes and build the next frontier.  Asynchronous;
+ * replays a captured HIP graph per level when use_graph is nonzero. */
+int sof_grow_level(sof_forest* forest, int use_graph, void* stream);
+
+/* Nodes in the current frontier (0 = the forest is complete).  Synchronises
+ * the stream (one 4-byte device-to-host copy). */
+int sof_forest_frontier_size(sof_forest* forest, int64_t* n_nodes, void* stream);
+
+/* Copy the node table to host memory (synchronises).  *n receives the node
+ * count; SOF_ERR_INVALID_ARG when cap is smaller. */
+int sof_forest_export(sof_forest* forest, sof_tree_node* host_nodes, int64_t cap, int64_t* n,
+                      void* stream);
+
+/* Crossover microbenchmark (section 4.1: run once before training): times the
+ * sort and histogram paths on synthetic frontiers of growing node size on this
+ * device and picks the sort threshold (first size where histograms win) and
+ * a bin-count switch for small nodes.  Allocates and synchronises. */
+int sof_autotune(sof_ctx* ctx, int32_t n_classes, int32_t k, int32_t nnz, int32_t bins,
+                 sof_tune* out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SOF_H */

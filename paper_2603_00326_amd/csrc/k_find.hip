@@ -1,0 +1,1144 @@
+// k_find.hip -- batched split search over a whole frontier (paper section 4,
+// steps 1-3; section 4.1 for the per-node choice between histograms and
+// sorting; section 6 names batching many nodes into one GPU launch as the
+// next step, which is what this launch sequence does).
+//
+// Launch sequence on one stream (every launch is a persistent grid that reads
+// its work counts from device memory, so the sequence is graph-capturable):
+//   k_reset    zero the queue counters
+//   k_plan     classify nodes by path and size, allocate queue entries
+//   k_expand   write the (descriptor, sub-item) entries of every queue
+//   k_main     big-node min/max chunks, mid nodes (one block per node and
+//              projection), small nodes (one block per node, one wave per
+//              projection); all single pass, projected values in registers
+//   k_sortblk  sort-path nodes of 65..8192 samples: bitonic sort in LDS
+//   k_bighist  big-node histogram chunks (second pass after the global range)
+//   k_bigscan  big-node boundary scans
+//   k_reduce   best projection per node for nodes with per-projection slots
+#include "sof_device.h"
+#include "sof_internal.h"
+
+namespace sof {
+
+enum { CAT_NONE = 0, CAT_NOSPLIT, CAT_SMALL, CAT_MID, CAT_SB, CAT_BIG };
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ int64_t clamp64(int64_t x, int64_t lo, int64_t hi) {
+    return x < lo ? lo : (x > hi ? hi : x);
+}
+
+__device__ __forceinline__ int n_nodes_of(const FindArgs& A) {
+    if (!A.n_nodes_dev) return A.n_nodes;
+    int n = *A.n_nodes_dev;
+    return n < 0 ? 0 : (n > A.n_nodes ? A.n_nodes : n);
+}
+
+__device__ __forceinline__ void node_range(const FindArgs& A, int v, int64_t& s0, int64_t& n) {
+    int64_t a = clamp64(A.node_offsets[v], 0, A.n_samples);
+    int64_t b = clamp64(A.node_offsets[v + 1], a, A.n_samples);
+    s0 = a;
+    n = b - a;
+}
+
+__device__ __forceinline__ int node_bins(const FindArgs& A, int v) {
+    if (!A.node_bins) return A.bins;
+    int b = A.node_bins[v];
+    return b < 2 ? 2 : (b > A.bins ? A.bins : b);
+}
+
+__device__ __forceinline__ int row_of(const FindArgs& A, int64_t at) {
+    uint32_t r = (uint32_t)A.sample_idx[at];
+    return r < (uint32_t)A.n_rows ? (int)r : 0;
+}
+
+__device__ __forceinline__ int label_of(const FindArgs& A, int row) {
+    uint32_t c = (uint32_t)A.y[row];
+    return c < (uint32_t)A.n_classes ? (int)c : 0;
+}
+
+// ---------------------------------------------------------------------------
+// projection sources
+
+__device__ __forceinline__ int proj_count(const ProjCSR& P, int v) {
+    int a = (int)clamp64(P.proj_offsets[v], 0, P.n_proj);
+    int b = (int)clamp64(P.proj_offsets[v + 1], a, P.n_proj);
+    return b - a;
+}
+__device__ __forceinline__ int proj_global(const ProjCSR& P, int v, int p) {
+    return (int)clamp64(P.proj_offsets[v], 0, P.n_proj) + p;
+}
+// Stage the nonzeros of node-local projection p into per-wave LDS (called by
+// a whole wave).  Returns z.
+__device__ __forceinline__ int proj_stage(const ProjCSR& P, int v, int p, int d, int32_t* lf,
+                                          uint32_t* ls) {
+    int q = proj_global(P, v, p);
+    int64_t j0 = clamp64(P.nz_offsets[q], 0, P.n_nz);
+    int64_t j1 = clamp64(P.nz_offsets[q + 1], j0, P.n_nz);
+    if (j1 - j0 > SOF_MAX_NNZ) j1 = j0 + SOF_MAX_NNZ;
+    int z = (int)(j1 - j0);
+    int lane = lane_id();
+    if (lane < z) {
+        uint32_t f = (uint32_t)P.nz_feature[j0 + lane];
+        lf[lane] = f < (uint32_t)d ? (int)f : 0;
+        ls[lane] = P.nz_weight[j0 + lane] < 0 ? 0x80000000u : 0u;
+    }
+    wave_sync();
+    return z;
+}
+
+// SplitMix64 (Steele, Lea and Flood, OOPSLA 2014): the c-th output of the
+// stream started at `seed`.
+__device__ __forceinline__ uint64_t splitmix_at(uint64_t seed, uint64_t c) {
+    uint64_t z = seed + c * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+__device__ __forceinline__ uint64_t draw_counter(int tree, int level, int pos, int p, int draw) {
+    uint64_t c = (uint64_t)tree * 64u + (uint64_t)level;
+    c = (c << 24) + (uint64_t)pos;
+    c = (c << 10) + (uint64_t)p;
+    return (c << 4) + (uint64_t)draw;
+}
+
+__device__ __forceinline__ int proj_count(const ProjHash& P, int) { return P.k; }
+__device__ __forceinline__ int proj_global(const ProjHash& P, int v, int p) { return v * P.k + p; }
+// z distinct features by Floyd's sampling (Bentley and Floyd, CACM 1987):
+// draw j (j = 0..z-1) proposes t uniform in [0, d-z+j] by multiply-shift of
+// the hash's top 32 bits; a proposal already taken is replaced by d-z+j.
+// Features are stored ascending; sign of the s-th = bit s of draw 15.
+__device__ __forceinline__ int proj_stage(const ProjHash& P, int v, int p, int d, int32_t* lf,
+                                          uint32_t* ls) {
+    const int lane = lane_id();
+    const int z = P.z;
+    const int tree = P.tree_of[v], pos = P.pos_of[v], level = *P.level;
+    uint32_t t = 0;
+    if (lane < z) {
+        uint32_t top = (uint32_t)(d - z + lane) + 1u;
+        uint64_t r = splitmix_at(P.seed, draw_counter(tree, level, pos, p, lane));
+        t = (uint32_t)(((r >> 32) * (uint64_t)top) >> 32);
+    }
+    int mine = (int)t;
+    for (int j = 0; j < z; ++j) {
+        int cj = __shfl((int)t, j);
+        bool taken = __ballot(lane < j && mine == cj) != 0ull;
+        if (lane == j) mine = taken ? d - z + j : cj;
+    }
+    int rank = 0;
+    for (int i = 0; i < z; ++i) {
+        int ci = __shfl(mine, i);
+        rank += (ci < mine) ? 1 : 0;
+    }
+    uint64_t sg = splitmix_at(P.seed, draw_counter(tree, level, pos, p, 15));
+    if (lane < z) {
+        lf[rank] = mine;
+        ls[rank] = ((sg >> rank) & 1ull) ? 0x80000000u : 0u;
+    }
+    wave_sync();
+    return z;
+}
+
+// ---------------------------------------------------------------------------
+// allocation helpers
+
+// Wave-aggregated atomic allocation: returns this lane's base for cnt entries.
+__device__ __forceinline__ int wave_alloc(int32_t* ctr, int cnt) {
+    uint32_t incl = wave_incl_scan((uint32_t)cnt);
+    uint32_t total = __shfl(incl, 63);
+    int base = 0;
+    if (lane_id() == 63 && total) base = atomicAdd(ctr, (int)total);
+    base = __shfl(base, 63);
+    return base + (int)(incl - (uint32_t)cnt);
+}
+
+__device__ __forceinline__ int block_dequeue(int32_t* ctr, int* s_item) {
+    __syncthreads();
+    if (threadIdx.x == 0) *s_item = atomicAdd(ctr, 1);
+    __syncthreads();
+    return *s_item;
+}
+
+__device__ __forceinline__ int count_of(const FindArgs& A, int h, int64_t cap) {
+    int c = A.ws.hdr[h];
+    return (int)(c < 0 ? 0 : (c > cap ? cap : c));
+}
+
+__device__ __forceinline__ void write_nosplit(const FindArgs& A, int v, int kind, int64_t n) {
+    SplitRec* o = (SplitRec*)A.out + v;
+    SplitRec r;
+    r.proj = -1; r.kind = kind; r.bin = -1; r.threshold = 0.f; r.lo = 0.f; r.scale = 0.f;
+    r.n_left = (int32_t)n; r.n_right = 0; r.flags = 0; r.gain = 0.f;
+    *o = r;
+}
+
+// hist_out row of global projection q from a count accessor (lanes of one wave)
+template <class H>
+__device__ __forceinline__ void write_hist_row(const FindArgs& A, int q, const H& h, int B) {
+    if (!A.hist_out) return;
+    const int C = A.n_classes, Bm = A.bins;
+    int32_t* row = A.hist_out + (int64_t)q * Bm * C;
+    for (int e = lane_id(); e < Bm * C; e += kWave) {
+        int b = e / C, c = e - b * C;
+        row[e] = b < B ? (int32_t)h(b, c) : 0;
+    }
+}
+__device__ __forceinline__ void write_zero_row(const FindArgs& A, int q) {
+    if (!A.hist_out) return;
+    const int n = A.bins * A.n_classes;
+    int32_t* row = A.hist_out + (int64_t)q * n;
+    for (int e = lane_id(); e < n; e += kWave) row[e] = 0;
+}
+
+struct LdsHist {
+    const int32_t* h;
+    int C;
+    __device__ uint32_t operator()(int b, int c) const { return (uint32_t)h[b * C + c]; }
+};
+struct LdsHist4 {   // sum of the four wave-private copies
+    const int32_t* h;
+    int C, stride;
+    __device__ uint32_t operator()(int b, int c) const {
+        int e = b * C + c;
+        return (uint32_t)(h[e] + h[e + stride] + h[e + 2 * stride] + h[e + 3 * stride]);
+    }
+};
+struct GlobalHist {
+    const int32_t* h;
+    int C;
+    __device__ uint32_t operator()(int b, int c) const { return (uint32_t)h[b * C + c]; }
+};
+
+// ---------------------------------------------------------------------------
+// boundary scans (one wave)
+
+// Histogram path: lane l owns bins 4l..4l+3.  Class-by-class wave prefix sums
+// give every boundary's left counts; the best boundary (largest Q, lowest bin)
+// wins.  Parent counts are the column totals.
+template <class H>
+__device__ Cand scan_hist(const H& h, int B, int C, int64_t n, float lo, float scale) {
+    const int lane = lane_id();
+    uint32_t nL[4] = {0, 0, 0, 0};
+    uint64_t SL[4] = {0, 0, 0, 0}, SR[4] = {0, 0, 0, 0};
+    uint64_t SP = 0;
+    for (int c = 0; c < C; ++c) {
+        uint32_t s[4];
+        uint32_t acc = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            int b = lane * 4 + i;
+            acc += b < B ? h(b, c) : 0u;
+            s[i] = acc;
+        }
+        uint32_t incl = wave_incl_scan(acc);
+        uint32_t excl = incl - acc;
+        uint32_t Pc = __shfl(incl, 63);
+        SP += (uint64_t)Pc * Pc;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            uint32_t l = excl + s[i];
+            uint32_t r = Pc - l;
+            nL[i] += l;
+            SL[i] += (uint64_t)l * l;
+            SR[i] += (uint64_t)r * r;
+        }
+    }
+    bool bv = false;
+    u128 bN = 0;
+    uint64_t bD = 0, bSL = 0, bSR = 0;
+    int bpos = 0;
+    uint32_t bnL = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        int b = lane * 4 + i;
+        u128 N;
+        uint64_t D;
+        if (b < B - 1 && make_q((int64_t)nL[i], n - (int64_t)nL[i], SL[i], SR[i], N, D)) {
+            if (!bv || q_greater(N, D, bN, bD)) {
+                bv = true; bN = N; bD = D; bpos = b; bnL = nL[i]; bSL = SL[i]; bSR = SR[i];
+            }
+        }
+    }
+    int win = wave_best_lane(bv, bN, bD, bpos);
+    Cand c;
+    cand_invalid(c);
+    c.SP = SP;
+    c.lo = lo;
+    c.scale = scale;
+    if (win >= 0) {
+        uint64_t nlo = __shfl((uint64_t)bN, win), nhi = __shfl((uint64_t)(bN >> 64), win);
+        c.N = ((u128)nhi << 64) | nlo;
+        c.D = __shfl(bD, win);
+        c.SL = __shfl(bSL, win);
+        c.SR = __shfl(bSR, win);
+        c.pos = __shfl(bpos, win);
+        c.nL = (int32_t)__shfl(bnL, win);
+        c.nR = (int32_t)(n - c.nL);
+        c.thr = hist_threshold(lo, scale, c.pos);
+    }
+    return c;
+}
+
+// Sort path for n <= 64: lane i holds (v_i, y_i); a bitonic network across
+// the wave sorts the (order-preserving key, label) pairs; left counts at
+// sorted position i come from per-class ballots; boundaries only between
+// distinct values.
+__device__ Cand scan_sort_wave(float val, int lab, int64_t n, int C, const int32_t* pc) {
+    const int lane = lane_id();
+    uint64_t key = lane < n ? (((uint64_t)fkey(val) << 32) | (uint32_t)lab) : ~0ull;
+#pragma unroll
+    for (int kk = 2; kk <= kWave; kk <<= 1) {
+#pragma unroll
+        for (int j = kk >> 1; j > 0; j >>= 1) {
+            uint64_t o = __shfl_xor(key, j);
+            bool asc = (lane & kk) == 0;
+            bool lower = (lane & j) == 0;
+            key = (asc == lower) ? (o < key ? o : key) : (o > key ? o : key);
+        }
+    }
+    const uint32_t myk = (uint32_t)(key >> 32);
+    const int mylab = (int)(uint32_t)key;
+    const uint32_t nextk = __shfl_down(myk, 1);
+    const bool real = lane < n;
+    const uint64_t le = lanes_le_mask();
+    uint64_t SL = 0, SR = 0, SP = 0;
+    for (int c = 0; c < C; ++c) {
+        uint64_t m = __ballot(real && mylab == c);
+        uint32_t l = (uint32_t)__popcll(m & le);
+        uint32_t Pc = (uint32_t)pc[c];
+        uint32_t r = Pc - l;
+        SL += (uint64_t)l * l;
+        SR += (uint64_t)r * r;
+        SP += (uint64_t)Pc * Pc;
+    }
+    u128 N = 0;
+    uint64_t D = 0;
+    bool ok = lane + 1 < n && myk < nextk &&
+              make_q((int64_t)lane + 1, n - (int64_t)lane - 1, SL, SR, N, D);
+    int win = wave_best_lane(ok, N, D, lane);
+    Cand c;
+    cand_invalid(c);
+    c.SP = SP;
+    c.lo = kfloat(__shfl(myk, 0));
+    if (win >= 0) {
+        uint64_t nlo = __shfl((uint64_t)N, win), nhi = __shfl((uint64_t)(N >> 64), win);
+        c.N = ((u128)nhi << 64) | nlo;
+        c.D = __shfl(D, win);
+        c.SL = __shfl(SL, win);
+        c.SR = __shfl(SR, win);
+        c.pos = win;
+        c.nL = win + 1;
+        c.nR = (int32_t)(n - c.nL);
+        c.thr = kfloat(__shfl(myk, win));
+        c.scale = 0.f;
+    }
+    return c;
+}
+
+// a better than b, ties to the lower projection
+__device__ __forceinline__ bool cand_better_proj(const Cand& a, const Cand& b) {
+    if (a.D == 0) return false;
+    if (b.D == 0) return true;
+    if (q_greater(a.N, a.D, b.N, b.D)) return true;
+    if (q_greater(b.N, b.D, a.N, a.D)) return false;
+    return a.proj < b.proj;
+}
+
+// ---------------------------------------------------------------------------
+// shared memory of the persistent block kernels
+
+struct WaveScratch {
+    int32_t lf[16];
+    uint32_t ls[16];
+    int32_t pc[16];
+    float red[2];
+    int32_t pad[2];
+    Cand best;
+};
+
+struct BlockShared {
+    int item;
+    int pad[3];
+    float lo[kWavesPerBlock];
+    float hi[kWavesPerBlock];
+    WaveScratch w[kWavesPerBlock];
+};
+
+size_t find_smem_main(int bins, int classes) {
+    return sizeof(BlockShared) + (size_t)kWavesPerBlock * bins * classes * sizeof(int32_t);
+}
+
+__device__ __forceinline__ BlockShared& block_shared(char* smem) { return *(BlockShared*)smem; }
+__device__ __forceinline__ int32_t* wave_hist(char* smem, int w, int bins, int C) {
+    return (int32_t*)(smem + sizeof(BlockShared)) + (size_t)w * bins * C;
+}
+
+// block-wide min/max of per-thread values (all threads call)
+__device__ __forceinline__ void block_minmax(BlockShared& S, float& lo, float& hi) {
+    const int w = threadIdx.x >> 6;
+    lo = wave_min(lo);
+    hi = wave_max(hi);
+    if (lane_id() == 0) { S.lo[w] = lo; S.hi[w] = hi; }
+    __syncthreads();
+    lo = fminf(fminf(S.lo[0], S.lo[1]), fminf(S.lo[2], S.lo[3]));
+    hi = fmaxf(fmaxf(S.hi[0], S.hi[1]), fmaxf(S.hi[2], S.hi[3]));
+}
+
+// ---------------------------------------------------------------------------
+// small nodes: one block per node, wave w takes projections w, w+4, ...
+
+constexpr int kSmallR = kSmallMax / kWave;   // 16 samples per lane
+
+template <typename T, class PS>
+__device__ void do_small(const FindArgs& A, const PS& P, int v, char* smem) {
+    BlockShared& S = block_shared(smem);
+    const int w = threadIdx.x >> 6, lane = lane_id();
+    const int C = A.n_classes, Bm = A.bins;
+    int64_t s0, n;
+    node_range(A, v, s0, n);
+    const int k = proj_count(P, v);
+    const int B = node_bins(A, v);
+    const bool sortp = n < A.sort_threshold;
+    WaveScratch& WS = S.w[w];
+    int32_t* hist = wave_hist(smem, w, Bm, C);
+    const int nr = (int)((n + kWave - 1) / kWave);
+
+    int idx[kSmallR], lab[kSmallR];
+    const int first = n > 0 ? row_of(A, s0) : 0;
+#pragma unroll
+    for (int r = 0; r < kSmallR; ++r) {
+        idx[r] = first;
+        lab[r] = -1;
+        if (r < nr) {
+            int64_t i = lane + (int64_t)r * kWave;
+            if (i < n) {
+                idx[r] = row_of(A, s0 + i);
+                lab[r] = label_of(A, idx[r]);
+            }
+        }
+    }
+    if (lane < 16) WS.pc[lane] = 0;
+    wave_sync();
+#pragma unroll
+    for (int r = 0; r < kSmallR; ++r)
+        if (r < nr && lab[r] >= 0) atomicAdd(&WS.pc[lab[r]], 1);
+    wave_sync();
+
+    Cand best;
+    cand_invalid(best);
+    for (int p = w; p < k; p += kWavesPerBlock) {
+        const int z = proj_stage(P, v, p, A.n_features, WS.lf, WS.ls);
+        float val[kSmallR];
+#pragma unroll
+        for (int r = 0; r < kSmallR; ++r) val[r] = 0.f;
+        for (int j = 0; j < z; ++j) {
+            const int f = __builtin_amdgcn_readfirstlane(WS.lf[j]);
+            const uint32_t sg = __builtin_amdgcn_readfirstlane(WS.ls[j]);
+            const T* col = (const T*)A.x + (int64_t)f * A.ld;
+#pragma unroll
+            for (int r = 0; r < kSmallR; ++r)
+                if (r < nr) val[r] = __fadd_rn(val[r], signed_term(ldx(col, idx[r]), sg));
+        }
+        float lo = INFINITY, hi = -INFINITY;
+#pragma unroll
+        for (int r = 0; r < kSmallR; ++r)
+            if (r < nr && lab[r] >= 0) { lo = fminf(lo, val[r]); hi = fmaxf(hi, val[r]); }
+        lo = wave_min(lo);
+        hi = wave_max(hi);
+        Cand c;
+        if (sortp) {
+            c = scan_sort_wave(val[0], lab[0], n, C, WS.pc);
+            write_zero_row(A, proj_global(P, v, p));
+        } else {
+            const float scale = bin_scale(B, lo, hi);
+            for (int e = lane; e < B * C; e += kWave) hist[e] = 0;
+            wave_sync();
+#pragma unroll
+            for (int r = 0; r < kSmallR; ++r)
+                if (r < nr && lab[r] >= 0)
+                    atomicAdd(&hist[bin_index(val[r], lo, scale, B) * C + lab[r]], 1);
+            wave_sync();
+            LdsHist h{hist, C};
+            write_hist_row(A, proj_global(P, v, p), h, B);
+            c = scan_hist(h, B, C, n, lo, scale);
+            wave_sync();
+        }
+        c.proj = p;
+        if (cand_better(c, best)) best = c;
+    }
+    if (lane == 0) WS.best = best;
+    __syncthreads();
+    if (w == 0) {
+        Cand b = S.w[0].best;
+        for (int ww = 1; ww < kWavesPerBlock; ++ww) {
+            const Cand& o = S.w[ww].best;
+            if (cand_better_proj(o, b)) b = o;
+        }
+        uint64_t SP = 0;
+        for (int c = 0; c < C; ++c) SP += (uint64_t)WS.pc[c] * (uint64_t)WS.pc[c];
+        b.SP = SP;
+        if (lane == 0) write_record((SplitRec*)A.out + v, b, sortp ? 1 : 0, (int32_t)n);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// mid nodes: one block per (node, projection), 32 samples per thread
+
+constexpr int kMidR = kMidMax / kBlock;
+
+template <typename T, class PS>
+__device__ void do_mid(const FindArgs& A, const PS& P, int4 D, int p, char* smem) {
+    BlockShared& S = block_shared(smem);
+    const int tid = threadIdx.x, w = tid >> 6, lane = lane_id();
+    const int C = A.n_classes, Bm = A.bins;
+    const int v = D.x;
+    int64_t s0, n;
+    node_range(A, v, s0, n);
+    const int B = node_bins(A, v);
+    const int nr = (int)((n + kBlock - 1) / kBlock);
+    WaveScratch& WS = S.w[w];
+
+    int idx[kMidR];
+    uint32_t labp[kMidR / 8];
+    const int first = n > 0 ? row_of(A, s0) : 0;
+#pragma unroll
+    for (int q = 0; q < kMidR / 8; ++q) labp[q] = 0;
+#pragma unroll
+    for (int r = 0; r < kMidR; ++r) {
+        idx[r] = first;
+        if (r < nr) {
+            int64_t i = tid + (int64_t)r * kBlock;
+            if (i < n) {
+                idx[r] = row_of(A, s0 + i);
+                labp[r >> 3] |= (uint32_t)label_of(A, idx[r]) << (4 * (r & 7));
+            }
+        }
+    }
+    const int z = proj_stage(P, v, p, A.n_features, WS.lf, WS.ls);
+    float val[kMidR];
+#pragma unroll
+    for (int r = 0; r < kMidR; ++r) val[r] = 0.f;
+    for (int j = 0; j < z; ++j) {
+        const int f = __builtin_amdgcn_readfirstlane(WS.lf[j]);
+        const uint32_t sg = __builtin_amdgcn_readfirstlane(WS.ls[j]);
+        const T* col = (const T*)A.x + (int64_t)f * A.ld;
+#pragma unroll
+        for (int r = 0; r < kMidR; ++r)
+            if (r < nr) val[r] = __fadd_rn(val[r], signed_term(ldx(col, idx[r]), sg));
+    }
+    float lo = INFINITY, hi = -INFINITY;
+#pragma unroll
+    for (int r = 0; r < kMidR; ++r)
+        if (r < nr && tid + (int64_t)r * kBlock < n) { lo = fminf(lo, val[r]); hi = fmaxf(hi, val[r]); }
+    block_minmax(S, lo, hi);
+    const float scale = bin_scale(B, lo, hi);
+    int32_t* hist = wave_hist(smem, w, Bm, C);
+    for (int e = lane; e < B * C; e += kWave) hist[e] = 0;
+    wave_sync();
+#pragma unroll
+    for (int r = 0; r < kMidR; ++r)
+        if (r < nr && tid + (int64_t)r * kBlock < n) {
+            int y = (int)((labp[r >> 3] >> (4 * (r & 7))) & 15u);
+            atomicAdd(&hist[bin_index(val[r], lo, scale, B) * C + y], 1);
+        }
+    __syncthreads();
+    if (w == 0) {
+        LdsHist4 h{wave_hist(smem, 0, Bm, C), C, Bm * C};
+        write_hist_row(A, proj_global(P, v, p), h, B);
+        Cand c = scan_hist(h, B, C, n, lo, scale);
+        c.proj = p;
+        if (lane == 0) ((Cand*)A.ws.slots)[D.y + p] = c;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// big nodes: (node, projection group, chunk) items
+
+struct BigDesc {
+    int node, slot, item_a, item_c, bigslot, k, nchunk, ngroup;
+};
+__device__ __forceinline__ BigDesc big_desc(const FindArgs& A, int d) {
+    int4 a = A.ws.desc_big[2 * d], b = A.ws.desc_big[2 * d + 1];
+    return BigDesc{a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+}
+
+// Load the chunk's rows and labels; returns the chunk's sample count.
+__device__ __forceinline__ int64_t big_chunk_rows(const FindArgs& A, const BigDesc& bd, int ch,
+                                                  int (&idx)[kMidR], uint32_t (&labp)[kMidR / 8],
+                                                  bool want_labels) {
+    int64_t s0, n;
+    node_range(A, bd.node, s0, n);
+    int64_t c0 = (int64_t)ch * kChunk;
+    int64_t cn = n - c0;
+    cn = cn < 0 ? 0 : (cn > kChunk ? kChunk : cn);
+    const int tid = threadIdx.x;
+    const int first = cn > 0 ? row_of(A, s0 + c0) : 0;
+#pragma unroll
+    for (int q = 0; q < kMidR / 8; ++q) labp[q] = 0;
+#pragma unroll
+    for (int r = 0; r < kMidR; ++r) {
+        idx[r] = first;
+        int64_t i = tid + (int64_t)r * kBlock;
+        if (i < cn) {
+            idx[r] = row_of(A, s0 + c0 + i);
+            if (want_labels) labp[r >> 3] |= (uint32_t)label_of(A, idx[r]) << (4 * (r & 7));
+        }
+    }
+    return cn;
+}
+
+template <typename T, class PS>
+__device__ __forceinline__ void chunk_project(const FindArgs& A, const PS& P, int v, int p,
+                                              WaveScratch& WS, const int (&idx)[kMidR], int nr,
+                                              float (&val)[kMidR]) {
+    const int z = proj_stage(P, v, p, A.n_features, WS.lf, WS.ls);
+#pragma unroll
+    for (int r = 0; r < kMidR; ++r) val[r] = 0.f;
+    for (int j = 0; j < z; ++j) {
+        const int f = __builtin_amdgcn_readfirstlane(WS.lf[j]);
+        const uint32_t sg = __builtin_amdgcn_readfirstlane(WS.ls[j]);
+        const T* col = (const T*)A.x + (int64_t)f * A.ld;
+#pragma unroll
+        for (int r = 0; r < kMidR; ++r)
+            if (r < nr) val[r] = __fadd_rn(val[r], signed_term(ldx(col, idx[r]), sg));
+    }
+}
+
+template <typename T, class PS>
+__device__ void do_big_range(const FindArgs& A, const PS& P, int d, int t, char* smem) {
+    BlockShared& S = block_shared(smem);
+    const int tid = threadIdx.x, w = tid >> 6;
+    const BigDesc bd = big_desc(A, d);
+    if (bd.nchunk <= 0) return;
+    const int g = t / bd.nchunk, ch = t - g * bd.nchunk;
+    int idx[kMidR];
+    uint32_t labp[kMidR / 8];
+    const int64_t cn = big_chunk_rows(A, bd, ch, idx, labp, false);
+    const int nr = (int)((cn + kBlock - 1) / kBlock);
+    const int p1 = min(bd.k, (g + 1) * kGroup);
+    for (int p = g * kGroup; p < p1; ++p) {
+        float val[kMidR];
+        chunk_project<T>(A, P, bd.node, p, S.w[w], idx, nr, val);
+        float lo = INFINITY, hi = -INFINITY;
+#pragma unroll
+        for (int r = 0; r < kMidR; ++r)
+            if (tid + (int64_t)r * kBlock < cn) { lo = fminf(lo, val[r]); hi = fmaxf(hi, val[r]); }
+        block_minmax(S, lo, hi);
+        if (tid == 0 && cn > 0) {
+            atomicMin(&A.ws.lohi[bd.bigslot + p].x, fkey(lo));
+            atomicMax(&A.ws.lohi[bd.bigslot + p].y, fkey(hi));
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T, class PS>
+__device__ void do_big_hist(const FindArgs& A, const PS& P, int d, int t, char* smem) {
+    BlockShared& S = block_shared(smem);
+    const int tid = threadIdx.x, w = tid >> 6, lane = lane_id();
+    const int C = A.n_classes, Bm = A.bins;
+    const BigDesc bd = big_desc(A, d);
+    if (bd.nchunk <= 0) return;
+    const int g = t / bd.nchunk, ch = t - g * bd.nchunk;
+    const int B = node_bins(A, bd.node);
+    int idx[kMidR];
+    uint32_t labp[kMidR / 8];
+    const int64_t cn = big_chunk_rows(A, bd, ch, idx, labp, true);
+    const int nr = (int)((cn + kBlock - 1) / kBlock);
+    const int p1 = min(bd.k, (g + 1) * kGroup);
+    int32_t* hist = wave_hist(smem, w, Bm, C);
+    for (int p = g * kGroup; p < p1; ++p) {
+        float val[kMidR];
+        chunk_project<T>(A, P, bd.node, p, S.w[w], idx, nr, val);
+        const uint2 lh = A.ws.lohi[bd.bigslot + p];
+        const float lo = kfloat(lh.x), hi = kfloat(lh.y);
+        const float scale = bin_scale(B, lo, hi);
+        for (int e = lane; e < B * C; e += kWave) hist[e] = 0;
+        wave_sync();
+#pragma unroll
+        for (int r = 0; r < kMidR; ++r)
+            if (tid + (int64_t)r * kBlock < cn) {
+                int y = (int)((labp[r >> 3] >> (4 * (r & 7))) & 15u);
+                atomicAdd(&hist[bin_index(val[r], lo, scale, B) * C + y], 1);
+            }
+        __syncthreads();
+        int32_t* gh = A.ws.big_hist + (int64_t)(bd.bigslot + p) * Bm * C;
+        const int32_t* h0 = wave_hist(smem, 0, Bm, C);
+        const int stride = Bm * C;
+        for (int e = tid; e < B * C; e += kBlock) {
+            int s = h0[e] + h0[e + stride] + h0[e + 2 * stride] + h0[e + 3 * stride];
+            if (s) atomicAdd(&gh[e], s);
+        }
+        __syncthreads();
+    }
+}
+
+template <class PS>
+__device__ void do_big_scan(const FindArgs& A, const PS& P, int d, int p) {
+    const int lane = lane_id();
+    const BigDesc bd = big_desc(A, d);
+    const int B = node_bins(A, bd.node);
+    int64_t s0, n;
+    node_range(A, bd.node, s0, n);
+    const uint2 lh = A.ws.lohi[bd.bigslot + p];
+    const float lo = kfloat(lh.x), hi = kfloat(lh.y);
+    const float scale = bin_scale(B, lo, hi);
+    GlobalHist h{A.ws.big_hist + (int64_t)(bd.bigslot + p) * A.bins * A.n_classes, A.n_classes};
+    write_hist_row(A, proj_global(P, bd.node, p), h, B);
+    Cand c = scan_hist(h, B, A.n_classes, n, lo, scale);
+    c.proj = p;
+    if (lane == 0) ((Cand*)A.ws.slots)[bd.slot + p] = c;
+}
+
+// ---------------------------------------------------------------------------
+// kernels
+
+__global__ void k_reset(int32_t* hdr) {
+    for (int i = threadIdx.x; i < H_COUNT; i += blockDim.x) hdr[i] = 0;
+}
+
+template <class PS>
+__global__ __launch_bounds__(kBlock) void k_plan(FindArgs A, PS P) {
+    const int N = n_nodes_of(A);
+    const FindWs& W = A.ws;
+    for (int base = blockIdx.x * kBlock; base < N; base += gridDim.x * kBlock) {
+        const int v = base + threadIdx.x;
+        const bool act = v < N;
+        int64_t s0 = 0, n = 0;
+        int k = 0;
+        if (act) {
+            node_range(A, v, s0, n);
+            k = proj_count(P, v);
+        }
+        const bool sortp = n < A.sort_threshold;
+        int cat = CAT_NONE;
+        if (act) {
+            if (k == 0) cat = CAT_NOSPLIT;
+            else if (sortp ? n <= kSortWaveMax : n <= kSmallMax) cat = CAT_SMALL;
+            else if (sortp) cat = CAT_SB;
+            else if (n <= kMidMax) cat = CAT_MID;
+            else cat = CAT_BIG;
+        }
+        const int nch = (int)((n + kChunk - 1) / kChunk), ngr = (k + kGroup - 1) / kGroup;
+        const bool slot_node = cat == CAT_MID || cat == CAT_SB || cat == CAT_BIG;
+        const int o_small = wave_alloc(&W.hdr[H_SMALL], cat == CAT_SMALL);
+        const int o_dmid = wave_alloc(&W.hdr[H_DMID], cat == CAT_MID);
+        const int o_imid = wave_alloc(&W.hdr[H_IMID], cat == CAT_MID ? k : 0);
+        const int o_dsb = wave_alloc(&W.hdr[H_DSB], cat == CAT_SB);
+        const int o_isb = wave_alloc(&W.hdr[H_ISB], cat == CAT_SB ? k : 0);
+        const int o_dbig = wave_alloc(&W.hdr[H_DBIG], cat == CAT_BIG);
+        const int o_ia = wave_alloc(&W.hdr[H_IBIGA], cat == CAT_BIG ? ngr * nch : 0);
+        const int o_ic = wave_alloc(&W.hdr[H_IBIGC], cat == CAT_BIG ? k : 0);
+        const int o_slot = wave_alloc(&W.hdr[H_SLOTS], slot_node ? k : 0);
+        const int o_bslot = wave_alloc(&W.hdr[H_BIGSLOTS], cat == CAT_BIG ? k : 0);
+        bool over = false;
+        if (slot_node && o_slot + (int64_t)k > W.cap_slots) over = true;
+        if (cat == CAT_SMALL && o_small >= W.cap_small) over = true;
+        if (cat == CAT_MID && (o_dmid >= W.cap_dmid || o_imid + (int64_t)k > W.cap_imid)) over = true;
+        if (cat == CAT_SB && (o_dsb >= W.cap_dsb || o_isb + (int64_t)k > W.cap_isb)) over = true;
+        if (cat == CAT_BIG && (o_dbig >= W.cap_dbig || o_ia + (int64_t)ngr * nch > W.cap_ibiga ||
+                               o_ic + (int64_t)k > W.cap_ibigc || o_bslot + (int64_t)k > W.cap_bigslots))
+            over = true;
+        if (over) {
+            // Capacity exceeded (impossible with truthful host-side sizes): flag
+            // it, record no split, and leave an empty descriptor so that every
+            // allocated descriptor slot below the capacity is initialised.
+            atomicOr(&W.hdr[H_ERR], 1);
+            write_nosplit(A, v, sortp ? 1 : 0, n);
+            if (cat == CAT_MID && o_dmid < W.cap_dmid) W.desc_mid[o_dmid] = make_int4(v, 0, 0, 0);
+            if (cat == CAT_SB && o_dsb < W.cap_dsb) W.desc_sb[o_dsb] = make_int4(v, 0, 0, 0);
+            if (cat == CAT_BIG && o_dbig < W.cap_dbig) {
+                W.desc_big[2 * o_dbig] = make_int4(v, 0, 0, 0);
+                W.desc_big[2 * o_dbig + 1] = make_int4(0, 0, 0, 0);
+            }
+            continue;
+        }
+        switch (cat) {
+        case CAT_NOSPLIT: write_nosplit(A, v, sortp ? 1 : 0, n); break;
+        case CAT_SMALL: W.small_items[o_small] = v; break;
+        case CAT_MID: W.desc_mid[o_dmid] = make_int4(v, o_slot, o_imid, k); break;
+        case CAT_SB: W.desc_sb[o_dsb] = make_int4(v, o_slot, o_isb, k); break;
+        case CAT_BIG:
+            W.desc_big[2 * o_dbig] = make_int4(v, o_slot, o_ia, o_ic);
+            W.desc_big[2 * o_dbig + 1] = make_int4(o_bslot, k, nch, ngr);
+            break;
+        default: break;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_expand(FindArgs A) {
+    const FindWs& W = A.ws;
+    const int tid = threadIdx.x;
+    const int nmid = count_of(A, H_DMID, W.cap_dmid);
+    const int nsb = count_of(A, H_DSB, W.cap_dsb);
+    const int nbig = count_of(A, H_DBIG, W.cap_dbig);
+    const int Bm = A.bins, C = A.n_classes;
+    for (int d = blockIdx.x; d < nmid + nsb + nbig; d += gridDim.x) {
+        if (d < nmid) {
+            int4 D = W.desc_mid[d];
+            for (int p = tid; p < D.w; p += kBlock)
+                if (D.z + (int64_t)p < W.cap_imid) W.items_mid[D.z + p] = make_int2(d, p);
+        } else if (d < nmid + nsb) {
+            int e = d - nmid;
+            int4 D = W.desc_sb[e];
+            for (int p = tid; p < D.w; p += kBlock)
+                if (D.z + (int64_t)p < W.cap_isb) W.items_sb[D.z + p] = make_int2(e, p);
+        } else {
+            int e = d - nmid - nsb;
+            BigDesc bd = big_desc(A, e);
+            int na = bd.ngroup * bd.nchunk;
+            for (int t = tid; t < na; t += kBlock)
+                if (bd.item_a + (int64_t)t < W.cap_ibiga) W.items_biga[bd.item_a + t] = make_int2(e, t);
+            for (int p = tid; p < bd.k; p += kBlock) {
+                if (bd.item_c + (int64_t)p < W.cap_ibigc) W.items_bigc[bd.item_c + p] = make_int2(e, p);
+                if (bd.bigslot + (int64_t)p < W.cap_bigslots) W.lohi[bd.bigslot + p] = make_uint2(0xffffffffu, 0u);
+            }
+            int64_t nh = (int64_t)bd.k * Bm * C;
+            int32_t* gh = W.big_hist + (int64_t)bd.bigslot * Bm * C;
+            if (bd.bigslot + (int64_t)bd.k <= W.cap_bigslots)
+                for (int64_t i = tid; i < nh; i += kBlock) gh[i] = 0;
+        }
+    }
+}
+
+template <typename T, class PS>
+__global__ __launch_bounds__(kBlock) void k_main(FindArgs A, PS P) {
+    extern __shared__ __align__(16) char smem[];
+    BlockShared& S = block_shared(smem);
+    const FindWs& W = A.ws;
+    const int na = count_of(A, H_IBIGA, W.cap_ibiga);
+    const int nbig = count_of(A, H_DBIG, W.cap_dbig);
+    for (;;) {
+        int it = block_dequeue(&W.hdr[H_Q_BIGA], &S.item);
+        if (it >= na) break;
+        int2 e = W.items_biga[it];
+        if (e.x < nbig) do_big_range<T>(A, P, e.x, e.y, smem);
+    }
+    const int nm = count_of(A, H_IMID, W.cap_imid);
+    const int nmd = count_of(A, H_DMID, W.cap_dmid);
+    for (;;) {
+        int it = block_dequeue(&W.hdr[H_Q_MID], &S.item);
+        if (it >= nm) break;
+        int2 e = W.items_mid[it];
+        if (e.x >= nmd) continue;
+        int4 D = W.desc_mid[e.x];
+        if (e.y < D.w) do_mid<T>(A, P, D, e.y, smem);
+    }
+    const int ns = count_of(A, H_SMALL, W.cap_small);
+    const int N = n_nodes_of(A);
+    for (;;) {
+        int it = block_dequeue(&W.hdr[H_Q_SMALL], &S.item);
+        if (it >= ns) break;
+        int v = W.small_items[it];
+        if (v >= 0 && v < N) do_small<T>(A, P, v, smem);
+    }
+}
+
+template <typename T, class PS>
+__global__ __launch_bounds__(kBlock) void k_bighist(FindArgs A, PS P) {
+    extern __shared__ __align__(16) char smem[];
+    BlockShared& S = block_shared(smem);
+    const FindWs& W = A.ws;
+    const int na = count_of(A, H_IBIGA, W.cap_ibiga);
+    const int nbig = count_of(A, H_DBIG, W.cap_dbig);
+    for (;;) {
+        int it = block_dequeue(&W.hdr[H_Q_BIGB], &S.item);
+        if (it >= na) break;
+        int2 e = W.items_biga[it];
+        if (e.x < nbig) do_big_hist<T>(A, P, e.x, e.y, smem);
+    }
+}
+
+template <class PS>
+__global__ __launch_bounds__(kBlock) void k_bigscan(FindArgs A, PS P) {
+    // one wave per item
+    const FindWs& W = A.ws;
+    const int nc = count_of(A, H_IBIGC, W.cap_ibigc);
+    const int nbig = count_of(A, H_DBIG, W.cap_dbig);
+    const int lane = lane_id();
+    for (;;) {
+        int it = 0;
+        if (lane == 0) it = atomicAdd(&W.hdr[H_Q_BIGC], 1);
+        it = __shfl(it, 0);
+        if (it >= nc) break;
+        int2 e = W.items_bigc[it];
+        if (e.x < nbig) do_big_scan(A, P, e.x, e.y);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_reduce(FindArgs A) {
+    const FindWs& W = A.ws;
+    const int nmid = count_of(A, H_DMID, W.cap_dmid);
+    const int nsb = count_of(A, H_DSB, W.cap_dsb);
+    const int nbig = count_of(A, H_DBIG, W.cap_dbig);
+    const int lane = lane_id();
+    const Cand* slots = (const Cand*)W.slots;
+    const int gw = (blockIdx.x * kBlock + threadIdx.x) >> 6;
+    const int nw = gridDim.x * kWavesPerBlock;
+    for (int d = gw; d < nmid + nsb + nbig; d += nw) {
+        int node, slot, k, kind;
+        if (d < nmid) {
+            int4 D = W.desc_mid[d]; node = D.x; slot = D.y; k = D.w; kind = 0;
+        } else if (d < nmid + nsb) {
+            int4 D = W.desc_sb[d - nmid]; node = D.x; slot = D.y; k = D.w; kind = 1;
+        } else {
+            BigDesc bd = big_desc(A, d - nmid - nsb); node = bd.node; slot = bd.slot; k = bd.k; kind = 0;
+        }
+        if (slot + (int64_t)k > W.cap_slots) continue;
+        bool bv = false;
+        u128 bN = 0;
+        uint64_t bD = 0;
+        int bp = 0;
+        for (int p = lane; p < k; p += kWave) {
+            const Cand& c = slots[slot + p];
+            if (c.D != 0 && (!bv || q_greater(c.N, c.D, bN, bD))) { bv = true; bN = c.N; bD = c.D; bp = p; }
+        }
+        int win = wave_best_lane(bv, bN, bD, bp);
+        int64_t s0, n;
+        node_range(A, node, s0, n);
+        Cand b;
+        if (win >= 0) b = slots[slot + __shfl(bp, win)];
+        else cand_invalid(b);
+        if (lane == 0) write_record((SplitRec*)A.out + node, b, kind, (int32_t)n);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// sort-path blocks: 64 < n <= 8192, bitonic sort of (key, label) in LDS
+
+struct SortShared {
+    int item;
+    int z;
+    int pad[2];
+    int32_t lf[16];
+    uint32_t ls[16];
+    int32_t pc[16];
+    uint64_t wtot[kWavesPerBlock][4];
+    uint64_t wN[kWavesPerBlock][2];
+    uint64_t wD[kWavesPerBlock];
+    uint64_t wSL[kWavesPerBlock];
+    uint64_t wSR[kWavesPerBlock];
+    int32_t wpos[kWavesPerBlock];
+};
+
+size_t find_smem_sort() { return sizeof(SortShared) + (size_t)kSortMax * sizeof(uint64_t); }
+
+__device__ __forceinline__ uint64_t wave_incl_scan64(uint64_t x) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        uint64_t t = __shfl_up(x, off);
+        if (lane >= off) x += t;
+    }
+    return x;
+}
+
+// One (node, projection) of a sort-path node with 64 < n <= 8192: project
+// into LDS as (order-preserving key << 32 | label), bitonic sort, then each
+// thread scans a contiguous run of sorted positions with 16-bit packed class
+// counters (four classes per 64-bit word) offset by a block prefix sum.
+template <typename T, class PS>
+__device__ void do_sortblock(const FindArgs& A, const PS& P, int4 D, int p, char* smem) {
+    SortShared& S = *(SortShared*)smem;
+    uint64_t* keys = (uint64_t*)(smem + sizeof(SortShared));
+    const int tid = threadIdx.x, w = tid >> 6, lane = lane_id();
+    const int C = A.n_classes;
+    const int v = D.x;
+    int64_t s0, n;
+    node_range(A, v, s0, n);
+    if (n > kSortMax) n = kSortMax;   // cannot happen: the threshold is clamped on the host
+    int P2 = 128;
+    while (P2 < n) P2 <<= 1;
+    if (w == 0) {
+        int z = proj_stage(P, v, p, A.n_features, S.lf, S.ls);
+        if (lane == 0) S.z = z;
+        if (lane < 16) S.pc[lane] = 0;
+    }
+    __syncthreads();
+    const int zn = S.z;
+    for (int i = tid; i < P2; i += kBlock) {
+        uint64_t key = ~0ull;
+        if (i < n) {
+            const int row = row_of(A, s0 + i);
+            const int y = label_of(A, row);
+            float acc = 0.f;
+            for (int j = 0; j < zn; ++j) {
+                const T* col = (const T*)A.x + (int64_t)S.lf[j] * A.ld;
+                acc = __fadd_rn(acc, signed_term(ldx(col, row), S.ls[j]));
+            }
+            atomicAdd(&S.pc[y], 1);
+            key = ((uint64_t)fkey(acc) << 32) | (uint32_t)y;
+        }
+        keys[i] = key;
+    }
+    __syncthreads();
+    for (int kk = 2; kk <= P2; kk <<= 1) {
+        for (int j = kk >> 1; j > 0; j >>= 1) {
+            const int lj = __ffs(j) - 1;
+            for (int t = tid; t < (P2 >> 1); t += kBlock) {
+                const int i = ((t >> lj) << (lj + 1)) + (t & (j - 1));
+                const int l = i + j;
+                const bool asc = (i & kk) == 0;
+                const uint64_t a = keys[i], b = keys[l];
+                if ((a > b) == asc) { keys[i] = b; keys[l] = a; }
+            }
+            __syncthreads();
+        }
+    }
+    const int E = P2 >= kBlock ? P2 / kBlock : 1;
+    const int t0 = tid * E;
+    const int CW = (C + 3) >> 2;
+    uint64_t loc[4] = {0, 0, 0, 0};
+    for (int e = 0; e < E; ++e) {
+        const int i = t0 + e;
+        if (i < n) {
+            const int y = (int)(uint32_t)keys[i];
+            const uint64_t one = 1ull << (16 * (y & 3));
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (q == (y >> 2)) loc[q] += one;
+        }
+    }
+    uint64_t excl[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const uint64_t incl = q < CW ? wave_incl_scan64(loc[q]) : 0ull;
+        excl[q] = incl - loc[q];
+        if (lane == 63) S.wtot[w][q] = incl;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        for (int ww = 0; ww < w; ++ww) excl[q] += S.wtot[ww][q];
+    uint64_t SP = 0;
+    for (int c = 0; c < C; ++c) SP += (uint64_t)S.pc[c] * (uint64_t)S.pc[c];
+    bool bv = false;
+    u128 bN = 0;
+    uint64_t bD = 0, bSL = 0, bSR = 0;
+    int bpos = 0;
+    uint64_t cur[4] = {excl[0], excl[1], excl[2], excl[3]};
+    for (int e = 0; e < E; ++e) {
+        const int i = t0 + e;
+        if (i >= n) break;
+        const uint64_t ki = keys[i];
+        const int y = (int)(uint32_t)ki;
+        const uint64_t one = 1ull << (16 * (y & 3));
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (q == (y >> 2)) cur[q] += one;
+        if (i + 1 < n && (uint32_t)(ki >> 32) < (uint32_t)(keys[i + 1] >> 32)) {
+            uint64_t SL = 0, SR = 0;
+            for (int c = 0; c < C; ++c) {
+                const uint32_t l = (uint32_t)((cur[c >> 2] >> (16 * (c & 3))) & 0xffffu);
+                const uint32_t r = (uint32_t)S.pc[c] - l;
+                SL += (uint64_t)l * l;
+                SR += (uint64_t)r * r;
+            }
+            u128 N;
+            uint64_t Dq;
+            if (make_q((int64_t)i + 1, n - i - 1, SL, SR, N, Dq) && (!bv || q_greater(N, Dq, bN, bD))) {
+                bv = true; bN = N; bD = Dq; bpos = i; bSL = SL; bSR = SR;
+            }
+        }
+    }
+    const int win = wave_best_lane(bv, bN, bD, bpos);
+    const int src = win < 0 ? 0 : win;
+    const uint64_t nlo = __shfl((uint64_t)bN, src), nhi = __shfl((uint64_t)(bN >> 64), src);
+    const uint64_t dd = __shfl(bD, src), sl = __shfl(bSL, src), sr = __shfl(bSR, src);
+    const int pp = __shfl(bpos, src);
+    if (lane == 0) {
+        S.wN[w][0] = nlo; S.wN[w][1] = nhi; S.wD[w] = win < 0 ? 0 : dd;
+        S.wSL[w] = sl; S.wSR[w] = sr; S.wpos[w] = pp;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int bw = -1;
+        for (int ww = 0; ww < kWavesPerBlock; ++ww) {
+            if (S.wD[ww] == 0) continue;
+            if (bw < 0) { bw = ww; continue; }
+            const u128 a = ((u128)S.wN[ww][1] << 64) | S.wN[ww][0];
+            const u128 b = ((u128)S.wN[bw][1] << 64) | S.wN[bw][0];
+            if (q_greater(a, S.wD[ww], b, S.wD[bw]) ||
+                (!q_greater(b, S.wD[bw], a, S.wD[ww]) && S.wpos[ww] < S.wpos[bw]))
+                bw = ww;
+        }
+        Cand c;
+        cand_invalid(c);
+        c.SP = SP;
+        c.proj = p;
+        c.lo = kfloat((uint32_t)(keys[0] >> 32));
+        if (bw >= 0) {
+            const int pos = S.wpos[bw];
+            c.N = ((u128)S.wN[bw][1] << 64) | S.wN[bw][0];
+            c.D = S.wD[bw];
+            c.SL = S.wSL[bw];
+            c.SR = S.wSR[bw];
+            c.pos = pos;
+            c.nL = pos + 1;
+            c.nR = (int32_t)(n - c.nL);
+            c.thr = kfloat((uint32_t)(keys[pos] >> 32));
+        }
+        ((Cand*)A.ws.slots)[D.y + p] = c;
+    }
+    if (w == 0) write_zero_row(A, proj_global(P, v, p));
+    __syncthreads();
+}
+
+template <typename T, class PS>
+__global__ __launch_bounds__(kBlock) void k_sortblk(FindArgs A, PS P) {
+    extern __shared__ __align__(16) char smem[];
+    SortShared& S = *(SortShared*)smem;
+    const FindWs& W = A.ws;
+    const int ni = count_of(A, H_ISB, W.cap_isb);
+    const int nd = count_of(A, H_DSB, W.cap_dsb);
+    for (;;) {
+        int it = block_dequeue(&W.hdr[H_Q_SB], &S.item);
+        if (it >= ni) break;
+        int2 e = W.items_sb[it];
+        if (e.x >= nd) continue;
+        int4 D = W.desc_sb[e.x];
+        if (e.y < D.w) do_sortblock<T>(A, P, D, e.y, smem);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+
+template <typename T, class PS>
+static hipError_t launch_find_t(const FindArgs& a, const PS& p, const LaunchCfg& cfg, hipStream_t s) {
+    const int Nc = a.n_nodes > 0 ? a.n_nodes : 1;
+    int grid_plan = (Nc + kBlock - 1) / kBlock;
+    if (grid_plan > 4 * cfg.n_cu) grid_plan = 4 * cfg.n_cu;
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, a.ws.hdr);
+    hipLaunchKernelGGL((k_plan<PS>), dim3(grid_plan), dim3(kBlock), 0, s, a, p);
+    hipLaunchKernelGGL(k_expand, dim3(cfg.grid_small), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((k_main<T, PS>), dim3(cfg.grid_main), dim3(kBlock), cfg.smem_main, s, a, p);
+    hipLaunchKernelGGL((k_sortblk<T, PS>), dim3(cfg.grid_sort), dim3(kBlock), cfg.smem_sort, s, a, p);
+    hipLaunchKernelGGL((k_bighist<T, PS>), dim3(cfg.grid_main), dim3(kBlock), cfg.smem_main, s, a, p);
+    hipLaunchKernelGGL((k_bigscan<PS>), dim3(cfg.grid_small), dim3(kBlock), 0, s, a, p);
+    hipLaunchKernelGGL(k_reduce, dim3(cfg.grid_small), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_find_csr(const FindArgs& a, const ProjCSR& p, const LaunchCfg& cfg, hipStream_t s) {
+    if (a.dtype == SOF_F16) return launch_find_t<_Float16>(a, p, cfg, s);
+    return launch_find_t<float>(a, p, cfg, s);
+}
+hipError_t launch_find_hash(const FindArgs& a, const ProjHash& p, const LaunchCfg& cfg, hipStream_t s) {
+    if (a.dtype == SOF_F16) return launch_find_t<_Float16>(a, p, cfg, s);
+    return launch_find_t<float>(a, p, cfg, s);
+}
+
+hipError_t find_occupancy(int bins, int classes, int* blocks_main, int* blocks_sort) {
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        blocks_main, (const void*)k_main<float, ProjCSR>, kBlock, find_smem_main(bins, classes));
+    if (e != hipSuccess) return e;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_sort, (const void*)k_sortblk<float, ProjCSR>,
+                                                        kBlock, find_smem_sort());
+}
+
+}  // namespace sof

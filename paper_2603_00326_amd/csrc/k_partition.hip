@@ -1,0 +1,440 @@
+// k_partition.hip -- stable partition of every node's samples by its split
+// (paper section 4: each node splits its samples between its children).
+//
+// The split rule is re-evaluated on recomputed projected values (the same FP32
+// CSR-order sums as the search): histogram splits send v left iff
+// bin(v) <= bin, sort splits iff v <= threshold.  Output per node: left
+// samples in input order, then right samples in input order.
+//
+//   k_pplan     per node: child offsets, small-node queue or chunk items
+//   k_psmall    nodes <= 8192 samples: one block per node; chunk items of
+//               larger nodes: predicate bits and left counts (first pass)
+//   k_pscatter  chunk items: prefix over the node's earlier chunks, scatter
+#include <cstring>
+
+#include "sof_device.h"
+#include "sof_host.h"
+#include "sof_internal.h"
+
+namespace sof {
+
+
+constexpr int kPartMax = 8192;             // one block per node up to here
+constexpr int kPR = kPartMax / kBlock;     // 32 samples per thread
+constexpr int kWordsPerChunk = kPartMax / kWave;
+
+enum { P_SMALL = 0, P_ITEMS, P_Q_SMALL = 8, P_Q_A, P_Q_B, P_COUNT = 16 };
+
+__device__ __forceinline__ void wave_sync_p() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ int64_t clampp(int64_t x, int64_t lo, int64_t hi) {
+    return x < lo ? lo : (x > hi ? hi : x);
+}
+
+__device__ __forceinline__ int nodes_of(const PartArgs& A) {
+    if (!A.n_nodes_dev) return A.n_nodes;
+    int n = *A.n_nodes_dev;
+    return n < 0 ? 0 : (n > A.n_nodes ? A.n_nodes : n);
+}
+
+__device__ __forceinline__ void prange(const PartArgs& A, int v, int64_t& s0, int64_t& n) {
+    int64_t a = clampp(A.node_offsets[v], 0, A.n_samples);
+    int64_t b = clampp(A.node_offsets[v + 1], a, A.n_samples);
+    s0 = a;
+    n = b - a;
+}
+
+__device__ __forceinline__ int prow(const PartArgs& A, int64_t at) {
+    uint32_t r = (uint32_t)A.sample_idx[at];
+    return r < (uint32_t)A.n_rows ? (int)r : 0;
+}
+
+// projection sources (same contracts as in the search)
+__device__ __forceinline__ int pcount(const ProjCSR& P, int v) {
+    int a = (int)clampp(P.proj_offsets[v], 0, P.n_proj);
+    int b = (int)clampp(P.proj_offsets[v + 1], a, P.n_proj);
+    return b - a;
+}
+__device__ __forceinline__ int pstage(const ProjCSR& P, int v, int p, int d, int32_t* lf, uint32_t* ls) {
+    int q = (int)clampp(P.proj_offsets[v], 0, P.n_proj) + p;
+    int64_t j0 = clampp(P.nz_offsets[q], 0, P.n_nz);
+    int64_t j1 = clampp(P.nz_offsets[q + 1], j0, P.n_nz);
+    if (j1 - j0 > SOF_MAX_NNZ) j1 = j0 + SOF_MAX_NNZ;
+    int z = (int)(j1 - j0);
+    int lane = lane_id();
+    if (lane < z) {
+        uint32_t f = (uint32_t)P.nz_feature[j0 + lane];
+        lf[lane] = f < (uint32_t)d ? (int)f : 0;
+        ls[lane] = P.nz_weight[j0 + lane] < 0 ? 0x80000000u : 0u;
+    }
+    wave_sync_p();
+    return z;
+}
+
+__device__ __forceinline__ uint64_t smix(uint64_t seed, uint64_t c) {
+    uint64_t z = seed + c * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+__device__ __forceinline__ uint64_t pcounter(int tree, int level, int pos, int p, int draw) {
+    uint64_t c = (uint64_t)tree * 64u + (uint64_t)level;
+    c = (c << 24) + (uint64_t)pos;
+    c = (c << 10) + (uint64_t)p;
+    return (c << 4) + (uint64_t)draw;
+}
+__device__ __forceinline__ int pcount(const ProjHash& P, int) { return P.k; }
+__device__ __forceinline__ int pstage(const ProjHash& P, int v, int p, int d, int32_t* lf, uint32_t* ls) {
+    const int lane = lane_id();
+    const int z = P.z;
+    const int tree = P.tree_of[v], pos = P.pos_of[v], level = *P.level;
+    uint32_t t = 0;
+    if (lane < z) {
+        uint32_t top = (uint32_t)(d - z + lane) + 1u;
+        uint64_t r = smix(P.seed, pcounter(tree, level, pos, p, lane));
+        t = (uint32_t)(((r >> 32) * (uint64_t)top) >> 32);
+    }
+    int mine = (int)t;
+    for (int j = 0; j < z; ++j) {
+        int cj = __shfl((int)t, j);
+        bool taken = __ballot(lane < j && mine == cj) != 0ull;
+        if (lane == j) mine = taken ? d - z + j : cj;
+    }
+    int rank = 0;
+    for (int i = 0; i < z; ++i) rank += (__shfl(mine, i) < mine) ? 1 : 0;
+    uint64_t sg = smix(P.seed, pcounter(tree, level, pos, p, 15));
+    if (lane < z) {
+        lf[rank] = mine;
+        ls[rank] = ((sg >> rank) & 1ull) ? 0x80000000u : 0u;
+    }
+    wave_sync_p();
+    return z;
+}
+
+struct PShared {
+    int item;
+    int z;
+    int nleft;
+    int pad;
+    int64_t base[2];
+    int32_t lf[16];
+    uint32_t ls[16];
+    int32_t cnt[kPR][kWavesPerBlock];
+    int32_t pre[kPR][kWavesPerBlock];
+    uint64_t mask[kPR][kWavesPerBlock];
+};
+
+// Predicate bits of up to 8192 samples starting at sample position `at`
+// (row r of 256 samples, wave w: bit lane of mask[r][w]).
+template <typename T, class PS>
+__device__ void predicates(const PartArgs& A, const PS& P, int v, int64_t at, int64_t cn, PShared& S) {
+    const int tid = threadIdx.x, w = tid >> 6;
+    const SplitRec sp = ((const SplitRec*)A.splits)[v];
+    const int k = pcount(P, v);
+    const bool all_left = sp.proj < 0 || sp.proj >= k;
+    if (w == 0) {
+        int z = all_left ? 0 : pstage(P, v, sp.proj, A.n_features, S.lf, S.ls);
+        if (lane_id() == 0) S.z = z;
+    }
+    __syncthreads();
+    const int z = S.z;
+    int B = A.bins;
+    if (A.node_bins) {
+        int b = A.node_bins[v];
+        B = b < 2 ? 2 : (b > A.bins ? A.bins : b);
+    }
+    const int nr = (int)((cn + kBlock - 1) / kBlock);
+    int idx[kPR];
+    float val[kPR];
+#pragma unroll
+    for (int r = 0; r < kPR; ++r) {
+        idx[r] = 0;
+        val[r] = 0.f;
+        int64_t i = tid + (int64_t)r * kBlock;
+        if (r < nr && i < cn) idx[r] = prow(A, at + i);
+    }
+    for (int j = 0; j < z; ++j) {
+        const int f = __builtin_amdgcn_readfirstlane(S.lf[j]);
+        const uint32_t sg = __builtin_amdgcn_readfirstlane(S.ls[j]);
+        const T* col = (const T*)A.x + (int64_t)f * A.ld;
+#pragma unroll
+        for (int r = 0; r < kPR; ++r)
+            if (r < nr) val[r] = __fadd_rn(val[r], signed_term(ldx(col, idx[r]), sg));
+    }
+#pragma unroll
+    for (int r = 0; r < kPR; ++r) {
+        if (r < nr) {
+            int64_t i = tid + (int64_t)r * kBlock;
+            bool left = true;
+            if (!all_left)
+                left = sp.kind == SOF_SPLIT_HIST ? bin_index(val[r], sp.lo, sp.scale, B) <= sp.bin
+                                                 : val[r] <= sp.threshold;
+            uint64_t m = __ballot(i < cn && left);
+            if (lane_id() == 0) {
+                S.mask[r][w] = m;
+                S.cnt[r][w] = __popcll(m);
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// Exclusive prefix of S.cnt in (row, wave) order; returns the total.
+__device__ int row_prefix(PShared& S, int nr) {
+    const int tid = threadIdx.x;
+    if (tid < kWave) {
+        // lane l owns entries 2l, 2l+1 of the row-major (row, wave) list
+        int e0 = 2 * tid, e1 = 2 * tid + 1;
+        int c0 = e0 < nr * kWavesPerBlock ? S.cnt[e0 >> 2][e0 & 3] : 0;
+        int c1 = e1 < nr * kWavesPerBlock ? S.cnt[e1 >> 2][e1 & 3] : 0;
+        uint32_t incl = wave_incl_scan((uint32_t)(c0 + c1));
+        uint32_t ex = incl - (uint32_t)(c0 + c1);
+        if (e0 < kPR * kWavesPerBlock) S.pre[e0 >> 2][e0 & 3] = (int)ex;
+        if (e1 < kPR * kWavesPerBlock) S.pre[e1 >> 2][e1 & 3] = (int)ex + c0;
+        if (tid == 63) S.nleft = (int)incl;
+    }
+    __syncthreads();
+    return S.nleft;
+}
+
+// Scatter the chunk's samples given the left block base and right block base;
+// destinations outside the node's range [lo, hi) (possible only for
+// inconsistent offsets) are dropped.
+__device__ void scatter(const PartArgs& A, PShared& S, int64_t at, int64_t cn, int64_t lbase,
+                        int64_t rbase, int64_t lo, int64_t hi) {
+    const int tid = threadIdx.x, w = tid >> 6, lane = lane_id();
+    const int nr = (int)((cn + kBlock - 1) / kBlock);
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    for (int r = 0; r < nr; ++r) {
+        int64_t i = tid + (int64_t)r * kBlock;
+        if (i >= cn) continue;
+        const uint64_t m = S.mask[r][w];
+        const int lpre = S.pre[r][w];
+        const int64_t before = (int64_t)r * kBlock + w * kWave;   // samples before this wave's first
+        const int32_t row = A.sample_idx[at + i];
+        const int64_t dst = ((m >> lane) & 1ull) ? lbase + lpre + __popcll(m & below)
+                                                 : rbase + (before - lpre) + __popcll(~m & below);
+        if (dst >= lo && dst < hi) A.out_idx[dst] = row;
+    }
+}
+
+template <class PS>
+__global__ __launch_bounds__(kBlock) void k_pplan(PartArgs A, PS P) {
+    const int N = nodes_of(A);
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        A.child_offsets[2 * N] = (int32_t)clampp(A.node_offsets[N], 0, A.n_samples);
+    for (int v = blockIdx.x * kBlock + threadIdx.x; v < N; v += gridDim.x * kBlock) {
+        int64_t s0, n;
+        prange(A, v, s0, n);
+        A.child_offsets[2 * v] = (int32_t)s0;
+        if (n <= kPartMax) {
+            int o = atomicAdd(&A.hdr[P_SMALL], 1);
+            A.big_items[A.cap_items + o] = make_int4(v, 0, 0, 0);   // small list lives after the items
+        } else {
+            int nch = (int)((n + kPartMax - 1) / kPartMax);
+            int base = atomicAdd(&A.hdr[P_ITEMS], nch);
+            for (int c = 0; c < nch; ++c)
+                if (base + (int64_t)c < A.cap_items) A.big_items[base + c] = make_int4(v, c, nch, base);
+        }
+    }
+}
+
+template <typename T, class PS>
+__global__ __launch_bounds__(kBlock) void k_psmall(PartArgs A, PS P) {
+    extern __shared__ __align__(16) char smem[];
+    PShared& S = *(PShared*)smem;
+    const int nsmall = A.hdr[P_SMALL];
+    const int nitems = (int)min((int64_t)A.hdr[P_ITEMS], A.cap_items);
+    const int N = nodes_of(A);
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) S.item = atomicAdd(&A.hdr[P_Q_SMALL], 1);
+        __syncthreads();
+        const int it = S.item;
+        if (it >= nsmall + nitems) break;
+        if (it < nsmall) {
+            const int v = A.big_items[A.cap_items + it].x;
+            if (v < 0 || v >= N) continue;
+            int64_t s0, n;
+            prange(A, v, s0, n);
+            predicates<T>(A, P, v, s0, n, S);
+            const int nr = (int)((n + kBlock - 1) / kBlock);
+            const int nl = row_prefix(S, nr);
+            scatter(A, S, s0, n, s0, s0 + nl, s0, s0 + n);
+            if (threadIdx.x == 0) A.child_offsets[2 * v + 1] = (int32_t)(s0 + nl);
+        } else {
+            const int e = it - nsmall;
+            const int4 d = A.big_items[e];
+            if (d.x < 0 || d.x >= N) continue;
+            int64_t s0, n;
+            prange(A, d.x, s0, n);
+            const int64_t c0 = (int64_t)d.y * kPartMax;
+            int64_t cn = n - c0;
+            cn = cn < 0 ? 0 : (cn > kPartMax ? kPartMax : cn);
+            predicates<T>(A, P, d.x, s0 + c0, cn, S);
+            const int tid = threadIdx.x;
+            if (tid < kWordsPerChunk) {
+                A.pred_bits[(int64_t)e * kWordsPerChunk + tid] = S.mask[tid >> 2][tid & 3];
+            }
+            if (tid == 0) {
+                int s = 0;
+                const int nr = (int)((cn + kBlock - 1) / kBlock);
+                for (int r = 0; r < nr; ++r)
+                    for (int w = 0; w < kWavesPerBlock; ++w) s += S.cnt[r][w];
+                A.chunk_left[e] = s;
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_pscatter(PartArgs A) {
+    extern __shared__ __align__(16) char smem[];
+    PShared& S = *(PShared*)smem;
+    int64_t* s_base = S.base;
+    const int nitems = (int)min((int64_t)A.hdr[P_ITEMS], A.cap_items);
+    const int N = nodes_of(A);
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) S.item = atomicAdd(&A.hdr[P_Q_B], 1);
+        __syncthreads();
+        const int e = S.item;
+        if (e >= nitems) break;
+        const int4 d = A.big_items[e];
+        if (d.x < 0 || d.x >= N) continue;
+        int64_t s0, n;
+        prange(A, d.x, s0, n);
+        const int64_t c0 = (int64_t)d.y * kPartMax;
+        int64_t cn = n - c0;
+        cn = cn < 0 ? 0 : (cn > kPartMax ? kPartMax : cn);
+        const int tid = threadIdx.x;
+        // left counts of the node's chunks before this one, and in total
+        if (tid < kWave) {
+            int64_t before = 0, total = 0;
+            for (int c = tid; c < d.z; c += kWave) {
+                int64_t item = (int64_t)d.w + c;
+                int l = item < nitems ? A.chunk_left[item] : 0;
+                total += l;
+                if (c < d.y) before += l;
+            }
+            for (int off = 32; off > 0; off >>= 1) {
+                before += __shfl_xor(before, off);
+                total += __shfl_xor(total, off);
+            }
+            if (tid == 0) { s_base[0] = before; s_base[1] = total; }
+        }
+        if (tid < kWordsPerChunk) {
+            uint64_t m = A.pred_bits[(int64_t)e * kWordsPerChunk + tid];
+            S.mask[tid >> 2][tid & 3] = m;
+            S.cnt[tid >> 2][tid & 3] = __popcll(m);
+        }
+        __syncthreads();
+        const int nr = (int)((cn + kBlock - 1) / kBlock);
+        row_prefix(S, nr);
+        const int64_t before = s_base[0], total = s_base[1];
+        scatter(A, S, s0 + c0, cn, s0 + before, s0 + total + (c0 - before), s0, s0 + n);
+        if (tid == 0 && d.y == 0) A.child_offsets[2 * d.x + 1] = (int32_t)(s0 + total);
+    }
+}
+
+__global__ void k_preset(int32_t* hdr) {
+    for (int i = threadIdx.x; i < P_COUNT; i += blockDim.x) hdr[i] = 0;
+}
+
+template <typename T, class PS>
+hipError_t launch_part_t(const PartArgs& a, const PS& p, int n_cu, hipStream_t s) {
+    const int Nc = a.n_nodes > 0 ? a.n_nodes : 1;
+    int grid_plan = (Nc + kBlock - 1) / kBlock;
+    if (grid_plan > 4 * n_cu) grid_plan = 4 * n_cu;
+    hipLaunchKernelGGL(k_preset, dim3(1), dim3(64), 0, s, a.hdr);
+    hipLaunchKernelGGL((k_pplan<PS>), dim3(grid_plan), dim3(kBlock), 0, s, a, p);
+    hipLaunchKernelGGL((k_psmall<T, PS>), dim3(n_cu * 4), dim3(kBlock), sizeof(PShared), s, a, p);
+    hipLaunchKernelGGL(k_pscatter, dim3(n_cu * 4), dim3(kBlock), sizeof(PShared), s, a);
+    return hipGetLastError();
+}
+
+size_t part_workspace(int64_t n_nodes, int64_t n_samples) {
+    int64_t items = n_samples / kPartMax + n_samples / (kPartMax + 1) + 2;
+    size_t o = 256;                                                   // header
+    o += (size_t)(items + n_nodes + 1) * sizeof(int4);                // items + small list
+    o = (o + 255) & ~(size_t)255;
+    o += (size_t)items * sizeof(int32_t);
+    o = (o + 255) & ~(size_t)255;
+    o += (size_t)items * kWordsPerChunk * sizeof(uint64_t);
+    return (o + 255) & ~(size_t)255;
+}
+
+void part_bind(int64_t n_nodes, int64_t n_samples, void* ws, PartArgs* a) {
+    int64_t items = n_samples / kPartMax + n_samples / (kPartMax + 1) + 2;
+    char* b = (char*)ws;
+    a->hdr = (int32_t*)b;
+    size_t o = 256;
+    a->big_items = (int4*)(b + o);
+    o += (size_t)(items + n_nodes + 1) * sizeof(int4);
+    o = (o + 255) & ~(size_t)255;
+    a->chunk_left = (int32_t*)(b + o);
+    o += (size_t)items * sizeof(int32_t);
+    o = (o + 255) & ~(size_t)255;
+    a->pred_bits = (uint64_t*)(b + o);
+    a->cap_items = items;
+}
+
+hipError_t launch_partition_csr(const PartArgs& a, const ProjCSR& p, int n_cu, hipStream_t s) {
+    if (a.dtype == SOF_F16) return launch_part_t<_Float16>(a, p, n_cu, s);
+    return launch_part_t<float>(a, p, n_cu, s);
+}
+hipError_t launch_partition_hash(const PartArgs& a, const ProjHash& p, int n_cu, hipStream_t s) {
+    if (a.dtype == SOF_F16) return launch_part_t<_Float16>(a, p, n_cu, s);
+    return launch_part_t<float>(a, p, n_cu, s);
+}
+
+}  // namespace sof
+
+// ---------------------------------------------------------------------------
+// C ABI
+
+using namespace sof;
+
+extern "C" int sof_partition(sof_ctx* ctx, const sof_data* data, const sof_frontier* fr,
+                             const sof_proj* proj, const sof_params* params, const sof_split* splits,
+                             int32_t* out_idx, int32_t* child_offsets, void* ws, size_t ws_bytes,
+                             void* stream) {
+    if (!ctx) return fail(SOF_ERR_INVALID_ARG, "ctx is NULL");
+    int rc;
+    if ((rc = check_data(data)) || (rc = check_frontier(fr)) || (rc = check_proj(proj, data)) ||
+        (rc = check_params(params)))
+        return rc;
+    if (!child_offsets) return fail(SOF_ERR_INVALID_ARG, "child_offsets is NULL");
+    if (fr->n_nodes > 0 && !splits) return fail(SOF_ERR_INVALID_ARG, "splits is NULL");
+    if (fr->n_samples > 0 && !out_idx) return fail(SOF_ERR_INVALID_ARG, "out_idx is NULL");
+    if (fr->n_samples > 0 && out_idx == fr->sample_idx)
+        return fail(SOF_ERR_INVALID_ARG, "out_idx must not alias sample_idx");
+    size_t need = part_workspace(fr->n_nodes, fr->n_samples);
+    if ((rc = check_ws_public(ws, ws_bytes, need))) return rc;
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    PartArgs a;
+    memset(&a, 0, sizeof(a));
+    a.x = data->x;
+    a.ld = data->ld;
+    a.n_rows = data->n_rows;
+    a.n_features = data->n_features;
+    a.dtype = data->dtype;
+    a.node_offsets = fr->node_offsets;
+    a.sample_idx = fr->sample_idx;
+    a.n_samples = fr->n_samples;
+    a.n_nodes = fr->n_nodes;
+    a.node_bins = params->node_bins;
+    a.bins = params->bins;
+    a.splits = splits;
+    a.out_idx = out_idx;
+    a.child_offsets = child_offsets;
+    part_bind(fr->n_nodes, fr->n_samples, ws, &a);
+    ProjCSR p{proj->proj_offsets, proj->nz_offsets, proj->nz_feature, proj->nz_weight, proj->n_proj,
+              proj->n_nz};
+    e = launch_partition_csr(a, p, ctx->n_cu, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "partition launch");
+    return SOF_OK;
+}

@@ -1,0 +1,302 @@
+// sof_api.hip -- host side of the C ABI: argument validation (runs without a
+// GPU), workspace layout, context and launch configuration.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <utility>
+
+#include "sof.h"
+#include "sof_internal.h"
+#include "sof_host.h"
+
+using namespace sof;
+
+// ---------------------------------------------------------------------------
+// errors
+
+static thread_local std::string g_err;
+
+int sof::fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int sof::hip_fail(hipError_t e, const char* what) {
+    return fail(SOF_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+extern "C" const char* sof_last_error(void) { return g_err.c_str(); }
+extern "C" const char* sof_version(void) { return "sof 0.1 gfx950"; }
+
+// ---------------------------------------------------------------------------
+// context
+
+extern "C" int sof_create(int device, sof_ctx** out) {
+    if (!out) return fail(SOF_ERR_INVALID_ARG, "sof_create: out is NULL");
+    *out = nullptr;
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+    if (device < 0 || device >= count)
+        return fail(SOF_ERR_INVALID_ARG, "sof_create: device %d of %d", device, count);
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, device);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(SOF_ERR_UNSUPPORTED, "sof_create: device is %s, this library is built for gfx950",
+                    prop.gcnArchName);
+    sof_ctx* c = new sof_ctx();
+    c->device = device;
+    c->n_cu = prop.multiProcessorCount;
+    c->lds_per_block = (size_t)prop.sharedMemPerBlock;
+    const char* chk = getenv("SOF_CHECK");
+    c->check = chk && chk[0] == '1';
+    *out = c;
+    return SOF_OK;
+}
+
+extern "C" int sof_destroy(sof_ctx* ctx) {
+    delete ctx;
+    return SOF_OK;
+}
+
+int sof::launch_cfg(sof_ctx* ctx, int bins, int classes, LaunchCfg* cfg) {
+    std::lock_guard<std::mutex> g(ctx->mu);
+    auto key = std::make_pair(bins, classes);
+    auto it = ctx->cfg.find(key);
+    if (it != ctx->cfg.end()) {
+        *cfg = it->second;
+        return SOF_OK;
+    }
+    int bm = 0, bs = 0;
+    hipError_t e = find_occupancy(bins, classes, &bm, &bs);
+    if (e != hipSuccess) return hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+    LaunchCfg c;
+    c.n_cu = ctx->n_cu;
+    c.smem_main = find_smem_main(bins, classes);
+    c.smem_sort = find_smem_sort();
+    if (c.smem_main > ctx->lds_per_block || c.smem_sort > ctx->lds_per_block)
+        return fail(SOF_ERR_UNSUPPORTED, "LDS need %zu/%zu bytes exceeds %zu per block", c.smem_main,
+                    c.smem_sort, ctx->lds_per_block);
+    c.grid_main = ctx->n_cu * (bm > 0 ? bm : 1);
+    c.grid_sort = ctx->n_cu * (bs > 0 ? bs : 1);
+    c.grid_small = ctx->n_cu * 4;
+    ctx->cfg[key] = c;
+    *cfg = c;
+    return SOF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// validation (host only)
+
+int sof::check_data(const sof_data* d) {
+    if (!d) return fail(SOF_ERR_INVALID_ARG, "data is NULL");
+    if (d->dtype != SOF_F32 && d->dtype != SOF_F16)
+        return fail(SOF_ERR_UNSUPPORTED, "dtype %d (expected SOF_F32 or SOF_F16)", d->dtype);
+    if (d->n_classes < 2 || d->n_classes > SOF_MAX_CLASSES)
+        return fail(SOF_ERR_UNSUPPORTED, "n_classes %d outside [2, %d]", d->n_classes, SOF_MAX_CLASSES);
+    if (d->n_rows < 1 || d->n_features < 1)
+        return fail(SOF_ERR_INVALID_ARG, "n_rows %d and n_features %d must be >= 1", d->n_rows,
+                    d->n_features);
+    if (d->ld < d->n_rows) return fail(SOF_ERR_INVALID_ARG, "ld %lld < n_rows %d", (long long)d->ld, d->n_rows);
+    if (d->n_rows > (1 << 30))
+        return fail(SOF_ERR_OVERFLOW, "n_rows %d above 2^30", d->n_rows);
+    if (!d->x || !d->y) return fail(SOF_ERR_INVALID_ARG, "data->x or data->y is NULL");
+    return SOF_OK;
+}
+
+int sof::check_frontier(const sof_frontier* f) {
+    if (!f) return fail(SOF_ERR_INVALID_ARG, "frontier is NULL");
+    if (f->n_nodes < 0) return fail(SOF_ERR_INVALID_ARG, "n_nodes %d < 0", f->n_nodes);
+    if (f->n_samples < 0) return fail(SOF_ERR_INVALID_ARG, "n_samples < 0");
+    if (f->n_samples > 0x7fffffffLL)
+        return fail(SOF_ERR_OVERFLOW, "n_samples %lld above 2^31-1", (long long)f->n_samples);
+    if (f->max_node_samples < 0) return fail(SOF_ERR_INVALID_ARG, "max_node_samples < 0");
+    if (f->max_node_samples > SOF_MAX_NODE_SAMPLES)
+        return fail(SOF_ERR_OVERFLOW, "max_node_samples %d above 2^24", f->max_node_samples);
+    if (f->max_node_samples > f->n_samples)
+        return fail(SOF_ERR_INVALID_ARG, "max_node_samples %d above n_samples %lld", f->max_node_samples,
+                    (long long)f->n_samples);
+    if (!f->node_offsets) return fail(SOF_ERR_INVALID_ARG, "node_offsets is NULL");
+    if (f->n_samples > 0 && !f->sample_idx) return fail(SOF_ERR_INVALID_ARG, "sample_idx is NULL");
+    return SOF_OK;
+}
+
+int sof::check_proj(const sof_proj* p, const sof_data* d) {
+    if (!p) return fail(SOF_ERR_INVALID_ARG, "proj is NULL");
+    if (p->n_proj < 0 || p->n_nz < 0) return fail(SOF_ERR_INVALID_ARG, "n_proj or n_nz < 0");
+    if (p->n_nz > 0x7fffffffLL) return fail(SOF_ERR_OVERFLOW, "n_nz above 2^31-1");
+    if (p->max_proj_per_node < 0 || p->max_proj_per_node > 1024)
+        return fail(SOF_ERR_INVALID_ARG, "max_proj_per_node %d outside [0, 1024]", p->max_proj_per_node);
+    if (p->max_proj_per_node > p->n_proj)
+        return fail(SOF_ERR_INVALID_ARG, "max_proj_per_node %d above n_proj %d", p->max_proj_per_node,
+                    p->n_proj);
+    if (!p->proj_offsets || !p->nz_offsets) return fail(SOF_ERR_INVALID_ARG, "proj offsets NULL");
+    if (p->n_nz > 0 && (!p->nz_feature || !p->nz_weight))
+        return fail(SOF_ERR_INVALID_ARG, "nz_feature or nz_weight is NULL");
+    (void)d;
+    return SOF_OK;
+}
+
+int sof::check_params(const sof_params* q) {
+    if (!q) return fail(SOF_ERR_INVALID_ARG, "params is NULL");
+    if (q->bins < SOF_MIN_BINS || q->bins > SOF_MAX_BINS)
+        return fail(SOF_ERR_UNSUPPORTED, "bins %d outside [2, 256]", q->bins);
+    if (q->sort_threshold < 0) return fail(SOF_ERR_INVALID_ARG, "sort_threshold < 0");
+    return SOF_OK;
+}
+
+int sof::clamp_threshold(int t) { return t > SOF_SORT_LIMIT + 1 ? SOF_SORT_LIMIT + 1 : t; }
+
+// ---------------------------------------------------------------------------
+// workspace layout
+
+static size_t align_up(size_t x) { return (x + SOF_WORKSPACE_ALIGN - 1) & ~(size_t)(SOF_WORKSPACE_ALIGN - 1); }
+static int64_t mn(int64_t a, int64_t b) { return a < b ? a : b; }
+
+FindLayout sof::find_layout(int64_t N, int64_t S, int64_t P, int64_t K, int bins, int classes) {
+    FindLayout L;
+    memset(&L, 0, sizeof(L));
+    FindWs& c = L.caps;
+    const int64_t nmid = mn(N, S / (kSmallMax + 1));
+    const int64_t nsb = mn(N, S / (kSortWaveMax + 1));
+    const int64_t nbig = mn(N, S / (kMidMax + 1));
+    c.cap_small = N + 1;
+    c.cap_dmid = nmid + 1;
+    c.cap_imid = mn(P, K * nmid) + 1;
+    c.cap_dsb = nsb + 1;
+    c.cap_isb = mn(P, K * nsb) + 1;
+    c.cap_dbig = nbig + 1;
+    c.cap_ibiga = ((K + kGroup - 1) / kGroup) * (S / kChunk + nbig) + 1;
+    c.cap_ibigc = mn(P, K * nbig) + 1;
+    c.cap_slots = mn(P, K * nsb) + 1;
+    c.cap_bigslots = mn(P, K * nbig) + 1;
+    size_t o = 0;
+    L.hdr = o; o = align_up(o + H_COUNT * sizeof(int32_t));
+    L.small_items = o; o = align_up(o + c.cap_small * sizeof(int32_t));
+    L.desc_mid = o; o = align_up(o + c.cap_dmid * sizeof(int4));
+    L.desc_sb = o; o = align_up(o + c.cap_dsb * sizeof(int4));
+    L.desc_big = o; o = align_up(o + 2 * c.cap_dbig * sizeof(int4));
+    L.items_mid = o; o = align_up(o + c.cap_imid * sizeof(int2));
+    L.items_sb = o; o = align_up(o + c.cap_isb * sizeof(int2));
+    L.items_biga = o; o = align_up(o + c.cap_ibiga * sizeof(int2));
+    L.items_bigc = o; o = align_up(o + c.cap_ibigc * sizeof(int2));
+    L.slots = o; o = align_up(o + c.cap_slots * 80);
+    L.lohi = o; o = align_up(o + c.cap_bigslots * sizeof(uint2));
+    L.big_hist = o; o = align_up(o + (size_t)c.cap_bigslots * bins * classes * sizeof(int32_t));
+    L.total = o;
+    return L;
+}
+
+void sof::find_bind(const FindLayout& L, void* ws, FindWs* w) {
+    char* b = (char*)ws;
+    *w = L.caps;
+    w->hdr = (int32_t*)(b + L.hdr);
+    w->small_items = (int32_t*)(b + L.small_items);
+    w->desc_mid = (int4*)(b + L.desc_mid);
+    w->desc_sb = (int4*)(b + L.desc_sb);
+    w->desc_big = (int4*)(b + L.desc_big);
+    w->items_mid = (int2*)(b + L.items_mid);
+    w->items_sb = (int2*)(b + L.items_sb);
+    w->items_biga = (int2*)(b + L.items_biga);
+    w->items_bigc = (int2*)(b + L.items_bigc);
+    w->slots = (void*)(b + L.slots);
+    w->lohi = (uint2*)(b + L.lohi);
+    w->big_hist = (int32_t*)(b + L.big_hist);
+}
+
+extern "C" int sof_workspace_size(const sof_ctx* ctx, const sof_data* data, const sof_frontier* fr,
+                                  const sof_proj* proj, const sof_params* params, size_t* bytes) {
+    (void)ctx;
+    if (!bytes) return fail(SOF_ERR_INVALID_ARG, "bytes is NULL");
+    int rc;
+    if ((rc = check_data(data)) || (rc = check_frontier(fr)) || (rc = check_proj(proj, data)) ||
+        (rc = check_params(params)))
+        return rc;
+    FindLayout L = find_layout(fr->n_nodes, fr->n_samples, proj->n_proj, proj->max_proj_per_node,
+                               params->bins, data->n_classes);
+    size_t need = L.total;
+    size_t part = part_workspace(fr->n_nodes, fr->n_samples);
+    if (part > need) need = part;
+    size_t pj = project_workspace(fr->n_nodes);
+    if (pj > need) need = pj;
+    *bytes = need;
+    return SOF_OK;
+}
+
+static int check_ws(void* ws, size_t ws_bytes, size_t need) {
+    if (need == 0) return SOF_OK;
+    if (!ws) return fail(SOF_ERR_WORKSPACE, "workspace is NULL (need %zu bytes)", need);
+    if (((uintptr_t)ws) % SOF_WORKSPACE_ALIGN)
+        return fail(SOF_ERR_WORKSPACE, "workspace not %d-byte aligned", SOF_WORKSPACE_ALIGN);
+    if (ws_bytes < need)
+        return fail(SOF_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, need);
+    return SOF_OK;
+}
+
+int sof::check_ws_public(void* ws, size_t ws_bytes, size_t need) { return check_ws(ws, ws_bytes, need); }
+
+// ---------------------------------------------------------------------------
+// find splits
+
+int sof::fill_find_args(const sof_data* data, const sof_frontier* fr, const sof_params* params,
+                        sof_split* out, int32_t* hist_out, FindArgs* a) {
+    memset(a, 0, sizeof(*a));
+    a->x = data->x;
+    a->ld = data->ld;
+    a->y = data->y;
+    a->n_rows = data->n_rows;
+    a->n_features = data->n_features;
+    a->n_classes = data->n_classes;
+    a->dtype = data->dtype;
+    a->node_offsets = fr->node_offsets;
+    a->sample_idx = fr->sample_idx;
+    a->n_samples = fr->n_samples;
+    a->n_nodes = fr->n_nodes;
+    a->n_nodes_dev = nullptr;
+    a->node_bins = params->node_bins;
+    a->bins = params->bins;
+    a->sort_threshold = clamp_threshold(params->sort_threshold);
+    a->out = out;
+    a->hist_out = hist_out;
+    return SOF_OK;
+}
+
+extern "C" int sof_find_splits(sof_ctx* ctx, const sof_data* data, const sof_frontier* fr,
+                               const sof_proj* proj, const sof_params* params, sof_split* out,
+                               int32_t* hist_out, void* ws, size_t ws_bytes, void* stream) {
+    if (!ctx) return fail(SOF_ERR_INVALID_ARG, "ctx is NULL");
+    int rc;
+    if ((rc = check_data(data)) || (rc = check_frontier(fr)) || (rc = check_proj(proj, data)) ||
+        (rc = check_params(params)))
+        return rc;
+    if (fr->n_nodes > 0 && !out) return fail(SOF_ERR_INVALID_ARG, "out is NULL");
+    FindLayout L = find_layout(fr->n_nodes, fr->n_samples, proj->n_proj, proj->max_proj_per_node,
+                               params->bins, data->n_classes);
+    if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
+    if (fr->n_nodes == 0) return SOF_OK;
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    LaunchCfg cfg;
+    if ((rc = launch_cfg(ctx, params->bins, data->n_classes, &cfg))) return rc;
+    if (ctx->check && (rc = device_check(ctx, data, fr, proj, params, (hipStream_t)stream))) return rc;
+    FindArgs a;
+    fill_find_args(data, fr, params, out, hist_out, &a);
+    find_bind(L, ws, &a.ws);
+    ProjCSR p{proj->proj_offsets, proj->nz_offsets, proj->nz_feature, proj->nz_weight, proj->n_proj,
+              proj->n_nz};
+    e = launch_find_csr(a, p, cfg, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "find_splits launch");
+    return SOF_OK;
+}

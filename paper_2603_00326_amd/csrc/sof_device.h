@@ -1,0 +1,205 @@
+// sof_device.h -- device helpers shared by the split-search kernels (gfx950).
+//
+// Arithmetic contract (paper section 4, steps 1-3, with the precision choices
+// of this library):
+//  * projected value: acc = +0.0f, then acc = acc + (+/-x) per nonzero in CSR
+//    order, every add correctly rounded (__fadd_rn, no contraction);
+//  * equal-width bins: scale = bins / (hi - lo) correctly rounded (__fdiv_rn),
+//    FLT_MAX when not finite; t = (v - lo) * scale with __fsub_rn/__fmul_rn;
+//    bin = t < bins ? trunc(t) : bins - 1;
+//  * Gini: maximise Q = S_L/n_L + S_R/n_R = N/D compared exactly as
+//    N1*D2 > N2*D1 in unsigned 128-bit integers; split iff n*N > S_P*D.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <float.h>
+
+namespace sof {
+
+typedef unsigned __int128 u128;
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;          // work-group size of the persistent kernels
+constexpr int kWavesPerBlock = kBlock / kWave;
+
+// ---------------------------------------------------------------------------
+// float keys that order like the floats (finite values; -0 < +0 never arises)
+
+__device__ __forceinline__ uint32_t fkey(float f) {
+    uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float kfloat(uint32_t k) {
+    uint32_t u = (k & 0x80000000u) ? (k & 0x7fffffffu) : ~k;
+    return __uint_as_float(u);
+}
+
+// ---------------------------------------------------------------------------
+// feature loads: FP32 as is, FP16 widened exactly
+
+__device__ __forceinline__ float ldx(const float* col, int32_t r) { return col[r]; }
+__device__ __forceinline__ float ldx(const _Float16* col, int32_t r) { return (float)col[r]; }
+
+// +x or -x (exact) by flipping the sign bit
+__device__ __forceinline__ float signed_term(float x, uint32_t sgn) {
+    return __uint_as_float(__float_as_uint(x) ^ sgn);
+}
+
+// ---------------------------------------------------------------------------
+// bins
+
+__device__ __forceinline__ float bin_scale(int bins, float lo, float hi) {
+    float s = __fdiv_rn((float)bins, __fsub_rn(hi, lo));
+    return (s <= FLT_MAX) ? s : FLT_MAX;
+}
+__device__ __forceinline__ int bin_index(float v, float lo, float scale, int bins) {
+    float t = __fmul_rn(__fsub_rn(v, lo), scale);
+    return t < (float)bins ? (int)t : bins - 1;
+}
+__device__ __forceinline__ float hist_threshold(float lo, float scale, int bin) {
+    return __fadd_rn(lo, __fdiv_rn((float)(bin + 1), scale));
+}
+
+// ---------------------------------------------------------------------------
+// wave primitives (wave64)
+
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        uint32_t t = __shfl_up(x, off);
+        if (lane >= off) x += t;
+    }
+    return x;
+}
+
+__device__ __forceinline__ float wave_min(float x) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x = fminf(x, __shfl_xor(x, off));
+    return x;
+}
+__device__ __forceinline__ float wave_max(float x) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x = fmaxf(x, __shfl_xor(x, off));
+    return x;
+}
+__device__ __forceinline__ uint32_t wave_sum(uint32_t x) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+    return x;
+}
+
+// bits of lanes strictly below / up to and including this lane
+__device__ __forceinline__ uint64_t lanes_le_mask() {
+    const int lane = lane_id();
+    return lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+}
+
+// ---------------------------------------------------------------------------
+// candidates
+
+// Q1 > Q2 with Q = N / D, D > 0.  N <= 2^70 and D <= 2^46 for n <= 2^24, so
+// both products fit in 128 bits.
+__device__ __forceinline__ bool q_greater(u128 n1, uint64_t d1, u128 n2, uint64_t d2) {
+    return n1 * (u128)d2 > n2 * (u128)d1;
+}
+
+// One candidate boundary, with what the node record needs.
+struct Cand {
+    u128     N;       // S_L*n_R + S_R*n_L
+    uint64_t D;       // n_L*n_R; 0 = invalid
+    uint64_t SL, SR, SP;
+    int32_t  pos;     // bin or sorted position
+    int32_t  proj;    // node-local projection
+    float    thr, lo, scale;
+    int32_t  nL, nR;
+};
+static_assert(sizeof(Cand) == 80, "slot layout");
+
+__device__ __forceinline__ void cand_invalid(Cand& c) {
+    c.N = 0; c.D = 0; c.SL = c.SR = c.SP = 0; c.pos = -1; c.proj = -1;
+    c.thr = c.lo = c.scale = 0.f; c.nL = c.nR = 0;
+}
+
+// a strictly better than b; invalid (D == 0) is worse than anything valid
+__device__ __forceinline__ bool cand_better(const Cand& a, const Cand& b) {
+    if (a.D == 0) return false;
+    if (b.D == 0) return true;
+    return q_greater(a.N, a.D, b.N, b.D);
+}
+
+// Lane holding the best (largest Q, then lowest pos) valid candidate, or -1.
+// Every lane returns the same value.
+__device__ __forceinline__ int wave_best_lane(bool valid, u128 N, uint64_t D, int32_t pos) {
+    uint64_t nlo = (uint64_t)N, nhi = (uint64_t)(N >> 64);
+    uint64_t d = valid ? D : 1ull;
+    if (!valid) { nlo = 0; nhi = 0; }
+    int32_t bp = valid ? pos : 0x7fffffff;
+    int32_t bl = lane_id();
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        uint64_t olo = __shfl_xor(nlo, off), ohi = __shfl_xor(nhi, off), od = __shfl_xor(d, off);
+        int32_t op = __shfl_xor(bp, off), ol = __shfl_xor(bl, off);
+        u128 on = ((u128)ohi << 64) | olo, mn = ((u128)nhi << 64) | nlo;
+        bool take = q_greater(on, od, mn, d) || (!q_greater(mn, d, on, od) && op < bp);
+        if (take) { nlo = olo; nhi = ohi; d = od; bp = op; bl = ol; }
+    }
+    return bp == 0x7fffffff ? -1 : bl;
+}
+
+// Evaluate the boundary with left counts summarised by n_L, S_L and right
+// summarised by n_R, S_R.
+__device__ __forceinline__ bool make_q(int64_t nL, int64_t nR, uint64_t SL, uint64_t SR, u128& N,
+                                       uint64_t& D) {
+    if (nL < 1 || nR < 1) return false;
+    N = (u128)SL * (u128)(uint64_t)nR + (u128)SR * (u128)(uint64_t)nL;
+    D = (uint64_t)nL * (uint64_t)nR;
+    return true;
+}
+
+// round-to-nearest u128 -> float
+__device__ __forceinline__ float u128_to_float(u128 x) {
+    uint64_t hi = (uint64_t)(x >> 64), lo = (uint64_t)x;
+    if (hi == 0) return (float)lo;
+    int sh = 64 - __clzll((long long)hi);
+    uint64_t m = (uint64_t)(x >> sh);
+    if (lo & ((1ull << sh) - 1ull)) m |= 1ull;   // sticky bit below the rounding point
+    return ldexpf((float)m, sh);
+}
+
+// The node record of the best candidate (n = node size).
+struct SplitRec {
+    int32_t proj, kind, bin;
+    float threshold, lo, scale;
+    int32_t n_left, n_right, flags;
+    float gain;
+};
+static_assert(sizeof(SplitRec) == 40, "sof_split layout");
+
+__device__ __forceinline__ void write_record(SplitRec* out, const Cand& b, int kind, int32_t n) {
+    SplitRec r;
+    bool split = false;
+    u128 lhs = 0, rhs = 0;
+    if (b.D != 0) {
+        lhs = (u128)(uint64_t)n * b.N;
+        rhs = (u128)b.SP * (u128)b.D;
+        split = lhs > rhs;
+    }
+    if (!split) {
+        r.proj = -1; r.kind = kind; r.bin = -1; r.threshold = 0.f; r.lo = 0.f; r.scale = 0.f;
+        r.n_left = n; r.n_right = 0; r.flags = 0; r.gain = 0.f;
+    } else {
+        r.proj = b.proj; r.kind = kind; r.bin = b.pos; r.threshold = b.thr; r.lo = b.lo;
+        r.scale = b.scale; r.n_left = b.nL; r.n_right = b.nR;
+        r.flags = (b.SL == (uint64_t)b.nL * (uint64_t)b.nL ? 1 : 0) |
+                  (b.SR == (uint64_t)b.nR * (uint64_t)b.nR ? 2 : 0);
+        u128 den = (u128)((uint64_t)n * (uint64_t)n) * (u128)b.D;
+        r.gain = __fdiv_rn(u128_to_float(lhs - rhs), u128_to_float(den));
+    }
+    *out = r;
+}
+
+}  // namespace sof

@@ -1,0 +1,74 @@
+// sof_host.h -- host-side internals of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <mutex>
+#include <utility>
+
+#include "sof.h"
+#include "sof_internal.h"
+
+struct sof_ctx {
+    int device = 0;
+    int n_cu = 0;
+    size_t lds_per_block = 0;
+    bool check = false;
+    std::mutex mu;
+    std::map<std::pair<int, int>, sof::LaunchCfg> cfg;
+};
+
+namespace sof {
+
+int fail(int code, const char* fmt, ...);
+int hip_fail(hipError_t e, const char* what);
+
+int check_data(const sof_data* d);
+int check_frontier(const sof_frontier* f);
+int check_proj(const sof_proj* p, const sof_data* d);
+int check_params(const sof_params* q);
+int check_ws_public(void* ws, size_t ws_bytes, size_t need);
+int clamp_threshold(int t);
+
+int launch_cfg(sof_ctx* ctx, int bins, int classes, LaunchCfg* cfg);
+int fill_find_args(const sof_data* data, const sof_frontier* fr, const sof_params* params,
+                   sof_split* out, int32_t* hist_out, FindArgs* a);
+
+// partition
+struct PartArgs {
+    const void* x;
+    int64_t ld;
+    int32_t n_rows, n_features, dtype;
+    const int32_t* node_offsets;
+    const int32_t* sample_idx;
+    int64_t n_samples;
+    int32_t n_nodes;
+    const int32_t* n_nodes_dev;
+    const int32_t* node_bins;
+    int32_t bins;
+    const void* splits;       // SplitRec[n_nodes]
+    int32_t* out_idx;
+    int32_t* child_offsets;
+    // workspace
+    int32_t* hdr;             // counters
+    int4* big_items;          // (node, chunk, chunk count, first item of the node)
+    int32_t* chunk_left;      // left count per chunk item
+    uint64_t* pred_bits;      // one bit per sample of every chunk item
+    int64_t cap_items;
+};
+size_t part_workspace(int64_t n_nodes, int64_t n_samples);
+void part_bind(int64_t n_nodes, int64_t n_samples, void* ws, PartArgs* a);
+hipError_t launch_partition_csr(const PartArgs& a, const ProjCSR& p, int n_cu, hipStream_t s);
+hipError_t launch_partition_hash(const PartArgs& a, const ProjHash& p, int n_cu, hipStream_t s);
+
+// projection only
+size_t project_workspace(int64_t n_nodes);
+hipError_t launch_project(const FindArgs& a, const ProjCSR& p, float* out, void* ws, int n_cu,
+                          hipStream_t s);
+
+// content checks (SOF_CHECK=1)
+int device_check(sof_ctx* ctx, const sof_data* data, const sof_frontier* fr, const sof_proj* proj,
+                 const sof_params* params, hipStream_t s);
+
+}  // namespace sof

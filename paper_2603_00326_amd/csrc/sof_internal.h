@@ -1,0 +1,122 @@
+// sof_internal.h -- host/device plumbing shared by the library's translation
+// units: argument blocks, work-queue layout and launch entry points.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "sof.h"
+
+namespace sof {
+
+// Size classes of the batched frontier launch.  A node takes the sort path
+// when n < T (T clamped to SOF_SORT_LIMIT + 1), else the histogram path.
+constexpr int kSortWaveMax = 64;     // sort nodes up to here: sorted in registers by one wave
+constexpr int kSmallMax = 1024;      // histogram nodes up to here: one block per node
+constexpr int kMidMax = 8192;        // histogram nodes up to here: one block per (node, projection)
+constexpr int kChunk = 8192;         // larger nodes: (node, projection group, sample chunk) items
+constexpr int kGroup = 8;            // projections per big-node item
+constexpr int kSortMax = SOF_SORT_LIMIT;
+
+// header counters of the find-splits workspace
+enum {
+    H_SMALL = 0,   // small node items
+    H_DMID,        // mid descriptors
+    H_IMID,        // mid items
+    H_DSB,         // sort-block descriptors
+    H_ISB,         // sort-block items
+    H_DBIG,        // big descriptors
+    H_IBIGA,       // big chunk items (min/max and histogram passes)
+    H_IBIGC,       // big scan items
+    H_SLOTS,       // candidate slots
+    H_BIGSLOTS,    // big projection slots (range, global histogram)
+    H_Q_BIGA = 16, // dequeue counters
+    H_Q_MID,
+    H_Q_SMALL,
+    H_Q_SB,
+    H_Q_BIGB,
+    H_Q_BIGC,
+    H_Q_RED,
+    H_ERR = 32,
+    H_COUNT = 64
+};
+
+struct ProjCSR {
+    const int32_t* proj_offsets;
+    const int32_t* nz_offsets;
+    const int32_t* nz_feature;
+    const int8_t* nz_weight;
+    int32_t n_proj;
+    int64_t n_nz;
+};
+
+// Projections drawn on the fly from a counter-based hash (forest growth):
+// node v of the frontier belongs to tree tree_of[v] at position pos_of[v] of
+// that tree's frontier at level *level.
+struct ProjHash {
+    const int32_t* tree_of;
+    const int32_t* pos_of;
+    const int32_t* level;
+    uint64_t seed;
+    int32_t k, z;
+};
+
+struct FindWs {
+    int32_t* hdr;
+    int32_t* small_items;
+    int4* desc_mid;
+    int4* desc_sb;
+    int4* desc_big;       // two int4 per big node
+    int2* items_mid;
+    int2* items_sb;
+    int2* items_biga;
+    int2* items_bigc;
+    void* slots;          // Cand[]
+    uint2* lohi;          // per big slot: ordered keys of min and max
+    int32_t* big_hist;    // per big slot: [bins][classes]
+    int64_t cap_small, cap_dmid, cap_imid, cap_dsb, cap_isb, cap_dbig, cap_ibiga, cap_ibigc;
+    int64_t cap_slots, cap_bigslots;
+};
+
+struct FindArgs {
+    const void* x;
+    int64_t ld;
+    const int32_t* y;
+    int32_t n_rows, n_features, n_classes, dtype;
+    const int32_t* node_offsets;
+    const int32_t* sample_idx;
+    int64_t n_samples;
+    int32_t n_nodes;            // host count, or the capacity when n_nodes_dev is set
+    const int32_t* n_nodes_dev; // device count (forest growth), or NULL
+    const int32_t* node_bins;
+    int32_t bins, sort_threshold;  // sort_threshold already clamped
+    void* out;                  // SplitRec[n_nodes]
+    int32_t* hist_out;
+    FindWs ws;
+};
+
+// Byte layout of the find-splits workspace for the given sizes.
+struct FindLayout {
+    size_t hdr, small_items, desc_mid, desc_sb, desc_big, items_mid, items_sb, items_biga, items_bigc;
+    size_t slots, lohi, big_hist, total;
+    FindWs caps;
+};
+FindLayout find_layout(int64_t n_nodes, int64_t n_samples, int64_t n_proj, int64_t max_k, int bins,
+                       int classes);
+void find_bind(const FindLayout& L, void* ws, FindWs* out);
+
+struct LaunchCfg {
+    int grid_main, grid_sort, grid_small;
+    int n_cu;
+    size_t smem_main, smem_sort;
+};
+
+// launchers (return hipError_t)
+hipError_t launch_find_csr(const FindArgs& a, const ProjCSR& p, const LaunchCfg& cfg, hipStream_t s);
+hipError_t launch_find_hash(const FindArgs& a, const ProjHash& p, const LaunchCfg& cfg, hipStream_t s);
+size_t find_smem_main(int bins, int classes);
+size_t find_smem_sort();
+hipError_t find_occupancy(int bins, int classes, int* blocks_main, int* blocks_sort);
+
+}  // namespace sof

@@ -1,0 +1,368 @@
+"""Python binding of libsof (the C ABI in include/sof.h).
+
+Argument marshalling only: every step of the split search runs in the HIP
+kernels of libsof.so.  PyTorch supplies device memory (tensors) and streams.
+The binding raises if the library is missing; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libsof.so")
+
+SOF_OK = 0
+SOF_ERR_INVALID_ARG = -1
+SOF_ERR_UNSUPPORTED = -2
+SOF_ERR_WORKSPACE = -3
+SOF_ERR_OVERFLOW = -4
+SOF_ERR_HIP = -5
+SOF_ERR_DEVICE = -6
+SOF_F32, SOF_F16 = 0, 1
+SORT_LIMIT = 8192
+INT32_MAX = 2**31 - 1
+
+EXPORTED = [
+    "sof_version", "sof_last_error", "sof_create", "sof_destroy", "sof_workspace_size",
+    "sof_project", "sof_find_splits", "sof_partition", "sof_forest_create", "sof_forest_destroy",
+    "sof_grow_level", "sof_forest_frontier_size", "sof_forest_export", "sof_autotune",
+]
+
+
+class SofError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libsof error {code}: {msg}")
+        self.code = code
+
+
+P = ctypes.c_void_p
+i32, i64, u64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
+
+
+class sof_data(ctypes.Structure):
+    _fields_ = [("x", P), ("y", P), ("ld", i64), ("n_rows", i32), ("n_features", i32),
+                ("n_classes", i32), ("dtype", i32)]
+
+
+class sof_frontier(ctypes.Structure):
+    _fields_ = [("node_offsets", P), ("sample_idx", P), ("n_samples", i64), ("n_nodes", i32),
+                ("max_node_samples", i32)]
+
+
+class sof_proj(ctypes.Structure):
+    _fields_ = [("proj_offsets", P), ("nz_offsets", P), ("nz_feature", P), ("nz_weight", P),
+                ("n_nz", i64), ("n_proj", i32), ("max_proj_per_node", i32)]
+
+
+class sof_params(ctypes.Structure):
+    _fields_ = [("node_bins", P), ("bins", i32), ("sort_threshold", i32)]
+
+
+class sof_forest_desc(ctypes.Structure):
+    _fields_ = [("root_offsets", P), ("root_idx", P), ("seed", u64), ("n_trees", i32),
+                ("first_tree", i32), ("k", i32), ("z", i32), ("bins", i32), ("sort_threshold", i32),
+                ("max_depth", i32), ("pad", i32)]
+
+
+class sof_tune(ctypes.Structure):
+    _fields_ = [("sort_threshold", i32), ("bins_small", i32), ("bins_switch", i32), ("n_points", i32),
+                ("sort_us", ctypes.c_float * 32), ("hist_us", ctypes.c_float * 32),
+                ("sizes", i32 * 32), ("elapsed_ms", ctypes.c_float)]
+
+
+SPLIT_DTYPE = np.dtype([
+    ("proj", "<i4"), ("kind", "<i4"), ("bin", "<i4"), ("threshold", "<f4"), ("lo", "<f4"),
+    ("scale", "<f4"), ("n_left", "<i4"), ("n_right", "<i4"), ("flags", "<i4"), ("gain", "<f4"),
+])
+assert SPLIT_DTYPE.itemsize == 40
+
+TREE_NODE_DTYPE = np.dtype([
+    ("tree", "<i4"), ("depth", "<i4"), ("parent", "<i4"), ("left", "<i4"), ("right", "<i4"),
+    ("n_samples", "<i4"), ("label", "<i4"), ("is_leaf", "<i4"), ("kind", "<i4"), ("bin", "<i4"),
+    ("threshold", "<f4"), ("lo", "<f4"), ("scale", "<f4"), ("n_bins", "<i4"), ("nnz", "<i4"),
+    ("pad", "<i4"), ("feature", "<i4", (16,)), ("weight", "i1", (16,)), ("gain", "<f8"),
+])
+assert TREE_NODE_DTYPE.itemsize == 152
+
+_lib = None
+
+
+def lib():
+    """Load libsof.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2603_00326_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        L.sof_version.restype = ctypes.c_char_p
+        L.sof_last_error.restype = ctypes.c_char_p
+        L.sof_create.argtypes = [ctypes.c_int, ctypes.POINTER(P)]
+        L.sof_destroy.argtypes = [P]
+        L.sof_workspace_size.argtypes = [P, ctypes.POINTER(sof_data), ctypes.POINTER(sof_frontier),
+                                         ctypes.POINTER(sof_proj), ctypes.POINTER(sof_params),
+                                         ctypes.POINTER(ctypes.c_size_t)]
+        L.sof_project.argtypes = [P, ctypes.POINTER(sof_data), ctypes.POINTER(sof_frontier),
+                                  ctypes.POINTER(sof_proj), P, P, ctypes.c_size_t, P]
+        L.sof_find_splits.argtypes = [P, ctypes.POINTER(sof_data), ctypes.POINTER(sof_frontier),
+                                      ctypes.POINTER(sof_proj), ctypes.POINTER(sof_params), P, P, P,
+                                      ctypes.c_size_t, P]
+        L.sof_partition.argtypes = [P, ctypes.POINTER(sof_data), ctypes.POINTER(sof_frontier),
+                                    ctypes.POINTER(sof_proj), ctypes.POINTER(sof_params), P, P, P, P,
+                                    ctypes.c_size_t, P]
+        if hasattr(L, "sof_forest_create"):
+            L.sof_forest_create.argtypes = [P, ctypes.POINTER(sof_data), ctypes.POINTER(sof_forest_desc),
+                                            ctypes.POINTER(P)]
+            L.sof_forest_destroy.argtypes = [P]
+            L.sof_grow_level.argtypes = [P, ctypes.c_int, P]
+            L.sof_forest_frontier_size.argtypes = [P, ctypes.POINTER(i64), P]
+            L.sof_forest_export.argtypes = [P, P, i64, ctypes.POINTER(i64), P]
+        if hasattr(L, "sof_autotune"):
+            L.sof_autotune.argtypes = [P, i32, i32, i32, i32, ctypes.POINTER(sof_tune), P]
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != SOF_OK:
+        raise SofError(rc, lib().sof_last_error().decode())
+
+
+def version() -> str:
+    return lib().sof_version().decode()
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+def _stream(stream) -> int | None:
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+class Context:
+    """A libsof context on one HIP device."""
+
+    def __init__(self, device: int = 0):
+        h = P()
+        _check(lib().sof_create(int(device), ctypes.byref(h)))
+        self.handle = h
+        self.device = device
+        self._ws = None
+
+    def close(self):
+        if self.handle:
+            lib().sof_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace(self, nbytes: int):
+        """A cached device workspace of at least nbytes (256-byte aligned)."""
+        import torch
+        if self._ws is None or self._ws.numel() < nbytes + 256:
+            self._ws = torch.empty(max(nbytes + 256, 1 << 16), dtype=torch.uint8,
+                                   device=f"cuda:{self.device}")
+        base = self._ws.data_ptr()
+        off = (-base) % 256
+        return base + off, self._ws.numel() - off
+
+
+@dataclass
+class DeviceFrontier:
+    """Device copies of one batch of split-search input (torch tensors)."""
+
+    X: object
+    y: object
+    n_classes: int
+    node_offsets: object
+    sample_idx: object
+    proj_offsets: object
+    nz_offsets: object
+    nz_feature: object
+    nz_weight: object
+    node_bins: object = None
+    max_node_samples: int = 0
+    max_proj_per_node: int = 0
+
+    @property
+    def n_nodes(self) -> int:
+        return int(self.node_offsets.numel() - 1)
+
+    def structs(self):
+        X = self.X
+        dtype = SOF_F16 if str(X.dtype) == "torch.float16" else SOF_F32
+        d = sof_data(_ptr(X), _ptr(self.y), int(X.stride(0)), int(X.shape[1]), int(X.shape[0]),
+                     int(self.n_classes), dtype)
+        f = sof_frontier(_ptr(self.node_offsets), _ptr(self.sample_idx), int(self.sample_idx.numel()),
+                         self.n_nodes, int(self.max_node_samples))
+        p = sof_proj(_ptr(self.proj_offsets), _ptr(self.nz_offsets), _ptr(self.nz_feature),
+                     _ptr(self.nz_weight), int(self.nz_feature.numel()), int(self.nz_offsets.numel() - 1),
+                     int(self.max_proj_per_node))
+        return d, f, p
+
+
+def to_device(wl, device="cuda:0", X=None) -> DeviceFrontier:
+    """Copy a workload's host arrays to the device (no computation)."""
+    import torch
+
+    def t(a, dt):
+        return torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).to(device)
+
+    n = np.diff(wl.node_offsets.astype(np.int64))
+    k = np.diff(wl.proj_offsets.astype(np.int64))
+    Xd = X if X is not None else torch.from_numpy(np.ascontiguousarray(wl.X)).to(device)
+    return DeviceFrontier(
+        X=Xd, y=t(wl.y, np.int32), n_classes=int(wl.n_classes),
+        node_offsets=t(wl.node_offsets, np.int32), sample_idx=t(wl.sample_idx, np.int32),
+        proj_offsets=t(wl.proj_offsets, np.int32), nz_offsets=t(wl.nz_offsets, np.int32),
+        nz_feature=t(wl.nz_feature, np.int32), nz_weight=t(wl.nz_weight, np.int8),
+        node_bins=None if wl.node_bins is None else t(wl.node_bins, np.int32),
+        max_node_samples=int(n.max()) if n.size else 0, max_proj_per_node=int(k.max()) if k.size else 0)
+
+
+def _params(dev: DeviceFrontier, bins: int, sort_threshold: int) -> sof_params:
+    return sof_params(_ptr(dev.node_bins), int(bins), int(sort_threshold))
+
+
+def workspace_size(dev: DeviceFrontier, bins: int = 256, sort_threshold: int = 0, ctx=None) -> int:
+    d, f, p = dev.structs()
+    q = _params(dev, bins, sort_threshold)
+    out = ctypes.c_size_t(0)
+    _check(lib().sof_workspace_size(ctx.handle if ctx else None, ctypes.byref(d), ctypes.byref(f),
+                                    ctypes.byref(p), ctypes.byref(q), ctypes.byref(out)))
+    return int(out.value)
+
+
+def find_splits(ctx: Context, dev: DeviceFrontier, *, bins=256, sort_threshold=0, hist=False,
+                out=None, stream=None):
+    """Best split per node.  Returns (splits int32 tensor (N, 10) in sof_split
+    layout, hist int32 tensor (P, bins, C) or None)."""
+    import torch
+    d, f, p = dev.structs()
+    q = _params(dev, bins, sort_threshold)
+    ws, wsb = ctx.workspace(workspace_size(dev, bins, sort_threshold, ctx))
+    N = dev.n_nodes
+    if out is None:
+        out = torch.empty((max(N, 1), 10), dtype=torch.int32, device=dev.node_offsets.device)
+    H = None
+    if hist:
+        H = torch.empty((int(dev.nz_offsets.numel() - 1), bins, dev.n_classes), dtype=torch.int32,
+                        device=dev.node_offsets.device)
+    _check(lib().sof_find_splits(ctx.handle, ctypes.byref(d), ctypes.byref(f), ctypes.byref(p),
+                                 ctypes.byref(q), _ptr(out), _ptr(H), ws, wsb, _stream(stream)))
+    return out, H
+
+
+def partition(ctx: Context, dev: DeviceFrontier, splits, *, bins=256, stream=None):
+    """Stable partition.  Returns (out_idx, child_offsets) int32 tensors."""
+    import torch
+    d, f, p = dev.structs()
+    q = _params(dev, bins, 0)
+    ws, wsb = ctx.workspace(workspace_size(dev, bins, 0, ctx))
+    out_idx = torch.empty_like(dev.sample_idx)
+    coff = torch.empty(2 * dev.n_nodes + 1, dtype=torch.int32, device=dev.sample_idx.device)
+    _check(lib().sof_partition(ctx.handle, ctypes.byref(d), ctypes.byref(f), ctypes.byref(p),
+                               ctypes.byref(q), _ptr(splits), _ptr(out_idx), _ptr(coff), ws, wsb,
+                               _stream(stream)))
+    return out_idx, coff
+
+
+def project(ctx: Context, dev: DeviceFrontier, *, stream=None):
+    """Projected values, node blocks [projection][sample] in node order."""
+    import torch
+    d, f, p = dev.structs()
+    n = torch.diff(dev.node_offsets.long()).cpu().numpy()
+    k = torch.diff(dev.proj_offsets.long()).cpu().numpy()
+    total = int((n * k).sum())
+    out = torch.empty(max(total, 1), dtype=torch.float32, device=dev.X.device)
+    ws, wsb = ctx.workspace(workspace_size(dev, 256, 0, ctx))
+    _check(lib().sof_project(ctx.handle, ctypes.byref(d), ctypes.byref(f), ctypes.byref(p), _ptr(out),
+                             ws, wsb, _stream(stream)))
+    return out[:total]
+
+
+def splits_to_numpy(t) -> np.ndarray:
+    """sof_split records (int32 tensor (N, 10)) as a numpy structured array."""
+    a = t.detach().cpu().numpy().astype(np.int32, copy=False)
+    return np.ascontiguousarray(a).view(SPLIT_DTYPE).reshape(-1)
+
+
+def splits_from_numpy(rec: np.ndarray, device="cuda:0"):
+    """Records with the sof_split fields (e.g. the oracle's) as an int32 device tensor."""
+    import torch
+    out = np.zeros(len(rec), SPLIT_DTYPE)
+    for name in SPLIT_DTYPE.names:
+        out[name] = rec[name]
+    return torch.from_numpy(out.view(np.int32).reshape(-1, 10).copy()).to(device)
+
+
+class Forest:
+    """Level-wise growth of several trees to purity on the device."""
+
+    def __init__(self, ctx: Context, X, y, n_classes: int, root_offsets, root_idx, *, k: int, z: int,
+                 seed: int, bins: int = 256, sort_threshold: int = 0, max_depth: int = 64,
+                 first_tree: int = 0):
+        self.ctx = ctx
+        self._keep = (X, y, root_idx)
+        dtype = SOF_F16 if str(X.dtype) == "torch.float16" else SOF_F32
+        self.data = sof_data(_ptr(X), _ptr(y), int(X.stride(0)), int(X.shape[1]), int(X.shape[0]),
+                             int(n_classes), dtype)
+        ro = np.ascontiguousarray(root_offsets, dtype=np.int64)
+        self._ro = ro
+        self.n_trees = len(ro) - 1
+        self.desc = sof_forest_desc(ro.ctypes.data, _ptr(root_idx), int(seed) & (2**64 - 1), self.n_trees,
+                                    int(first_tree), int(k), int(z), int(bins), int(sort_threshold),
+                                    int(max_depth), 0)
+        h = P()
+        _check(lib().sof_forest_create(ctx.handle, ctypes.byref(self.data), ctypes.byref(self.desc),
+                                       ctypes.byref(h)))
+        self.handle = h
+        self.max_nodes = 2 * int(ro[-1]) + self.n_trees + 2
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().sof_forest_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def grow_level(self, use_graph: bool = True, stream=None):
+        _check(lib().sof_grow_level(self.handle, int(bool(use_graph)), _stream(stream)))
+
+    def frontier_size(self, stream=None) -> int:
+        n = i64(0)
+        _check(lib().sof_forest_frontier_size(self.handle, ctypes.byref(n), _stream(stream)))
+        return int(n.value)
+
+    def export(self, stream=None) -> np.ndarray:
+        out = np.zeros(self.max_nodes, TREE_NODE_DTYPE)
+        n = i64(0)
+        _check(lib().sof_forest_export(self.handle, out.ctypes.data, int(self.max_nodes), ctypes.byref(n),
+                                       _stream(stream)))
+        return out[:n.value].copy()
+
+    def grow(self, use_graph: bool = True, stream=None, max_levels: int = 65):
+        """Grow until the frontier is empty; returns the frontier size before each level."""
+        sizes = []
+        for _ in range(max_levels):
+            n = self.frontier_size(stream)
+            if n == 0:
+                break
+            sizes.append(n)
+            self.grow_level(use_graph, stream)
+        return sizes

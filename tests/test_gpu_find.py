@@ -1,0 +1,141 @@
+"""GPU parity: batched split search, partition and projection through the C ABI
+against the CPU oracle on the same seeded inputs."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2603_00326_amd import workloads as W
+from tests.gpu_helpers import assert_splits_match, say
+
+pytestmark = pytest.mark.gpu
+
+# node sizes around every size-class edge of the batched launch (sort in
+# registers <= 64, small block <= 1024, mid block <= 8192, chunked above) and
+# the degenerate sizes 0, 1, 2
+EDGE_SIZES = [0, 1, 2, 3, 5, 17, 63, 64, 65, 100, 255, 256, 257, 511, 1000, 1023, 1024, 1025, 2049,
+              4097, 8191, 8192, 8193, 12000, 16385, 30001]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2603_00326_amd as S
+    return S.Context(0)
+
+
+def run_gpu(ctx, wl, hist=True, stream=None):
+    import paper_2603_00326_amd as S
+    import torch
+    dev = S.to_device(wl)
+    out, H = S.find_splits(ctx, dev, bins=wl.bins, sort_threshold=wl.sort_threshold, hist=hist)
+    torch.cuda.synchronize()
+    return dev, S.splits_to_numpy(out)[:wl.n_nodes], (H.cpu().numpy() if H is not None else None)
+
+
+def check_case(ctx, wl, tag):
+    say(f"[gpu] {tag}: nodes={wl.n_nodes} samples={wl.n_samples} proj={wl.n_proj} "
+        f"C={wl.n_classes} B={wl.bins} T={wl.sort_threshold} dtype={wl.X.dtype}")
+    dev, got, H = run_gpu(ctx, wl)
+    ref, Href = O.find_splits_w(wl, hist=True)
+    assert_splits_match(got, ref, tag)
+    bad = np.argwhere(H != Href)
+    assert bad.size == 0, f"{tag}: histogram differs at {bad[:5].tolist()}"
+    return dev, got, ref
+
+
+@pytest.mark.parametrize("T", [0, 64, 300, 2**31 - 1])
+def test_edge_sizes_all_paths(ctx, T):
+    wl = W.random_frontier(7, n_rows=60000, d=24, n_classes=3, sizes=EDGE_SIZES, k=6, z=3,
+                           bins=256, sort_threshold=T, layout="b")
+    check_case(ctx, wl, f"edge T={T}")
+
+
+@pytest.mark.parametrize("C,B", [(2, 256), (5, 128), (16, 256), (16, 2), (7, 3)])
+def test_classes_and_bins(ctx, C, B):
+    wl = W.random_frontier(100 + C, n_rows=40000, d=16, n_classes=C,
+                           sizes=[3, 40, 700, 3000, 9000, 20000], k=5, z=(1, 4), bins=B,
+                           sort_threshold=50, layout="r")
+    check_case(ctx, wl, f"C={C} B={B}")
+
+
+def test_integer_features_with_ties(ctx):
+    wl = W.random_frontier(21, n_rows=50000, d=10, n_classes=3, sizes=[10, 60, 200, 2000, 9000, 30000],
+                           k=8, z=3, bins=256, sort_threshold=500, layout="b", integer_features=2)
+    check_case(ctx, wl, "integer ties")
+
+
+def test_node_bins(ctx):
+    sizes = [30, 300, 3000, 10000]
+    wl = W.random_frontier(22, n_rows=20000, d=12, n_classes=3, sizes=sizes, k=6, z=3, bins=256,
+                           sort_threshold=0, layout="a", node_bins=[2, 128, 256, 37])
+    check_case(ctx, wl, "node bins")
+
+
+def test_fp16_storage(ctx):
+    wl = W.random_frontier(23, n_rows=40000, d=16, n_classes=2, sizes=[50, 900, 5000, 20000], k=8,
+                           z=(1, 8), bins=256, sort_threshold=100, layout="b", dtype=np.float16)
+    check_case(ctx, wl, "fp16")
+
+
+def test_many_small_nodes(ctx):
+    rng = np.random.default_rng(5)
+    sizes = rng.integers(2, 80, size=3000)
+    wl = W.random_frontier(24, n_rows=200000, d=32, n_classes=4, sizes=sizes, k=16, z=3, bins=256,
+                           sort_threshold=40, layout="r")
+    check_case(ctx, wl, "many small")
+
+
+def test_zero_projection_nodes(ctx):
+    wl = W.random_frontier(25, n_rows=5000, d=8, n_classes=2, sizes=[10, 500, 3000], k=4, z=2)
+    # drop node 1's four projections: nodes 0 and 2 keep theirs
+    keep = np.r_[0:4, 8:12]
+    zf = wl.nz_feature.reshape(12, 2)[keep].reshape(-1)
+    zw = wl.nz_weight.reshape(12, 2)[keep].reshape(-1)
+    wl.nz_feature, wl.nz_weight = zf.astype(np.int32), zw.astype(np.int8)
+    wl.nz_offsets = (np.arange(9) * 2).astype(np.int32)
+    wl.proj_offsets = np.array([0, 4, 4, 8], np.int32)
+    check_case(ctx, wl, "zero projections")
+
+
+def test_partition_matches_oracle(ctx):
+    import paper_2603_00326_amd as S
+    import torch
+    for T in (0, 200):
+        wl = W.random_frontier(31, n_rows=80000, d=20, n_classes=3, sizes=EDGE_SIZES, k=6, z=3, bins=256,
+                               sort_threshold=T, layout="r")
+        say(f"[gpu] partition T={T}")
+        ref, _ = O.find_splits_w(wl)
+        dev = S.to_device(wl)
+        sp = S.splits_from_numpy(ref)
+        out_idx, coff = S.partition(ctx, dev, sp, bins=wl.bins)
+        torch.cuda.synchronize()
+        want_idx, want_coff = O.partition(wl.X, wl.node_offsets, wl.sample_idx, wl.proj_offsets, wl.nz_offsets,
+                                          wl.nz_feature, wl.nz_weight, ref, bins=wl.bins)
+        assert np.array_equal(coff.cpu().numpy(), want_coff)
+        assert np.array_equal(out_idx.cpu().numpy(), want_idx)
+
+
+def test_project_matches_oracle(ctx):
+    import paper_2603_00326_amd as S
+    import torch
+    for dt in (np.float32, np.float16):
+        wl = W.random_frontier(41, n_rows=30000, d=20, n_classes=2, sizes=[0, 1, 77, 5000, 20000], k=5,
+                               z=(1, 16), layout="r", dtype=dt)
+        say(f"[gpu] project {dt.__name__}")
+        dev = S.to_device(wl)
+        got = S.project(ctx, dev)
+        torch.cuda.synchronize()
+        want = O.project(wl.X, wl.node_offsets, wl.sample_idx, wl.proj_offsets, wl.nz_offsets,
+                         wl.nz_feature, wl.nz_weight)
+        assert np.array_equal(got.cpu().numpy().view(np.uint32), want.view(np.uint32))
+
+
+def test_repeat_runs_identical(ctx):
+    wl = W.random_frontier(51, n_rows=60000, d=16, n_classes=3, sizes=EDGE_SIZES, k=4, z=3, bins=256,
+                           sort_threshold=100, layout="r")
+    say("[gpu] determinism")
+    _, a, Ha = run_gpu(ctx, wl)
+    for _ in range(4):
+        _, b, Hb = run_gpu(ctx, wl)
+        assert a.tobytes() == b.tobytes() and np.array_equal(Ha, Hb)
