@@ -248,6 +248,30 @@ int sof_forest_export(sof_forest* forest, sof_tree_node* host_nodes, int64_t cap
 int sof_autotune(sof_ctx* ctx, int32_t n_classes, int32_t k, int32_t nnz, int32_t bins,
                  sof_tune* out, void* stream);
 
+/* Benchmark instrumentation.  The launch sequence of sof_find_splits runs in
+ * these stages, in this order: */
+enum {
+    SOF_STAGE_PLAN = 0,   /* counter reset, node classification, queue expansion */
+    SOF_STAGE_BIG_RANGE,  /* nodes above 8192 samples: range of each (projection, chunk) */
+    SOF_STAGE_BIG_MERGE,  /* ... range of each projection over the node */
+    SOF_STAGE_BIG_HIST,   /* ... class histogram of each (projection, chunk) */
+    SOF_STAGE_BIG_SCAN,   /* ... summed histograms, boundary scan */
+    SOF_STAGE_MID,        /* histogram nodes of 1025..8192 samples */
+    SOF_STAGE_SMALL,      /* histogram nodes up to 1024, sort nodes up to 64 */
+    SOF_STAGE_SORT,       /* sort nodes of 65..8192 samples */
+    SOF_STAGE_REDUCE,     /* best projection per node */
+    SOF_STAGE_COUNT
+};
+/* While enabled, every sof_find_splits call records HIP events on its own
+ * stream between the stages (events are created on first use, so enabling
+ * is not for graph capture).  sof_timing_read waits for the recorded events
+ * and writes summed milliseconds since the last read: ms[s] for stage s and
+ * ms[SOF_STAGE_COUNT] for the whole sequence (ms holds SOF_STAGE_COUNT + 1
+ * floats), and the number of calls.  Errors: SOF_ERR_INVALID_ARG for NULL
+ * arguments, SOF_ERR_HIP if an event query fails. */
+int sof_timing_enable(sof_ctx* ctx, int enable);
+int sof_timing_read(sof_ctx* ctx, float* ms, int32_t* calls);
+
 #ifdef __cplusplus
 }
 #endif

@@ -3,18 +3,23 @@
 // sorting; section 6 names batching many nodes into one GPU launch as the
 // next step, which is what this launch sequence does).
 //
-// Launch sequence on one stream (every launch is a persistent grid that reads
-// its work counts from device memory, so the sequence is graph-capturable):
+// Launch sequence on one stream.  Every kernel reads its work counts from
+// device memory, so the sequence is graph-capturable:
 //   k_reset    zero the queue counters
 //   k_plan     classify nodes by path and size, allocate queue entries
 //   k_expand   write the (descriptor, sub-item) entries of every queue
-//   k_main     big-node min/max chunks, mid nodes (one block per node and
-//              projection), small nodes (one block per node, one wave per
-//              projection); all single pass, projected values in registers
-//   k_sortblk  sort-path nodes of 65..8192 samples: bitonic sort in LDS
-//   k_bighist  big-node histogram chunks (second pass after the global range)
-//   k_bigscan  big-node boundary scans
+//   k_brange   big nodes: range of every (projection, chunk); one wave each
+//   k_bmerge   big nodes: range of every projection over its chunks
+//   k_bhist    big nodes: histogram of every (projection, chunk); one wave each
+//   k_bscan    big nodes: chunk histograms summed, boundary scan
+//   k_mid      histogram nodes of 1025..8192 samples: one block per (node, projection)
+//   k_small    histogram nodes up to 1024 samples and sort nodes up to 64:
+//              one block per node, one wave per projection
+//   k_sortblk  sort nodes of 65..8192 samples: bitonic sort in LDS
 //   k_reduce   best projection per node for nodes with per-projection slots
+// Partial results of big nodes go to distinct workspace entries with plain
+// stores and are combined by the next kernel; no global atomics take part in
+// the arithmetic, and no kernel waits on another block.
 #include "sof_device.h"
 #include "sof_internal.h"
 
@@ -282,62 +287,6 @@ __device__ Cand scan_hist(const H& h, int B, int C, int64_t n, float lo, float s
     return c;
 }
 
-// Sort path for n <= 64: lane i holds (v_i, y_i); a bitonic network across
-// the wave sorts the (order-preserving key, label) pairs; left counts at
-// sorted position i come from per-class ballots; boundaries only between
-// distinct values.
-__device__ Cand scan_sort_wave(float val, int lab, int64_t n, int C, const int32_t* pc) {
-    const int lane = lane_id();
-    uint64_t key = lane < n ? (((uint64_t)fkey(val) << 32) | (uint32_t)lab) : ~0ull;
-#pragma unroll
-    for (int kk = 2; kk <= kWave; kk <<= 1) {
-#pragma unroll
-        for (int j = kk >> 1; j > 0; j >>= 1) {
-            uint64_t o = __shfl_xor(key, j);
-            bool asc = (lane & kk) == 0;
-            bool lower = (lane & j) == 0;
-            key = (asc == lower) ? (o < key ? o : key) : (o > key ? o : key);
-        }
-    }
-    const uint32_t myk = (uint32_t)(key >> 32);
-    const int mylab = (int)(uint32_t)key;
-    const uint32_t nextk = __shfl_down(myk, 1);
-    const bool real = lane < n;
-    const uint64_t le = lanes_le_mask();
-    uint64_t SL = 0, SR = 0, SP = 0;
-    for (int c = 0; c < C; ++c) {
-        uint64_t m = __ballot(real && mylab == c);
-        uint32_t l = (uint32_t)__popcll(m & le);
-        uint32_t Pc = (uint32_t)pc[c];
-        uint32_t r = Pc - l;
-        SL += (uint64_t)l * l;
-        SR += (uint64_t)r * r;
-        SP += (uint64_t)Pc * Pc;
-    }
-    u128 N = 0;
-    uint64_t D = 0;
-    bool ok = lane + 1 < n && myk < nextk &&
-              make_q((int64_t)lane + 1, n - (int64_t)lane - 1, SL, SR, N, D);
-    int win = wave_best_lane(ok, N, D, lane);
-    Cand c;
-    cand_invalid(c);
-    c.SP = SP;
-    c.lo = kfloat(__shfl(myk, 0));
-    if (win >= 0) {
-        uint64_t nlo = __shfl((uint64_t)N, win), nhi = __shfl((uint64_t)(N >> 64), win);
-        c.N = ((u128)nhi << 64) | nlo;
-        c.D = __shfl(D, win);
-        c.SL = __shfl(SL, win);
-        c.SR = __shfl(SR, win);
-        c.pos = win;
-        c.nL = win + 1;
-        c.nR = (int32_t)(n - c.nL);
-        c.thr = kfloat(__shfl(myk, win));
-        c.scale = 0.f;
-    }
-    return c;
-}
-
 // a better than b, ties to the lower projection
 __device__ __forceinline__ bool cand_better_proj(const Cand& a, const Cand& b) {
     if (a.D == 0) return false;
@@ -357,6 +306,8 @@ struct WaveScratch {
     float red[2];
     int32_t pad[2];
     Cand best;
+    uint32_t sk[kWave];   // sort path of small nodes: keys, then sorted keys
+    int32_t sl[kWave];    // sorted labels
 };
 
 struct BlockShared {
@@ -385,6 +336,66 @@ __device__ __forceinline__ void block_minmax(BlockShared& S, float& lo, float& h
     __syncthreads();
     lo = fminf(fminf(S.lo[0], S.lo[1]), fminf(S.lo[2], S.lo[3]));
     hi = fmaxf(fmaxf(S.hi[0], S.hi[1]), fmaxf(S.hi[2], S.hi[3]));
+}
+
+// Sort path for n <= 64 (one wave; lane i < n holds sample i's value and
+// label).  Each lane ranks its order-preserving key against all n keys in LDS
+// (ties by lane), scatters (key, label) to its rank, then per-class inclusive
+// scans over the sorted labels give the left counts at every sorted
+// position.  Boundaries only between distinct values.
+__device__ Cand scan_sort_small(WaveScratch& WS, float val, int lab, int64_t n, int C) {
+    const int lane = lane_id();
+    const bool real = lane < n;
+    const uint32_t key = fkey(val);
+    if (real) WS.sk[lane] = key;
+    wave_sync();
+    int rank = 0;
+    for (int j = 0; j < n; ++j) {
+        const uint32_t kj = WS.sk[j];
+        rank += (kj < key || (kj == key && j < lane)) ? 1 : 0;
+    }
+    wave_sync();
+    if (real) {
+        WS.sk[rank] = key;
+        WS.sl[rank] = lab;
+    }
+    wave_sync();
+    const uint32_t myk = real ? WS.sk[lane] : 0xffffffffu;
+    const int mylab = real ? WS.sl[lane] : -1;
+    const uint32_t nextk = lane + 1 < n ? WS.sk[lane + 1] : 0xffffffffu;
+    const uint32_t k0 = WS.sk[0];
+    wave_sync();
+    uint64_t SL = 0, SR = 0, SP = 0;
+    for (int c = 0; c < C; ++c) {
+        const uint32_t l = wave_incl_scan((real && mylab == c) ? 1u : 0u);
+        const uint32_t Pc = (uint32_t)WS.pc[c];
+        const uint32_t r = Pc - l;
+        SL += (uint64_t)l * l;
+        SR += (uint64_t)r * r;
+        SP += (uint64_t)Pc * Pc;
+    }
+    u128 N = 0;
+    uint64_t D = 0;
+    const bool ok = lane + 1 < n && myk < nextk &&
+                    make_q((int64_t)lane + 1, n - (int64_t)lane - 1, SL, SR, N, D);
+    const int win = wave_best_lane(ok, N, D, lane);
+    Cand c;
+    cand_invalid(c);
+    c.SP = SP;
+    c.lo = kfloat(k0);
+    if (win >= 0) {
+        const uint64_t nlo = __shfl((uint64_t)N, win), nhi = __shfl((uint64_t)(N >> 64), win);
+        c.N = ((u128)nhi << 64) | nlo;
+        c.D = __shfl(D, win);
+        c.SL = __shfl(SL, win);
+        c.SR = __shfl(SR, win);
+        c.pos = win;
+        c.nL = win + 1;
+        c.nR = (int32_t)(n - c.nL);
+        c.thr = kfloat(__shfl(myk, win));
+        c.scale = 0.f;
+    }
+    return c;
 }
 
 // ---------------------------------------------------------------------------
@@ -450,7 +461,7 @@ __device__ void do_small(const FindArgs& A, const PS& P, int v, char* smem) {
         hi = wave_max(hi);
         Cand c;
         if (sortp) {
-            c = scan_sort_wave(val[0], lab[0], n, C, WS.pc);
+            c = scan_sort_small(WS, val[0], lab[0], n, C);
             write_zero_row(A, proj_global(P, v, p));
         } else {
             const float scale = bin_scale(B, lo, hi);
@@ -555,142 +566,67 @@ __device__ void do_mid(const FindArgs& A, const PS& P, int4 D, int p, char* smem
 }
 
 // ---------------------------------------------------------------------------
-// big nodes: (node, projection group, chunk) items
+// big nodes (more than 8192 samples, histogram path): the node's samples are
+// cut into chunks of kChunk; a work item is one (projection, chunk) and is
+// taken by one wave.  Items of big descriptor d are numbered
+// item_a + p * nchunk + ch, and every per-item partial (range, histogram) is
+// stored at that number.
 
 struct BigDesc {
-    int node, slot, item_a, item_c, bigslot, k, nchunk, ngroup;
+    int node, slot, item_a, item_c, bigslot, k, nchunk, pad;
 };
 __device__ __forceinline__ BigDesc big_desc(const FindArgs& A, int d) {
     int4 a = A.ws.desc_big[2 * d], b = A.ws.desc_big[2 * d + 1];
     return BigDesc{a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
 }
 
-// Load the chunk's rows and labels; returns the chunk's sample count.
-__device__ __forceinline__ int64_t big_chunk_rows(const FindArgs& A, const BigDesc& bd, int ch,
-                                                  int (&idx)[kMidR], uint32_t (&labp)[kMidR / 8],
-                                                  bool want_labels) {
-    int64_t s0, n;
-    node_range(A, bd.node, s0, n);
-    int64_t c0 = (int64_t)ch * kChunk;
-    int64_t cn = n - c0;
-    cn = cn < 0 ? 0 : (cn > kChunk ? kChunk : cn);
-    const int tid = threadIdx.x;
-    const int first = cn > 0 ? row_of(A, s0 + c0) : 0;
-#pragma unroll
-    for (int q = 0; q < kMidR / 8; ++q) labp[q] = 0;
-#pragma unroll
-    for (int r = 0; r < kMidR; ++r) {
-        idx[r] = first;
-        int64_t i = tid + (int64_t)r * kBlock;
-        if (i < cn) {
-            idx[r] = row_of(A, s0 + c0 + i);
-            if (want_labels) labp[r >> 3] |= (uint32_t)label_of(A, idx[r]) << (4 * (r & 7));
-        }
-    }
-    return cn;
-}
+constexpr int kBR = 4;   // samples per lane per step of a chunk loop
 
-template <typename T, class PS>
-__device__ __forceinline__ void chunk_project(const FindArgs& A, const PS& P, int v, int p,
-                                              WaveScratch& WS, const int (&idx)[kMidR], int nr,
-                                              float (&val)[kMidR]) {
-    const int z = proj_stage(P, v, p, A.n_features, WS.lf, WS.ls);
-#pragma unroll
-    for (int r = 0; r < kMidR; ++r) val[r] = 0.f;
-    for (int j = 0; j < z; ++j) {
-        const int f = __builtin_amdgcn_readfirstlane(WS.lf[j]);
-        const uint32_t sg = __builtin_amdgcn_readfirstlane(WS.ls[j]);
-        const T* col = (const T*)A.x + (int64_t)f * A.ld;
-#pragma unroll
-        for (int r = 0; r < kMidR; ++r)
-            if (r < nr) val[r] = __fadd_rn(val[r], signed_term(ldx(col, idx[r]), sg));
-    }
-}
-
-template <typename T, class PS>
-__device__ void do_big_range(const FindArgs& A, const PS& P, int d, int t, char* smem) {
-    BlockShared& S = block_shared(smem);
-    const int tid = threadIdx.x, w = tid >> 6;
-    const BigDesc bd = big_desc(A, d);
-    if (bd.nchunk <= 0) return;
-    const int g = t / bd.nchunk, ch = t - g * bd.nchunk;
-    int idx[kMidR];
-    uint32_t labp[kMidR / 8];
-    const int64_t cn = big_chunk_rows(A, bd, ch, idx, labp, false);
-    const int nr = (int)((cn + kBlock - 1) / kBlock);
-    const int p1 = min(bd.k, (g + 1) * kGroup);
-    for (int p = g * kGroup; p < p1; ++p) {
-        float val[kMidR];
-        chunk_project<T>(A, P, bd.node, p, S.w[w], idx, nr, val);
-        float lo = INFINITY, hi = -INFINITY;
-#pragma unroll
-        for (int r = 0; r < kMidR; ++r)
-            if (tid + (int64_t)r * kBlock < cn) { lo = fminf(lo, val[r]); hi = fmaxf(hi, val[r]); }
-        block_minmax(S, lo, hi);
-        if (tid == 0 && cn > 0) {
-            atomicMin(&A.ws.lohi[bd.bigslot + p].x, fkey(lo));
-            atomicMax(&A.ws.lohi[bd.bigslot + p].y, fkey(hi));
-        }
-        __syncthreads();
-    }
-}
-
-template <typename T, class PS>
-__device__ void do_big_hist(const FindArgs& A, const PS& P, int d, int t, char* smem) {
-    BlockShared& S = block_shared(smem);
-    const int tid = threadIdx.x, w = tid >> 6, lane = lane_id();
-    const int C = A.n_classes, Bm = A.bins;
-    const BigDesc bd = big_desc(A, d);
-    if (bd.nchunk <= 0) return;
-    const int g = t / bd.nchunk, ch = t - g * bd.nchunk;
-    const int B = node_bins(A, bd.node);
-    int idx[kMidR];
-    uint32_t labp[kMidR / 8];
-    const int64_t cn = big_chunk_rows(A, bd, ch, idx, labp, true);
-    const int nr = (int)((cn + kBlock - 1) / kBlock);
-    const int p1 = min(bd.k, (g + 1) * kGroup);
-    int32_t* hist = wave_hist(smem, w, Bm, C);
-    for (int p = g * kGroup; p < p1; ++p) {
-        float val[kMidR];
-        chunk_project<T>(A, P, bd.node, p, S.w[w], idx, nr, val);
-        const uint2 lh = A.ws.lohi[bd.bigslot + p];
-        const float lo = kfloat(lh.x), hi = kfloat(lh.y);
-        const float scale = bin_scale(B, lo, hi);
-        for (int e = lane; e < B * C; e += kWave) hist[e] = 0;
-        wave_sync();
-#pragma unroll
-        for (int r = 0; r < kMidR; ++r)
-            if (tid + (int64_t)r * kBlock < cn) {
-                int y = (int)((labp[r >> 3] >> (4 * (r & 7))) & 15u);
-                atomicAdd(&hist[bin_index(val[r], lo, scale, B) * C + y], 1);
-            }
-        __syncthreads();
-        int32_t* gh = A.ws.big_hist + (int64_t)(bd.bigslot + p) * Bm * C;
-        const int32_t* h0 = wave_hist(smem, 0, Bm, C);
-        const int stride = Bm * C;
-        for (int e = tid; e < B * C; e += kBlock) {
-            int s = h0[e] + h0[e + stride] + h0[e + 2 * stride] + h0[e + 3 * stride];
-            if (s) atomicAdd(&gh[e], s);
-        }
-        __syncthreads();
-    }
-}
-
-template <class PS>
-__device__ void do_big_scan(const FindArgs& A, const PS& P, int d, int p) {
+// Range (pass 1) or class histogram (pass 2) of projection p over chunk ch
+// of a big node, by one wave.  Pass 2 counts into the wave's LDS histogram.
+template <typename T, class PS, bool kHist>
+__device__ __forceinline__ void big_chunk(const FindArgs& A, const PS& P, const BigDesc& bd, int p,
+                                          int ch, WaveScratch& WS, float& lo, float& hi,
+                                          int32_t* hist, float hlo, float hscale, int B) {
     const int lane = lane_id();
-    const BigDesc bd = big_desc(A, d);
-    const int B = node_bins(A, bd.node);
+    const int C = A.n_classes;
     int64_t s0, n;
     node_range(A, bd.node, s0, n);
-    const uint2 lh = A.ws.lohi[bd.bigslot + p];
-    const float lo = kfloat(lh.x), hi = kfloat(lh.y);
-    const float scale = bin_scale(B, lo, hi);
-    GlobalHist h{A.ws.big_hist + (int64_t)(bd.bigslot + p) * A.bins * A.n_classes, A.n_classes};
-    write_hist_row(A, proj_global(P, bd.node, p), h, B);
-    Cand c = scan_hist(h, B, A.n_classes, n, lo, scale);
-    c.proj = p;
-    if (lane == 0) ((Cand*)A.ws.slots)[bd.slot + p] = c;
+    const int64_t c0 = (int64_t)ch * kChunk;
+    const int64_t cn = clamp64(n - c0, 0, kChunk);
+    const int z = proj_stage(P, bd.node, p, A.n_features, WS.lf, WS.ls);
+    lo = INFINITY;
+    hi = -INFINITY;
+    for (int64_t i0 = 0; i0 < cn; i0 += kWave * kBR) {
+        int row[kBR];
+        bool ok[kBR];
+        float v[kBR];
+#pragma unroll
+        for (int r = 0; r < kBR; ++r) {
+            const int64_t i = i0 + r * kWave + lane;
+            ok[r] = i < cn;
+            row[r] = ok[r] ? row_of(A, s0 + c0 + i) : 0;
+            v[r] = 0.f;
+        }
+        for (int j = 0; j < z; ++j) {
+            const int f = __builtin_amdgcn_readfirstlane(WS.lf[j]);
+            const uint32_t sg = __builtin_amdgcn_readfirstlane(WS.ls[j]);
+            const T* col = (const T*)A.x + (int64_t)f * A.ld;
+#pragma unroll
+            for (int r = 0; r < kBR; ++r)
+                if (ok[r]) v[r] = __fadd_rn(v[r], signed_term(ldx(col, row[r]), sg));
+        }
+#pragma unroll
+        for (int r = 0; r < kBR; ++r) {
+            if (!ok[r]) continue;
+            if (kHist) {
+                atomicAdd(&hist[bin_index(v[r], hlo, hscale, B) * C + label_of(A, row[r])], 1);
+            } else {
+                lo = fminf(lo, v[r]);
+                hi = fmaxf(hi, v[r]);
+            }
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -722,7 +658,7 @@ __global__ __launch_bounds__(kBlock) void k_plan(FindArgs A, PS P) {
             else if (n <= kMidMax) cat = CAT_MID;
             else cat = CAT_BIG;
         }
-        const int nch = (int)((n + kChunk - 1) / kChunk), ngr = (k + kGroup - 1) / kGroup;
+        const int nch = (int)((n + kChunk - 1) / kChunk);
         const bool slot_node = cat == CAT_MID || cat == CAT_SB || cat == CAT_BIG;
         const int o_small = wave_alloc(&W.hdr[H_SMALL], cat == CAT_SMALL);
         const int o_dmid = wave_alloc(&W.hdr[H_DMID], cat == CAT_MID);
@@ -730,7 +666,7 @@ __global__ __launch_bounds__(kBlock) void k_plan(FindArgs A, PS P) {
         const int o_dsb = wave_alloc(&W.hdr[H_DSB], cat == CAT_SB);
         const int o_isb = wave_alloc(&W.hdr[H_ISB], cat == CAT_SB ? k : 0);
         const int o_dbig = wave_alloc(&W.hdr[H_DBIG], cat == CAT_BIG);
-        const int o_ia = wave_alloc(&W.hdr[H_IBIGA], cat == CAT_BIG ? ngr * nch : 0);
+        const int o_ia = wave_alloc(&W.hdr[H_IBIGA], cat == CAT_BIG ? k * nch : 0);
         const int o_ic = wave_alloc(&W.hdr[H_IBIGC], cat == CAT_BIG ? k : 0);
         const int o_slot = wave_alloc(&W.hdr[H_SLOTS], slot_node ? k : 0);
         const int o_bslot = wave_alloc(&W.hdr[H_BIGSLOTS], cat == CAT_BIG ? k : 0);
@@ -739,7 +675,7 @@ __global__ __launch_bounds__(kBlock) void k_plan(FindArgs A, PS P) {
         if (cat == CAT_SMALL && o_small >= W.cap_small) over = true;
         if (cat == CAT_MID && (o_dmid >= W.cap_dmid || o_imid + (int64_t)k > W.cap_imid)) over = true;
         if (cat == CAT_SB && (o_dsb >= W.cap_dsb || o_isb + (int64_t)k > W.cap_isb)) over = true;
-        if (cat == CAT_BIG && (o_dbig >= W.cap_dbig || o_ia + (int64_t)ngr * nch > W.cap_ibiga ||
+        if (cat == CAT_BIG && (o_dbig >= W.cap_dbig || o_ia + (int64_t)k * nch > W.cap_ibiga ||
                                o_ic + (int64_t)k > W.cap_ibigc || o_bslot + (int64_t)k > W.cap_bigslots))
             over = true;
         if (over) {
@@ -763,7 +699,7 @@ __global__ __launch_bounds__(kBlock) void k_plan(FindArgs A, PS P) {
         case CAT_SB: W.desc_sb[o_dsb] = make_int4(v, o_slot, o_isb, k); break;
         case CAT_BIG:
             W.desc_big[2 * o_dbig] = make_int4(v, o_slot, o_ia, o_ic);
-            W.desc_big[2 * o_dbig + 1] = make_int4(o_bslot, k, nch, ngr);
+            W.desc_big[2 * o_dbig + 1] = make_int4(o_bslot, k, nch, 0);
             break;
         default: break;
         }
@@ -790,44 +726,171 @@ __global__ __launch_bounds__(kBlock) void k_expand(FindArgs A) {
         } else {
             int e = d - nmid - nsb;
             BigDesc bd = big_desc(A, e);
-            int na = bd.ngroup * bd.nchunk;
+            const int na = bd.k * bd.nchunk;
             for (int t = tid; t < na; t += kBlock)
                 if (bd.item_a + (int64_t)t < W.cap_ibiga) W.items_biga[bd.item_a + t] = make_int2(e, t);
-            for (int p = tid; p < bd.k; p += kBlock) {
+            for (int p = tid; p < bd.k; p += kBlock)
                 if (bd.item_c + (int64_t)p < W.cap_ibigc) W.items_bigc[bd.item_c + p] = make_int2(e, p);
-                if (bd.bigslot + (int64_t)p < W.cap_bigslots) W.lohi[bd.bigslot + p] = make_uint2(0xffffffffu, 0u);
-            }
-            int64_t nh = (int64_t)bd.k * Bm * C;
-            int32_t* gh = W.big_hist + (int64_t)bd.bigslot * Bm * C;
-            if (bd.bigslot + (int64_t)bd.k <= W.cap_bigslots)
-                for (int64_t i = tid; i < nh; i += kBlock) gh[i] = 0;
         }
     }
 }
 
+// wave index over the grid and wave count, for kernels that hand one item to
+// each wave
+__device__ __forceinline__ int grid_wave() { return (int)((blockIdx.x * kBlock + threadIdx.x) >> 6); }
+__device__ __forceinline__ int grid_waves() { return (int)(gridDim.x * kWavesPerBlock); }
+
+// big item it -> (descriptor, projection, chunk); false if out of range
+__device__ __forceinline__ bool big_item(const FindArgs& A, int it, int nbig, BigDesc& bd, int& p,
+                                         int& ch) {
+    const int2 e = A.ws.items_biga[it];
+    if (e.x < 0 || e.x >= nbig) return false;
+    bd = big_desc(A, e.x);
+    if (bd.nchunk <= 0 || e.y < 0 || e.y >= bd.k * bd.nchunk) return false;
+    p = e.y / bd.nchunk;
+    ch = e.y - p * bd.nchunk;
+    return true;
+}
+
 template <typename T, class PS>
-__global__ __launch_bounds__(kBlock) void k_main(FindArgs A, PS P) {
+__global__ __launch_bounds__(kBlock) void k_brange(FindArgs A, PS P) {
     extern __shared__ __align__(16) char smem[];
     BlockShared& S = block_shared(smem);
     const FindWs& W = A.ws;
     const int na = count_of(A, H_IBIGA, W.cap_ibiga);
     const int nbig = count_of(A, H_DBIG, W.cap_dbig);
-    for (;;) {
-        int it = block_dequeue(&W.hdr[H_Q_BIGA], &S.item);
-        if (it >= na) break;
-        int2 e = W.items_biga[it];
-        if (e.x < nbig) do_big_range<T>(A, P, e.x, e.y, smem);
+    WaveScratch& WS = S.w[threadIdx.x >> 6];
+    for (int it = grid_wave(); it < na; it += grid_waves()) {
+        BigDesc bd;
+        int p, ch;
+        if (!big_item(A, it, nbig, bd, p, ch)) continue;
+        float lo, hi;
+        big_chunk<T, PS, false>(A, P, bd, p, ch, WS, lo, hi, nullptr, 0.f, 0.f, 0);
+        lo = wave_min(lo);
+        hi = wave_max(hi);
+        if (lane_id() == 0) W.crange[it] = make_float2(lo, hi);
     }
+}
+
+// range of every (big node, projection): min and max over its chunks
+__global__ __launch_bounds__(kBlock) void k_bmerge(FindArgs A) {
+    const FindWs& W = A.ws;
+    const int nc = count_of(A, H_IBIGC, W.cap_ibigc);
+    const int nbig = count_of(A, H_DBIG, W.cap_dbig);
+    for (int it = grid_wave(); it < nc; it += grid_waves()) {
+        const int2 e = W.items_bigc[it];
+        if (e.x < 0 || e.x >= nbig) continue;
+        const BigDesc bd = big_desc(A, e.x);
+        const int p = e.y;
+        if (p < 0 || p >= bd.k) continue;
+        float lo = INFINITY, hi = -INFINITY;
+        const int64_t base = (int64_t)bd.item_a + (int64_t)p * bd.nchunk;
+        for (int ch = lane_id(); ch < bd.nchunk; ch += kWave) {
+            if (base + ch >= W.cap_ibiga) break;
+            const float2 r = W.crange[base + ch];
+            lo = fminf(lo, r.x);
+            hi = fmaxf(hi, r.y);
+        }
+        lo = wave_min(lo);
+        hi = wave_max(hi);
+        if (lane_id() == 0 && bd.bigslot + (int64_t)p < W.cap_bigslots)
+            W.brange[bd.bigslot + p] = make_float2(lo, hi);
+    }
+}
+
+template <typename T, class PS>
+__global__ __launch_bounds__(kBlock) void k_bhist(FindArgs A, PS P) {
+    extern __shared__ __align__(16) char smem[];
+    BlockShared& S = block_shared(smem);
+    const FindWs& W = A.ws;
+    const int na = count_of(A, H_IBIGA, W.cap_ibiga);
+    const int nbig = count_of(A, H_DBIG, W.cap_dbig);
+    const int w = threadIdx.x >> 6, lane = lane_id();
+    const int C = A.n_classes, Bm = A.bins;
+    WaveScratch& WS = S.w[w];
+    int32_t* hist = wave_hist(smem, w, Bm, C);
+    for (int it = grid_wave(); it < na; it += grid_waves()) {
+        BigDesc bd;
+        int p, ch;
+        if (!big_item(A, it, nbig, bd, p, ch)) continue;
+        if (bd.bigslot + (int64_t)p >= W.cap_bigslots) continue;
+        const int B = node_bins(A, bd.node);
+        const float2 r = W.brange[bd.bigslot + p];
+        const float scale = bin_scale(B, r.x, r.y);
+        for (int e = lane; e < B * C; e += kWave) hist[e] = 0;
+        wave_sync();
+        float lo, hi;
+        big_chunk<T, PS, true>(A, P, bd, p, ch, WS, lo, hi, hist, r.x, scale, B);
+        wave_sync();
+        int32_t* out = W.chist + (int64_t)it * Bm * C;
+        for (int e = lane; e < B * C; e += kWave) out[e] = hist[e];
+        wave_sync();
+    }
+}
+
+// Per (big node, projection): sum the chunk histograms into the wave's LDS
+// histogram, then the boundary scan.
+template <class PS>
+__global__ __launch_bounds__(kBlock) void k_bscan(FindArgs A, PS P) {
+    extern __shared__ __align__(16) char smem[];
+    const FindWs& W = A.ws;
+    const int nc = count_of(A, H_IBIGC, W.cap_ibigc);
+    const int nbig = count_of(A, H_DBIG, W.cap_dbig);
+    const int w = threadIdx.x >> 6, lane = lane_id();
+    const int C = A.n_classes, Bm = A.bins;
+    int32_t* hist = wave_hist(smem, w, Bm, C);
+    for (int it = grid_wave(); it < nc; it += grid_waves()) {
+        const int2 e = W.items_bigc[it];
+        if (e.x < 0 || e.x >= nbig) continue;
+        const BigDesc bd = big_desc(A, e.x);
+        const int p = e.y;
+        if (p < 0 || p >= bd.k || bd.bigslot + (int64_t)p >= W.cap_bigslots ||
+            bd.slot + (int64_t)p >= W.cap_slots)
+            continue;
+        const int64_t base = (int64_t)bd.item_a + (int64_t)p * bd.nchunk;
+        if (base + bd.nchunk > W.cap_ibiga) continue;
+        const int B = node_bins(A, bd.node);
+        int64_t s0, n;
+        node_range(A, bd.node, s0, n);
+        for (int q = lane; q < B * C; q += kWave) {
+            int32_t acc = 0;
+            for (int ch = 0; ch < bd.nchunk; ++ch) acc += W.chist[(base + ch) * Bm * C + q];
+            hist[q] = acc;
+        }
+        wave_sync();
+        const float2 r = W.brange[bd.bigslot + p];
+        const float scale = bin_scale(B, r.x, r.y);
+        LdsHist h{hist, C};
+        write_hist_row(A, proj_global(P, bd.node, p), h, B);
+        Cand c = scan_hist(h, B, C, n, r.x, scale);
+        c.proj = p;
+        if (lane == 0) ((Cand*)W.slots)[bd.slot + p] = c;
+        wave_sync();
+    }
+}
+
+template <typename T, class PS>
+__global__ __launch_bounds__(kBlock) void k_mid(FindArgs A, PS P) {
+    extern __shared__ __align__(16) char smem[];
+    BlockShared& S = block_shared(smem);
+    const FindWs& W = A.ws;
     const int nm = count_of(A, H_IMID, W.cap_imid);
     const int nmd = count_of(A, H_DMID, W.cap_dmid);
     for (;;) {
         int it = block_dequeue(&W.hdr[H_Q_MID], &S.item);
         if (it >= nm) break;
         int2 e = W.items_mid[it];
-        if (e.x >= nmd) continue;
+        if (e.x < 0 || e.x >= nmd) continue;
         int4 D = W.desc_mid[e.x];
         if (e.y < D.w) do_mid<T>(A, P, D, e.y, smem);
     }
+}
+
+template <typename T, class PS>
+__global__ __launch_bounds__(kBlock) void k_small(FindArgs A, PS P) {
+    extern __shared__ __align__(16) char smem[];
+    BlockShared& S = block_shared(smem);
+    const FindWs& W = A.ws;
     const int ns = count_of(A, H_SMALL, W.cap_small);
     const int N = n_nodes_of(A);
     for (;;) {
@@ -835,38 +898,6 @@ __global__ __launch_bounds__(kBlock) void k_main(FindArgs A, PS P) {
         if (it >= ns) break;
         int v = W.small_items[it];
         if (v >= 0 && v < N) do_small<T>(A, P, v, smem);
-    }
-}
-
-template <typename T, class PS>
-__global__ __launch_bounds__(kBlock) void k_bighist(FindArgs A, PS P) {
-    extern __shared__ __align__(16) char smem[];
-    BlockShared& S = block_shared(smem);
-    const FindWs& W = A.ws;
-    const int na = count_of(A, H_IBIGA, W.cap_ibiga);
-    const int nbig = count_of(A, H_DBIG, W.cap_dbig);
-    for (;;) {
-        int it = block_dequeue(&W.hdr[H_Q_BIGB], &S.item);
-        if (it >= na) break;
-        int2 e = W.items_biga[it];
-        if (e.x < nbig) do_big_hist<T>(A, P, e.x, e.y, smem);
-    }
-}
-
-template <class PS>
-__global__ __launch_bounds__(kBlock) void k_bigscan(FindArgs A, PS P) {
-    // one wave per item
-    const FindWs& W = A.ws;
-    const int nc = count_of(A, H_IBIGC, W.cap_ibigc);
-    const int nbig = count_of(A, H_DBIG, W.cap_dbig);
-    const int lane = lane_id();
-    for (;;) {
-        int it = 0;
-        if (lane == 0) it = atomicAdd(&W.hdr[H_Q_BIGC], 1);
-        it = __shfl(it, 0);
-        if (it >= nc) break;
-        int2 e = W.items_bigc[it];
-        if (e.x < nbig) do_big_scan(A, P, e.x, e.y);
     }
 }
 
@@ -1109,36 +1140,80 @@ __global__ __launch_bounds__(kBlock) void k_sortblk(FindArgs A, PS P) {
 // host side
 
 template <typename T, class PS>
-static hipError_t launch_find_t(const FindArgs& a, const PS& p, const LaunchCfg& cfg, hipStream_t s) {
+static hipError_t launch_find_t(const FindArgs& a, const PS& p, const LaunchCfg& cfg, hipStream_t s,
+                                const hipEvent_t* ev) {
     const int Nc = a.n_nodes > 0 ? a.n_nodes : 1;
     int grid_plan = (Nc + kBlock - 1) / kBlock;
     if (grid_plan > 4 * cfg.n_cu) grid_plan = 4 * cfg.n_cu;
+    const size_t sm = cfg.smem_main;
+    int st = 0;
+    auto mark = [&]() {
+        if (ev) (void)hipEventRecord(ev[st++], s);
+    };
+    mark();
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, a.ws.hdr);
     hipLaunchKernelGGL((k_plan<PS>), dim3(grid_plan), dim3(kBlock), 0, s, a, p);
-    hipLaunchKernelGGL(k_expand, dim3(cfg.grid_small), dim3(kBlock), 0, s, a);
-    hipLaunchKernelGGL((k_main<T, PS>), dim3(cfg.grid_main), dim3(kBlock), cfg.smem_main, s, a, p);
+    hipLaunchKernelGGL(k_expand, dim3(cfg.grid_light), dim3(kBlock), 0, s, a);
+    mark();
+    hipLaunchKernelGGL((k_brange<T, PS>), dim3(cfg.grid_brange), dim3(kBlock), sm, s, a, p);
+    mark();
+    hipLaunchKernelGGL(k_bmerge, dim3(cfg.grid_light), dim3(kBlock), 0, s, a);
+    mark();
+    hipLaunchKernelGGL((k_bhist<T, PS>), dim3(cfg.grid_bhist), dim3(kBlock), sm, s, a, p);
+    mark();
+    hipLaunchKernelGGL((k_bscan<PS>), dim3(cfg.grid_bscan), dim3(kBlock), sm, s, a, p);
+    mark();
+    hipLaunchKernelGGL((k_mid<T, PS>), dim3(cfg.grid_mid), dim3(kBlock), sm, s, a, p);
+    mark();
+    hipLaunchKernelGGL((k_small<T, PS>), dim3(cfg.grid_small), dim3(kBlock), sm, s, a, p);
+    mark();
     hipLaunchKernelGGL((k_sortblk<T, PS>), dim3(cfg.grid_sort), dim3(kBlock), cfg.smem_sort, s, a, p);
-    hipLaunchKernelGGL((k_bighist<T, PS>), dim3(cfg.grid_main), dim3(kBlock), cfg.smem_main, s, a, p);
-    hipLaunchKernelGGL((k_bigscan<PS>), dim3(cfg.grid_small), dim3(kBlock), 0, s, a, p);
-    hipLaunchKernelGGL(k_reduce, dim3(cfg.grid_small), dim3(kBlock), 0, s, a);
+    mark();
+    hipLaunchKernelGGL(k_reduce, dim3(cfg.grid_light), dim3(kBlock), 0, s, a);
+    mark();
     return hipGetLastError();
 }
 
-hipError_t launch_find_csr(const FindArgs& a, const ProjCSR& p, const LaunchCfg& cfg, hipStream_t s) {
-    if (a.dtype == SOF_F16) return launch_find_t<_Float16>(a, p, cfg, s);
-    return launch_find_t<float>(a, p, cfg, s);
+hipError_t launch_find_csr(const FindArgs& a, const ProjCSR& p, const LaunchCfg& cfg, hipStream_t s,
+                           const hipEvent_t* ev) {
+    if (a.dtype == SOF_F16) return launch_find_t<_Float16>(a, p, cfg, s, ev);
+    return launch_find_t<float>(a, p, cfg, s, ev);
 }
-hipError_t launch_find_hash(const FindArgs& a, const ProjHash& p, const LaunchCfg& cfg, hipStream_t s) {
-    if (a.dtype == SOF_F16) return launch_find_t<_Float16>(a, p, cfg, s);
-    return launch_find_t<float>(a, p, cfg, s);
+hipError_t launch_find_hash(const FindArgs& a, const ProjHash& p, const LaunchCfg& cfg, hipStream_t s,
+                            const hipEvent_t* ev) {
+    if (a.dtype == SOF_F16) return launch_find_t<_Float16>(a, p, cfg, s, ev);
+    return launch_find_t<float>(a, p, cfg, s, ev);
 }
 
-hipError_t find_occupancy(int bins, int classes, int* blocks_main, int* blocks_sort) {
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        blocks_main, (const void*)k_main<float, ProjCSR>, kBlock, find_smem_main(bins, classes));
-    if (e != hipSuccess) return e;
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_sort, (const void*)k_sortblk<float, ProjCSR>,
-                                                        kBlock, find_smem_sort());
+// resident blocks per CU of a kernel (at least 1)
+static hipError_t occ(const void* f, size_t smem, int* out) {
+    int b = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, f, kBlock, smem);
+    *out = b > 0 ? b : 1;
+    return e;
+}
+
+hipError_t find_occupancy(int bins, int classes, int n_cu, LaunchCfg* cfg) {
+    const size_t sm = find_smem_main(bins, classes), ss = find_smem_sort();
+    int b = 0;
+    hipError_t e;
+    cfg->n_cu = n_cu;
+    cfg->smem_main = sm;
+    cfg->smem_sort = ss;
+    if ((e = occ((const void*)k_mid<float, ProjCSR>, sm, &b)) != hipSuccess) return e;
+    cfg->grid_mid = n_cu * b;
+    if ((e = occ((const void*)k_small<float, ProjCSR>, sm, &b)) != hipSuccess) return e;
+    cfg->grid_small = n_cu * b;
+    if ((e = occ((const void*)k_sortblk<float, ProjCSR>, ss, &b)) != hipSuccess) return e;
+    cfg->grid_sort = n_cu * b;
+    if ((e = occ((const void*)k_brange<float, ProjCSR>, sm, &b)) != hipSuccess) return e;
+    cfg->grid_brange = n_cu * b;
+    if ((e = occ((const void*)k_bhist<float, ProjCSR>, sm, &b)) != hipSuccess) return e;
+    cfg->grid_bhist = n_cu * b;
+    if ((e = occ((const void*)k_bscan<ProjCSR>, sm, &b)) != hipSuccess) return e;
+    cfg->grid_bscan = n_cu * b;
+    cfg->grid_light = n_cu * 4;
+    return hipSuccess;
 }
 
 }  // namespace sof

@@ -67,8 +67,50 @@ extern "C" int sof_create(int device, sof_ctx** out) {
 }
 
 extern "C" int sof_destroy(sof_ctx* ctx) {
+    if (ctx)
+        for (auto& a : ctx->tev)
+            for (hipEvent_t e : a) (void)hipEventDestroy(e);
     delete ctx;
     return SOF_OK;
+}
+
+extern "C" int sof_timing_enable(sof_ctx* ctx, int enable) {
+    if (!ctx) return fail(SOF_ERR_INVALID_ARG, "ctx is NULL");
+    ctx->timing = enable != 0;
+    ctx->tev_used = 0;
+    return SOF_OK;
+}
+
+extern "C" int sof_timing_read(sof_ctx* ctx, float* ms, int32_t* calls) {
+    if (!ctx || !ms || !calls) return fail(SOF_ERR_INVALID_ARG, "NULL argument");
+    for (int i = 0; i <= SOF_STAGE_COUNT; ++i) ms[i] = 0.f;
+    for (size_t c = 0; c < ctx->tev_used; ++c) {
+        auto& e = ctx->tev[c];
+        hipError_t r = hipEventSynchronize(e[SOF_STAGE_COUNT]);
+        if (r != hipSuccess) return hip_fail(r, "hipEventSynchronize");
+        for (int i = 0; i <= SOF_STAGE_COUNT; ++i) {
+            float t = 0.f;
+            r = i < SOF_STAGE_COUNT ? hipEventElapsedTime(&t, e[i], e[i + 1])
+                                    : hipEventElapsedTime(&t, e[0], e[SOF_STAGE_COUNT]);
+            if (r != hipSuccess) return hip_fail(r, "hipEventElapsedTime");
+            ms[i] += t;
+        }
+    }
+    *calls = (int32_t)ctx->tev_used;
+    ctx->tev_used = 0;
+    return SOF_OK;
+}
+
+// next event set for an instrumented call (allocates events on first use)
+static const hipEvent_t* timing_events(sof_ctx* ctx) {
+    if (!ctx->timing) return nullptr;
+    if (ctx->tev_used == ctx->tev.size()) {
+        std::array<hipEvent_t, SOF_STAGE_COUNT + 1> a;
+        for (auto& e : a)
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        ctx->tev.push_back(a);
+    }
+    return ctx->tev[ctx->tev_used++].data();
 }
 
 int sof::launch_cfg(sof_ctx* ctx, int bins, int classes, LaunchCfg* cfg) {
@@ -79,19 +121,12 @@ int sof::launch_cfg(sof_ctx* ctx, int bins, int classes, LaunchCfg* cfg) {
         *cfg = it->second;
         return SOF_OK;
     }
-    int bm = 0, bs = 0;
-    hipError_t e = find_occupancy(bins, classes, &bm, &bs);
-    if (e != hipSuccess) return hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
     LaunchCfg c;
-    c.n_cu = ctx->n_cu;
-    c.smem_main = find_smem_main(bins, classes);
-    c.smem_sort = find_smem_sort();
+    hipError_t e = find_occupancy(bins, classes, ctx->n_cu, &c);
+    if (e != hipSuccess) return hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
     if (c.smem_main > ctx->lds_per_block || c.smem_sort > ctx->lds_per_block)
         return fail(SOF_ERR_UNSUPPORTED, "LDS need %zu/%zu bytes exceeds %zu per block", c.smem_main,
                     c.smem_sort, ctx->lds_per_block);
-    c.grid_main = ctx->n_cu * (bm > 0 ? bm : 1);
-    c.grid_sort = ctx->n_cu * (bs > 0 ? bs : 1);
-    c.grid_small = ctx->n_cu * 4;
     ctx->cfg[key] = c;
     *cfg = c;
     return SOF_OK;
@@ -178,7 +213,7 @@ FindLayout sof::find_layout(int64_t N, int64_t S, int64_t P, int64_t K, int bins
     c.cap_dsb = nsb + 1;
     c.cap_isb = mn(P, K * nsb) + 1;
     c.cap_dbig = nbig + 1;
-    c.cap_ibiga = ((K + kGroup - 1) / kGroup) * (S / kChunk + nbig) + 1;
+    c.cap_ibiga = K * (S / kChunk + nbig) + 1;
     c.cap_ibigc = mn(P, K * nbig) + 1;
     c.cap_slots = mn(P, K * nsb) + 1;
     c.cap_bigslots = mn(P, K * nbig) + 1;
@@ -193,8 +228,9 @@ FindLayout sof::find_layout(int64_t N, int64_t S, int64_t P, int64_t K, int bins
     L.items_biga = o; o = align_up(o + c.cap_ibiga * sizeof(int2));
     L.items_bigc = o; o = align_up(o + c.cap_ibigc * sizeof(int2));
     L.slots = o; o = align_up(o + c.cap_slots * 80);
-    L.lohi = o; o = align_up(o + c.cap_bigslots * sizeof(uint2));
-    L.big_hist = o; o = align_up(o + (size_t)c.cap_bigslots * bins * classes * sizeof(int32_t));
+    L.crange = o; o = align_up(o + c.cap_ibiga * sizeof(float2));
+    L.brange = o; o = align_up(o + c.cap_bigslots * sizeof(float2));
+    L.chist = o; o = align_up(o + (size_t)c.cap_ibiga * bins * classes * sizeof(int32_t));
     L.total = o;
     return L;
 }
@@ -212,8 +248,9 @@ void sof::find_bind(const FindLayout& L, void* ws, FindWs* w) {
     w->items_biga = (int2*)(b + L.items_biga);
     w->items_bigc = (int2*)(b + L.items_bigc);
     w->slots = (void*)(b + L.slots);
-    w->lohi = (uint2*)(b + L.lohi);
-    w->big_hist = (int32_t*)(b + L.big_hist);
+    w->crange = (float2*)(b + L.crange);
+    w->brange = (float2*)(b + L.brange);
+    w->chist = (int32_t*)(b + L.chist);
 }
 
 extern "C" int sof_workspace_size(const sof_ctx* ctx, const sof_data* data, const sof_frontier* fr,
@@ -296,7 +333,7 @@ extern "C" int sof_find_splits(sof_ctx* ctx, const sof_data* data, const sof_fro
     find_bind(L, ws, &a.ws);
     ProjCSR p{proj->proj_offsets, proj->nz_offsets, proj->nz_feature, proj->nz_weight, proj->n_proj,
               proj->n_nz};
-    e = launch_find_csr(a, p, cfg, (hipStream_t)stream);
+    e = launch_find_csr(a, p, cfg, (hipStream_t)stream, timing_events(ctx));
     if (e != hipSuccess) return hip_fail(e, "find_splits launch");
     return SOF_OK;
 }

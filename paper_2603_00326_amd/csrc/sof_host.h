@@ -3,9 +3,11 @@
 
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <map>
 #include <mutex>
 #include <utility>
+#include <vector>
 
 #include "sof.h"
 #include "sof_internal.h"
@@ -17,6 +19,9 @@ struct sof_ctx {
     bool check = false;
     std::mutex mu;
     std::map<std::pair<int, int>, sof::LaunchCfg> cfg;
+    bool timing = false;                             // benchmark instrumentation
+    std::vector<std::array<hipEvent_t, SOF_STAGE_COUNT + 1>> tev;  // one event set per recorded call
+    size_t tev_used = 0;
 };
 
 namespace sof {

@@ -15,8 +15,7 @@ namespace sof {
 constexpr int kSortWaveMax = 64;     // sort nodes up to here: sorted in registers by one wave
 constexpr int kSmallMax = 1024;      // histogram nodes up to here: one block per node
 constexpr int kMidMax = 8192;        // histogram nodes up to here: one block per (node, projection)
-constexpr int kChunk = 8192;         // larger nodes: (node, projection group, sample chunk) items
-constexpr int kGroup = 8;            // projections per big-node item
+constexpr int kChunk = 8192;         // larger nodes: (node, projection, sample chunk) items
 constexpr int kSortMax = SOF_SORT_LIMIT;
 
 // header counters of the find-splits workspace
@@ -27,17 +26,13 @@ enum {
     H_DSB,         // sort-block descriptors
     H_ISB,         // sort-block items
     H_DBIG,        // big descriptors
-    H_IBIGA,       // big chunk items (min/max and histogram passes)
-    H_IBIGC,       // big scan items
+    H_IBIGA,       // big (projection, chunk) items
+    H_IBIGC,       // big (node, projection) items
     H_SLOTS,       // candidate slots
-    H_BIGSLOTS,    // big projection slots (range, global histogram)
-    H_Q_BIGA = 16, // dequeue counters
-    H_Q_MID,
+    H_BIGSLOTS,    // big projection slots (merged range)
+    H_Q_MID = 16,  // dequeue counters
     H_Q_SMALL,
     H_Q_SB,
-    H_Q_BIGB,
-    H_Q_BIGC,
-    H_Q_RED,
     H_ERR = 32,
     H_COUNT = 64
 };
@@ -73,8 +68,9 @@ struct FindWs {
     int2* items_biga;
     int2* items_bigc;
     void* slots;          // Cand[]
-    uint2* lohi;          // per big slot: ordered keys of min and max
-    int32_t* big_hist;    // per big slot: [bins][classes]
+    float2* crange;       // per big item: (min, max) of the chunk
+    float2* brange;       // per big slot: (min, max) over the node
+    int32_t* chist;       // per big item: [bins][classes] of the chunk
     int64_t cap_small, cap_dmid, cap_imid, cap_dsb, cap_isb, cap_dbig, cap_ibiga, cap_ibigc;
     int64_t cap_slots, cap_bigslots;
 };
@@ -99,7 +95,7 @@ struct FindArgs {
 // Byte layout of the find-splits workspace for the given sizes.
 struct FindLayout {
     size_t hdr, small_items, desc_mid, desc_sb, desc_big, items_mid, items_sb, items_biga, items_bigc;
-    size_t slots, lohi, big_hist, total;
+    size_t slots, crange, brange, chist, total;
     FindWs caps;
 };
 FindLayout find_layout(int64_t n_nodes, int64_t n_samples, int64_t n_proj, int64_t max_k, int bins,
@@ -107,16 +103,20 @@ FindLayout find_layout(int64_t n_nodes, int64_t n_samples, int64_t n_proj, int64
 void find_bind(const FindLayout& L, void* ws, FindWs* out);
 
 struct LaunchCfg {
-    int grid_main, grid_sort, grid_small;
     int n_cu;
+    int grid_mid, grid_small, grid_sort, grid_brange, grid_bhist, grid_bscan, grid_light;
     size_t smem_main, smem_sort;
 };
 
 // launchers (return hipError_t)
-hipError_t launch_find_csr(const FindArgs& a, const ProjCSR& p, const LaunchCfg& cfg, hipStream_t s);
-hipError_t launch_find_hash(const FindArgs& a, const ProjHash& p, const LaunchCfg& cfg, hipStream_t s);
+// ev (optional, SOF_STAGE_COUNT + 1 events): recorded before the first stage
+// and after every stage of the sequence
+hipError_t launch_find_csr(const FindArgs& a, const ProjCSR& p, const LaunchCfg& cfg, hipStream_t s,
+                           const hipEvent_t* ev = nullptr);
+hipError_t launch_find_hash(const FindArgs& a, const ProjHash& p, const LaunchCfg& cfg, hipStream_t s,
+                            const hipEvent_t* ev = nullptr);
 size_t find_smem_main(int bins, int classes);
 size_t find_smem_sort();
-hipError_t find_occupancy(int bins, int classes, int* blocks_main, int* blocks_sort);
+hipError_t find_occupancy(int bins, int classes, int n_cu, LaunchCfg* cfg);
 
 }  // namespace sof

@@ -30,6 +30,7 @@ EXPORTED = [
     "sof_version", "sof_last_error", "sof_create", "sof_destroy", "sof_workspace_size",
     "sof_project", "sof_find_splits", "sof_partition", "sof_forest_create", "sof_forest_destroy",
     "sof_grow_level", "sof_forest_frontier_size", "sof_forest_export", "sof_autotune",
+    "sof_timing_enable", "sof_timing_read",
 ]
 
 
@@ -120,6 +121,8 @@ def lib():
             L.sof_grow_level.argtypes = [P, ctypes.c_int, P]
             L.sof_forest_frontier_size.argtypes = [P, ctypes.POINTER(i64), P]
             L.sof_forest_export.argtypes = [P, P, i64, ctypes.POINTER(i64), P]
+        L.sof_timing_enable.argtypes = [P, ctypes.c_int]
+        L.sof_timing_read.argtypes = [P, P, ctypes.POINTER(i32)]
         if hasattr(L, "sof_autotune"):
             L.sof_autotune.argtypes = [P, i32, i32, i32, i32, ctypes.POINTER(sof_tune), P]
         _lib = L
@@ -166,6 +169,22 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def timing(self, enable: bool):
+        """Benchmark instrumentation: HIP events around each find_splits call."""
+        _check(lib().sof_timing_enable(self.handle, int(bool(enable))))
+
+    STAGES = ("plan", "big_range", "big_merge", "big_hist", "big_scan", "mid", "small", "sort", "reduce")
+
+    def timing_read(self):
+        """({stage: ms, ..., "total": ms}, calls) summed since the last read."""
+        n = len(self.STAGES)
+        ms = (ctypes.c_float * (n + 1))()
+        calls = i32(0)
+        _check(lib().sof_timing_read(self.handle, ctypes.cast(ms, P), ctypes.byref(calls)))
+        out = {name: float(ms[i]) for i, name in enumerate(self.STAGES)}
+        out["total"] = float(ms[n])
+        return out, int(calls.value)
 
     def workspace(self, nbytes: int):
         """A cached device workspace of at least nbytes (256-byte aligned)."""

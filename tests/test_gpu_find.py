@@ -44,6 +44,33 @@ def check_case(ctx, wl, tag):
     return dev, got, ref
 
 
+# One size class at a time first (pytest -x stops at the first failure), then
+# frontiers mixing every class.
+
+def test_class_histogram_small_and_mid(ctx):
+    wl = W.random_frontier(61, n_rows=20000, d=12, n_classes=3, sizes=[4, 10, 300, 1024, 1025, 1500, 8192],
+                           k=6, z=3, bins=256, sort_threshold=0, layout="b")
+    check_case(ctx, wl, "hist small+mid")
+
+
+def test_class_sort_in_one_wave(ctx):
+    wl = W.random_frontier(62, n_rows=5000, d=12, n_classes=3, sizes=[0, 1, 2, 3, 17, 40, 63, 64], k=6,
+                           z=3, bins=256, sort_threshold=2**31 - 1, layout="r")
+    check_case(ctx, wl, "sort <= 64")
+
+
+def test_class_sort_block(ctx):
+    wl = W.random_frontier(63, n_rows=30000, d=12, n_classes=3, sizes=[65, 100, 777, 4096, 8192], k=5, z=3,
+                           bins=256, sort_threshold=2**31 - 1, layout="b")
+    check_case(ctx, wl, "sort 65..8192")
+
+
+def test_class_big(ctx):
+    wl = W.random_frontier(64, n_rows=60000, d=12, n_classes=3, sizes=[8193, 12000, 30001], k=10, z=3,
+                           bins=256, sort_threshold=0, layout="b")
+    check_case(ctx, wl, "big")
+
+
 @pytest.mark.parametrize("T", [0, 64, 300, 2**31 - 1])
 def test_edge_sizes_all_paths(ctx, T):
     wl = W.random_frontier(7, n_rows=60000, d=24, n_classes=3, sizes=EDGE_SIZES, k=6, z=3,
