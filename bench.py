@@ -1,0 +1,373 @@
+#!/usr/bin/env python3
+"""Split-search benchmark on one GPU.
+
+One step is the whole hot path over one frontier: the batched split search
+(projection, node range, histogram or sort, Gini scan and argmax; paper
+section 4, steps 1-3) followed by the stable partition of every node's
+samples.  Inputs are seeded and synthetic and are resident in device memory
+before the timed region starts.
+
+Prints one JSON line:
+  value            node-sample x projection per second of the whole step
+  roofline         the dominant kernel: algorithmic bytes per launch over its
+                   mean duration (HIP events recorded on the launch stream
+                   inside the timed region), against 8 TB/s of HBM
+  cpu_baseline     the CPU oracle on the same frontier (or a bounded sample)
+  plain_per_node   the same library called once per node from a host loop
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+SORT_LIMIT = 8192
+WAVE_SORT_MAX, SMALL_MAX, MID_MAX = 64, 1024, 8192
+
+WORKLOADS = {
+    "c3a": "batched frontier, 4096 log-normal nodes (median 300, 2..100000, ~4.0M samples) over a "
+           "4.0M x 512 FP32 matrix, node rows contiguous, 3 classes, k=64, z=4, B=256",
+    "c3b": "as c3a, each node's rows an ascending random subset of the matrix",
+    "c2": "single root node, n=1048576, d=256 FP32, 2 classes, k=256, z=3, B=256, histogram path",
+    "c5": "single root node, n=10M, d=128 FP16 on the 1/256 grid, 2 classes, k=128, z=1..8, B=256",
+    "c5f32": "as c5 with the same values stored FP32",
+    "c1": "single root node, n=4096, d=64 FP32, 2 classes, k=64, z=3, B=256",
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_workload(name: str):
+    from paper_2603_00326_amd import workloads as W
+    if name == "c3a":
+        return W.config3("a")
+    if name == "c3b":
+        return W.config3("b")
+    if name == "c2":
+        return W.config2()
+    if name == "c5":
+        return W.config5(fp16=True)
+    if name == "c5f32":
+        return W.config5(fp16=False)
+    if name == "c1":
+        return W.config1()
+    raise SystemExit(f"unknown workload {name}; choose from {sorted(WORKLOADS)}")
+
+
+# ---------------------------------------------------------------------------
+# algorithmic bytes per kernel (each projection gathers its own z columns over
+# the node's samples; sample indices and labels are read once per node)
+
+def node_classes(wl, T: int):
+    """Size class of every node as the library classifies it: 'none' (no
+    projections), 'small', 'mid', 'sort', 'big'."""
+    n = np.diff(wl.node_offsets.astype(np.int64))
+    k = np.diff(wl.proj_offsets.astype(np.int64))
+    Te = min(int(T), SORT_LIMIT + 1)
+    sortp = n < Te
+    cls = np.full(len(n), "big", dtype=object)
+    cls[~sortp & (n <= MID_MAX)] = "mid"
+    cls[~sortp & (n <= SMALL_MAX)] = "small"
+    cls[sortp] = "sort"
+    cls[sortp & (n <= WAVE_SORT_MAX)] = "small"
+    cls[k == 0] = "none"
+    return n, k, cls
+
+
+def stage_bytes(wl, T: int):
+    """Algorithmic bytes of each stage of one find-splits call."""
+    n, k, cls = node_classes(wl, T)
+    sx = wl.X.dtype.itemsize
+    zsum = np.add.reduceat(np.diff(wl.nz_offsets.astype(np.int64)), wl.proj_offsets[:-1].astype(np.int64)) \
+        if wl.n_proj else np.zeros(len(n), np.int64)
+    zsum = np.where(k > 0, zsum, 0)
+    cols = n * zsum * sx          # sum over the node's projections of n * z_p * s_x
+    idx_lab = n * (4 + 4)
+    out = {}
+    for name, c in (("small", "small"), ("mid", "mid"), ("sort", "sort")):
+        m = cls == c
+        out[name] = float((idx_lab[m] + cols[m]).sum())
+    m = cls == "big"
+    out["big_range"] = float((n[m] * 4 + cols[m]).sum())
+    out["big_hist"] = float((idx_lab[m] + cols[m]).sum())
+    out["find"] = float((idx_lab[cls != "none"] + cols[cls != "none"]).sum())
+    return out
+
+
+def partition_bytes(wl, splits):
+    """Algorithmic bytes of the partition: n (z_{p*} s_x + 2 s_i) per split node."""
+    n = np.diff(wl.node_offsets.astype(np.int64))
+    po = wl.proj_offsets.astype(np.int64)
+    zo = wl.nz_offsets.astype(np.int64)
+    sx = wl.X.dtype.itemsize
+    total = 0
+    for v in np.nonzero(splits["proj"] >= 0)[0]:
+        q = po[v] + splits["proj"][v]
+        total += n[v] * ((zo[q + 1] - zo[q]) * sx + 8)
+    return float(total)
+
+
+# ---------------------------------------------------------------------------
+# the CPU oracle on a bounded sample of the same frontier
+
+def sub_workload(wl, nodes):
+    """The frontier restricted to the given nodes (same matrix and labels)."""
+    from paper_2603_00326_amd.workloads import Workload
+    no = wl.node_offsets.astype(np.int64)
+    po = wl.proj_offsets.astype(np.int64)
+    zo = wl.nz_offsets.astype(np.int64)
+    idx, offs, pof, zof, zf, zw = [], [0], [0], [0], [], []
+    for v in nodes:
+        idx.append(wl.sample_idx[no[v]:no[v + 1]])
+        offs.append(offs[-1] + int(no[v + 1] - no[v]))
+        for q in range(po[v], po[v + 1]):
+            zf.append(wl.nz_feature[zo[q]:zo[q + 1]])
+            zw.append(wl.nz_weight[zo[q]:zo[q + 1]])
+            zof.append(zof[-1] + int(zo[q + 1] - zo[q]))
+        pof.append(pof[-1] + int(po[v + 1] - po[v]))
+    cat = lambda xs, dt: np.concatenate(xs).astype(dt) if xs else np.zeros(0, dt)
+    nb = None if wl.node_bins is None else wl.node_bins[np.asarray(nodes)].astype(np.int32)
+    return Workload(wl.name + "_sample", wl.X, wl.y, wl.n_classes, np.asarray(offs, np.int32),
+                    cat(idx, np.int32), np.asarray(pof, np.int32), np.asarray(zof, np.int32),
+                    cat(zf, np.int32), cat(zw, np.int8), wl.bins, wl.sort_threshold, nb, dict(wl.meta))
+
+
+def cpu_baseline(wl, T, budget_units: float):
+    from oracle import oracle as O
+    O.lib()
+    units_all = wl.units
+    if units_all <= budget_units:
+        sample, nodes = wl, None
+        desc = "whole frontier, one oracle call (find splits + partition)"
+    else:
+        rng = np.random.default_rng(12345)
+        order = rng.permutation(wl.n_nodes)
+        n = np.diff(wl.node_offsets.astype(np.int64))
+        k = np.diff(wl.proj_offsets.astype(np.int64))
+        acc, nodes = 0, []
+        for v in order:
+            nodes.append(int(v))
+            acc += int(n[v] * k[v])
+            if acc >= budget_units:
+                break
+        nodes.sort()
+        sample = sub_workload(wl, nodes)
+        desc = (f"{len(nodes)} of {wl.n_nodes} nodes drawn uniformly (seed 12345), "
+                f"{sample.units} of {units_all} units, find splits + partition")
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+    t0 = time.perf_counter()
+    ref, _ = O.find_splits(sample.X, sample.y, sample.n_classes, sample.node_offsets, sample.sample_idx,
+                           sample.proj_offsets, sample.nz_offsets, sample.nz_feature, sample.nz_weight,
+                           bins=sample.bins, sort_threshold=T, node_bins=sample.node_bins,
+                           threads=threads)
+    O.partition(sample.X, sample.node_offsets, sample.sample_idx, sample.proj_offsets, sample.nz_offsets,
+                sample.nz_feature, sample.nz_weight, ref, bins=sample.bins, node_bins=sample.node_bins)
+    el = time.perf_counter() - t0
+    return {"value": sample.units / el, "unit": "node-sample*projection/s", "cores": threads,
+            "kind": "oracle", "sample": desc, "seconds": round(el, 3)}
+
+
+# ---------------------------------------------------------------------------
+# the plain form: one single-node call per node from a host loop
+
+class PlainForm:
+    """Per-node frontiers over views of the batched device arrays."""
+
+    def __init__(self, ctx, dev, wl, T):
+        import torch
+        from paper_2603_00326_amd import sof as S
+        self.S, self.ctx, self.T = S, ctx, T
+        no = wl.node_offsets.astype(np.int64)
+        po = wl.proj_offsets.astype(np.int64)
+        zo = wl.nz_offsets.astype(np.int64)
+        dv = dev.X.device
+        self.items = []
+        self.keep = []
+        max_ws = 0
+        for v in range(wl.n_nodes):
+            n, k = int(no[v + 1] - no[v]), int(po[v + 1] - po[v])
+            z0 = int(zo[po[v]])
+            offs = torch.tensor([0, n], dtype=torch.int32, device=dv)
+            pof = torch.tensor([0, k], dtype=torch.int32, device=dv)
+            zof = torch.from_numpy((zo[po[v]:po[v + 1] + 1] - z0).astype(np.int32)).to(dv)
+            nb = None if dev.node_bins is None else dev.node_bins[v:v + 1]
+            f = S.DeviceFrontier(X=dev.X, y=dev.y, n_classes=dev.n_classes, node_offsets=offs,
+                                 sample_idx=dev.sample_idx[no[v]:no[v + 1]], proj_offsets=pof,
+                                 nz_offsets=zof, nz_feature=dev.nz_feature[z0:],
+                                 nz_weight=dev.nz_weight[z0:], node_bins=nb, max_node_samples=n,
+                                 max_proj_per_node=k)
+            out = torch.empty((1, 10), dtype=torch.int32, device=dv)
+            oidx = torch.empty(max(n, 1), dtype=torch.int32, device=dv)
+            coff = torch.empty(3, dtype=torch.int32, device=dv)
+            d, fr, p = f.structs()
+            q = S.sof_params(S._ptr(nb), int(wl.bins), int(T))
+            sz = ctypes.c_size_t(0)
+            S._check(S.lib().sof_workspace_size(ctx.handle, ctypes.byref(d), ctypes.byref(fr), ctypes.byref(p),
+                                                ctypes.byref(q), ctypes.byref(sz)))
+            max_ws = max(max_ws, sz.value)
+            self.items.append((d, fr, p, q, out, oidx, coff))
+            self.keep.append((f, out, oidx, coff, nb))
+        self.ws, self.wsb = ctx.workspace(max_ws)
+
+    def step(self, stream):
+        S, L = self.S, self.S.lib()
+        h = self.ctx.handle
+        for d, fr, p, q, out, oidx, coff in self.items:
+            S._check(L.sof_find_splits(h, ctypes.byref(d), ctypes.byref(fr), ctypes.byref(p), ctypes.byref(q),
+                                       out.data_ptr(), None, self.ws, self.wsb, stream))
+            S._check(L.sof_partition(h, ctypes.byref(d), ctypes.byref(fr), ctypes.byref(p), ctypes.byref(q),
+                                     out.data_ptr(), oidx.data_ptr(), coff.data_ptr(), self.ws, self.wsb,
+                                     stream))
+
+
+# ---------------------------------------------------------------------------
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c3a", choices=sorted(WORKLOADS))
+    ap.add_argument("--threshold", type=int, default=None,
+                    help="sort/histogram switch T (default: the autotuner's choice)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--plain", type=int, default=2,
+                    help="steps of the per-node-launch form (0 skips it)")
+    ap.add_argument("--cpu-units", type=float, default=3e9,
+                    help="bound on the oracle sample, in node-sample*projection units")
+    ap.add_argument("--copy-only", type=float, default=0.0,
+                    help="run only a plain device copy of this many GiB (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              f"(the library has no multi-GPU path)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2603_00326_amd import sof as S
+
+    dev_name = "cuda:0"
+    if args.copy_only > 0:
+        n = int(args.copy_only * (1 << 30)) // 4
+        a = torch.ones(n, dtype=torch.float32, device=dev_name)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "launches": 3}))
+        return
+
+    t0 = time.perf_counter()
+    wl = make_workload(args.workload)
+    log(f"[bench] workload {args.workload}: {wl.n_nodes} nodes, {wl.n_samples} samples, "
+        f"{wl.n_proj} projections, units {wl.units} (generated in {time.perf_counter() - t0:.1f}s)")
+    ctx = S.Context(0)
+    dev = S.to_device(wl, dev_name)
+    torch.cuda.synchronize()
+
+    T = args.threshold
+    tune = None
+    if T is None:
+        tune = S.autotune(ctx, wl.n_classes, int(wl.meta.get("k", 64)), int(wl.meta.get("z", 3)), wl.bins,
+                          dtype=wl.X.dtype)
+        T = int(tune["sort_threshold"])
+    log(f"[bench] sort threshold T={T}" + (f" (autotuned in {tune['ms']:.1f} ms)" if tune else ""))
+
+    stream = torch.cuda.current_stream()
+    out = torch.empty((max(wl.n_nodes, 1), 10), dtype=torch.int32, device=dev_name)
+
+    def step():
+        S.find_splits(ctx, dev, bins=wl.bins, sort_threshold=T, out=out)
+        S.partition(ctx, dev, out, bins=wl.bins)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    ctx.timing_read()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stage_ms, calls = ctx.timing_read()
+    ctx.timing(False)
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    value = wl.units / (ms_per_step * 1e-3)
+
+    splits = S.splits_to_numpy(out)[:wl.n_nodes]
+    sb = stage_bytes(wl, T)
+    per = {k: v / max(calls, 1) for k, v in stage_ms.items()}
+    data_stages = ("big_range", "big_hist", "mid", "small", "sort")
+    dom = max(data_stages, key=lambda s: per[s])
+    kernel_name = {"big_range": "k_brange", "big_hist": "k_bhist", "mid": "k_mid", "small": "k_small",
+                   "sort": "k_sortblk"}[dom]
+    achieved = sb[dom] / (per[dom] * 1e-3) / 1e9 if per[dom] > 0 else 0.0
+    roof = {"bound": "hbm", "kernel": kernel_name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "bytes_per_launch": sb[dom], "ms_per_launch": round(per[dom], 5)}
+    find_gbs = sb["find"] / (per["total"] * 1e-3) / 1e9 if per["total"] > 0 else 0.0
+    pb = partition_bytes(wl, splits)
+
+    result = {
+        "metric": "split-search throughput: node-sample×projection/s + % of HBM roofline",
+        "value": value,
+        "unit": "node-sample*projection/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f16" if wl.X.dtype == np.float16 else "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "description": WORKLOADS[args.workload],
+                   "nodes": wl.n_nodes, "samples": int(wl.n_samples), "units": int(wl.units),
+                   "sort_threshold": T, "bins": wl.bins, "step": "find_splits + partition"},
+        "roofline": roof,
+        "find_splits": {"ms": round(per["total"], 4), "algorithmic_bytes": sb["find"],
+                        "achieved_GBs": round(find_gbs, 1), "frac": round(find_gbs / HBM_PEAK_GBS, 4),
+                        "stage_ms": {k: round(v, 4) for k, v in per.items()},
+                        "stage_bytes": sb},
+        "partition": {"algorithmic_bytes": pb},
+    }
+    if tune:
+        result["autotune"] = tune
+
+    if args.plain > 0:
+        log(f"[bench] plain per-node form: {wl.n_nodes} single-node calls per step")
+        pf = PlainForm(ctx, dev, wl, T)
+        pf.step(stream.cuda_stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.plain):
+            pf.step(stream.cuda_stream)
+        torch.cuda.synchronize()
+        pms = (time.perf_counter() - t0) * 1e3 / args.plain
+        result["plain_per_node"] = {"value": wl.units / (pms * 1e-3), "ms_per_step": round(pms, 3),
+                                    "steps": args.plain, "speedup_of_batched": round(pms / ms_per_step, 2)}
+
+    if not args.no_cpu:
+        log("[bench] CPU oracle baseline")
+        result["cpu_baseline"] = cpu_baseline(wl, T, args.cpu_units)
+
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -241,11 +241,18 @@ int sof_forest_frontier_size(sof_forest* forest, int64_t* n_nodes, void* stream)
 int sof_forest_export(sof_forest* forest, sof_tree_node* host_nodes, int64_t cap, int64_t* n,
                       void* stream);
 
-/* Crossover microbenchmark (section 4.1: run once before training): times the
- * sort and histogram paths on synthetic frontiers of growing node size on this
- * device and picks the sort threshold (first size where histograms win) and
- * a bin-count switch for small nodes.  Allocates and synchronises. */
-int sof_autotune(sof_ctx* ctx, int32_t n_classes, int32_t k, int32_t nnz, int32_t bins,
+/* Crossover microbenchmark (section 4.1: run once before training, a search
+ * for the node size where histograms overtake sorting): times the sort and
+ * histogram paths on synthetic frontiers of equal nodes of growing size, on
+ * this device, with the caller's storage type (SOF_F32 or SOF_F16), class
+ * count, projections per node (capped at 64 for timing), nonzeros per
+ * projection and bin count.  Picks the sort threshold (the smallest measured
+ * size from which the histogram path is never slower) and a bin-count switch
+ * for small nodes (below the first size where full bins cost at most 10% more
+ * than half bins, half the bins).  Allocates its own device buffers, frees
+ * them, and synchronises `stream`.  Errors: SOF_ERR_INVALID_ARG (NULL, k or
+ * nnz out of range), SOF_ERR_UNSUPPORTED (dtype, classes, bins), SOF_ERR_HIP. */
+int sof_autotune(sof_ctx* ctx, int32_t dtype, int32_t n_classes, int32_t k, int32_t nnz, int32_t bins,
                  sof_tune* out, void* stream);
 
 /* Benchmark instrumentation.  The launch sequence of sof_find_splits runs in

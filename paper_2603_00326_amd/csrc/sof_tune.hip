@@ -1,0 +1,216 @@
+// sof_tune.hip -- crossover microbenchmark behind sof_autotune (paper section
+// 4.1: histograms win on large nodes and sorting on small ones, and the
+// crossover is measured once before training).
+//
+// For a ladder of node sizes s, a synthetic frontier of equal nodes of s
+// contiguous rows (about 2^18 samples in all, k projections of nnz features)
+// is searched twice through sof_find_splits: all nodes on the sort path
+// (T = INT32_MAX) and all on the histogram path (T = 0).  The chosen T is the
+// smallest measured size from which the histogram path is never slower.  The
+// same frontiers, searched with half the bins, give the bin-count switch for
+// small nodes: below the first size where full bins cost at most 10% more
+// than half bins, nodes use half the bins.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cstring>
+#include <vector>
+
+#include "sof.h"
+#include "sof_host.h"
+
+namespace sof {
+
+__device__ __forceinline__ uint32_t tune_hash(uint32_t x) {
+    // 32-bit integer finaliser of MurmurHash3 (Appleby)
+    x ^= x >> 16;
+    x *= 0x85ebca6bu;
+    x ^= x >> 13;
+    x *= 0xc2b2ae35u;
+    x ^= x >> 16;
+    return x;
+}
+
+// X[f][r] uniform in [-1, 1) on a 2^-10 grid, labels hash % C
+__global__ void k_tune_data(float* x, _Float16* xh, int32_t* y, int n_rows, int d, int C) {
+    const int64_t total = (int64_t)n_rows * d;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t h = tune_hash((uint32_t)i * 2654435761u + 12345u);
+        const float v = (float)((int)(h & 2047u) - 1024) * (1.0f / 1024.0f);
+        x[i] = v;
+        xh[i] = (_Float16)v;
+        if (i < n_rows) y[i] = (int32_t)(tune_hash((uint32_t)i + 777u) % (uint32_t)C);
+    }
+}
+
+// frontier of N nodes of s contiguous rows; k projections per node, nnz
+// distinct features each (consecutive from a hashed start), signs hashed
+__global__ void k_tune_frontier(int32_t* node_off, int32_t* idx, int32_t* proj_off, int32_t* nz_off,
+                                int32_t* nz_f, int8_t* nz_w, int N, int s, int k, int nnz, int d) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    for (int64_t v = t0; v <= N; v += stride) {
+        node_off[v] = (int32_t)(v * s);
+        proj_off[v] = (int32_t)(v * k);
+    }
+    for (int64_t i = t0; i < (int64_t)N * s; i += stride) idx[i] = (int32_t)i;
+    const int64_t P = (int64_t)N * k;
+    for (int64_t q = t0; q <= P; q += stride) nz_off[q] = (int32_t)(q * nnz);
+    for (int64_t q = t0; q < P; q += stride) {
+        const uint32_t h = tune_hash((uint32_t)q * 0x9e3779b9u + 99u);
+        const int f0 = (int)(h % (uint32_t)(d - nnz + 1));
+        for (int j = 0; j < nnz; ++j) {
+            nz_f[q * nnz + j] = f0 + j;
+            nz_w[q * nnz + j] = ((h >> (8 + j)) & 1u) ? (int8_t)-1 : (int8_t)1;
+        }
+    }
+}
+
+}  // namespace sof
+
+using namespace sof;
+
+namespace {
+
+struct TuneBufs {
+    std::vector<void*> ptrs;
+    ~TuneBufs() {
+        for (void* p : ptrs) (void)hipFree(p);
+    }
+    template <class T>
+    hipError_t get(T** p, size_t n) {
+        void* q = nullptr;
+        hipError_t e = hipMalloc(&q, n * sizeof(T) < 256 ? 256 : n * sizeof(T));
+        if (e == hipSuccess) ptrs.push_back(q);
+        *p = (T*)q;
+        return e;
+    }
+};
+
+}  // namespace
+
+extern "C" int sof_autotune(sof_ctx* ctx, int32_t dtype, int32_t n_classes, int32_t k, int32_t nnz,
+                            int32_t bins, sof_tune* out, void* stream) {
+    if (!ctx || !out) return fail(SOF_ERR_INVALID_ARG, "sof_autotune: NULL argument");
+    if (dtype != SOF_F32 && dtype != SOF_F16) return fail(SOF_ERR_UNSUPPORTED, "sof_autotune: dtype %d", dtype);
+    if (n_classes < 2 || n_classes > SOF_MAX_CLASSES)
+        return fail(SOF_ERR_UNSUPPORTED, "sof_autotune: n_classes %d", n_classes);
+    if (k < 1 || k > 1024) return fail(SOF_ERR_INVALID_ARG, "sof_autotune: k %d outside [1, 1024]", k);
+    if (nnz < 1 || nnz > SOF_MAX_NNZ) return fail(SOF_ERR_INVALID_ARG, "sof_autotune: nnz %d", nnz);
+    if (bins < SOF_MIN_BINS || bins > SOF_MAX_BINS) return fail(SOF_ERR_UNSUPPORTED, "sof_autotune: bins %d", bins);
+    auto wall0 = std::chrono::steady_clock::now();
+    memset(out, 0, sizeof(*out));
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+
+    static const int kSizes[] = {4, 8, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048,
+                                 3072, 4096, 6144, 8192};
+    const int n_sizes = (int)(sizeof(kSizes) / sizeof(kSizes[0]));
+    const int n_rows = 1 << 18;
+    const int d = 64;
+    const int kk = k > 64 ? 64 : k;   // per node-projection cost is what is compared
+    int maxN = 0;
+    for (int i = 0; i < n_sizes; ++i) maxN = n_rows / kSizes[i] > maxN ? n_rows / kSizes[i] : maxN;
+    const int64_t maxP = (int64_t)maxN * kk;
+
+    TuneBufs B;
+    float* x;
+    _Float16* xh;
+    int32_t *y, *no, *idx, *po, *zo, *zf, *node_bins;
+    int8_t* zw;
+    sof_split* sp;
+    if ((e = B.get(&x, (size_t)n_rows * d)) || (e = B.get(&xh, (size_t)n_rows * d)) || (e = B.get(&y, n_rows)) ||
+        (e = B.get(&no, maxN + 1)) || (e = B.get(&idx, n_rows)) || (e = B.get(&po, maxN + 1)) ||
+        (e = B.get(&zo, maxP + 1)) || (e = B.get(&zf, maxP * nnz)) || (e = B.get(&zw, maxP * nnz)) ||
+        (e = B.get(&sp, maxN)) || (e = B.get(&node_bins, maxN)))
+        return hip_fail(e, "sof_autotune: hipMalloc");
+    hipLaunchKernelGGL(k_tune_data, dim3(1024), dim3(256), 0, s, x, xh, y, n_rows, d, n_classes);
+
+    sof_data data;
+    memset(&data, 0, sizeof(data));
+    data.x = dtype == SOF_F16 ? (const void*)xh : (const void*)x;
+    data.y = y;
+    data.ld = n_rows;
+    data.n_rows = n_rows;
+    data.n_features = d;
+    data.n_classes = n_classes;
+    data.dtype = dtype;
+
+    // workspace for the largest frontier
+    size_t ws_bytes = 0;
+    for (int i = 0; i < n_sizes; ++i) {
+        const int N = n_rows / kSizes[i];
+        sof_frontier fr{no, idx, (int64_t)N * kSizes[i], N, kSizes[i]};
+        sof_proj pj{po, zo, zf, zw, (int64_t)N * kk * nnz, N * kk, kk};
+        sof_params q{nullptr, bins, 0};
+        size_t b = 0;
+        int rc = sof_workspace_size(ctx, &data, &fr, &pj, &q, &b);
+        if (rc) return rc;
+        ws_bytes = b > ws_bytes ? b : ws_bytes;
+    }
+    void* ws;
+    if ((e = B.get((char**)&ws, ws_bytes))) return hip_fail(e, "sof_autotune: hipMalloc");
+    hipEvent_t ev0, ev1;
+    if ((e = hipEventCreate(&ev0)) != hipSuccess) return hip_fail(e, "hipEventCreate");
+    if ((e = hipEventCreate(&ev1)) != hipSuccess) {
+        (void)hipEventDestroy(ev0);
+        return hip_fail(e, "hipEventCreate");
+    }
+    float half_us[32];
+    int rc = SOF_OK;
+    const int half_bins = bins / 2 >= SOF_MIN_BINS ? bins / 2 : SOF_MIN_BINS;
+    for (int i = 0; i < n_sizes && rc == SOF_OK; ++i) {
+        const int sz = kSizes[i], N = n_rows / sz;
+        hipLaunchKernelGGL(k_tune_frontier, dim3(512), dim3(256), 0, s, no, idx, po, zo, zf, zw, N, sz, kk, nnz, d);
+        sof_frontier fr{no, idx, (int64_t)N * sz, N, sz};
+        sof_proj pj{po, zo, zf, zw, (int64_t)N * kk * nnz, N * kk, kk};
+        float best[3] = {1e30f, 1e30f, 1e30f};
+        for (int path = 0; path < 3 && rc == SOF_OK; ++path) {
+            // 0: sort path, 1: histogram path, 2: histogram path with half the bins
+            sof_params q{nullptr, path == 2 ? half_bins : bins, path == 0 ? 0x7fffffff : 0};
+            for (int rep = 0; rep < 3 && rc == SOF_OK; ++rep) {
+                (void)hipEventRecord(ev0, s);
+                rc = sof_find_splits(ctx, &data, &fr, &pj, &q, sp, nullptr, ws, ws_bytes, stream);
+                (void)hipEventRecord(ev1, s);
+                if (rc) break;
+                if ((e = hipEventSynchronize(ev1)) != hipSuccess) {
+                    rc = hip_fail(e, "hipEventSynchronize");
+                    break;
+                }
+                float ms = 0.f;
+                (void)hipEventElapsedTime(&ms, ev0, ev1);
+                if (rep > 0 && ms < best[path]) best[path] = ms;   // first run warms up
+            }
+        }
+        const float per = 1e3f / (float)((int64_t)N * kk);   // ms per call -> us per node-projection
+        out->sizes[i] = sz;
+        out->sort_us[i] = best[0] * per;
+        out->hist_us[i] = best[1] * per;
+        half_us[i] = best[2] * per;
+    }
+    (void)hipEventDestroy(ev0);
+    (void)hipEventDestroy(ev1);
+    if (rc) return rc;
+    out->n_points = n_sizes;
+    // T: smallest size from which the histogram path is never slower
+    int T = SOF_SORT_LIMIT + 1;
+    for (int i = n_sizes - 1; i >= 0; --i) {
+        if (out->hist_us[i] <= out->sort_us[i]) T = kSizes[i];
+        else break;
+    }
+    out->sort_threshold = T;
+    // bins switch: first size where full bins cost at most 10% more than half bins
+    int sw = 0;
+    for (int i = 0; i < n_sizes; ++i)
+        if (out->hist_us[i] <= 1.1f * half_us[i]) {
+            sw = kSizes[i];
+            break;
+        }
+    out->bins_small = half_bins;
+    out->bins_switch = sw;
+    out->elapsed_ms =
+        std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - wall0).count();
+    return SOF_OK;
+}

@@ -124,7 +124,7 @@ def lib():
         L.sof_timing_enable.argtypes = [P, ctypes.c_int]
         L.sof_timing_read.argtypes = [P, P, ctypes.POINTER(i32)]
         if hasattr(L, "sof_autotune"):
-            L.sof_autotune.argtypes = [P, i32, i32, i32, i32, ctypes.POINTER(sof_tune), P]
+            L.sof_autotune.argtypes = [P, i32, i32, i32, i32, i32, ctypes.POINTER(sof_tune), P]
         _lib = L
     return _lib
 
@@ -324,6 +324,22 @@ def splits_from_numpy(rec: np.ndarray, device="cuda:0"):
     for name in SPLIT_DTYPE.names:
         out[name] = rec[name]
     return torch.from_numpy(out.view(np.int32).reshape(-1, 10).copy()).to(device)
+
+
+def autotune(ctx: Context, n_classes: int, k: int, z: int, bins: int = 256, *, dtype=np.float32,
+             stream=None) -> dict:
+    """Run the library's crossover microbenchmark (sof_autotune) and return
+    its choice: sort threshold, small-node bin rule and the measured curve."""
+    t = sof_tune()
+    code = SOF_F16 if np.dtype(dtype) == np.float16 else SOF_F32
+    _check(lib().sof_autotune(ctx.handle, code, int(n_classes), int(k), int(z), int(bins), ctypes.byref(t),
+                              _stream(stream)))
+    n = int(t.n_points)
+    return {"sort_threshold": int(t.sort_threshold), "bins_small": int(t.bins_small),
+            "bins_switch": int(t.bins_switch), "ms": float(t.elapsed_ms),
+            "sizes": [int(t.sizes[i]) for i in range(n)],
+            "sort_us": [round(float(t.sort_us[i]), 5) for i in range(n)],
+            "hist_us": [round(float(t.hist_us[i]), 5) for i in range(n)]}
 
 
 class Forest:
