@@ -120,6 +120,29 @@ def partition_bytes(wl, splits):
 
 
 # ---------------------------------------------------------------------------
+# measured HBM traffic of a kernel (rocprofv3 FETCH_SIZE / WRITE_SIZE, per
+# dispatch, scaled by a device-copy calibration), from the committed profile
+# summary; None when the kernel source changed since the counters were taken
+
+def measured_traffic(kernel: str, workload: str):
+    import hashlib
+    src = os.path.join(ROOT, "paper_2603_00326_amd", "csrc", "k_find.hip")
+    prof = os.path.join(ROOT, "profiles", f"find_{workload}_hbm_traffic.md")
+    if not os.path.exists(prof) or not os.path.exists(src):
+        return None
+    md5 = hashlib.md5(open(src, "rb").read()).hexdigest()
+    for line in open(prof):
+        parts = line.split()
+        if not parts or parts[0] != "traffic":
+            continue
+        kv = dict(p.split("=", 1) for p in parts[1:] if "=" in p)
+        if kv.get("kernel") == kernel and kv.get("workload") == workload and kv.get("source_md5") == md5:
+            return (float(kv["fetch_kib"]) * float(kv["fetch_scale"]) +
+                    float(kv["write_kib"]) * float(kv["write_scale"])) * 1024.0
+    return None
+
+
+# ---------------------------------------------------------------------------
 # the CPU oracle on a bounded sample of the same frontier
 
 def sub_workload(wl, nodes):
@@ -318,7 +341,8 @@ def main():
                    "sort": "k_sortblk"}[dom]
     achieved = sb[dom] / (per[dom] * 1e-3) / 1e9 if per[dom] > 0 else 0.0
     roof = {"bound": "hbm", "kernel": kernel_name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(kernel_name, args.workload),
             "bytes_per_launch": sb[dom], "ms_per_launch": round(per[dom], 5)}
     find_gbs = sb["find"] / (per["total"] * 1e-3) / 1e9 if per["total"] > 0 else 0.0
     pb = partition_bytes(wl, splits)
