@@ -399,64 +399,79 @@ __device__ Cand scan_sort_small(WaveScratch& WS, float val, int lab, int64_t n, 
 }
 
 // ---------------------------------------------------------------------------
+// Row loads shared by the small and mid nodes.  A thread holds R samples
+// (sample t + r * stride in slot r).  Slots past the node's end repeat its
+// last sample (row 0 for an empty node), so every address is valid and the
+// loads of one column are issued together, without a branch per slot; those
+// slots are masked out of the range and the histogram by `lab < 0` (small)
+// or by the sample index (mid).  Columns are addressed as a uniform base plus
+// a 32-bit byte offset per slot (row ids are below 2^30).
+
+template <typename T>
+__device__ __forceinline__ float ldx_off(const T* col, uint32_t off) {
+    return ldx((const T*)((const char*)col + off), 0);
+}
+
+template <typename T, int R>
+__device__ __forceinline__ void gather_rows(const FindArgs& A, const int32_t* lf, const uint32_t* ls, int z,
+                                            const uint32_t (&off)[R], float (&val)[R]) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) val[r] = 0.f;
+    for (int j = 0; j < z; ++j) {
+        const int f = __builtin_amdgcn_readfirstlane(lf[j]);
+        const uint32_t sg = __builtin_amdgcn_readfirstlane(ls[j]);
+        const T* col = (const T*)A.x + (int64_t)f * A.ld;
+        float x[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) x[r] = ldx_off(col, off[r]);
+#pragma unroll
+        for (int r = 0; r < R; ++r) val[r] = __fadd_rn(val[r], signed_term(x[r], sg));
+    }
+}
+
+// ---------------------------------------------------------------------------
 // small nodes: one block per node, wave w takes projections w, w+4, ...
 
-constexpr int kSmallR = kSmallMax / kWave;   // 16 samples per lane
+constexpr int kSmallR = kSmallMax / kWave;   // up to 16 samples per lane
 
-template <typename T, class PS>
-__device__ void do_small(const FindArgs& A, const PS& P, int v, char* smem) {
+template <typename T, class PS, int R>
+__device__ void do_small_r(const FindArgs& A, const PS& P, int v, int64_t s0, int64_t n, char* smem) {
     BlockShared& S = block_shared(smem);
     const int w = threadIdx.x >> 6, lane = lane_id();
     const int C = A.n_classes, Bm = A.bins;
-    int64_t s0, n;
-    node_range(A, v, s0, n);
     const int k = proj_count(P, v);
     const int B = node_bins(A, v);
     const bool sortp = n < A.sort_threshold;
     WaveScratch& WS = S.w[w];
     int32_t* hist = wave_hist(smem, w, Bm, C);
-    const int nr = (int)((n + kWave - 1) / kWave);
 
-    int idx[kSmallR], lab[kSmallR];
-    const int first = n > 0 ? row_of(A, s0) : 0;
+    uint32_t off[R];
+    int lab[R];
 #pragma unroll
-    for (int r = 0; r < kSmallR; ++r) {
-        idx[r] = first;
-        lab[r] = -1;
-        if (r < nr) {
-            int64_t i = lane + (int64_t)r * kWave;
-            if (i < n) {
-                idx[r] = row_of(A, s0 + i);
-                lab[r] = label_of(A, idx[r]);
-            }
-        }
+    for (int r = 0; r < R; ++r) {
+        const int64_t i = lane + (int64_t)r * kWave;
+        const int row = n > 0 ? row_of(A, s0 + (i < n ? i : n - 1)) : 0;
+        off[r] = (uint32_t)row * (uint32_t)sizeof(T);
+        const int y = label_of(A, row);
+        lab[r] = i < n ? y : -1;
     }
     if (lane < 16) WS.pc[lane] = 0;
     wave_sync();
 #pragma unroll
-    for (int r = 0; r < kSmallR; ++r)
-        if (r < nr && lab[r] >= 0) atomicAdd(&WS.pc[lab[r]], 1);
+    for (int r = 0; r < R; ++r)
+        if (lab[r] >= 0) atomicAdd(&WS.pc[lab[r]], 1);
     wave_sync();
 
     Cand best;
     cand_invalid(best);
     for (int p = w; p < k; p += kWavesPerBlock) {
-        const int z = proj_stage(P, v, p, A.n_features, WS.lf, WS.ls);
-        float val[kSmallR];
-#pragma unroll
-        for (int r = 0; r < kSmallR; ++r) val[r] = 0.f;
-        for (int j = 0; j < z; ++j) {
-            const int f = __builtin_amdgcn_readfirstlane(WS.lf[j]);
-            const uint32_t sg = __builtin_amdgcn_readfirstlane(WS.ls[j]);
-            const T* col = (const T*)A.x + (int64_t)f * A.ld;
-#pragma unroll
-            for (int r = 0; r < kSmallR; ++r)
-                if (r < nr) val[r] = __fadd_rn(val[r], signed_term(ldx(col, idx[r]), sg));
-        }
+        const int z = __builtin_amdgcn_readfirstlane(proj_stage(P, v, p, A.n_features, WS.lf, WS.ls));
+        float val[R];
+        gather_rows<T, R>(A, WS.lf, WS.ls, z, off, val);
         float lo = INFINITY, hi = -INFINITY;
 #pragma unroll
-        for (int r = 0; r < kSmallR; ++r)
-            if (r < nr && lab[r] >= 0) { lo = fminf(lo, val[r]); hi = fmaxf(hi, val[r]); }
+        for (int r = 0; r < R; ++r)
+            if (lab[r] >= 0) { lo = fminf(lo, val[r]); hi = fmaxf(hi, val[r]); }
         lo = wave_min(lo);
         hi = wave_max(hi);
         Cand c;
@@ -468,9 +483,8 @@ __device__ void do_small(const FindArgs& A, const PS& P, int v, char* smem) {
             for (int e = lane; e < B * C; e += kWave) hist[e] = 0;
             wave_sync();
 #pragma unroll
-            for (int r = 0; r < kSmallR; ++r)
-                if (r < nr && lab[r] >= 0)
-                    atomicAdd(&hist[bin_index(val[r], lo, scale, B) * C + lab[r]], 1);
+            for (int r = 0; r < R; ++r)
+                if (lab[r] >= 0) atomicAdd(&hist[bin_index(val[r], lo, scale, B) * C + lab[r]], 1);
             wave_sync();
             LdsHist h{hist, C};
             write_hist_row(A, proj_global(P, v, p), h, B);
@@ -495,64 +509,60 @@ __device__ void do_small(const FindArgs& A, const PS& P, int v, char* smem) {
     }
 }
 
+template <typename T, class PS>
+__device__ void do_small(const FindArgs& A, const PS& P, int v, char* smem) {
+    int64_t s0, n;
+    node_range(A, v, s0, n);
+    if (n > kSmallMax) n = kSmallMax;   // the plan never queues larger nodes here
+    const int nr = (int)((n + kWave - 1) / kWave);
+    if (nr <= 1) do_small_r<T, PS, 1>(A, P, v, s0, n, smem);
+    else if (nr <= 2) do_small_r<T, PS, 2>(A, P, v, s0, n, smem);
+    else if (nr <= 4) do_small_r<T, PS, 4>(A, P, v, s0, n, smem);
+    else if (nr <= 8) do_small_r<T, PS, 8>(A, P, v, s0, n, smem);
+    else do_small_r<T, PS, kSmallR>(A, P, v, s0, n, smem);
+}
+
 // ---------------------------------------------------------------------------
 // mid nodes: one block per (node, projection), 32 samples per thread
 
-constexpr int kMidR = kMidMax / kBlock;
+constexpr int kMidR = kMidMax / kBlock;   // up to 32 samples per thread
 
-template <typename T, class PS>
-__device__ void do_mid(const FindArgs& A, const PS& P, int4 D, int p, char* smem) {
+template <typename T, class PS, int R>
+__device__ void do_mid_r(const FindArgs& A, const PS& P, int4 D, int p, int64_t s0, int64_t n, char* smem) {
     BlockShared& S = block_shared(smem);
     const int tid = threadIdx.x, w = tid >> 6, lane = lane_id();
     const int C = A.n_classes, Bm = A.bins;
     const int v = D.x;
-    int64_t s0, n;
-    node_range(A, v, s0, n);
     const int B = node_bins(A, v);
-    const int nr = (int)((n + kBlock - 1) / kBlock);
     WaveScratch& WS = S.w[w];
 
-    int idx[kMidR];
-    uint32_t labp[kMidR / 8];
-    const int first = n > 0 ? row_of(A, s0) : 0;
+    uint32_t off[R];
+    uint32_t labp[(R + 7) / 8];
 #pragma unroll
-    for (int q = 0; q < kMidR / 8; ++q) labp[q] = 0;
+    for (int q = 0; q < (R + 7) / 8; ++q) labp[q] = 0;
 #pragma unroll
-    for (int r = 0; r < kMidR; ++r) {
-        idx[r] = first;
-        if (r < nr) {
-            int64_t i = tid + (int64_t)r * kBlock;
-            if (i < n) {
-                idx[r] = row_of(A, s0 + i);
-                labp[r >> 3] |= (uint32_t)label_of(A, idx[r]) << (4 * (r & 7));
-            }
-        }
+    for (int r = 0; r < R; ++r) {
+        const int64_t i = tid + (int64_t)r * kBlock;
+        const int row = n > 0 ? row_of(A, s0 + (i < n ? i : n - 1)) : 0;
+        off[r] = (uint32_t)row * (uint32_t)sizeof(T);
+        labp[r >> 3] |= (uint32_t)label_of(A, row) << (4 * (r & 7));
     }
-    const int z = proj_stage(P, v, p, A.n_features, WS.lf, WS.ls);
-    float val[kMidR];
-#pragma unroll
-    for (int r = 0; r < kMidR; ++r) val[r] = 0.f;
-    for (int j = 0; j < z; ++j) {
-        const int f = __builtin_amdgcn_readfirstlane(WS.lf[j]);
-        const uint32_t sg = __builtin_amdgcn_readfirstlane(WS.ls[j]);
-        const T* col = (const T*)A.x + (int64_t)f * A.ld;
-#pragma unroll
-        for (int r = 0; r < kMidR; ++r)
-            if (r < nr) val[r] = __fadd_rn(val[r], signed_term(ldx(col, idx[r]), sg));
-    }
+    const int z = __builtin_amdgcn_readfirstlane(proj_stage(P, v, p, A.n_features, WS.lf, WS.ls));
+    float val[R];
+    gather_rows<T, R>(A, WS.lf, WS.ls, z, off, val);
     float lo = INFINITY, hi = -INFINITY;
 #pragma unroll
-    for (int r = 0; r < kMidR; ++r)
-        if (r < nr && tid + (int64_t)r * kBlock < n) { lo = fminf(lo, val[r]); hi = fmaxf(hi, val[r]); }
+    for (int r = 0; r < R; ++r)
+        if (tid + (int64_t)r * kBlock < n) { lo = fminf(lo, val[r]); hi = fmaxf(hi, val[r]); }
     block_minmax(S, lo, hi);
     const float scale = bin_scale(B, lo, hi);
     int32_t* hist = wave_hist(smem, w, Bm, C);
     for (int e = lane; e < B * C; e += kWave) hist[e] = 0;
     wave_sync();
 #pragma unroll
-    for (int r = 0; r < kMidR; ++r)
-        if (r < nr && tid + (int64_t)r * kBlock < n) {
-            int y = (int)((labp[r >> 3] >> (4 * (r & 7))) & 15u);
+    for (int r = 0; r < R; ++r)
+        if (tid + (int64_t)r * kBlock < n) {
+            const int y = (int)((labp[r >> 3] >> (4 * (r & 7))) & 15u);
             atomicAdd(&hist[bin_index(val[r], lo, scale, B) * C + y], 1);
         }
     __syncthreads();
@@ -563,6 +573,18 @@ __device__ void do_mid(const FindArgs& A, const PS& P, int4 D, int p, char* smem
         c.proj = p;
         if (lane == 0) ((Cand*)A.ws.slots)[D.y + p] = c;
     }
+}
+
+// mid nodes: one block per (node, projection), R samples per thread
+template <typename T, class PS>
+__device__ void do_mid(const FindArgs& A, const PS& P, int4 D, int p, char* smem) {
+    int64_t s0, n;
+    node_range(A, D.x, s0, n);
+    if (n > kMidMax) n = kMidMax;   // the plan never queues larger nodes here
+    const int nr = (int)((n + kBlock - 1) / kBlock);
+    if (nr <= 8) do_mid_r<T, PS, 8>(A, P, D, p, s0, n, smem);
+    else if (nr <= 16) do_mid_r<T, PS, 16>(A, P, D, p, s0, n, smem);
+    else do_mid_r<T, PS, kMidR>(A, P, D, p, s0, n, smem);
 }
 
 // ---------------------------------------------------------------------------
