@@ -32,7 +32,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 SORT_LIMIT = 8192
-WAVE_SORT_MAX, SMALL_MAX, MID_MAX = 64, 1024, 8192
+WAVE_SORT_MAX, SMALL_MAX, MID_MAX = 64, 512, 8192
 
 WORKLOADS = {
     "c3a": "batched frontier, 4096 log-normal nodes (median 300, 2..100000, ~4.0M samples) over a "

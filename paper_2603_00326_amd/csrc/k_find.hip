@@ -12,8 +12,8 @@
 //   k_bmerge   big nodes: range of every projection over its chunks
 //   k_bhist    big nodes: histogram of every (projection, chunk); one wave each
 //   k_bscan    big nodes: chunk histograms summed, boundary scan
-//   k_mid      histogram nodes of 1025..8192 samples: one block per (node, projection)
-//   k_small    histogram nodes up to 1024 samples and sort nodes up to 64:
+//   k_mid      histogram nodes of 513..8192 samples: one block per (node, projection)
+//   k_small    histogram nodes up to 512 samples and sort nodes up to 64:
 //              one block per node, one wave per projection
 //   k_sortblk  sort nodes of 65..8192 samples: bitonic sort in LDS
 //   k_reduce   best projection per node for nodes with per-projection slots
@@ -220,71 +220,111 @@ struct GlobalHist {
 // ---------------------------------------------------------------------------
 // boundary scans (one wave)
 
-// Histogram path: lane l owns bins 4l..4l+3.  Class-by-class wave prefix sums
-// give every boundary's left counts; the best boundary (largest Q, lowest bin)
-// wins.  Parent counts are the column totals.
+// Histogram path, screened scan by one wave over a histogram accessor
+// h(b, c) (lane l owns bins 4l..4l+3; B <= 256).
+//
+// Screening: every boundary after a non-empty bin gets an FP32 score
+// q = S_L / n_L + S_R / n_R.  Counts below 2^24 are exact in FP32, so only
+// the C fused squares-and-adds, the two reciprocals (1 ulp each) and the
+// final product and sum round: |q - Q| <= (C + 4) 2^-24 Q <= 20 * 2^-24 Q
+// for C <= 16.  Any boundary whose exact Q could reach the largest then scores
+// at least qmax (1 - 2^-16).  Those contenders (usually one) are evaluated
+// exactly from integer left counts summed over the wave, and compared as
+// N1 D2 > N2 D1 in 128 bits, ties to the lower bin.  A boundary after an
+// empty bin repeats the previous boundary's counts, so it can never win under
+// that tie rule and is skipped.  pc: 16 ints of wave scratch in LDS.
+constexpr float kScreenKeep = 1.0f - 1.0f / 65536.0f;
+
 template <class H>
-__device__ Cand scan_hist(const H& h, int B, int C, int64_t n, float lo, float scale) {
+__device__ Cand scan_hist_fast(const H& h, int B, int C, int64_t n, float lo, float scale, int32_t* pc) {
     const int lane = lane_id();
-    uint32_t nL[4] = {0, 0, 0, 0};
-    uint64_t SL[4] = {0, 0, 0, 0}, SR[4] = {0, 0, 0, 0};
+    const int b0 = lane * 4;
+    const float nf = (float)n;
+    float nL[4] = {0.f, 0.f, 0.f, 0.f}, SL[4] = {0.f, 0.f, 0.f, 0.f}, SR[4] = {0.f, 0.f, 0.f, 0.f};
+    uint32_t filled = 0;
     uint64_t SP = 0;
     for (int c = 0; c < C; ++c) {
-        uint32_t s[4];
-        uint32_t acc = 0;
+        uint32_t hv[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) hv[i] = b0 + i < B ? h(b0 + i, c) : 0u;
+        const float s0 = (float)hv[0], s1 = s0 + (float)hv[1], s2 = s1 + (float)hv[2], s3 = s2 + (float)hv[3];
+        const float incl = wave_scan_f(s3);
+        const float excl = incl - s3;
+        const float Pc = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(incl), 63));
+        const uint32_t Pi = (uint32_t)Pc;
+        SP += (uint64_t)Pi * Pi;
+        if (lane == 0) pc[c] = (int32_t)Pi;
+        const float l[4] = {excl + s0, excl + s1, excl + s2, excl + s3};
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            int b = lane * 4 + i;
-            acc += b < B ? h(b, c) : 0u;
-            s[i] = acc;
-        }
-        uint32_t incl = wave_incl_scan(acc);
-        uint32_t excl = incl - acc;
-        uint32_t Pc = __shfl(incl, 63);
-        SP += (uint64_t)Pc * Pc;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            uint32_t l = excl + s[i];
-            uint32_t r = Pc - l;
-            nL[i] += l;
-            SL[i] += (uint64_t)l * l;
-            SR[i] += (uint64_t)r * r;
+            const float r = Pc - l[i];
+            nL[i] += l[i];
+            SL[i] = __fmaf_rn(l[i], l[i], SL[i]);
+            SR[i] = __fmaf_rn(r, r, SR[i]);
+            if (hv[i] != 0) filled |= 1u << i;
         }
     }
-    bool bv = false;
+    float q[4];
+    float qb = -1.f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const bool ok = b0 + i < B - 1 && ((filled >> i) & 1u) && nL[i] < nf;
+        q[i] = ok ? SL[i] * __builtin_amdgcn_rcpf(nL[i]) + SR[i] * __builtin_amdgcn_rcpf(nf - nL[i]) : -1.f;
+        qb = fmaxf(qb, q[i]);
+    }
+    const float qmax = wave_max_f(qb);
+    Cand best;
+    cand_invalid(best);
+    best.SP = SP;
+    best.lo = lo;
+    best.scale = scale;
+    if (!(qmax >= 0.f)) return best;
+    const float keep = qmax * kScreenKeep;
+    wave_sync();   // pc[] written by lane 0 is read by every lane below
+    bool have = false;
     u128 bN = 0;
     uint64_t bD = 0, bSL = 0, bSR = 0;
-    int bpos = 0;
+    int bb = 0;
     uint32_t bnL = 0;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        int b = lane * 4 + i;
-        u128 N;
-        uint64_t D;
-        if (b < B - 1 && make_q((int64_t)nL[i], n - (int64_t)nL[i], SL[i], SR[i], N, D)) {
-            if (!bv || q_greater(N, D, bN, bD)) {
-                bv = true; bN = N; bD = D; bpos = b; bnL = nL[i]; bSL = SL[i]; bSR = SR[i];
+        uint64_t m = __ballot(q[i] >= 0.f && q[i] >= keep);
+        while (m) {
+            const int ln = __builtin_ctzll(m);
+            m &= m - 1;
+            const int b = ln * 4 + i;
+            uint32_t nLx = 0;
+            uint64_t SLx = 0, SRx = 0;
+            for (int c = 0; c < C; ++c) {
+                uint32_t part = 0;
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    if (b0 + t <= b && b0 + t < B) part += h(b0 + t, c);
+                const uint32_t lc = wave_sum_u(part);
+                const uint32_t rc = (uint32_t)pc[c] - lc;
+                nLx += lc;
+                SLx += (uint64_t)lc * lc;
+                SRx += (uint64_t)rc * rc;
+            }
+            u128 N;
+            uint64_t D;
+            if (!make_q((int64_t)nLx, n - (int64_t)nLx, SLx, SRx, N, D)) continue;
+            if (!have || q_greater(N, D, bN, bD) || (!q_greater(bN, bD, N, D) && b < bb)) {
+                have = true; bN = N; bD = D; bSL = SLx; bSR = SRx; bb = b; bnL = nLx;
             }
         }
     }
-    int win = wave_best_lane(bv, bN, bD, bpos);
-    Cand c;
-    cand_invalid(c);
-    c.SP = SP;
-    c.lo = lo;
-    c.scale = scale;
-    if (win >= 0) {
-        uint64_t nlo = __shfl((uint64_t)bN, win), nhi = __shfl((uint64_t)(bN >> 64), win);
-        c.N = ((u128)nhi << 64) | nlo;
-        c.D = __shfl(bD, win);
-        c.SL = __shfl(bSL, win);
-        c.SR = __shfl(bSR, win);
-        c.pos = __shfl(bpos, win);
-        c.nL = (int32_t)__shfl(bnL, win);
-        c.nR = (int32_t)(n - c.nL);
-        c.thr = hist_threshold(lo, scale, c.pos);
+    if (have) {
+        best.N = bN;
+        best.D = bD;
+        best.SL = bSL;
+        best.SR = bSR;
+        best.pos = bb;
+        best.nL = (int32_t)bnL;
+        best.nR = (int32_t)(n - (int64_t)bnL);
+        best.thr = hist_threshold(lo, scale, bb);
     }
-    return c;
+    return best;
 }
 
 // a better than b, ties to the lower projection
@@ -303,6 +343,7 @@ struct WaveScratch {
     int32_t lf[16];
     uint32_t ls[16];
     int32_t pc[16];
+    int32_t pcs[16];      // parent counts written by the histogram scan
     float red[2];
     int32_t pad[2];
     Cand best;
@@ -432,7 +473,7 @@ __device__ __forceinline__ void gather_rows(const FindArgs& A, const int32_t* lf
 // ---------------------------------------------------------------------------
 // small nodes: one block per node, wave w takes projections w, w+4, ...
 
-constexpr int kSmallR = kSmallMax / kWave;   // up to 16 samples per lane
+constexpr int kSmallR = kSmallMax / kWave;   // up to 8 samples per lane
 
 template <typename T, class PS, int R>
 __device__ void do_small_r(const FindArgs& A, const PS& P, int v, int64_t s0, int64_t n, char* smem) {
@@ -488,7 +529,7 @@ __device__ void do_small_r(const FindArgs& A, const PS& P, int v, int64_t s0, in
             wave_sync();
             LdsHist h{hist, C};
             write_hist_row(A, proj_global(P, v, p), h, B);
-            c = scan_hist(h, B, C, n, lo, scale);
+            c = scan_hist_fast(h, B, C, n, lo, scale, WS.pcs);
             wave_sync();
         }
         c.proj = p;
@@ -518,7 +559,6 @@ __device__ void do_small(const FindArgs& A, const PS& P, int v, char* smem) {
     if (nr <= 1) do_small_r<T, PS, 1>(A, P, v, s0, n, smem);
     else if (nr <= 2) do_small_r<T, PS, 2>(A, P, v, s0, n, smem);
     else if (nr <= 4) do_small_r<T, PS, 4>(A, P, v, s0, n, smem);
-    else if (nr <= 8) do_small_r<T, PS, 8>(A, P, v, s0, n, smem);
     else do_small_r<T, PS, kSmallR>(A, P, v, s0, n, smem);
 }
 
@@ -569,20 +609,21 @@ __device__ void do_mid_r(const FindArgs& A, const PS& P, int4 D, int p, int64_t 
     if (w == 0) {
         LdsHist4 h{wave_hist(smem, 0, Bm, C), C, Bm * C};
         write_hist_row(A, proj_global(P, v, p), h, B);
-        Cand c = scan_hist(h, B, C, n, lo, scale);
+        Cand c = scan_hist_fast(h, B, C, n, lo, scale, WS.pcs);
         c.proj = p;
         if (lane == 0) ((Cand*)A.ws.slots)[D.y + p] = c;
     }
 }
 
-// mid nodes: one block per (node, projection), R samples per thread
+// mid nodes (kSmallMax < n <= kMidMax): one block per (node, projection), R samples per thread
 template <typename T, class PS>
 __device__ void do_mid(const FindArgs& A, const PS& P, int4 D, int p, char* smem) {
     int64_t s0, n;
     node_range(A, D.x, s0, n);
     if (n > kMidMax) n = kMidMax;   // the plan never queues larger nodes here
     const int nr = (int)((n + kBlock - 1) / kBlock);
-    if (nr <= 8) do_mid_r<T, PS, 8>(A, P, D, p, s0, n, smem);
+    if (nr <= 4) do_mid_r<T, PS, 4>(A, P, D, p, s0, n, smem);
+    else if (nr <= 8) do_mid_r<T, PS, 8>(A, P, D, p, s0, n, smem);
     else if (nr <= 16) do_mid_r<T, PS, 16>(A, P, D, p, s0, n, smem);
     else do_mid_r<T, PS, kMidR>(A, P, D, p, s0, n, smem);
 }
@@ -602,10 +643,13 @@ __device__ __forceinline__ BigDesc big_desc(const FindArgs& A, int d) {
     return BigDesc{a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
 }
 
-constexpr int kBR = 4;   // samples per lane per step of a chunk loop
+constexpr int kBR = 16;   // samples per lane per step of a chunk loop
 
 // Range (pass 1) or class histogram (pass 2) of projection p over chunk ch
 // of a big node, by one wave.  Pass 2 counts into the wave's LDS histogram.
+// Each step covers kWave * kBR samples; the next step's row ids are loaded
+// before this step's columns, and slots past the chunk's end repeat its last
+// sample (valid addresses, masked out of the result).
 template <typename T, class PS, bool kHist>
 __device__ __forceinline__ void big_chunk(const FindArgs& A, const PS& P, const BigDesc& bd, int p,
                                           int ch, WaveScratch& WS, float& lo, float& hi,
@@ -615,34 +659,42 @@ __device__ __forceinline__ void big_chunk(const FindArgs& A, const PS& P, const 
     int64_t s0, n;
     node_range(A, bd.node, s0, n);
     const int64_t c0 = (int64_t)ch * kChunk;
-    const int64_t cn = clamp64(n - c0, 0, kChunk);
-    const int z = proj_stage(P, bd.node, p, A.n_features, WS.lf, WS.ls);
+    const int cn = (int)clamp64(n - c0, 0, kChunk);
+    const int z = __builtin_amdgcn_readfirstlane(proj_stage(P, bd.node, p, A.n_features, WS.lf, WS.ls));
     lo = INFINITY;
     hi = -INFINITY;
-    for (int64_t i0 = 0; i0 < cn; i0 += kWave * kBR) {
-        int row[kBR];
-        bool ok[kBR];
+    if (cn <= 0) return;
+    const int32_t* sidx = A.sample_idx + s0 + c0;
+    int nxt[kBR];
+#pragma unroll
+    for (int r = 0; r < kBR; ++r) {
+        const int i = r * kWave + lane;
+        nxt[r] = sidx[i < cn ? i : cn - 1];
+    }
+    for (int i0 = 0; i0 < cn; i0 += kWave * kBR) {
+        uint32_t off[kBR];
+        int lab[kBR];
+#pragma unroll
+        for (int r = 0; r < kBR; ++r) {
+            const int row = (uint32_t)nxt[r] < (uint32_t)A.n_rows ? nxt[r] : 0;
+            off[r] = (uint32_t)row * (uint32_t)sizeof(T);
+            lab[r] = kHist ? label_of(A, row) : 0;
+        }
+        const int i1 = i0 + kWave * kBR;
+        if (i1 < cn) {
+#pragma unroll
+            for (int r = 0; r < kBR; ++r) {
+                const int i = i1 + r * kWave + lane;
+                nxt[r] = sidx[i < cn ? i : cn - 1];
+            }
+        }
         float v[kBR];
+        gather_rows<T, kBR>(A, WS.lf, WS.ls, z, off, v);
 #pragma unroll
         for (int r = 0; r < kBR; ++r) {
-            const int64_t i = i0 + r * kWave + lane;
-            ok[r] = i < cn;
-            row[r] = ok[r] ? row_of(A, s0 + c0 + i) : 0;
-            v[r] = 0.f;
-        }
-        for (int j = 0; j < z; ++j) {
-            const int f = __builtin_amdgcn_readfirstlane(WS.lf[j]);
-            const uint32_t sg = __builtin_amdgcn_readfirstlane(WS.ls[j]);
-            const T* col = (const T*)A.x + (int64_t)f * A.ld;
-#pragma unroll
-            for (int r = 0; r < kBR; ++r)
-                if (ok[r]) v[r] = __fadd_rn(v[r], signed_term(ldx(col, row[r]), sg));
-        }
-#pragma unroll
-        for (int r = 0; r < kBR; ++r) {
-            if (!ok[r]) continue;
+            if (i0 + r * kWave + lane >= cn) continue;
             if (kHist) {
-                atomicAdd(&hist[bin_index(v[r], hlo, hscale, B) * C + label_of(A, row[r])], 1);
+                atomicAdd(&hist[bin_index(v[r], hlo, hscale, B) * C + lab[r]], 1);
             } else {
                 lo = fminf(lo, v[r]);
                 hi = fmaxf(hi, v[r]);
@@ -884,7 +936,7 @@ __global__ __launch_bounds__(kBlock) void k_bscan(FindArgs A, PS P) {
         const float scale = bin_scale(B, r.x, r.y);
         LdsHist h{hist, C};
         write_hist_row(A, proj_global(P, bd.node, p), h, B);
-        Cand c = scan_hist(h, B, C, n, r.x, scale);
+        Cand c = scan_hist_fast(h, B, C, n, r.x, scale, block_shared(smem).w[w].pcs);
         c.proj = p;
         if (lane == 0) ((Cand*)W.slots)[bd.slot + p] = c;
         wave_sync();

@@ -128,9 +128,12 @@ struct PShared {
 };
 
 // Predicate bits of up to 8192 samples starting at sample position `at`
-// (row r of 256 samples, wave w: bit lane of mask[r][w]).
-template <typename T, class PS>
-__device__ void predicates(const PartArgs& A, const PS& P, int v, int64_t at, int64_t cn, PShared& S) {
+// (row r of 256 samples, wave w: bit lane of mask[r][w]), with R >= the
+// number of 256-sample rows.  Slots past the end repeat the last sample, so
+// the loads of one column are issued together at valid addresses; their
+// predicate bits are cleared by the i < cn test.
+template <typename T, class PS, int R>
+__device__ void predicates_r(const PartArgs& A, const PS& P, int v, int64_t at, int64_t cn, PShared& S) {
     const int tid = threadIdx.x, w = tid >> 6;
     const SplitRec sp = ((const SplitRec*)A.splits)[v];
     const int k = pcount(P, v);
@@ -140,46 +143,57 @@ __device__ void predicates(const PartArgs& A, const PS& P, int v, int64_t at, in
         if (lane_id() == 0) S.z = z;
     }
     __syncthreads();
-    const int z = S.z;
+    const int z = __builtin_amdgcn_readfirstlane(S.z);
     int B = A.bins;
     if (A.node_bins) {
         int b = A.node_bins[v];
         B = b < 2 ? 2 : (b > A.bins ? A.bins : b);
     }
-    const int nr = (int)((cn + kBlock - 1) / kBlock);
-    int idx[kPR];
-    float val[kPR];
+    uint32_t off[R];
 #pragma unroll
-    for (int r = 0; r < kPR; ++r) {
-        idx[r] = 0;
-        val[r] = 0.f;
-        int64_t i = tid + (int64_t)r * kBlock;
-        if (r < nr && i < cn) idx[r] = prow(A, at + i);
+    for (int r = 0; r < R; ++r) {
+        const int64_t i = tid + (int64_t)r * kBlock;
+        const int row = cn > 0 ? prow(A, at + (i < cn ? i : cn - 1)) : 0;
+        off[r] = (uint32_t)row * (uint32_t)sizeof(T);
     }
+    float val[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) val[r] = 0.f;
     for (int j = 0; j < z; ++j) {
         const int f = __builtin_amdgcn_readfirstlane(S.lf[j]);
         const uint32_t sg = __builtin_amdgcn_readfirstlane(S.ls[j]);
         const T* col = (const T*)A.x + (int64_t)f * A.ld;
+        float x[R];
 #pragma unroll
-        for (int r = 0; r < kPR; ++r)
-            if (r < nr) val[r] = __fadd_rn(val[r], signed_term(ldx(col, idx[r]), sg));
+        for (int r = 0; r < R; ++r) x[r] = ldx((const T*)((const char*)col + off[r]), 0);
+#pragma unroll
+        for (int r = 0; r < R; ++r) val[r] = __fadd_rn(val[r], signed_term(x[r], sg));
     }
 #pragma unroll
-    for (int r = 0; r < kPR; ++r) {
-        if (r < nr) {
-            int64_t i = tid + (int64_t)r * kBlock;
-            bool left = true;
-            if (!all_left)
-                left = sp.kind == SOF_SPLIT_HIST ? bin_index(val[r], sp.lo, sp.scale, B) <= sp.bin
-                                                 : val[r] <= sp.threshold;
-            uint64_t m = __ballot(i < cn && left);
-            if (lane_id() == 0) {
-                S.mask[r][w] = m;
-                S.cnt[r][w] = __popcll(m);
-            }
+    for (int r = 0; r < R; ++r) {
+        const int64_t i = tid + (int64_t)r * kBlock;
+        bool left = true;
+        if (!all_left)
+            left = sp.kind == SOF_SPLIT_HIST ? bin_index(val[r], sp.lo, sp.scale, B) <= sp.bin
+                                             : val[r] <= sp.threshold;
+        const uint64_t m = __ballot(i < cn && left);
+        if (lane_id() == 0) {
+            S.mask[r][w] = m;
+            S.cnt[r][w] = __popcll(m);
         }
     }
     __syncthreads();
+}
+
+template <typename T, class PS>
+__device__ void predicates(const PartArgs& A, const PS& P, int v, int64_t at, int64_t cn, PShared& S) {
+    const int nr = (int)((cn + kBlock - 1) / kBlock);
+    if (nr <= 1) predicates_r<T, PS, 1>(A, P, v, at, cn, S);
+    else if (nr <= 2) predicates_r<T, PS, 2>(A, P, v, at, cn, S);
+    else if (nr <= 4) predicates_r<T, PS, 4>(A, P, v, at, cn, S);
+    else if (nr <= 8) predicates_r<T, PS, 8>(A, P, v, at, cn, S);
+    else if (nr <= 16) predicates_r<T, PS, 16>(A, P, v, at, cn, S);
+    else predicates_r<T, PS, kPR>(A, P, v, at, cn, S);
 }
 
 // Exclusive prefix of S.cnt in (row, wave) order; returns the total.

@@ -92,6 +92,86 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t x) {
     return x;
 }
 
+// ---------------------------------------------------------------------------
+// DPP (data-parallel primitives) cross-lane steps of the GFX9 family.  Each
+// reads a neighbouring lane of the same 16-lane row without going through the
+// LDS crossbar.  update_dpp(old, src, ctrl, row_mask, bank_mask, bound_ctrl):
+// lanes whose source is outside the row read 0 when bound_ctrl is set;
+// lanes of rows disabled by row_mask keep `old`.
+
+enum : int {
+    kDppXor1 = 0xB1,          // quad_perm [1,0,3,2]
+    kDppXor2 = 0x4E,          // quad_perm [2,3,0,1]
+    kDppShr1 = 0x111,         // row_shr:1
+    kDppShr2 = 0x112,
+    kDppShr4 = 0x114,
+    kDppShr8 = 0x118,
+    kDppRowMirror = 0x140,    // lane i <- lane 15-i of the row
+    kDppHalfMirror = 0x141,   // lane i <- lane 7-i of the half row
+    kDppBcast15 = 0x142,      // lane 15 of each row -> the next row
+    kDppBcast31 = 0x143,      // lane 31 -> rows 2 and 3
+};
+
+template <int kCtrl>
+__device__ __forceinline__ uint32_t dpp_u(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kCtrl, 0xf, 0xf, true);
+}
+template <int kCtrl>
+__device__ __forceinline__ float dpp_f(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), kCtrl, 0xf, 0xf, true));
+}
+
+// inclusive prefix sum over the 64 lanes (exact for integers; for floats
+// holding integers below 2^24 as well)
+__device__ __forceinline__ uint32_t wave_scan_u(uint32_t x) {
+    x += dpp_u<kDppShr1>(x);
+    x += dpp_u<kDppShr2>(x);
+    x += dpp_u<kDppShr4>(x);
+    x += dpp_u<kDppShr8>(x);
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kDppBcast15, 0xa, 0xf, false);
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kDppBcast31, 0xc, 0xf, false);
+    return x;
+}
+__device__ __forceinline__ float wave_scan_f(float x) {
+    x += dpp_f<kDppShr1>(x);
+    x += dpp_f<kDppShr2>(x);
+    x += dpp_f<kDppShr4>(x);
+    x += dpp_f<kDppShr8>(x);
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), kDppBcast15, 0xa, 0xf, false));
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), kDppBcast31, 0xc, 0xf, false));
+    return x;
+}
+
+// Butterfly over each 16-lane row (every lane ends with its row's result),
+// then the four row results read with readlane: the wave result, uniform.
+__device__ __forceinline__ float wave_min_f(float x) {
+    x = fminf(x, dpp_f<kDppXor1>(x));
+    x = fminf(x, dpp_f<kDppXor2>(x));
+    x = fminf(x, dpp_f<kDppHalfMirror>(x));
+    x = fminf(x, dpp_f<kDppRowMirror>(x));
+    const int b = __float_as_int(x);
+    return fminf(fminf(__int_as_float(__builtin_amdgcn_readlane(b, 0)), __int_as_float(__builtin_amdgcn_readlane(b, 16))),
+                 fminf(__int_as_float(__builtin_amdgcn_readlane(b, 32)), __int_as_float(__builtin_amdgcn_readlane(b, 48))));
+}
+__device__ __forceinline__ float wave_max_f(float x) {
+    x = fmaxf(x, dpp_f<kDppXor1>(x));
+    x = fmaxf(x, dpp_f<kDppXor2>(x));
+    x = fmaxf(x, dpp_f<kDppHalfMirror>(x));
+    x = fmaxf(x, dpp_f<kDppRowMirror>(x));
+    const int b = __float_as_int(x);
+    return fmaxf(fmaxf(__int_as_float(__builtin_amdgcn_readlane(b, 0)), __int_as_float(__builtin_amdgcn_readlane(b, 16))),
+                 fmaxf(__int_as_float(__builtin_amdgcn_readlane(b, 32)), __int_as_float(__builtin_amdgcn_readlane(b, 48))));
+}
+__device__ __forceinline__ uint32_t wave_sum_u(uint32_t x) {
+    x += dpp_u<kDppXor1>(x);
+    x += dpp_u<kDppXor2>(x);
+    x += dpp_u<kDppHalfMirror>(x);
+    x += dpp_u<kDppRowMirror>(x);
+    const int b = (int)x;
+    return (uint32_t)__builtin_amdgcn_readlane(b, 0) + (uint32_t)__builtin_amdgcn_readlane(b, 16) +
+           (uint32_t)__builtin_amdgcn_readlane(b, 32) + (uint32_t)__builtin_amdgcn_readlane(b, 48);
+}
+
 // bits of lanes strictly below / up to and including this lane
 __device__ __forceinline__ uint64_t lanes_le_mask() {
     const int lane = lane_id();

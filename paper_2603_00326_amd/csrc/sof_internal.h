@@ -13,7 +13,7 @@ namespace sof {
 // Size classes of the batched frontier launch.  A node takes the sort path
 // when n < T (T clamped to SOF_SORT_LIMIT + 1), else the histogram path.
 constexpr int kSortWaveMax = 64;     // sort nodes up to here: sorted in registers by one wave
-constexpr int kSmallMax = 1024;      // histogram nodes up to here: one block per node
+constexpr int kSmallMax = 512;       // histogram nodes up to here: one block per node (8 samples per lane)
 constexpr int kMidMax = 8192;        // histogram nodes up to here: one block per (node, projection)
 constexpr int kChunk = 8192;         // larger nodes: (node, projection, sample chunk) items
 constexpr int kSortMax = SOF_SORT_LIMIT;

@@ -12,9 +12,9 @@ from tests.gpu_helpers import assert_splits_match, say
 pytestmark = pytest.mark.gpu
 
 # node sizes around every size-class edge of the batched launch (sort in
-# registers <= 64, small block <= 1024, mid block <= 8192, chunked above) and
+# registers <= 64, small block <= 512, mid block <= 8192, chunked above) and
 # the degenerate sizes 0, 1, 2
-EDGE_SIZES = [0, 1, 2, 3, 5, 17, 63, 64, 65, 100, 255, 256, 257, 511, 1000, 1023, 1024, 1025, 2049,
+EDGE_SIZES = [0, 1, 2, 3, 5, 17, 63, 64, 65, 100, 255, 256, 257, 511, 512, 513, 1000, 1023, 1024, 1025, 2049,
               4097, 8191, 8192, 8193, 12000, 16385, 30001]
 
 
@@ -48,7 +48,7 @@ def check_case(ctx, wl, tag):
 # frontiers mixing every class.
 
 def test_class_histogram_small_and_mid(ctx):
-    wl = W.random_frontier(61, n_rows=20000, d=12, n_classes=3, sizes=[4, 10, 300, 1024, 1025, 1500, 8192],
+    wl = W.random_frontier(61, n_rows=20000, d=12, n_classes=3, sizes=[4, 10, 300, 512, 513, 1024, 1025, 1500, 8192],
                            k=6, z=3, bins=256, sort_threshold=0, layout="b")
     check_case(ctx, wl, "hist small+mid")
 
