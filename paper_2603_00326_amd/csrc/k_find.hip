@@ -12,7 +12,8 @@
 //   k_bmerge   big nodes: range of every projection over its chunks
 //   k_bhist    big nodes: histogram of every (projection, chunk); one wave each
 //   k_bscan    big nodes: chunk histograms summed, boundary scan
-//   k_mid      histogram nodes of 513..8192 samples: one block per (node, projection)
+//   k_mid      histogram nodes of 513..8192 samples: one block per (node, group of 4
+//              projections)
 //   k_small    histogram nodes up to 512 samples and sort nodes up to 64:
 //              one block per node, one wave per projection
 //   k_sortblk  sort nodes of 65..8192 samples: bitonic sort in LDS
@@ -351,11 +352,17 @@ struct WaveScratch {
     int32_t sl[kWave];    // sorted labels
 };
 
+constexpr int kMidGroup = kWavesPerBlock;   // projections of one mid-node item
+
 struct BlockShared {
     int item;
     int pad[3];
     float lo[kWavesPerBlock];
     float hi[kWavesPerBlock];
+    float glo[kMidGroup][kWavesPerBlock];   // mid items: range of projection j seen by wave w
+    float ghi[kMidGroup][kWavesPerBlock];
+    int32_t gz[kMidGroup];                  // mid items: nonzeros of projection j
+    int32_t gpad[4 - kMidGroup % 4];
     WaveScratch w[kWavesPerBlock];
 };
 
@@ -567,15 +574,30 @@ __device__ void do_small(const FindArgs& A, const PS& P, int v, char* smem) {
 
 constexpr int kMidR = kMidMax / kBlock;   // up to 32 samples per thread
 
+// One mid-node item: projections g*kMidGroup .. of node D.x, by one block.
+// The node's row ids and labels are loaded once; wave j stages projection j's
+// nonzeros; then for each projection all threads gather its values, the block
+// reduces its range (one barrier) and counts it into that projection's own LDS
+// histogram; finally wave j scans histogram j, so the group's scans run in
+// parallel.  Range slots glo/ghi are indexed by projection, so no slot is
+// rewritten while another wave may still read it.
 template <typename T, class PS, int R>
-__device__ void do_mid_r(const FindArgs& A, const PS& P, int4 D, int p, int64_t s0, int64_t n, char* smem) {
+__device__ void do_mid_r(const FindArgs& A, const PS& P, int4 D, int g, int64_t s0, int64_t n, char* smem) {
     BlockShared& S = block_shared(smem);
     const int tid = threadIdx.x, w = tid >> 6, lane = lane_id();
     const int C = A.n_classes, Bm = A.bins;
     const int v = D.x;
     const int B = node_bins(A, v);
-    WaveScratch& WS = S.w[w];
-
+    const int p0 = g * kMidGroup;
+    const int np = D.w - p0 < kMidGroup ? D.w - p0 : kMidGroup;
+    if (w < np) {
+        const int z = proj_stage(P, v, p0 + w, A.n_features, S.w[w].lf, S.w[w].ls);
+        if (lane == 0) S.gz[w] = z;
+    }
+    for (int j = 0; j < np; ++j) {
+        int32_t* hist = wave_hist(smem, j, Bm, C);
+        for (int e = tid; e < B * C; e += kBlock) hist[e] = 0;
+    }
     uint32_t off[R];
     uint32_t labp[(R + 7) / 8];
 #pragma unroll
@@ -587,45 +609,55 @@ __device__ void do_mid_r(const FindArgs& A, const PS& P, int4 D, int p, int64_t 
         off[r] = (uint32_t)row * (uint32_t)sizeof(T);
         labp[r >> 3] |= (uint32_t)label_of(A, row) << (4 * (r & 7));
     }
-    const int z = __builtin_amdgcn_readfirstlane(proj_stage(P, v, p, A.n_features, WS.lf, WS.ls));
-    float val[R];
-    gather_rows<T, R>(A, WS.lf, WS.ls, z, off, val);
-    float lo = INFINITY, hi = -INFINITY;
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-        if (tid + (int64_t)r * kBlock < n) { lo = fminf(lo, val[r]); hi = fmaxf(hi, val[r]); }
-    block_minmax(S, lo, hi);
-    const float scale = bin_scale(B, lo, hi);
-    int32_t* hist = wave_hist(smem, w, Bm, C);
-    for (int e = lane; e < B * C; e += kWave) hist[e] = 0;
-    wave_sync();
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-        if (tid + (int64_t)r * kBlock < n) {
-            const int y = (int)((labp[r >> 3] >> (4 * (r & 7))) & 15u);
-            atomicAdd(&hist[bin_index(val[r], lo, scale, B) * C + y], 1);
-        }
     __syncthreads();
-    if (w == 0) {
-        LdsHist4 h{wave_hist(smem, 0, Bm, C), C, Bm * C};
-        write_hist_row(A, proj_global(P, v, p), h, B);
-        Cand c = scan_hist_fast(h, B, C, n, lo, scale, WS.pcs);
-        c.proj = p;
-        if (lane == 0) ((Cand*)A.ws.slots)[D.y + p] = c;
+    for (int j = 0; j < np; ++j) {
+        const int z = __builtin_amdgcn_readfirstlane(S.gz[j]);
+        float val[R];
+        gather_rows<T, R>(A, S.w[j].lf, S.w[j].ls, z, off, val);
+        float lo = INFINITY, hi = -INFINITY;
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (tid + (int64_t)r * kBlock < n) { lo = fminf(lo, val[r]); hi = fmaxf(hi, val[r]); }
+        lo = wave_min_f(lo);
+        hi = wave_max_f(hi);
+        if (lane == 0) { S.glo[j][w] = lo; S.ghi[j][w] = hi; }
+        __syncthreads();
+        lo = fminf(fminf(S.glo[j][0], S.glo[j][1]), fminf(S.glo[j][2], S.glo[j][3]));
+        hi = fmaxf(fmaxf(S.ghi[j][0], S.ghi[j][1]), fmaxf(S.ghi[j][2], S.ghi[j][3]));
+        const float scale = bin_scale(B, lo, hi);
+        int32_t* hist = wave_hist(smem, j, Bm, C);
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (tid + (int64_t)r * kBlock < n) {
+                const int y = (int)((labp[r >> 3] >> (4 * (r & 7))) & 15u);
+                atomicAdd(&hist[bin_index(val[r], lo, scale, B) * C + y], 1);
+            }
+    }
+    __syncthreads();
+    if (w < np) {
+        const float lo = fminf(fminf(S.glo[w][0], S.glo[w][1]), fminf(S.glo[w][2], S.glo[w][3]));
+        const float hi = fmaxf(fmaxf(S.ghi[w][0], S.ghi[w][1]), fmaxf(S.ghi[w][2], S.ghi[w][3]));
+        const float scale = bin_scale(B, lo, hi);
+        LdsHist h{wave_hist(smem, w, Bm, C), C};
+        write_hist_row(A, proj_global(P, v, p0 + w), h, B);
+        Cand c = scan_hist_fast(h, B, C, n, lo, scale, S.w[w].pcs);
+        c.proj = p0 + w;
+        if (lane == 0) ((Cand*)A.ws.slots)[D.y + p0 + w] = c;
     }
 }
 
-// mid nodes (kSmallMax < n <= kMidMax): one block per (node, projection), R samples per thread
+// mid nodes (kSmallMax < n <= kMidMax): one block per (node, group of
+// kMidGroup projections), R samples per thread
 template <typename T, class PS>
-__device__ void do_mid(const FindArgs& A, const PS& P, int4 D, int p, char* smem) {
+__device__ void do_mid(const FindArgs& A, const PS& P, int4 D, int g, char* smem) {
     int64_t s0, n;
     node_range(A, D.x, s0, n);
     if (n > kMidMax) n = kMidMax;   // the plan never queues larger nodes here
     const int nr = (int)((n + kBlock - 1) / kBlock);
-    if (nr <= 4) do_mid_r<T, PS, 4>(A, P, D, p, s0, n, smem);
-    else if (nr <= 8) do_mid_r<T, PS, 8>(A, P, D, p, s0, n, smem);
-    else if (nr <= 16) do_mid_r<T, PS, 16>(A, P, D, p, s0, n, smem);
-    else do_mid_r<T, PS, kMidR>(A, P, D, p, s0, n, smem);
+    if (nr <= 4) do_mid_r<T, PS, 4>(A, P, D, g, s0, n, smem);
+    else if (nr <= 8) do_mid_r<T, PS, 8>(A, P, D, g, s0, n, smem);
+    else if (nr <= 16) do_mid_r<T, PS, 16>(A, P, D, g, s0, n, smem);
+    else do_mid_r<T, PS, kMidR>(A, P, D, g, s0, n, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -736,7 +768,8 @@ __global__ __launch_bounds__(kBlock) void k_plan(FindArgs A, PS P) {
         const bool slot_node = cat == CAT_MID || cat == CAT_SB || cat == CAT_BIG;
         const int o_small = wave_alloc(&W.hdr[H_SMALL], cat == CAT_SMALL);
         const int o_dmid = wave_alloc(&W.hdr[H_DMID], cat == CAT_MID);
-        const int o_imid = wave_alloc(&W.hdr[H_IMID], cat == CAT_MID ? k : 0);
+        const int gmid = (k + kMidGroup - 1) / kMidGroup;
+        const int o_imid = wave_alloc(&W.hdr[H_IMID], cat == CAT_MID ? gmid : 0);
         const int o_dsb = wave_alloc(&W.hdr[H_DSB], cat == CAT_SB);
         const int o_isb = wave_alloc(&W.hdr[H_ISB], cat == CAT_SB ? k : 0);
         const int o_dbig = wave_alloc(&W.hdr[H_DBIG], cat == CAT_BIG);
@@ -747,7 +780,7 @@ __global__ __launch_bounds__(kBlock) void k_plan(FindArgs A, PS P) {
         bool over = false;
         if (slot_node && o_slot + (int64_t)k > W.cap_slots) over = true;
         if (cat == CAT_SMALL && o_small >= W.cap_small) over = true;
-        if (cat == CAT_MID && (o_dmid >= W.cap_dmid || o_imid + (int64_t)k > W.cap_imid)) over = true;
+        if (cat == CAT_MID && (o_dmid >= W.cap_dmid || o_imid + (int64_t)gmid > W.cap_imid)) over = true;
         if (cat == CAT_SB && (o_dsb >= W.cap_dsb || o_isb + (int64_t)k > W.cap_isb)) over = true;
         if (cat == CAT_BIG && (o_dbig >= W.cap_dbig || o_ia + (int64_t)k * nch > W.cap_ibiga ||
                                o_ic + (int64_t)k > W.cap_ibigc || o_bslot + (int64_t)k > W.cap_bigslots))
@@ -790,8 +823,9 @@ __global__ __launch_bounds__(kBlock) void k_expand(FindArgs A) {
     for (int d = blockIdx.x; d < nmid + nsb + nbig; d += gridDim.x) {
         if (d < nmid) {
             int4 D = W.desc_mid[d];
-            for (int p = tid; p < D.w; p += kBlock)
-                if (D.z + (int64_t)p < W.cap_imid) W.items_mid[D.z + p] = make_int2(d, p);
+            const int ng = (D.w + kMidGroup - 1) / kMidGroup;
+            for (int g = tid; g < ng; g += kBlock)
+                if (D.z + (int64_t)g < W.cap_imid) W.items_mid[D.z + g] = make_int2(d, g);
         } else if (d < nmid + nsb) {
             int e = d - nmid;
             int4 D = W.desc_sb[e];
@@ -956,7 +990,7 @@ __global__ __launch_bounds__(kBlock) void k_mid(FindArgs A, PS P) {
         int2 e = W.items_mid[it];
         if (e.x < 0 || e.x >= nmd) continue;
         int4 D = W.desc_mid[e.x];
-        if (e.y < D.w) do_mid<T>(A, P, D, e.y, smem);
+        if (e.y >= 0 && e.y * kMidGroup < D.w) do_mid<T>(A, P, D, e.y, smem);
     }
 }
 
