@@ -345,6 +345,9 @@ struct WaveScratch {
     uint32_t ls[16];
     int32_t pc[16];
     int32_t pcs[16];      // parent counts written by the histogram scan
+    int32_t bz[8];        // small nodes: nonzeros of the staged batch of projections
+    int32_t blf[8 * 16];  // ... their feature ids (16 per projection)
+    uint32_t bls[8 * 16]; // ... and sign masks
     float red[2];
     int32_t pad[2];
     Cand best;
@@ -460,21 +463,84 @@ __device__ __forceinline__ float ldx_off(const T* col, uint32_t off) {
     return ldx((const T*)((const char*)col + off), 0);
 }
 
-template <typename T, int R>
+// v[r] = sum over the projection's z nonzeros (lf/ls, CSR order) of
+// +/- x[f][row r].  FB columns are requested per round trip; when fewer than
+// FB remain, the spare requests read the first column of the batch (a valid
+// address) and are not added.  Adds stay in CSR order.
+template <typename T, int R, int FB = 1>
 __device__ __forceinline__ void gather_rows(const FindArgs& A, const int32_t* lf, const uint32_t* ls, int z,
                                             const uint32_t (&off)[R], float (&val)[R]) {
 #pragma unroll
     for (int r = 0; r < R; ++r) val[r] = 0.f;
-    for (int j = 0; j < z; ++j) {
-        const int f = __builtin_amdgcn_readfirstlane(lf[j]);
-        const uint32_t sg = __builtin_amdgcn_readfirstlane(ls[j]);
-        const T* col = (const T*)A.x + (int64_t)f * A.ld;
-        float x[R];
+    for (int j = 0; j < z; j += FB) {
+        const int nf = z - j < FB ? z - j : FB;
+        float x[FB][R];
+        uint32_t sg[FB];
 #pragma unroll
-        for (int r = 0; r < R; ++r) x[r] = ldx_off(col, off[r]);
+        for (int t = 0; t < FB; ++t) {
+            const int jt = t < nf ? j + t : j;
+            const int f = __builtin_amdgcn_readfirstlane(lf[jt]);
+            sg[t] = __builtin_amdgcn_readfirstlane(ls[jt]);
+            const T* col = (const T*)A.x + (int64_t)f * A.ld;
 #pragma unroll
-        for (int r = 0; r < R; ++r) val[r] = __fadd_rn(val[r], signed_term(x[r], sg));
+            for (int r = 0; r < R; ++r) x[t][r] = ldx_off(col, off[r]);
+        }
+#pragma unroll
+        for (int t = 0; t < FB; ++t) {
+            if (t >= nf) break;
+#pragma unroll
+            for (int r = 0; r < R; ++r) val[r] = __fadd_rn(val[r], signed_term(x[t][r], sg[t]));
+        }
     }
+}
+
+// ---------------------------------------------------------------------------
+// Small nodes stage the nonzeros of a batch of kSmallBatch projections
+// (p0, p0 + pstep, ...; those >= k get none) into the wave's scratch with one
+// round of loads: lane g reads projection g's CSR range, then every lane
+// fetches two of the batch's 128 (projection, nonzero) slots.  Every index is
+// clamped into its array.
+
+constexpr int kSmallBatch = 8;
+
+__device__ __forceinline__ void stage_batch(const ProjCSR& P, int v, int p0, int pstep, int k, int d,
+                                            WaveScratch& WS) {
+    const int lane = lane_id();
+    int64_t a = 0;
+    int cnt = 0;
+    if (lane < kSmallBatch) {
+        const int p = p0 + pstep * lane;
+        if (p < k) {
+            const int q = proj_global(P, v, p);
+            a = clamp64(P.nz_offsets[q], 0, P.n_nz);
+            const int64_t b = clamp64(P.nz_offsets[q + 1], a, P.n_nz);
+            cnt = (int)(b - a > SOF_MAX_NNZ ? SOF_MAX_NNZ : b - a);
+        }
+        WS.bz[lane] = cnt;
+    }
+#pragma unroll
+    for (int i = 0; i < kSmallBatch * SOF_MAX_NNZ / kWave; ++i) {
+        const int e = lane + kWave * i;
+        const int g = e / SOF_MAX_NNZ, t = e % SOF_MAX_NNZ;
+        const int64_t ag = __shfl(a, g);
+        const int cg = __shfl(cnt, g);
+        if (t < cg) {
+            const uint32_t f = (uint32_t)P.nz_feature[ag + t];
+            WS.blf[e] = f < (uint32_t)d ? (int)f : 0;
+            WS.bls[e] = P.nz_weight[ag + t] < 0 ? 0x80000000u : 0u;
+        }
+    }
+    wave_sync();
+}
+__device__ __forceinline__ void stage_batch(const ProjHash& P, int v, int p0, int pstep, int k, int d,
+                                            WaveScratch& WS) {
+    for (int g = 0; g < kSmallBatch; ++g) {
+        const int p = p0 + pstep * g;
+        int z = 0;
+        if (p < k) z = proj_stage(P, v, p, d, WS.blf + SOF_MAX_NNZ * g, WS.bls + SOF_MAX_NNZ * g);
+        if (lane_id() == 0) WS.bz[g] = z;
+    }
+    wave_sync();
 }
 
 // ---------------------------------------------------------------------------
@@ -512,10 +578,14 @@ __device__ void do_small_r(const FindArgs& A, const PS& P, int v, int64_t s0, in
 
     Cand best;
     cand_invalid(best);
-    for (int p = w; p < k; p += kWavesPerBlock) {
-        const int z = __builtin_amdgcn_readfirstlane(proj_stage(P, v, p, A.n_features, WS.lf, WS.ls));
+    for (int pb = w; pb < k; pb += kWavesPerBlock * kSmallBatch) {
+      stage_batch(P, v, pb, kWavesPerBlock, k, A.n_features, WS);
+      for (int gi = 0; gi < kSmallBatch; ++gi) {
+        const int p = pb + kWavesPerBlock * gi;
+        if (p >= k) break;
+        const int z = __builtin_amdgcn_readfirstlane(WS.bz[gi]);
         float val[R];
-        gather_rows<T, R>(A, WS.lf, WS.ls, z, off, val);
+        gather_rows<T, R, 4>(A, WS.blf + SOF_MAX_NNZ * gi, WS.bls + SOF_MAX_NNZ * gi, z, off, val);
         float lo = INFINITY, hi = -INFINITY;
 #pragma unroll
         for (int r = 0; r < R; ++r)
@@ -541,6 +611,7 @@ __device__ void do_small_r(const FindArgs& A, const PS& P, int v, int64_t s0, in
         }
         c.proj = p;
         if (cand_better(c, best)) best = c;
+      }
     }
     if (lane == 0) WS.best = best;
     __syncthreads();
@@ -613,7 +684,7 @@ __device__ void do_mid_r(const FindArgs& A, const PS& P, int4 D, int g, int64_t 
     for (int j = 0; j < np; ++j) {
         const int z = __builtin_amdgcn_readfirstlane(S.gz[j]);
         float val[R];
-        gather_rows<T, R>(A, S.w[j].lf, S.w[j].ls, z, off, val);
+        gather_rows<T, R, (R <= 8 ? 4 : (R <= 16 ? 2 : 1))>(A, S.w[j].lf, S.w[j].ls, z, off, val);
         float lo = INFINITY, hi = -INFINITY;
 #pragma unroll
         for (int r = 0; r < R; ++r)
