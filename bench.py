@@ -32,7 +32,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 SORT_LIMIT = 8192
-WAVE_SORT_MAX, SMALL_MAX, MID_MAX = 64, 512, 8192
+WAVE_SORT_MAX, SMALL_MAX, MID_SPLIT, MID_MAX = 64, 512, 4096, 8192
 
 WORKLOADS = {
     "c3a": "batched frontier, 4096 log-normal nodes (median 300, 2..100000, ~4.0M samples) over a "
@@ -72,13 +72,14 @@ def make_workload(name: str):
 
 def node_classes(wl, T: int):
     """Size class of every node as the library classifies it: 'none' (no
-    projections), 'small', 'mid', 'sort', 'big'."""
+    projections), 'small', 'mid', 'mid2', 'sort', 'big'."""
     n = np.diff(wl.node_offsets.astype(np.int64))
     k = np.diff(wl.proj_offsets.astype(np.int64))
     Te = min(int(T), SORT_LIMIT + 1)
     sortp = n < Te
     cls = np.full(len(n), "big", dtype=object)
-    cls[~sortp & (n <= MID_MAX)] = "mid"
+    cls[~sortp & (n <= MID_MAX)] = "mid2"
+    cls[~sortp & (n <= MID_SPLIT)] = "mid"
     cls[~sortp & (n <= SMALL_MAX)] = "small"
     cls[sortp] = "sort"
     cls[sortp & (n <= WAVE_SORT_MAX)] = "small"
@@ -96,7 +97,7 @@ def stage_bytes(wl, T: int):
     cols = n * zsum * sx          # sum over the node's projections of n * z_p * s_x
     idx_lab = n * (4 + 4)
     out = {}
-    for name, c in (("small", "small"), ("mid", "mid"), ("sort", "sort")):
+    for name, c in (("small", "small"), ("mid", "mid"), ("mid2", "mid2"), ("sort", "sort")):
         m = cls == c
         out[name] = float((idx_lab[m] + cols[m]).sum())
     m = cls == "big"
@@ -335,10 +336,10 @@ def main():
     splits = S.splits_to_numpy(out)[:wl.n_nodes]
     sb = stage_bytes(wl, T)
     per = {k: v / max(calls, 1) for k, v in stage_ms.items()}
-    data_stages = ("big_range", "big_hist", "mid", "small", "sort")
+    data_stages = ("big_range", "big_hist", "mid", "mid2", "small", "sort")
     dom = max(data_stages, key=lambda s: per[s])
-    kernel_name = {"big_range": "k_brange", "big_hist": "k_bhist", "mid": "k_mid", "small": "k_small",
-                   "sort": "k_sortblk"}[dom]
+    kernel_name = {"big_range": "k_brange", "big_hist": "k_bhist", "mid": "k_mid", "mid2": "k_mid_large",
+                   "small": "k_small", "sort": "k_sortblk"}[dom]
     achieved = sb[dom] / (per[dom] * 1e-3) / 1e9 if per[dom] > 0 else 0.0
     roof = {"bound": "hbm", "kernel": kernel_name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),

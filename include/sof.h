@@ -263,7 +263,8 @@ enum {
     SOF_STAGE_BIG_MERGE,  /* ... range of each projection over the node */
     SOF_STAGE_BIG_HIST,   /* ... class histogram of each (projection, chunk) */
     SOF_STAGE_BIG_SCAN,   /* ... summed histograms, boundary scan */
-    SOF_STAGE_MID,        /* histogram nodes of 513..8192 samples */
+    SOF_STAGE_MID,        /* histogram nodes of 513..4096 samples */
+    SOF_STAGE_MID2,       /* histogram nodes of 4097..8192 samples */
     SOF_STAGE_SMALL,      /* histogram nodes up to 512, sort nodes up to 64 */
     SOF_STAGE_SORT,       /* sort nodes of 65..8192 samples */
     SOF_STAGE_REDUCE,     /* best projection per node */

@@ -13,7 +13,7 @@
 //   k_bhist    big nodes: histogram of every (projection, chunk); one wave each
 //   k_bscan    big nodes: chunk histograms summed, boundary scan
 //   k_mid      histogram nodes of 513..8192 samples: one block per (node, group of 4
-//              projections)
+//              projections); one instance up to 4096 samples, one above
 //   k_small    histogram nodes up to 512 samples and sort nodes up to 64:
 //              one block per node, one wave per projection
 //   k_sortblk  sort nodes of 65..8192 samples: bitonic sort in LDS
@@ -26,7 +26,7 @@
 
 namespace sof {
 
-enum { CAT_NONE = 0, CAT_NOSPLIT, CAT_SMALL, CAT_MID, CAT_SB, CAT_BIG };
+enum { CAT_NONE = 0, CAT_NOSPLIT, CAT_SMALL, CAT_MID, CAT_MID2, CAT_SB, CAT_BIG };
 
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -199,24 +199,29 @@ __device__ __forceinline__ void write_zero_row(const FindArgs& A, int q) {
     for (int e = lane_id(); e < n; e += kWave) row[e] = 0;
 }
 
-struct LdsHist {
+// Histogram accessors: h(b, c) is the count of class c in bin b; load4(b0, c,
+// B) gives bins b0..b0+3 of class c (0 for bins >= B).
+struct LdsHist {      // bin-major h[b * C + c] (big-node chunk histograms)
     const int32_t* h;
     int C;
     __device__ uint32_t operator()(int b, int c) const { return (uint32_t)h[b * C + c]; }
-};
-struct LdsHist4 {   // sum of the four wave-private copies
-    const int32_t* h;
-    int C, stride;
-    __device__ uint32_t operator()(int b, int c) const {
-        int e = b * C + c;
-        return (uint32_t)(h[e] + h[e + stride] + h[e + 2 * stride] + h[e + 3 * stride]);
+    __device__ uint4 load4(int b0, int c, int B) const {
+        uint4 v;
+        v.x = b0 < B ? (uint32_t)h[b0 * C + c] : 0u;
+        v.y = b0 + 1 < B ? (uint32_t)h[(b0 + 1) * C + c] : 0u;
+        v.z = b0 + 2 < B ? (uint32_t)h[(b0 + 2) * C + c] : 0u;
+        v.w = b0 + 3 < B ? (uint32_t)h[(b0 + 3) * C + c] : 0u;
+        return v;
     }
 };
-struct GlobalHist {
+struct LdsHistCM {    // class-major h[c * Bs + b], Bs a multiple of 4, bins B..Bs-1 zero
     const int32_t* h;
-    int C;
-    __device__ uint32_t operator()(int b, int c) const { return (uint32_t)h[b * C + c]; }
+    int Bs;
+    __device__ uint32_t operator()(int b, int c) const { return (uint32_t)h[c * Bs + b]; }
+    __device__ uint4 load4(int b0, int c, int) const { return *(const uint4*)(h + c * Bs + b0); }
 };
+
+__host__ __device__ constexpr int bins_stride(int bins) { return (bins + 3) & ~3; }
 
 // ---------------------------------------------------------------------------
 // boundary scans (one wave)
@@ -245,9 +250,11 @@ __device__ Cand scan_hist_fast(const H& h, int B, int C, int64_t n, float lo, fl
     uint32_t filled = 0;
     uint64_t SP = 0;
     for (int c = 0; c < C; ++c) {
-        uint32_t hv[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) hv[i] = b0 + i < B ? h(b0 + i, c) : 0u;
+        uint32_t hv[4] = {0u, 0u, 0u, 0u};
+        if (b0 < B) {
+            const uint4 q4 = h.load4(b0, c, B);
+            hv[0] = q4.x; hv[1] = q4.y; hv[2] = q4.z; hv[3] = q4.w;
+        }
         const float s0 = (float)hv[0], s1 = s0 + (float)hv[1], s2 = s1 + (float)hv[2], s3 = s2 + (float)hv[3];
         const float incl = wave_scan_f(s3);
         const float excl = incl - s3;
@@ -370,12 +377,12 @@ struct BlockShared {
 };
 
 size_t find_smem_main(int bins, int classes) {
-    return sizeof(BlockShared) + (size_t)kWavesPerBlock * bins * classes * sizeof(int32_t);
+    return sizeof(BlockShared) + (size_t)kWavesPerBlock * bins_stride(bins) * classes * sizeof(int32_t);
 }
 
 __device__ __forceinline__ BlockShared& block_shared(char* smem) { return *(BlockShared*)smem; }
 __device__ __forceinline__ int32_t* wave_hist(char* smem, int w, int bins, int C) {
-    return (int32_t*)(smem + sizeof(BlockShared)) + (size_t)w * bins * C;
+    return (int32_t*)(smem + sizeof(BlockShared)) + (size_t)w * bins_stride(bins) * C;
 }
 
 // block-wide min/max of per-thread values (all threads call)
@@ -460,6 +467,10 @@ __device__ Cand scan_sort_small(WaveScratch& WS, float val, int lab, int64_t n, 
 
 template <typename T>
 __device__ __forceinline__ float ldx_off(const T* col, uint32_t off) {
+    // keep the offset a 32-bit register at each load: otherwise the compiler
+    // hoists its widening out of the column loop and holds a 64-bit copy of
+    // every slot's offset across the whole projection
+    asm volatile("" : "+v"(off));
     return ldx((const T*)((const char*)col + off), 0);
 }
 
@@ -598,13 +609,14 @@ __device__ void do_small_r(const FindArgs& A, const PS& P, int v, int64_t s0, in
             write_zero_row(A, proj_global(P, v, p));
         } else {
             const float scale = bin_scale(B, lo, hi);
-            for (int e = lane; e < B * C; e += kWave) hist[e] = 0;
+            const int Bs = bins_stride(Bm);
+            for (int e = lane * 4; e < C * Bs; e += kWave * 4) *(int4*)(hist + e) = make_int4(0, 0, 0, 0);
             wave_sync();
 #pragma unroll
             for (int r = 0; r < R; ++r)
-                if (lab[r] >= 0) atomicAdd(&hist[bin_index(val[r], lo, scale, B) * C + lab[r]], 1);
+                if (lab[r] >= 0) atomicAdd(&hist[lab[r] * Bs + bin_index(val[r], lo, scale, B)], 1);
             wave_sync();
-            LdsHist h{hist, C};
+            LdsHistCM h{hist, Bs};
             write_hist_row(A, proj_global(P, v, p), h, B);
             c = scan_hist_fast(h, B, C, n, lo, scale, WS.pcs);
             wave_sync();
@@ -665,9 +677,10 @@ __device__ void do_mid_r(const FindArgs& A, const PS& P, int4 D, int g, int64_t 
         const int z = proj_stage(P, v, p0 + w, A.n_features, S.w[w].lf, S.w[w].ls);
         if (lane == 0) S.gz[w] = z;
     }
+    const int Bs = bins_stride(Bm);
     for (int j = 0; j < np; ++j) {
         int32_t* hist = wave_hist(smem, j, Bm, C);
-        for (int e = tid; e < B * C; e += kBlock) hist[e] = 0;
+        for (int e = tid * 4; e < C * Bs; e += kBlock * 4) *(int4*)(hist + e) = make_int4(0, 0, 0, 0);
     }
     uint32_t off[R];
     uint32_t labp[(R + 7) / 8];
@@ -701,7 +714,7 @@ __device__ void do_mid_r(const FindArgs& A, const PS& P, int4 D, int g, int64_t 
         for (int r = 0; r < R; ++r)
             if (tid + (int64_t)r * kBlock < n) {
                 const int y = (int)((labp[r >> 3] >> (4 * (r & 7))) & 15u);
-                atomicAdd(&hist[bin_index(val[r], lo, scale, B) * C + y], 1);
+                atomicAdd(&hist[y * Bs + bin_index(val[r], lo, scale, B)], 1);
             }
     }
     __syncthreads();
@@ -709,26 +722,12 @@ __device__ void do_mid_r(const FindArgs& A, const PS& P, int4 D, int g, int64_t 
         const float lo = fminf(fminf(S.glo[w][0], S.glo[w][1]), fminf(S.glo[w][2], S.glo[w][3]));
         const float hi = fmaxf(fmaxf(S.ghi[w][0], S.ghi[w][1]), fmaxf(S.ghi[w][2], S.ghi[w][3]));
         const float scale = bin_scale(B, lo, hi);
-        LdsHist h{wave_hist(smem, w, Bm, C), C};
+        LdsHistCM h{wave_hist(smem, w, Bm, C), Bs};
         write_hist_row(A, proj_global(P, v, p0 + w), h, B);
         Cand c = scan_hist_fast(h, B, C, n, lo, scale, S.w[w].pcs);
         c.proj = p0 + w;
         if (lane == 0) ((Cand*)A.ws.slots)[D.y + p0 + w] = c;
     }
-}
-
-// mid nodes (kSmallMax < n <= kMidMax): one block per (node, group of
-// kMidGroup projections), R samples per thread
-template <typename T, class PS>
-__device__ void do_mid(const FindArgs& A, const PS& P, int4 D, int g, char* smem) {
-    int64_t s0, n;
-    node_range(A, D.x, s0, n);
-    if (n > kMidMax) n = kMidMax;   // the plan never queues larger nodes here
-    const int nr = (int)((n + kBlock - 1) / kBlock);
-    if (nr <= 4) do_mid_r<T, PS, 4>(A, P, D, g, s0, n, smem);
-    else if (nr <= 8) do_mid_r<T, PS, 8>(A, P, D, g, s0, n, smem);
-    else if (nr <= 16) do_mid_r<T, PS, 16>(A, P, D, g, s0, n, smem);
-    else do_mid_r<T, PS, kMidR>(A, P, D, g, s0, n, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -832,15 +831,18 @@ __global__ __launch_bounds__(kBlock) void k_plan(FindArgs A, PS P) {
             if (k == 0) cat = CAT_NOSPLIT;
             else if (sortp ? n <= kSortWaveMax : n <= kSmallMax) cat = CAT_SMALL;
             else if (sortp) cat = CAT_SB;
-            else if (n <= kMidMax) cat = CAT_MID;
+            else if (n <= kMidSplit) cat = CAT_MID;
+            else if (n <= kMidMax) cat = CAT_MID2;
             else cat = CAT_BIG;
         }
         const int nch = (int)((n + kChunk - 1) / kChunk);
-        const bool slot_node = cat == CAT_MID || cat == CAT_SB || cat == CAT_BIG;
+        const bool slot_node = cat == CAT_MID || cat == CAT_MID2 || cat == CAT_SB || cat == CAT_BIG;
         const int o_small = wave_alloc(&W.hdr[H_SMALL], cat == CAT_SMALL);
         const int o_dmid = wave_alloc(&W.hdr[H_DMID], cat == CAT_MID);
         const int gmid = (k + kMidGroup - 1) / kMidGroup;
         const int o_imid = wave_alloc(&W.hdr[H_IMID], cat == CAT_MID ? gmid : 0);
+        const int o_dmid2 = wave_alloc(&W.hdr[H_DMID2], cat == CAT_MID2);
+        const int o_imid2 = wave_alloc(&W.hdr[H_IMID2], cat == CAT_MID2 ? gmid : 0);
         const int o_dsb = wave_alloc(&W.hdr[H_DSB], cat == CAT_SB);
         const int o_isb = wave_alloc(&W.hdr[H_ISB], cat == CAT_SB ? k : 0);
         const int o_dbig = wave_alloc(&W.hdr[H_DBIG], cat == CAT_BIG);
@@ -852,6 +854,7 @@ __global__ __launch_bounds__(kBlock) void k_plan(FindArgs A, PS P) {
         if (slot_node && o_slot + (int64_t)k > W.cap_slots) over = true;
         if (cat == CAT_SMALL && o_small >= W.cap_small) over = true;
         if (cat == CAT_MID && (o_dmid >= W.cap_dmid || o_imid + (int64_t)gmid > W.cap_imid)) over = true;
+        if (cat == CAT_MID2 && (o_dmid2 >= W.cap_dmid2 || o_imid2 + (int64_t)gmid > W.cap_imid2)) over = true;
         if (cat == CAT_SB && (o_dsb >= W.cap_dsb || o_isb + (int64_t)k > W.cap_isb)) over = true;
         if (cat == CAT_BIG && (o_dbig >= W.cap_dbig || o_ia + (int64_t)k * nch > W.cap_ibiga ||
                                o_ic + (int64_t)k > W.cap_ibigc || o_bslot + (int64_t)k > W.cap_bigslots))
@@ -863,6 +866,7 @@ __global__ __launch_bounds__(kBlock) void k_plan(FindArgs A, PS P) {
             atomicOr(&W.hdr[H_ERR], 1);
             write_nosplit(A, v, sortp ? 1 : 0, n);
             if (cat == CAT_MID && o_dmid < W.cap_dmid) W.desc_mid[o_dmid] = make_int4(v, 0, 0, 0);
+            if (cat == CAT_MID2 && o_dmid2 < W.cap_dmid2) W.desc_mid2[o_dmid2] = make_int4(v, 0, 0, 0);
             if (cat == CAT_SB && o_dsb < W.cap_dsb) W.desc_sb[o_dsb] = make_int4(v, 0, 0, 0);
             if (cat == CAT_BIG && o_dbig < W.cap_dbig) {
                 W.desc_big[2 * o_dbig] = make_int4(v, 0, 0, 0);
@@ -874,6 +878,7 @@ __global__ __launch_bounds__(kBlock) void k_plan(FindArgs A, PS P) {
         case CAT_NOSPLIT: write_nosplit(A, v, sortp ? 1 : 0, n); break;
         case CAT_SMALL: W.small_items[o_small] = v; break;
         case CAT_MID: W.desc_mid[o_dmid] = make_int4(v, o_slot, o_imid, k); break;
+        case CAT_MID2: W.desc_mid2[o_dmid2] = make_int4(v, o_slot, o_imid2, k); break;
         case CAT_SB: W.desc_sb[o_dsb] = make_int4(v, o_slot, o_isb, k); break;
         case CAT_BIG:
             W.desc_big[2 * o_dbig] = make_int4(v, o_slot, o_ia, o_ic);
@@ -890,9 +895,15 @@ __global__ __launch_bounds__(kBlock) void k_expand(FindArgs A) {
     const int nmid = count_of(A, H_DMID, W.cap_dmid);
     const int nsb = count_of(A, H_DSB, W.cap_dsb);
     const int nbig = count_of(A, H_DBIG, W.cap_dbig);
-    const int Bm = A.bins, C = A.n_classes;
-    for (int d = blockIdx.x; d < nmid + nsb + nbig; d += gridDim.x) {
-        if (d < nmid) {
+    const int nmid2 = count_of(A, H_DMID2, W.cap_dmid2);
+    for (int d = blockIdx.x; d < nmid + nsb + nbig + nmid2; d += gridDim.x) {
+        if (d >= nmid + nsb + nbig) {
+            const int e = d - nmid - nsb - nbig;
+            const int4 D = W.desc_mid2[e];
+            const int ng = (D.w + kMidGroup - 1) / kMidGroup;
+            for (int g = tid; g < ng; g += kBlock)
+                if (D.z + (int64_t)g < W.cap_imid2) W.items_mid2[D.z + g] = make_int2(e, g);
+        } else if (d < nmid) {
             int4 D = W.desc_mid[d];
             const int ng = (D.w + kMidGroup - 1) / kMidGroup;
             for (int g = tid; g < ng; g += kBlock)
@@ -1048,20 +1059,37 @@ __global__ __launch_bounds__(kBlock) void k_bscan(FindArgs A, PS P) {
     }
 }
 
-template <typename T, class PS>
+// kLarge: nodes of kMidSplit+1 .. kMidMax samples (32 per thread); else
+// kSmallMax+1 .. kMidSplit (up to 16 per thread).  Separate kernels so that
+// each gets the register allocation of its own size class.
+template <typename T, class PS, bool kLarge>
 __global__ __launch_bounds__(kBlock) void k_mid(FindArgs A, PS P) {
     extern __shared__ __align__(16) char smem[];
     BlockShared& S = block_shared(smem);
     const FindWs& W = A.ws;
-    const int nm = count_of(A, H_IMID, W.cap_imid);
-    const int nmd = count_of(A, H_DMID, W.cap_dmid);
+    const int nm = kLarge ? count_of(A, H_IMID2, W.cap_imid2) : count_of(A, H_IMID, W.cap_imid);
+    const int nmd = kLarge ? count_of(A, H_DMID2, W.cap_dmid2) : count_of(A, H_DMID, W.cap_dmid);
+    const int2* items = kLarge ? W.items_mid2 : W.items_mid;
+    const int4* desc = kLarge ? W.desc_mid2 : W.desc_mid;
     for (;;) {
-        int it = block_dequeue(&W.hdr[H_Q_MID], &S.item);
+        int it = block_dequeue(&W.hdr[kLarge ? H_Q_MID2 : H_Q_MID], &S.item);
         if (it >= nm) break;
-        int2 e = W.items_mid[it];
+        int2 e = items[it];
         if (e.x < 0 || e.x >= nmd) continue;
-        int4 D = W.desc_mid[e.x];
-        if (e.y >= 0 && e.y * kMidGroup < D.w) do_mid<T>(A, P, D, e.y, smem);
+        int4 D = desc[e.x];
+        if (e.y < 0 || e.y * kMidGroup >= D.w) continue;
+        int64_t s0, n;
+        node_range(A, D.x, s0, n);
+        if (kLarge) {
+            if (n > kMidMax) n = kMidMax;   // the plan never queues larger nodes here
+            do_mid_r<T, PS, kMidR>(A, P, D, e.y, s0, n, smem);
+        } else {
+            if (n > kMidSplit) n = kMidSplit;   // the plan never queues larger nodes here
+            const int nr = (int)((n + kBlock - 1) / kBlock);
+            if (nr <= 4) do_mid_r<T, PS, 4>(A, P, D, e.y, s0, n, smem);
+            else if (nr <= 8) do_mid_r<T, PS, 8>(A, P, D, e.y, s0, n, smem);
+            else do_mid_r<T, PS, 16>(A, P, D, e.y, s0, n, smem);
+        }
     }
 }
 
@@ -1085,13 +1113,16 @@ __global__ __launch_bounds__(kBlock) void k_reduce(FindArgs A) {
     const int nmid = count_of(A, H_DMID, W.cap_dmid);
     const int nsb = count_of(A, H_DSB, W.cap_dsb);
     const int nbig = count_of(A, H_DBIG, W.cap_dbig);
+    const int nmid2 = count_of(A, H_DMID2, W.cap_dmid2);
     const int lane = lane_id();
     const Cand* slots = (const Cand*)W.slots;
     const int gw = (blockIdx.x * kBlock + threadIdx.x) >> 6;
     const int nw = gridDim.x * kWavesPerBlock;
-    for (int d = gw; d < nmid + nsb + nbig; d += nw) {
+    for (int d = gw; d < nmid + nsb + nbig + nmid2; d += nw) {
         int node, slot, k, kind;
-        if (d < nmid) {
+        if (d >= nmid + nsb + nbig) {
+            int4 D = W.desc_mid2[d - nmid - nsb - nbig]; node = D.x; slot = D.y; k = D.w; kind = 0;
+        } else if (d < nmid) {
             int4 D = W.desc_mid[d]; node = D.x; slot = D.y; k = D.w; kind = 0;
         } else if (d < nmid + nsb) {
             int4 D = W.desc_sb[d - nmid]; node = D.x; slot = D.y; k = D.w; kind = 1;
@@ -1342,7 +1373,9 @@ static hipError_t launch_find_t(const FindArgs& a, const PS& p, const LaunchCfg&
     mark();
     hipLaunchKernelGGL((k_bscan<PS>), dim3(cfg.grid_bscan), dim3(kBlock), sm, s, a, p);
     mark();
-    hipLaunchKernelGGL((k_mid<T, PS>), dim3(cfg.grid_mid), dim3(kBlock), sm, s, a, p);
+    hipLaunchKernelGGL((k_mid<T, PS, false>), dim3(cfg.grid_mid), dim3(kBlock), sm, s, a, p);
+    mark();
+    hipLaunchKernelGGL((k_mid<T, PS, true>), dim3(cfg.grid_mid2), dim3(kBlock), sm, s, a, p);
     mark();
     hipLaunchKernelGGL((k_small<T, PS>), dim3(cfg.grid_small), dim3(kBlock), sm, s, a, p);
     mark();
@@ -1379,8 +1412,10 @@ hipError_t find_occupancy(int bins, int classes, int n_cu, LaunchCfg* cfg) {
     cfg->n_cu = n_cu;
     cfg->smem_main = sm;
     cfg->smem_sort = ss;
-    if ((e = occ((const void*)k_mid<float, ProjCSR>, sm, &b)) != hipSuccess) return e;
+    if ((e = occ((const void*)k_mid<float, ProjCSR, false>, sm, &b)) != hipSuccess) return e;
     cfg->grid_mid = n_cu * b;
+    if ((e = occ((const void*)k_mid<float, ProjCSR, true>, sm, &b)) != hipSuccess) return e;
+    cfg->grid_mid2 = n_cu * b;
     if ((e = occ((const void*)k_small<float, ProjCSR>, sm, &b)) != hipSuccess) return e;
     cfg->grid_small = n_cu * b;
     if ((e = occ((const void*)k_sortblk<float, ProjCSR>, ss, &b)) != hipSuccess) return e;

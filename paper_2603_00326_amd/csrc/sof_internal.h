@@ -14,7 +14,8 @@ namespace sof {
 // when n < T (T clamped to SOF_SORT_LIMIT + 1), else the histogram path.
 constexpr int kSortWaveMax = 64;     // sort nodes up to here: sorted in registers by one wave
 constexpr int kSmallMax = 512;       // histogram nodes up to here: one block per node (8 samples per lane)
-constexpr int kMidMax = 8192;        // histogram nodes up to here: one block per (node, projection)
+constexpr int kMidSplit = 4096;      // mid nodes up to here: at most 16 samples per thread
+constexpr int kMidMax = 8192;        // histogram nodes up to here: one block per (node, projection group)
 constexpr int kChunk = 8192;         // larger nodes: (node, projection, sample chunk) items
 constexpr int kSortMax = SOF_SORT_LIMIT;
 
@@ -30,9 +31,12 @@ enum {
     H_IBIGC,       // big (node, projection) items
     H_SLOTS,       // candidate slots
     H_BIGSLOTS,    // big projection slots (merged range)
+    H_DMID2,       // mid descriptors of nodes above kMidSplit samples
+    H_IMID2,       // their items
     H_Q_MID = 16,  // dequeue counters
     H_Q_SMALL,
     H_Q_SB,
+    H_Q_MID2,
     H_ERR = 32,
     H_COUNT = 64
 };
@@ -61,9 +65,11 @@ struct FindWs {
     int32_t* hdr;
     int32_t* small_items;
     int4* desc_mid;
+    int4* desc_mid2;
     int4* desc_sb;
     int4* desc_big;       // two int4 per big node
     int2* items_mid;
+    int2* items_mid2;
     int2* items_sb;
     int2* items_biga;
     int2* items_bigc;
@@ -72,7 +78,7 @@ struct FindWs {
     float2* brange;       // per big slot: (min, max) over the node
     int32_t* chist;       // per big item: [bins][classes] of the chunk
     int64_t cap_small, cap_dmid, cap_imid, cap_dsb, cap_isb, cap_dbig, cap_ibiga, cap_ibigc;
-    int64_t cap_slots, cap_bigslots;
+    int64_t cap_slots, cap_bigslots, cap_dmid2, cap_imid2;
 };
 
 struct FindArgs {
@@ -94,7 +100,8 @@ struct FindArgs {
 
 // Byte layout of the find-splits workspace for the given sizes.
 struct FindLayout {
-    size_t hdr, small_items, desc_mid, desc_sb, desc_big, items_mid, items_sb, items_biga, items_bigc;
+    size_t hdr, small_items, desc_mid, desc_mid2, desc_sb, desc_big, items_mid, items_mid2, items_sb, items_biga,
+        items_bigc;
     size_t slots, crange, brange, chist, total;
     FindWs caps;
 };
@@ -104,7 +111,7 @@ void find_bind(const FindLayout& L, void* ws, FindWs* out);
 
 struct LaunchCfg {
     int n_cu;
-    int grid_mid, grid_small, grid_sort, grid_brange, grid_bhist, grid_bscan, grid_light;
+    int grid_mid, grid_mid2, grid_small, grid_sort, grid_brange, grid_bhist, grid_bscan, grid_light;
     size_t smem_main, smem_sort;
 };
 

@@ -174,7 +174,8 @@ class Context:
         """Benchmark instrumentation: HIP events around each find_splits call."""
         _check(lib().sof_timing_enable(self.handle, int(bool(enable))))
 
-    STAGES = ("plan", "big_range", "big_merge", "big_hist", "big_scan", "mid", "small", "sort", "reduce")
+    STAGES = ("plan", "big_range", "big_merge", "big_hist", "big_scan", "mid", "mid2", "small", "sort",
+              "reduce")
 
     def timing_read(self):
         """({stage: ms, ..., "total": ms}, calls) summed since the last read."""
