@@ -42,6 +42,8 @@ WORKLOADS = {
     "c5": "single root node, n=10M, d=128 FP16 on the 1/256 grid, 2 classes, k=128, z=1..8, B=256",
     "c5f32": "as c5 with the same values stored FP32",
     "c1": "single root node, n=4096, d=64 FP32, 2 classes, k=64, z=3, B=256",
+    "c4": "full training: 8 trees grown to purity level by level from bootstrap roots of a 2M x 1024 FP32 "
+          "matrix (90% zeros), 4 classes, k=128, z=3 from the device sampler, B=256, max depth 64",
 }
 
 
@@ -107,6 +109,21 @@ def stage_bytes(wl, T: int):
     return out
 
 
+def bmin_bytes(wl, T: int) -> float:
+    """The floor of the split search's HBM bytes when every distinct (sample,
+    feature) cell a node uses is read once, whatever number of its
+    projections share the feature: n (s_i + s_y) + n |distinct features| s_x."""
+    n, k, cls = node_classes(wl, T)
+    sx = wl.X.dtype.itemsize
+    po = wl.proj_offsets.astype(np.int64)
+    zo = wl.nz_offsets.astype(np.int64)
+    total = 0
+    for v in np.nonzero(cls != "none")[0]:
+        f = wl.nz_feature[zo[po[v]]:zo[po[v + 1]]]
+        total += int(n[v]) * (8 + np.unique(f).size * sx)
+    return float(total)
+
+
 def partition_bytes(wl, splits):
     """Algorithmic bytes of the partition: n (z_{p*} s_x + 2 s_i) per split node."""
     n = np.diff(wl.node_offsets.astype(np.int64))
@@ -146,30 +163,9 @@ def measured_traffic(kernel: str, workload: str):
 # ---------------------------------------------------------------------------
 # the CPU oracle on a bounded sample of the same frontier
 
-def sub_workload(wl, nodes):
-    """The frontier restricted to the given nodes (same matrix and labels)."""
-    from paper_2603_00326_amd.workloads import Workload
-    no = wl.node_offsets.astype(np.int64)
-    po = wl.proj_offsets.astype(np.int64)
-    zo = wl.nz_offsets.astype(np.int64)
-    idx, offs, pof, zof, zf, zw = [], [0], [0], [0], [], []
-    for v in nodes:
-        idx.append(wl.sample_idx[no[v]:no[v + 1]])
-        offs.append(offs[-1] + int(no[v + 1] - no[v]))
-        for q in range(po[v], po[v + 1]):
-            zf.append(wl.nz_feature[zo[q]:zo[q + 1]])
-            zw.append(wl.nz_weight[zo[q]:zo[q + 1]])
-            zof.append(zof[-1] + int(zo[q + 1] - zo[q]))
-        pof.append(pof[-1] + int(po[v + 1] - po[v]))
-    cat = lambda xs, dt: np.concatenate(xs).astype(dt) if xs else np.zeros(0, dt)
-    nb = None if wl.node_bins is None else wl.node_bins[np.asarray(nodes)].astype(np.int32)
-    return Workload(wl.name + "_sample", wl.X, wl.y, wl.n_classes, np.asarray(offs, np.int32),
-                    cat(idx, np.int32), np.asarray(pof, np.int32), np.asarray(zof, np.int32),
-                    cat(zf, np.int32), cat(zw, np.int8), wl.bins, wl.sort_threshold, nb, dict(wl.meta))
-
-
 def cpu_baseline(wl, T, budget_units: float):
     from oracle import oracle as O
+    from paper_2603_00326_amd import workloads as W
     O.lib()
     units_all = wl.units
     if units_all <= budget_units:
@@ -187,20 +183,41 @@ def cpu_baseline(wl, T, budget_units: float):
             if acc >= budget_units:
                 break
         nodes.sort()
-        sample = sub_workload(wl, nodes)
+        sample = W.sub_frontier(wl, nodes)
         desc = (f"{len(nodes)} of {wl.n_nodes} nodes drawn uniformly (seed 12345), "
                 f"{sample.units} of {units_all} units, find splits + partition")
     threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
-    t0 = time.perf_counter()
-    ref, _ = O.find_splits(sample.X, sample.y, sample.n_classes, sample.node_offsets, sample.sample_idx,
-                           sample.proj_offsets, sample.nz_offsets, sample.nz_feature, sample.nz_weight,
-                           bins=sample.bins, sort_threshold=T, node_bins=sample.node_bins,
-                           threads=threads)
-    O.partition(sample.X, sample.node_offsets, sample.sample_idx, sample.proj_offsets, sample.nz_offsets,
-                sample.nz_feature, sample.nz_weight, ref, bins=sample.bins, node_bins=sample.node_bins)
-    el = time.perf_counter() - t0
-    return {"value": sample.units / el, "unit": "node-sample*projection/s", "cores": threads,
-            "kind": "oracle", "sample": desc, "seconds": round(el, 3)}
+
+    def once(nt):
+        t0 = time.perf_counter()
+        ref, _ = O.find_splits(sample.X, sample.y, sample.n_classes, sample.node_offsets, sample.sample_idx,
+                               sample.proj_offsets, sample.nz_offsets, sample.nz_feature, sample.nz_weight,
+                               bins=sample.bins, sort_threshold=T, node_bins=sample.node_bins, threads=nt)
+        O.partition(sample.X, sample.node_offsets, sample.sample_idx, sample.proj_offsets, sample.nz_offsets,
+                    sample.nz_feature, sample.nz_weight, ref, bins=sample.bins, node_bins=sample.node_bins)
+        return time.perf_counter() - t0
+
+    runs = [once(threads)]
+    while len(runs) < 5 and sum(runs) < 20.0:
+        runs.append(once(threads))
+    el = float(np.median(runs))
+    out = {"value": sample.units / el, "unit": "node-sample*projection/s", "cores": threads,
+           "kind": "oracle", "sample": desc, "seconds": round(el, 3), "runs": len(runs),
+           "cpu_model": cpu_model()}
+    if el * threads <= 40.0:
+        one = once(1)
+        out["single_thread"] = {"value": sample.units / one, "seconds": round(one, 3)}
+    return out
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 # ---------------------------------------------------------------------------
@@ -257,6 +274,120 @@ class PlainForm:
 
 
 # ---------------------------------------------------------------------------
+# full training: level-wise growth of a forest
+
+def run_growth(args, S, ctx):
+    """One step grows every tree of the forest to purity (or the depth cap):
+    per level, device projection sampling, batched split search, partition,
+    leaf detection and node records, replayed from a captured HIP graph."""
+    import torch
+    from paper_2603_00326_amd import workloads as W
+    t0 = time.perf_counter()
+    X, y, C, ro, ri = W.config4_data()
+    k, z, bins, max_depth, seed = 128, 3, 256, 64, 4
+    log(f"[bench] c4 data {X.shape[1]} x {X.shape[0]}, {len(ro) - 1} trees, {ri.size} root samples "
+        f"(generated in {time.perf_counter() - t0:.1f}s)")
+    dev_name = "cuda:0"
+    Xd = torch.from_numpy(X).to(dev_name)
+    yd = torch.from_numpy(y).to(dev_name)
+    rid = torch.from_numpy(ri).to(dev_name)
+    torch.cuda.synchronize()
+    T, tune = args.threshold, None
+    if T is None:
+        tune = S.autotune(ctx, C, k, z, bins, dtype=np.float32)
+        T = int(tune["sort_threshold"])
+    log(f"[bench] sort threshold T={T}")
+    stream = torch.cuda.current_stream()
+    sx = 4
+
+    def grow_once(timed):
+        f = S.Forest(ctx, Xd, yd, C, ro, rid, k=k, z=z, seed=seed, bins=bins, sort_threshold=T,
+                     max_depth=max_depth)
+        torch.cuda.synchronize()
+        levels, evs = [], []
+        t_start = time.perf_counter()
+        while True:
+            nn, ns, depth = f.frontier_stats()
+            if nn == 0:
+                break
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            f.grow_level(True)
+            e1.record(stream)
+            levels.append((depth, nn, ns))
+            evs.append((e0, e1))
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t_start
+        nodes = f.export() if timed else None
+        f.close()
+        return wall, levels, [a.elapsed_time(b) for a, b in evs], nodes
+
+    for _ in range(args.warmup):
+        grow_once(False)
+    walls, last = [], None
+    for _ in range(args.steps):
+        wall, levels, lms, nodes = grow_once(True)
+        walls.append(wall)
+        last = (levels, lms, nodes)
+    levels, lms, nodes = last
+    units = sum(ns * k for _, _, ns in levels)
+    ms_per_step = float(np.mean(walls)) * 1e3
+    # algorithmic bytes per level: the split search reads each sample's index,
+    # label and k*z feature values; the partition re-reads z values and moves
+    # two indices per sample of every split node
+    internal = nodes[nodes["is_leaf"] == 0]
+    rows, tot_b, tot_ms = [], 0.0, 0.0
+    for (depth, nn, ns), ms in zip(levels, lms):
+        split_n = int(internal["n_samples"][internal["depth"] == depth].astype(np.int64).sum())
+        b = ns * (8 + k * z * sx) + split_n * (z * sx + 8)
+        tot_b += b
+        tot_ms += ms
+        rows.append({"depth": depth, "nodes": nn, "samples": ns, "units": ns * k, "ms": round(ms, 4),
+                     "GBs": round(b / (ms * 1e-3) / 1e9, 1) if ms > 0 else None})
+    achieved = tot_b / (tot_ms * 1e-3) / 1e9 if tot_ms > 0 else 0.0
+    result = {
+        "metric": "split-search throughput: node-sample×projection/s + % of HBM roofline",
+        "value": units / (ms_per_step * 1e-3),
+        "unit": "node-sample*projection/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "c4", "description": WORKLOADS["c4"], "trees": len(ro) - 1,
+                   "root_samples": int(ri.size), "k": k, "z": z, "bins": bins, "sort_threshold": T,
+                   "max_depth": max_depth, "levels": len(levels), "nodes": int(len(nodes)),
+                   "units": int(units), "step": "grow every tree to purity (one forest)"},
+        "roofline": {"bound": "hbm", "kernel": "grow_level (every kernel of a level, summed over levels)",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "bytes_per_launch": tot_b / max(len(levels), 1),
+                     "ms_per_launch": round(tot_ms / max(len(levels), 1), 5)},
+        "levels": rows,
+        "level_ms_sum": round(tot_ms, 3),
+    }
+    if tune:
+        result["autotune"] = tune
+    if not args.no_cpu:
+        from oracle import oracle as O
+        O.lib()
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+        D = min(args.cpu_depth, max_depth)
+        log(f"[bench] CPU oracle baseline: tree 0 of the forest to depth {D}")
+        t0 = time.perf_counter()
+        _, _, lu = O.grow_forest(X, y, C, ro[:2], ri[:int(ro[1])], k=k, z=z, seed=seed, bins=bins,
+                                 sort_threshold=T, max_depth=D, threads=threads)
+        el = time.perf_counter() - t0
+        top = [i for i, r in enumerate(rows) if r["depth"] < D]
+        gpu_top = sum(rows[i]["units"] for i in top) / (sum(lms[i] for i in top) * 1e-3) if top else None
+        result["cpu_baseline"] = {"value": float(lu.sum()) / el, "unit": "node-sample*projection/s",
+                                  "cores": threads, "kind": "oracle",
+                                  "sample": f"tree 0 of {len(ro) - 1}, levels 0..{D - 1} ({int(lu.sum())} units)",
+                                  "seconds": round(el, 3),
+                                  "gpu_same_levels": gpu_top}
+    print(json.dumps(result), flush=True)
+
+
+# ---------------------------------------------------------------------------
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
@@ -271,6 +402,8 @@ def main():
                     help="steps of the per-node-launch form (0 skips it)")
     ap.add_argument("--cpu-units", type=float, default=3e9,
                     help="bound on the oracle sample, in node-sample*projection units")
+    ap.add_argument("--cpu-depth", type=int, default=20,
+                    help="c4: depth bound of the oracle's sample tree")
     ap.add_argument("--copy-only", type=float, default=0.0,
                     help="run only a plain device copy of this many GiB (counter calibration)")
     args = ap.parse_args()
@@ -292,6 +425,10 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "launches": 3}))
+        return
+
+    if args.workload == "c4":
+        run_growth(args, S, S.Context(0))
         return
 
     t0 = time.perf_counter()
@@ -346,6 +483,8 @@ def main():
             "traffic": measured_traffic(kernel_name, args.workload),
             "bytes_per_launch": sb[dom], "ms_per_launch": round(per[dom], 5)}
     find_gbs = sb["find"] / (per["total"] * 1e-3) / 1e9 if per["total"] > 0 else 0.0
+    bmin = bmin_bytes(wl, T)
+    bmin_gbs = bmin / (per["total"] * 1e-3) / 1e9 if per["total"] > 0 else 0.0
     pb = partition_bytes(wl, splits)
 
     result = {
@@ -367,6 +506,8 @@ def main():
         "roofline": roof,
         "find_splits": {"ms": round(per["total"], 4), "algorithmic_bytes": sb["find"],
                         "achieved_GBs": round(find_gbs, 1), "frac": round(find_gbs / HBM_PEAK_GBS, 4),
+                        "bmin_bytes": bmin, "bmin_GBs": round(bmin_gbs, 1),
+                        "bmin_frac": round(bmin_gbs / HBM_PEAK_GBS, 4),
                         "stage_ms": {k: round(v, 4) for k, v in per.items()},
                         "stage_bytes": sb},
         "partition": {"algorithmic_bytes": pb},

@@ -26,7 +26,8 @@
  *  - Compute calls are asynchronous on `stream` (a hipStream_t passed as void*,
  *    NULL = the default stream), allocate nothing and do not synchronise; they
  *    can be captured in a HIP graph.  sof_create, sof_forest_create,
- *    sof_forest_frontier_size, sof_forest_export and sof_autotune allocate
+ *    sof_forest_frontier_size, sof_forest_frontier_stats, sof_forest_export
+ *    and sof_autotune allocate
  *    and/or synchronise.
  *  - Every call returns a status; sof_last_error() gives a thread-local message
  *    for the last failure.  Host-side argument checks run before any launch
@@ -235,6 +236,13 @@ int sof_grow_level(sof_forest* forest, int use_graph, void* stream);
 /* Nodes in the current frontier (0 = the forest is complete).  Synchronises
  * the stream (one 4-byte device-to-host copy). */
 int sof_forest_frontier_size(sof_forest* forest, int64_t* n_nodes, void* stream);
+
+/* The current frontier of the forest: its node count, the total samples of
+ * those nodes (the projection units of the next level are n_samples * k) and
+ * the depth of its nodes.  Synchronises the stream (one 32-byte
+ * device-to-host copy).  Errors: SOF_ERR_INVALID_ARG (NULL), SOF_ERR_HIP. */
+int sof_forest_frontier_stats(sof_forest* forest, int64_t* n_nodes, int64_t* n_samples, int32_t* depth,
+                              void* stream);
 
 /* Copy the node table to host memory (synchronises).  *n receives the node
  * count; SOF_ERR_INVALID_ARG when cap is smaller. */

@@ -7,7 +7,7 @@
 // captured once in a HIP graph and replayed):
 //   find splits      projections drawn on the fly (counter hash + Floyd)
 //   partition        stable left/right blocks per node
-//   k_gcount         class counts of every child segment -> labels
+//   k_gzero, k_gcount  class counts of every child segment -> labels
 //   k_glevel         per node: children made, next-frontier nodes and samples
 //   scans            exclusive scans of those counts (deterministic ids)
 //   k_gwrite         node records, next frontier (offsets, tree, position)
@@ -25,7 +25,7 @@
 
 namespace sof {
 
-enum { G_NFRONT = 0, G_LEVEL = 1, G_NNODES = 2, G_NEXTN = 3, G_COUNT = 8 };
+enum { G_NFRONT = 0, G_LEVEL = 1, G_NNODES = 2, G_NEXTN = 3, G_NSAMP = 4, G_COUNT = 8 };
 
 struct GrowArgs {
     const int32_t* y;
@@ -98,32 +98,75 @@ __device__ void g_sample(uint64_t seed, int tree, int level, int pos, int p, int
     }
 }
 
-// class counts of M consecutive segments [off[j], off[j+1]) of idx; one wave
-// per segment (segments are contiguous, sizes arbitrary)
+// Work over the concatenation of M contiguous segments [off[j], off[j+1])
+// (monotone offsets from 0): each wave takes chunks of kSegChunk positions and
+// walks the segments a chunk overlaps, so one huge segment and many tiny ones
+// both spread over the whole grid.
+constexpr int kSegChunk = 2048;
+
+// the segment that holds position pos, for off[0] <= pos < off[M]: the last j
+// with off[j] <= pos (empty segments before it are skipped)
+__device__ __forceinline__ int seg_find(const int32_t* off, int M, int64_t pos) {
+    int lo = 0, hi = M - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= pos) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// zero the class counts that k_gcount accumulates into (a kernel rather than
+// a memset node, so that graph replays stay exact)
+__global__ __launch_bounds__(256) void k_gzero(GrowArgs g, int use_children) {
+    const int N = gN(g);
+    const int64_t n = (int64_t)(use_children ? 2 * N : N) * g.n_classes;
+    for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) g.child_cnt[i] = 0;
+}
+
+// class counts of M consecutive segments of idx (children after the
+// partition, or the roots): per 64 positions one ballot per class, then one
+// atomic add per (segment, class) per chunk
 __global__ __launch_bounds__(256) void k_gcount(GrowArgs g, int use_children) {
     const int N = gN(g);
     const int M = use_children ? 2 * N : N;
+    if (M <= 0) return;
     const int32_t* off = use_children ? g.child_off : g.f_off;
     const int32_t* idx = use_children ? g.part_idx : g.f_idx;
     const int lane = threadIdx.x & 63;
     const int C = g.n_classes;
-    for (int j = (blockIdx.x * 256 + threadIdx.x) >> 6; j < M; j += gridDim.x * 4) {
-        int64_t a = off[j], b = off[j + 1];
-        if (a < 0) a = 0;
-        if (b > g.n_samples) b = g.n_samples;
-        uint32_t cnt[16];
-        for (int c = 0; c < 16; ++c) cnt[c] = 0;
-        for (int64_t i = a + lane; i < b; i += 64) {
-            uint32_t r = (uint32_t)idx[i];
-            uint32_t y = (uint32_t)g.y[r < (uint32_t)g.n_rows ? r : 0];
-            y = y < (uint32_t)C ? y : 0;
+    int64_t total = off[M];
+    if (total > g.n_samples) total = g.n_samples;
+    const int64_t waves = (int64_t)gridDim.x * 4;
+    for (int64_t ch = (blockIdx.x * 256 + threadIdx.x) >> 6; ch * kSegChunk < total; ch += waves) {
+        const int64_t cs = ch * kSegChunk;
+        const int64_t ce = cs + kSegChunk < total ? cs + kSegChunk : total;
+        for (int j = seg_find(off, M, cs); j < M; ++j) {
+            const int64_t o0 = off[j], o1 = off[j + 1];
+            const int64_t a = o0 > cs ? o0 : cs;
+            const int64_t b = o1 < ce ? o1 : ce;
+            uint32_t cnt[16];
 #pragma unroll
-            for (int c = 0; c < 16; ++c) cnt[c] += (y == (uint32_t)c) ? 1u : 0u;
+            for (int c = 0; c < 16; ++c) cnt[c] = 0;
+            for (int64_t i0 = a; i0 < b; i0 += 64) {
+                const int64_t i = i0 + lane;
+                uint32_t yv = 16;
+                if (i < b) {
+                    const uint32_t r = (uint32_t)idx[i];
+                    yv = (uint32_t)g.y[r < (uint32_t)g.n_rows ? r : 0];
+                    yv = yv < (uint32_t)C ? yv : 0;
+                }
+#pragma unroll
+                for (int c = 0; c < 16; ++c)
+                    if (c < C) cnt[c] += (uint32_t)__popcll(__ballot(yv == (uint32_t)c));
+            }
+            uint32_t mine = 0;
+#pragma unroll
+            for (int c = 0; c < 16; ++c)
+                if (lane == c) mine = cnt[c];
+            if (lane < C && mine) atomicAdd(&g.child_cnt[(int64_t)j * C + lane], (int32_t)mine);
+            if (o1 >= ce) break;
         }
-#pragma unroll
-        for (int c = 0; c < 16; ++c) cnt[c] = wave_sum(cnt[c]);
-        if (lane == 0)
-            for (int c = 0; c < C; ++c) g.child_cnt[(int64_t)j * C + c] = (int32_t)cnt[c];
     }
 }
 
@@ -321,17 +364,30 @@ __global__ __launch_bounds__(256) void k_gnext(GrowArgs g) {
     }
 }
 
-// copy child sample blocks: one wave per next-frontier node
+// copy the surviving children's sample blocks into the next frontier, chunked
+// over the destination positions like k_gcount
 __global__ __launch_bounds__(256) void k_gcopy(GrowArgs g) {
     const int N = gN(g);
     int64_t nn = g.scan_a[N] & 0xffffffffll;
-    if (nn > g.cap_front) nn = g.cap_front;
+    if (nn <= 0 || nn > g.cap_front) return;
+    const int M = (int)nn;
     const int lane = threadIdx.x & 63;
-    for (int64_t j = (blockIdx.x * 256 + threadIdx.x) >> 6; j < nn; j += gridDim.x * 4) {
-        int64_t d0 = g.n_off[j], d1 = g.n_off[j + 1];
-        int64_t s0 = g.n_src[j];
-        if (d0 < 0 || d1 > g.n_samples || d1 < d0 || s0 < 0 || s0 + (d1 - d0) > g.n_samples) continue;
-        for (int64_t i = lane; i < d1 - d0; i += 64) g.n_idx[d0 + i] = g.part_idx[s0 + i];
+    int64_t total = g.n_off[M];
+    if (total > g.n_samples) total = g.n_samples;
+    const int64_t waves = (int64_t)gridDim.x * 4;
+    for (int64_t ch = (blockIdx.x * 256 + threadIdx.x) >> 6; ch * kSegChunk < total; ch += waves) {
+        const int64_t cs = ch * kSegChunk;
+        const int64_t ce = cs + kSegChunk < total ? cs + kSegChunk : total;
+        for (int j = seg_find(g.n_off, M, cs); j < M; ++j) {
+            const int64_t d0 = g.n_off[j], d1 = g.n_off[j + 1];
+            const int64_t s0 = g.n_src[j];
+            if (!(d0 < 0 || d1 > g.n_samples || d1 < d0 || s0 < 0 || s0 + (d1 - d0) > g.n_samples)) {
+                const int64_t a = d0 > cs ? d0 : cs;
+                const int64_t b = d1 < ce ? d1 : ce;
+                for (int64_t i = a + lane; i < b; i += 64) g.n_idx[i] = g.part_idx[s0 + (i - d0)];
+            }
+            if (d1 >= ce) break;
+        }
     }
 }
 
@@ -342,6 +398,7 @@ __global__ void k_gfinish(GrowArgs g) {
     g.cnt[G_NNODES] += (int32_t)(a >> 32);
     g.cnt[G_NEXTN] = (int32_t)(a & 0xffffffffll);
     g.cnt[G_NFRONT] = (int32_t)(a & 0xffffffffll);
+    g.cnt[G_NSAMP] = (int32_t)g.scan_b[N];
     g.cnt[G_LEVEL] += 1;
 }
 
@@ -488,6 +545,7 @@ static hipError_t level_launch(sof_forest* f, hipStream_t s) {
     const int grid = f->ctx->n_cu * 4;
     const int nb_scan = (int)((f->cap_front + 1 + kScanBlock - 1) / kScanBlock);
     const int g_scan = nb_scan < grid ? nb_scan : grid;
+    hipLaunchKernelGGL(k_gzero, dim3(grid), dim3(256), 0, s, g, 1);
     hipLaunchKernelGGL(k_gcount, dim3(grid), dim3(256), 0, s, g, 1);
     hipLaunchKernelGGL(k_glevel, dim3(grid), dim3(256), 0, s, g);
     for (int64_t* arr : {g.scan_a, g.scan_b}) {
@@ -582,7 +640,8 @@ extern "C" int sof_forest_create(sof_ctx* ctx, const sof_data* data, const sof_f
     if (e == hipSuccess) e = hipMemcpy(b.cnt, cnt0, sizeof(cnt0), hipMemcpyHostToDevice);
     if (e != hipSuccess) { forest_free(f); return hip_fail(e, "forest roots"); }
     GrowArgs g = grow_args(f);
-    hipLaunchKernelGGL(k_gcount, dim3(ctx->n_cu), dim3(256), 0, nullptr, g, 0);
+    hipLaunchKernelGGL(k_gzero, dim3(ctx->n_cu), dim3(256), 0, nullptr, g, 0);
+    hipLaunchKernelGGL(k_gcount, dim3(ctx->n_cu * 4), dim3(256), 0, nullptr, g, 0);
     std::vector<int32_t> cnt((size_t)T * C);
     e = hipGetLastError();
     if (e == hipSuccess) e = hipMemcpy(cnt.data(), b.child_cnt, cnt.size() * 4, hipMemcpyDeviceToHost);
@@ -628,7 +687,7 @@ extern "C" int sof_forest_create(sof_ctx* ctx, const sof_data* data, const sof_f
     if (e == hipSuccess && N0 > 0) e = hipMemcpy(b.tree[0], ftree.data(), N0 * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess && N0 > 0) e = hipMemcpy(b.pos[0], fpos.data(), N0 * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(b.tstart[0], tstart.data(), (T + 1) * 4, hipMemcpyHostToDevice);
-    int32_t cnt1[G_COUNT] = {N0, 0, T, 0, 0, 0, 0, 0};
+    int32_t cnt1[G_COUNT] = {N0, 0, T, 0, foff.back(), 0, 0, 0};
     if (e == hipSuccess) e = hipMemcpy(b.cnt, cnt1, sizeof(cnt1), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) { forest_free(f); return hip_fail(e, "forest setup"); }
@@ -682,6 +741,19 @@ extern "C" int sof_forest_frontier_size(sof_forest* f, int64_t* n, void* stream)
     if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "frontier size");
     *n = v;
+    return SOF_OK;
+}
+
+extern "C" int sof_forest_frontier_stats(sof_forest* f, int64_t* n_nodes, int64_t* n_samples, int32_t* depth,
+                                         void* stream) {
+    if (!f || !n_nodes || !n_samples || !depth) return fail(SOF_ERR_INVALID_ARG, "NULL argument");
+    int32_t cnt[G_COUNT];
+    hipError_t e = hipMemcpyAsync(cnt, f->b.cnt, sizeof(cnt), hipMemcpyDeviceToHost, (hipStream_t)stream);
+    if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "frontier stats");
+    *n_nodes = cnt[G_NFRONT];
+    *n_samples = cnt[G_NFRONT] > 0 ? cnt[G_NSAMP] : 0;
+    *depth = cnt[G_LEVEL];
     return SOF_OK;
 }
 

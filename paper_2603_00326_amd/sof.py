@@ -29,7 +29,8 @@ INT32_MAX = 2**31 - 1
 EXPORTED = [
     "sof_version", "sof_last_error", "sof_create", "sof_destroy", "sof_workspace_size",
     "sof_project", "sof_find_splits", "sof_partition", "sof_forest_create", "sof_forest_destroy",
-    "sof_grow_level", "sof_forest_frontier_size", "sof_forest_export", "sof_autotune",
+    "sof_grow_level", "sof_forest_frontier_size", "sof_forest_frontier_stats", "sof_forest_export",
+    "sof_autotune",
     "sof_timing_enable", "sof_timing_read",
 ]
 
@@ -120,6 +121,8 @@ def lib():
             L.sof_forest_destroy.argtypes = [P]
             L.sof_grow_level.argtypes = [P, ctypes.c_int, P]
             L.sof_forest_frontier_size.argtypes = [P, ctypes.POINTER(i64), P]
+            L.sof_forest_frontier_stats.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                                    ctypes.POINTER(ctypes.c_int32), P]
             L.sof_forest_export.argtypes = [P, P, i64, ctypes.POINTER(i64), P]
         L.sof_timing_enable.argtypes = [P, ctypes.c_int]
         L.sof_timing_read.argtypes = [P, P, ctypes.POINTER(i32)]
@@ -384,6 +387,13 @@ class Forest:
         n = i64(0)
         _check(lib().sof_forest_frontier_size(self.handle, ctypes.byref(n), _stream(stream)))
         return int(n.value)
+
+    def frontier_stats(self, stream=None):
+        """(nodes, samples, depth) of the current frontier."""
+        n, m, d = i64(0), i64(0), ctypes.c_int32(0)
+        _check(lib().sof_forest_frontier_stats(self.handle, ctypes.byref(n), ctypes.byref(m), ctypes.byref(d),
+                                               _stream(stream)))
+        return int(n.value), int(m.value), int(d.value)
 
     def export(self, stream=None) -> np.ndarray:
         out = np.zeros(self.max_nodes, TREE_NODE_DTYPE)

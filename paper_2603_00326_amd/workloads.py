@@ -322,6 +322,28 @@ def config5(seed: int = 5, n: int = 10_000_000, fp16: bool = True) -> Workload:
                     meta=dict(config=5, k=k, d=d))
 
 
+def sub_frontier(wl: Workload, nodes) -> Workload:
+    """The frontier restricted to the given nodes, in the given order (same
+    matrix and labels; each node keeps its samples and projections)."""
+    no = wl.node_offsets.astype(np.int64)
+    po = wl.proj_offsets.astype(np.int64)
+    zo = wl.nz_offsets.astype(np.int64)
+    idx, offs, pof, zof, zf, zw = [], [0], [0], [0], [], []
+    for v in nodes:
+        idx.append(wl.sample_idx[no[v]:no[v + 1]])
+        offs.append(offs[-1] + int(no[v + 1] - no[v]))
+        zf.append(wl.nz_feature[zo[po[v]]:zo[po[v + 1]]])
+        zw.append(wl.nz_weight[zo[po[v]]:zo[po[v + 1]]])
+        z = np.diff(zo[po[v]:po[v + 1] + 1])
+        zof.extend((zof[-1] + np.cumsum(z)).tolist())
+        pof.append(pof[-1] + int(po[v + 1] - po[v]))
+    cat = lambda xs, dt: np.concatenate(xs).astype(dt) if xs else np.zeros(0, dt)
+    nb = None if wl.node_bins is None else wl.node_bins[np.asarray(nodes, np.int64)].astype(np.int32)
+    return Workload(wl.name + "_sample", wl.X, wl.y, wl.n_classes, np.asarray(offs, np.int32),
+                    cat(idx, np.int32), np.asarray(pof, np.int32), np.asarray(zof, np.int32),
+                    cat(zf, np.int32), cat(zw, np.int8), wl.bins, wl.sort_threshold, nb, dict(wl.meta))
+
+
 # ----------------------------------------------------------------------------
 # small random frontiers for parity tests
 # ----------------------------------------------------------------------------

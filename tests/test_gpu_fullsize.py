@@ -1,0 +1,133 @@
+"""Parity at the benchmark's full sizes, in the launch configuration the
+benchmark times (one batched call over the whole frontier, the autotuned sort
+threshold, then the partition of every node): sampled nodes of every size
+class against the oracle node by node, and over every node the properties
+that hold at any size (each node's output block is a permutation of its
+samples, split into a left block of the measured size that matches the
+split's left count)."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2603_00326_amd import workloads as W
+from tests.gpu_helpers import assert_splits_match, say
+
+pytestmark = pytest.mark.gpu
+
+CLASS_EDGES = [(0, 64), (65, 512), (513, 4096), (4097, 8192), (8193, 1 << 30)]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2603_00326_amd import sof as S
+    return S.Context(0)
+
+
+def tuned_threshold(ctx, wl):
+    from paper_2603_00326_amd import sof as S
+    t = S.autotune(ctx, wl.n_classes, int(wl.meta.get("k", 64)), int(wl.meta.get("z", 3)), wl.bins,
+                   dtype=wl.X.dtype)
+    return int(t["sort_threshold"])
+
+
+def sample_nodes(wl, seed, per_class=10):
+    """The three largest nodes plus up to per_class nodes of each size class."""
+    rng = np.random.default_rng(seed)
+    n = np.diff(wl.node_offsets.astype(np.int64))
+    pick = set(np.argsort(n, kind="stable")[-3:].tolist())
+    for lo, hi in CLASS_EDGES:
+        cand = np.nonzero((n >= lo) & (n <= hi))[0]
+        if cand.size:
+            pick.update(rng.choice(cand, size=min(per_class, cand.size), replace=False).tolist())
+    return sorted(int(v) for v in pick)
+
+
+def run_full(ctx, wl, T):
+    import torch
+    from paper_2603_00326_amd import sof as S
+    dev = S.to_device(wl)
+    out, _ = S.find_splits(ctx, dev, bins=wl.bins, sort_threshold=T)
+    out_idx, coff = S.partition(ctx, dev, out, bins=wl.bins)
+    torch.cuda.synchronize()
+    got = S.splits_to_numpy(out)[:wl.n_nodes]
+    res = got.copy(), out_idx.cpu().numpy(), coff.cpu().numpy()
+    del dev, out, out_idx, coff
+    torch.cuda.empty_cache()
+    return res
+
+
+def check_partition_properties(wl, got, out_idx, coff):
+    N = wl.n_nodes
+    no = wl.node_offsets.astype(np.int64)
+    n = np.diff(no)
+    assert coff[2 * N] == no[-1]
+    assert np.array_equal(coff[0:2 * N:2], no[:-1]), "child block starts"
+    n_left = coff[1:2 * N:2].astype(np.int64) - no[:-1]
+    split = got["proj"] >= 0
+    assert np.array_equal(n_left[split], got["n_left"][split]), "measured left count vs the split's"
+    assert np.array_equal(n_left[~split], n[~split]), "an unsplit node keeps every sample on the left"
+    node_of = np.repeat(np.arange(N), n)
+    a = np.lexsort((wl.sample_idx, node_of))
+    b = np.lexsort((out_idx, node_of))
+    assert np.array_equal(wl.sample_idx[a], out_idx[b]), "per-node permutation"
+
+
+def check_sampled(wl, T, got, out_idx, coff, nodes, tag):
+    sub = W.sub_frontier(wl, nodes)
+    sub.sort_threshold = T
+    ref, _ = O.find_splits_w(sub)
+    assert_splits_match(got[nodes], ref, tag)
+    want_idx, want_coff = O.partition(sub.X, sub.node_offsets, sub.sample_idx, sub.proj_offsets,
+                                      sub.nz_offsets, sub.nz_feature, sub.nz_weight, ref, bins=sub.bins,
+                                      node_bins=sub.node_bins)
+    no, so = wl.node_offsets.astype(np.int64), sub.node_offsets.astype(np.int64)
+    for i, v in enumerate(nodes):
+        assert np.array_equal(out_idx[no[v]:no[v + 1]], want_idx[so[i]:so[i + 1]]), f"{tag}: node {v} order"
+        assert coff[2 * v + 1] - no[v] == want_coff[2 * i + 1] - so[i], f"{tag}: node {v} left size"
+
+
+@pytest.mark.parametrize("layout", ["a", "b"])
+def test_frontier_4096_lognormal_nodes(ctx, layout):
+    wl = W.config3(layout)
+    for T in sorted({tuned_threshold(ctx, wl), 48}):
+        nodes = sample_nodes(wl, seed=17)
+        say(f"[gpu] full frontier layout={layout} nodes={wl.n_nodes} samples={wl.n_samples} T={T} "
+            f"sampled={len(nodes)}")
+        got, out_idx, coff = run_full(ctx, wl, T)
+        check_partition_properties(wl, got, out_idx, coff)
+        check_sampled(wl, T, got, out_idx, coff, nodes, f"c3{layout} T={T}")
+
+
+def test_root_1m_rows_256_projections(ctx):
+    wl = W.config2()
+    T = tuned_threshold(ctx, wl)
+    say(f"[gpu] root n={wl.n_samples} k={wl.n_proj} T={T}")
+    got, out_idx, coff = run_full(ctx, wl, T)
+    check_partition_properties(wl, got, out_idx, coff)
+    check_sampled(wl, T, got, out_idx, coff, [0], "c2")
+
+
+def test_root_10m_rows_fp16_equals_fp32_and_oracle(ctx):
+    w16 = W.config5(fp16=True)
+    T = tuned_threshold(ctx, w16)
+    say(f"[gpu] root n={w16.n_samples} FP16 T={T}")
+    g16, i16, c16 = run_full(ctx, w16, T)
+    check_partition_properties(w16, g16, i16, c16)
+    check_sampled(w16, T, g16, i16, c16, [0], "c5 fp16")
+    del w16
+    w32 = W.config5(fp16=False)
+    say(f"[gpu] root n={w32.n_samples} FP32 T={T}")
+    g32, i32, c32 = run_full(ctx, w32, T)
+    assert g16.tobytes() == g32.tobytes(), "FP16 and FP32 storage give different split records"
+    assert np.array_equal(i16, i32) and np.array_equal(c16, c32), "FP16 and FP32 partitions differ"
+
+
+@pytest.mark.parametrize("T", [0, 2**31 - 1])
+def test_root_4096_rows_both_paths(ctx, T):
+    wl = W.config1(sort=T != 0)
+    say(f"[gpu] root n={wl.n_samples} T={T}")
+    got, out_idx, coff = run_full(ctx, wl, T)
+    check_partition_properties(wl, got, out_idx, coff)
+    check_sampled(wl, T, got, out_idx, coff, [0], f"c1 T={T}")

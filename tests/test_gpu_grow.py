@@ -19,7 +19,8 @@ def ctx():
     return S.Context(0)
 
 
-def grow_case(ctx, *, seed, d, n, C, trees, k, z, bins, T, max_depth=64, graph=True, dtype=np.float32):
+def grow_case(ctx, *, seed, d, n, C, trees, k, z, bins, T, max_depth=64, graph=True, dtype=np.float32,
+              stats=False):
     import torch
     from paper_2603_00326_amd import sof as S
     say(f"[gpu] grow seed={seed} d={d} n={n} C={C} trees={trees} k={k} z={z} B={bins} T={T} "
@@ -33,12 +34,24 @@ def grow_case(ctx, *, seed, d, n, C, trees, k, z, bins, T, max_depth=64, graph=T
              for t in range(trees)]
     ro = np.arange(trees + 1, dtype=np.int64) * n
     ri = np.concatenate(roots)
-    ref, ref_levels, _ = O.grow_forest(X, y, C, ro, ri, k=k, z=z, seed=seed + 7, bins=bins,
-                                       sort_threshold=T, max_depth=max_depth)
+    ref, ref_levels, ref_units = O.grow_forest(X, y, C, ro, ri, k=k, z=z, seed=seed + 7, bins=bins,
+                                               sort_threshold=T, max_depth=max_depth)
     Xd = torch.from_numpy(X.astype(dtype)).to("cuda:0")
     f = S.Forest(ctx, Xd, torch.from_numpy(y).to("cuda:0"), C, ro, torch.from_numpy(ri).to("cuda:0"),
                  k=k, z=z, seed=seed + 7, bins=bins, sort_threshold=T, max_depth=max_depth)
-    sizes = f.grow(use_graph=graph)
+    if stats:
+        sizes, units = [], []
+        while True:
+            nn, ns, depth = f.frontier_stats()
+            if nn == 0:
+                break
+            assert depth == len(sizes), f"frontier depth {depth} at level {len(sizes)}"
+            sizes.append(nn)
+            units.append(ns * k)
+            f.grow_level(graph)
+        assert units == ref_units.tolist(), f"level units {units} vs {ref_units.tolist()}"
+    else:
+        sizes = f.grow(use_graph=graph)
     got = f.export()
     torch.cuda.synchronize()
     assert sizes == ref_levels.tolist(), f"frontier sizes {sizes} vs {ref_levels.tolist()}"
@@ -61,6 +74,12 @@ def test_grow_three_trees_graph(ctx):
 
 def test_grow_three_trees_no_graph(ctx):
     grow_case(ctx, seed=51, d=10, n=400, C=3, trees=3, k=6, z=2, bins=64, T=50, graph=False)
+
+
+def test_grow_frontier_stats_per_level(ctx):
+    """Nodes, samples and depth of every frontier, read before each level,
+    against the oracle's per-level node counts and projection units."""
+    grow_case(ctx, seed=52, d=12, n=1500, C=4, trees=4, k=8, z=3, bins=128, T=64, stats=True)
 
 
 def test_grow_histogram_only_depth_cap(ctx):
