@@ -135,14 +135,18 @@ __global__ __launch_bounds__(256) void k_gcount(GrowArgs g, int use_children) {
     const int32_t* idx = use_children ? g.part_idx : g.f_idx;
     const int lane = threadIdx.x & 63;
     const int C = g.n_classes;
-    int64_t total = off[M];
+    int64_t total = __builtin_amdgcn_readfirstlane(off[M]);
     if (total > g.n_samples) total = g.n_samples;
     const int64_t waves = (int64_t)gridDim.x * 4;
-    for (int64_t ch = (blockIdx.x * 256 + threadIdx.x) >> 6; ch * kSegChunk < total; ch += waves) {
+    // every loop bound below is a scalar, so the lane-subset atomic at the end
+    // of an iteration closes before the next iteration's ballots
+    const int wave = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * 256 + threadIdx.x) >> 6));
+    for (int64_t ch = wave; ch * kSegChunk < total; ch += waves) {
         const int64_t cs = ch * kSegChunk;
         const int64_t ce = cs + kSegChunk < total ? cs + kSegChunk : total;
-        for (int j = seg_find(off, M, cs); j < M; ++j) {
-            const int64_t o0 = off[j], o1 = off[j + 1];
+        for (int j = __builtin_amdgcn_readfirstlane(seg_find(off, M, cs)); j < M; ++j) {
+            const int64_t o0 = __builtin_amdgcn_readfirstlane(off[j]);
+            const int64_t o1 = __builtin_amdgcn_readfirstlane(off[j + 1]);
             const int64_t a = o0 > cs ? o0 : cs;
             const int64_t b = o1 < ce ? o1 : ce;
             uint32_t cnt[16];

@@ -6,7 +6,8 @@
 // bin(v) <= bin, sort splits iff v <= threshold.  Output per node: left
 // samples in input order, then right samples in input order.
 //
-//   k_pplan     per node: child offsets, small-node queue or chunk items
+//   k_pplan     per node: child offsets, tiny/small-node queues or chunk items
+//   k_ptiny     nodes <= 1024 samples: one wave per node, all in registers
 //   k_psmall    nodes <= 8192 samples: one block per node; chunk items of
 //               larger nodes: predicate bits and left counts (first pass)
 //   k_pscatter  chunk items: prefix over the node's earlier chunks, scatter
@@ -19,11 +20,12 @@
 namespace sof {
 
 
+constexpr int kPartTiny = 1024;            // one wave per node up to here
 constexpr int kPartMax = 8192;             // one block per node up to here
 constexpr int kPR = kPartMax / kBlock;     // 32 samples per thread
 constexpr int kWordsPerChunk = kPartMax / kWave;
 
-enum { P_SMALL = 0, P_ITEMS, P_Q_SMALL = 8, P_Q_A, P_Q_B, P_COUNT = 16 };
+enum { P_SMALL = 0, P_ITEMS, P_TINY, P_Q_SMALL = 8, P_Q_A, P_Q_B, P_Q_TINY, P_COUNT = 16 };
 
 __device__ __forceinline__ void wave_sync_p() {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -112,6 +114,144 @@ __device__ __forceinline__ int pstage(const ProjHash& P, int v, int p, int d, in
     }
     wave_sync_p();
     return z;
+}
+
+// The split projection in registers: lane j < z holds the j-th feature
+// (ascending order) and its sign bit; returns z.
+__device__ __forceinline__ int preg(const ProjCSR& P, int v, int p, int d, int& fj, uint32_t& sj) {
+    int q = (int)clampp(P.proj_offsets[v], 0, P.n_proj) + p;
+    int64_t j0 = clampp(P.nz_offsets[q], 0, P.n_nz);
+    int64_t j1 = clampp(P.nz_offsets[q + 1], j0, P.n_nz);
+    if (j1 - j0 > SOF_MAX_NNZ) j1 = j0 + SOF_MAX_NNZ;
+    const int z = (int)(j1 - j0);
+    const int lane = lane_id();
+    fj = 0;
+    sj = 0;
+    if (lane < z) {
+        uint32_t f = (uint32_t)P.nz_feature[j0 + lane];
+        fj = f < (uint32_t)d ? (int)f : 0;
+        sj = P.nz_weight[j0 + lane] < 0 ? 0x80000000u : 0u;
+    }
+    return z;
+}
+__device__ __forceinline__ int preg(const ProjHash& P, int v, int p, int d, int& fj, uint32_t& sj) {
+    const int lane = lane_id();
+    const int z = P.z;
+    const int tree = P.tree_of[v], pos = P.pos_of[v], level = *P.level;
+    uint32_t t = 0;
+    if (lane < z) {
+        uint32_t top = (uint32_t)(d - z + lane) + 1u;
+        uint64_t r = smix(P.seed, pcounter(tree, level, pos, p, lane));
+        t = (uint32_t)(((r >> 32) * (uint64_t)top) >> 32);
+    }
+    int mine = (int)t;
+    for (int j = 0; j < z; ++j) {
+        int cj = __shfl((int)t, j);
+        bool taken = __ballot(lane < j && mine == cj) != 0ull;
+        if (lane == j) mine = taken ? d - z + j : cj;
+    }
+    int rank = 0;
+    for (int i = 0; i < z; ++i) rank += (__shfl(mine, i) < mine) ? 1 : 0;
+    // lane j takes the draw of rank j
+    fj = 0;
+    for (int i = 0; i < z; ++i) {
+        const int ri = __shfl(rank, i), mi = __shfl(mine, i);
+        if (ri == lane) fj = mi;
+    }
+    const uint64_t sg = smix(P.seed, pcounter(tree, level, pos, p, 15));
+    sj = (lane < z && ((sg >> lane) & 1ull)) ? 0x80000000u : 0u;
+    return z;
+}
+
+// One wave partitions a node of n <= 64 R samples: each lane holds R samples
+// (sample i at lane i mod 64, row i / 64), the left masks of the R rows stay
+// in scalar registers, and each sample goes straight to its destination.
+// Slots past the end repeat the last sample so every column load is issued at
+// a valid address.
+template <typename T, class PS, int R>
+__device__ void ptiny_r(const PartArgs& A, const PS& P, int v, int64_t s0, int n) {
+    const int lane = lane_id();
+    const SplitRec sp = ((const SplitRec*)A.splits)[v];
+    const int k = pcount(P, v);
+    const bool all_left = sp.proj < 0 || sp.proj >= k;
+    int fj = 0;
+    uint32_t sj = 0;
+    const int z = __builtin_amdgcn_readfirstlane(all_left ? 0 : preg(P, v, sp.proj, A.n_features, fj, sj));
+    int B = A.bins;
+    if (A.node_bins) {
+        int b = A.node_bins[v];
+        B = b < 2 ? 2 : (b > A.bins ? A.bins : b);
+    }
+    int32_t raw[R];
+    uint32_t off[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = lane + r * kWave;
+        raw[r] = A.sample_idx[s0 + (i < n ? i : n - 1)];
+        const uint32_t row = (uint32_t)raw[r] < (uint32_t)A.n_rows ? (uint32_t)raw[r] : 0u;
+        off[r] = row * (uint32_t)sizeof(T);
+    }
+    float val[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) val[r] = 0.f;
+    for (int j = 0; j < z; ++j) {
+        const int f = __builtin_amdgcn_readlane(fj, j);
+        const uint32_t sg = (uint32_t)__builtin_amdgcn_readlane((int)sj, j);
+        const T* col = (const T*)A.x + (int64_t)f * A.ld;
+        float x[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) x[r] = ldx((const T*)((const char*)col + off[r]), 0);
+#pragma unroll
+        for (int r = 0; r < R; ++r) val[r] = __fadd_rn(val[r], signed_term(x[r], sg));
+    }
+    uint64_t m[R];
+    int nl = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = lane + r * kWave;
+        bool left = true;
+        if (!all_left)
+            left = sp.kind == SOF_SPLIT_HIST ? bin_index(val[r], sp.lo, sp.scale, B) <= sp.bin
+                                             : val[r] <= sp.threshold;
+        m[r] = __ballot(i < n && left);
+        nl += __popcll(m[r]);
+    }
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    int lpre = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = lane + r * kWave;
+        const int64_t dst = ((m[r] >> lane) & 1ull) ? s0 + lpre + __popcll(m[r] & below)
+                                                    : s0 + nl + (r * kWave - lpre) + __popcll(~m[r] & below);
+        if (i < n && dst >= s0 && dst < s0 + n) A.out_idx[dst] = raw[r];
+        lpre += __popcll(m[r]);
+    }
+    A.child_offsets[2 * v + 1] = (int32_t)(s0 + nl);   // every lane stores the same value
+}
+
+// Tiny nodes are dealt to waves round-robin (no queue): every value that
+// steers the loop is read into a scalar register, and no lane-subset branch
+// precedes a cross-lane operation, so the wave stays converged throughout.
+template <typename T, class PS>
+__global__ __launch_bounds__(kBlock) void k_ptiny(PartArgs A, PS P) {
+    const int ntiny = __builtin_amdgcn_readfirstlane(A.hdr[P_TINY]);
+    const int N = nodes_of(A);
+    const int wave = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6)));
+    const int nwaves = (int)gridDim.x * kWavesPerBlock;
+    for (int it = wave; it < ntiny; it += nwaves) {
+        const int v = __builtin_amdgcn_readfirstlane(A.big_items[A.cap_items + A.n_nodes - 1 - it].x);
+        if (v < 0 || v >= N) continue;
+        int64_t s0, n;
+        prange(A, v, s0, n);
+        const int s0u = __builtin_amdgcn_readfirstlane((int)s0);
+        const int nu = __builtin_amdgcn_readfirstlane((int)n);
+        if (nu <= 0) A.child_offsets[2 * v + 1] = s0u;   // every lane stores the same value
+        else if (nu <= 64) ptiny_r<T, PS, 1>(A, P, v, s0u, nu);
+        else if (nu <= 128) ptiny_r<T, PS, 2>(A, P, v, s0u, nu);
+        else if (nu <= 256) ptiny_r<T, PS, 4>(A, P, v, s0u, nu);
+        else if (nu <= 512) ptiny_r<T, PS, 8>(A, P, v, s0u, nu);
+        else ptiny_r<T, PS, 16>(A, P, v, s0u, nu < kPartTiny ? nu : kPartTiny);
+    }
 }
 
 struct PShared {
@@ -244,7 +384,11 @@ __global__ __launch_bounds__(kBlock) void k_pplan(PartArgs A, PS P) {
         int64_t s0, n;
         prange(A, v, s0, n);
         A.child_offsets[2 * v] = (int32_t)s0;
-        if (n <= kPartMax) {
+        if (n <= kPartTiny) {
+            // tiny list fills the node-list region from its far end
+            int o = atomicAdd(&A.hdr[P_TINY], 1);
+            A.big_items[A.cap_items + A.n_nodes - 1 - o] = make_int4(v, 0, 0, 0);
+        } else if (n <= kPartMax) {
             int o = atomicAdd(&A.hdr[P_SMALL], 1);
             A.big_items[A.cap_items + o] = make_int4(v, 0, 0, 0);   // small list lives after the items
         } else {
@@ -364,6 +508,7 @@ hipError_t launch_part_t(const PartArgs& a, const PS& p, int n_cu, hipStream_t s
     if (grid_plan > 4 * n_cu) grid_plan = 4 * n_cu;
     hipLaunchKernelGGL(k_preset, dim3(1), dim3(64), 0, s, a.hdr);
     hipLaunchKernelGGL((k_pplan<PS>), dim3(grid_plan), dim3(kBlock), 0, s, a, p);
+    hipLaunchKernelGGL((k_ptiny<T, PS>), dim3(n_cu * 4), dim3(kBlock), 0, s, a, p);
     hipLaunchKernelGGL((k_psmall<T, PS>), dim3(n_cu * 4), dim3(kBlock), sizeof(PShared), s, a, p);
     hipLaunchKernelGGL(k_pscatter, dim3(n_cu * 4), dim3(kBlock), sizeof(PShared), s, a);
     return hipGetLastError();
