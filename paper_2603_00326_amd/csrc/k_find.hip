@@ -199,26 +199,16 @@ __device__ __forceinline__ void write_zero_row(const FindArgs& A, int q) {
     for (int e = lane_id(); e < n; e += kWave) row[e] = 0;
 }
 
-// Histogram accessors: h(b, c) is the count of class c in bin b; load4(b0, c,
-// B) gives bins b0..b0+3 of class c (0 for bins >= B).
-struct LdsHist {      // bin-major h[b * C + c] (big-node chunk histograms)
-    const int32_t* h;
-    int C;
-    __device__ uint32_t operator()(int b, int c) const { return (uint32_t)h[b * C + c]; }
-    __device__ uint4 load4(int b0, int c, int B) const {
-        uint4 v;
-        v.x = b0 < B ? (uint32_t)h[b0 * C + c] : 0u;
-        v.y = b0 + 1 < B ? (uint32_t)h[(b0 + 1) * C + c] : 0u;
-        v.z = b0 + 2 < B ? (uint32_t)h[(b0 + 2) * C + c] : 0u;
-        v.w = b0 + 3 < B ? (uint32_t)h[(b0 + 3) * C + c] : 0u;
-        return v;
-    }
-};
-struct LdsHistCM {    // class-major h[c * Bs + b], Bs a multiple of 4, bins B..Bs-1 zero
-    const int32_t* h;
+// Histogram accessor over a wave's class-major LDS histogram h[c * Bs + b]
+// (Bs a multiple of 4, bins B..Bs-1 zero): h(b, c) is the count of class c in
+// bin b; load4/store4 move bins b0..b0+3 of class c as one 16-byte access.
+// The boundary scan overwrites the counts with left counts (prefix sums).
+struct LdsHistCM {
+    int32_t* h;
     int Bs;
     __device__ uint32_t operator()(int b, int c) const { return (uint32_t)h[c * Bs + b]; }
-    __device__ uint4 load4(int b0, int c, int) const { return *(const uint4*)(h + c * Bs + b0); }
+    __device__ uint4 load4(int b0, int c) const { return *(const uint4*)(h + c * Bs + b0); }
+    __device__ void store4(int b0, int c, uint4 v) const { *(uint4*)(h + c * Bs + b0) = v; }
 };
 
 __host__ __device__ constexpr int bins_stride(int bins) { return (bins + 3) & ~3; }
@@ -226,8 +216,10 @@ __host__ __device__ constexpr int bins_stride(int bins) { return (bins + 3) & ~3
 // ---------------------------------------------------------------------------
 // boundary scans (one wave)
 
-// Histogram path, screened scan by one wave over a histogram accessor
-// h(b, c) (lane l owns bins 4l..4l+3; B <= 256).
+// Histogram path, screened scan by one wave over a class-major histogram
+// (lane l owns bins 4l..4l+3; B <= 256).  Class by class, an integer prefix
+// over the wave gives every boundary's left count, which is written back over
+// the counts in place.
 //
 // Screening: every boundary after a non-empty bin gets an FP32 score
 // q = S_L / n_L + S_R / n_R.  Counts below 2^24 are exact in FP32, so only
@@ -235,14 +227,14 @@ __host__ __device__ constexpr int bins_stride(int bins) { return (bins + 3) & ~3
 // final product and sum round: |q - Q| <= (C + 4) 2^-24 Q <= 20 * 2^-24 Q
 // for C <= 16.  Any boundary whose exact Q could reach the largest then scores
 // at least qmax (1 - 2^-16).  Those contenders (usually one) are evaluated
-// exactly from integer left counts summed over the wave, and compared as
-// N1 D2 > N2 D1 in 128 bits, ties to the lower bin.  A boundary after an
-// empty bin repeats the previous boundary's counts, so it can never win under
-// that tie rule and is skipped.  pc: 16 ints of wave scratch in LDS.
+// exactly from their integer left counts (lane c reads class c's from LDS)
+// and compared as N1 D2 > N2 D1 in 128 bits, ties to the lower bin.  A
+// boundary after an empty bin repeats the previous boundary's counts, so it
+// can never win under that tie rule and is skipped.  pc: 16 ints of wave
+// scratch in LDS (the node's class totals).
 constexpr float kScreenKeep = 1.0f - 1.0f / 65536.0f;
 
-template <class H>
-__device__ Cand scan_hist_fast(const H& h, int B, int C, int64_t n, float lo, float scale, int32_t* pc) {
+__device__ Cand scan_hist_fast(const LdsHistCM& h, int B, int C, int64_t n, float lo, float scale, int32_t* pc) {
     const int lane = lane_id();
     const int b0 = lane * 4;
     const float nf = (float)n;
@@ -250,24 +242,24 @@ __device__ Cand scan_hist_fast(const H& h, int B, int C, int64_t n, float lo, fl
     uint32_t filled = 0;
     uint64_t SP = 0;
     for (int c = 0; c < C; ++c) {
-        uint32_t hv[4] = {0u, 0u, 0u, 0u};
-        if (b0 < B) {
-            const uint4 q4 = h.load4(b0, c, B);
-            hv[0] = q4.x; hv[1] = q4.y; hv[2] = q4.z; hv[3] = q4.w;
-        }
-        const float s0 = (float)hv[0], s1 = s0 + (float)hv[1], s2 = s1 + (float)hv[2], s3 = s2 + (float)hv[3];
-        const float incl = wave_scan_f(s3);
-        const float excl = incl - s3;
-        const float Pc = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(incl), 63));
-        const uint32_t Pi = (uint32_t)Pc;
+        uint4 q4 = make_uint4(0u, 0u, 0u, 0u);
+        if (b0 < B) q4 = h.load4(b0, c);
+        const uint32_t s0 = q4.x, s1 = s0 + q4.y, s2 = s1 + q4.z, s3 = s2 + q4.w;
+        const uint32_t incl = wave_scan_u(s3);
+        const uint32_t excl = incl - s3;
+        const uint32_t Pi = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
         SP += (uint64_t)Pi * Pi;
         if (lane == 0) pc[c] = (int32_t)Pi;
-        const float l[4] = {excl + s0, excl + s1, excl + s2, excl + s3};
+        const uint32_t li[4] = {excl + s0, excl + s1, excl + s2, excl + s3};
+        if (b0 < B) h.store4(b0, c, make_uint4(li[0], li[1], li[2], li[3]));
+        const uint32_t hv[4] = {q4.x, q4.y, q4.z, q4.w};
+        const float Pf = (float)Pi;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const float r = Pc - l[i];
-            nL[i] += l[i];
-            SL[i] = __fmaf_rn(l[i], l[i], SL[i]);
+            const float l = (float)li[i];
+            const float r = Pf - l;
+            nL[i] += l;
+            SL[i] = __fmaf_rn(l, l, SL[i]);
             SR[i] = __fmaf_rn(r, r, SR[i]);
             if (hv[i] != 0) filled |= 1u << i;
         }
@@ -288,7 +280,8 @@ __device__ Cand scan_hist_fast(const H& h, int B, int C, int64_t n, float lo, fl
     best.scale = scale;
     if (!(qmax >= 0.f)) return best;
     const float keep = qmax * kScreenKeep;
-    wave_sync();   // pc[] written by lane 0 is read by every lane below
+    wave_sync();   // pc[] and the left counts written above are read by other lanes below
+    const uint32_t pcv = lane < C ? (uint32_t)pc[lane] : 0u;
     bool have = false;
     u128 bN = 0;
     uint64_t bD = 0, bSL = 0, bSR = 0;
@@ -301,15 +294,12 @@ __device__ Cand scan_hist_fast(const H& h, int B, int C, int64_t n, float lo, fl
             const int ln = __builtin_ctzll(m);
             m &= m - 1;
             const int b = ln * 4 + i;
+            const uint32_t lcv = lane < C ? h(b, lane) : 0u;
             uint32_t nLx = 0;
             uint64_t SLx = 0, SRx = 0;
             for (int c = 0; c < C; ++c) {
-                uint32_t part = 0;
-#pragma unroll
-                for (int t = 0; t < 4; ++t)
-                    if (b0 + t <= b && b0 + t < B) part += h(b0 + t, c);
-                const uint32_t lc = wave_sum_u(part);
-                const uint32_t rc = (uint32_t)pc[c] - lc;
+                const uint32_t lc = (uint32_t)__builtin_amdgcn_readlane((int)lcv, c);
+                const uint32_t rc = (uint32_t)__builtin_amdgcn_readlane((int)pcv, c) - lc;
                 nLx += lc;
                 SLx += (uint64_t)lc * lc;
                 SRx += (uint64_t)rc * rc;
@@ -1042,15 +1032,18 @@ __global__ __launch_bounds__(kBlock) void k_bscan(FindArgs A, PS P) {
         const int B = node_bins(A, bd.node);
         int64_t s0, n;
         node_range(A, bd.node, s0, n);
-        for (int q = lane; q < B * C; q += kWave) {
+        const int Bs = bins_stride(Bm);
+        for (int e = lane; e < C * Bs; e += kWave) {
+            const int c = e / Bs, b = e - c * Bs;
             int32_t acc = 0;
-            for (int ch = 0; ch < bd.nchunk; ++ch) acc += W.chist[(base + ch) * Bm * C + q];
-            hist[q] = acc;
+            if (b < B)
+                for (int ch = 0; ch < bd.nchunk; ++ch) acc += W.chist[(base + ch) * Bm * C + b * C + c];
+            hist[e] = acc;
         }
         wave_sync();
         const float2 r = W.brange[bd.bigslot + p];
         const float scale = bin_scale(B, r.x, r.y);
-        LdsHist h{hist, C};
+        LdsHistCM h{hist, Bs};
         write_hist_row(A, proj_global(P, bd.node, p), h, B);
         Cand c = scan_hist_fast(h, B, C, n, r.x, scale, block_shared(smem).w[w].pcs);
         c.proj = p;
