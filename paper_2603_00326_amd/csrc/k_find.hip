@@ -1056,7 +1056,7 @@ __global__ __launch_bounds__(kBlock) void k_bscan(FindArgs A, PS P) {
 // kSmallMax+1 .. kMidSplit (up to 16 per thread).  Separate kernels so that
 // each gets the register allocation of its own size class.
 template <typename T, class PS, bool kLarge>
-__global__ __launch_bounds__(kBlock) void k_mid(FindArgs A, PS P) {
+__global__ __launch_bounds__(kBlock, kLarge ? 1 : 4) void k_mid(FindArgs A, PS P) {
     extern __shared__ __align__(16) char smem[];
     BlockShared& S = block_shared(smem);
     const FindWs& W = A.ws;
@@ -1087,7 +1087,7 @@ __global__ __launch_bounds__(kBlock) void k_mid(FindArgs A, PS P) {
 }
 
 template <typename T, class PS>
-__global__ __launch_bounds__(kBlock) void k_small(FindArgs A, PS P) {
+__global__ __launch_bounds__(kBlock, 4) void k_small(FindArgs A, PS P) {
     extern __shared__ __align__(16) char smem[];
     BlockShared& S = block_shared(smem);
     const FindWs& W = A.ws;
