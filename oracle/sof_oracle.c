@@ -26,6 +26,15 @@
  *        t     = (v - lo) * scale
  *        bin   = t < B ? trunc(t) : B - 1
  *     Candidate split after bin b (b = 0..B-2): left = samples with bin <= b.
+ *  3''. Random-width bins (the Introduction's footnote: bin boundaries at
+ *     random-width intervals; the paper gives no sampling rule, so this one is
+ *     a reading): for projection q (its index in the call) the B bin widths are
+ *     integers g_j = 1 + (bits 63..48 of SplitMix64 output 256 q + j of the
+ *     stream started at the seed), G_i = g_0 + ... + g_{i-1} (exact, G_B <=
+ *     2^24), and boundary i = 1..B-1 is t_i = lo + (G_i / G_B) * (hi - lo),
+ *     each operation rounded once.  A value's bin is the number of boundaries
+ *     <= v (std::upper_bound), so bin(v) <= b iff v < t_{b+1}: the split keeps
+ *     t_{b+1} as its threshold.
  *  3'. Sort path (section 4.1: sorting for low-cardinality nodes): sort the
  *     projected values; candidates between sorted positions i and i+1 where
  *     v_(i) < v_(i+1), left = first i+1 samples, threshold v_(i).
@@ -134,6 +143,32 @@ int or_bin_index(float v, float lo, float scale, int n_bins)
     return t < (float)n_bins ? (int)t : n_bins - 1;
 }
 
+/* Random-width boundaries t[0..B-2] of projection q (step 3'' above). */
+void or_rw_boundaries(uint64_t seed, int64_t q, int n_bins, float lo, float hi, float* t)
+{
+    uint32_t G[257];
+    G[0] = 0;
+    for (int j = 0; j < n_bins; ++j)
+        G[j + 1] = G[j] + 1u + (uint32_t)(or_hash(seed, (uint64_t)q * 256u + (uint64_t)j) >> 48);
+    float width = hi - lo;
+    float total = (float)G[n_bins];
+    for (int i = 1; i < n_bins; ++i) {
+        float r = (float)G[i] / total;
+        float off = r * width;
+        t[i - 1] = lo + off;
+    }
+}
+
+/* Random-width bin of v: how many of the B-1 boundaries are <= v. */
+int or_rw_bin(const float* t, int n_bins, float v)
+{
+    int b = 0;
+    for (int i = 0; i + 1 < n_bins; ++i)
+        if (t[i] <= v)
+            ++b;
+    return b;
+}
+
 /* ------------------------------------------------------------------------ */
 /* step 4: exact candidate comparison                                        */
 /* ------------------------------------------------------------------------ */
@@ -208,6 +243,7 @@ static int effective_threshold(int32_t T)
 static void eval_projection(const void* x, int dtype, int64_t ld, const int32_t* y, int C,
                             const int32_t* idx, int32_t n, const int64_t* parent,
                             const int32_t* feat, const int8_t* w, int z, int B, int sort_path,
+                            int bin_mode, uint64_t bin_seed, int64_t q,
                             cand_t* best, int32_t* hist_row, int32_t bins_stride)
 {
     memset(best, 0, sizeof(*best));
@@ -221,9 +257,14 @@ static void eval_projection(const void* x, int dtype, int64_t ld, const int32_t*
     int64_t* l = (int64_t*)calloc((size_t)C, sizeof(int64_t));
     if (!sort_path) {
         float scale = or_bin_scale(B, lo, hi);
+        float t[256];
+        if (bin_mode == OR_BINS_RANDOM)
+            or_rw_boundaries(bin_seed, q, B, lo, hi, t);
         int64_t* H = (int64_t*)calloc((size_t)B * C, sizeof(int64_t));
-        for (int32_t i = 0; i < n; ++i)
-            H[(int64_t)or_bin_index(v[i], lo, scale, B) * C + y[idx[i]]] += 1;
+        for (int32_t i = 0; i < n; ++i) {
+            int b = bin_mode == OR_BINS_RANDOM ? or_rw_bin(t, B, v[i]) : or_bin_index(v[i], lo, scale, B);
+            H[(int64_t)b * C + y[idx[i]]] += 1;
+        }
         if (hist_row)
             for (int b = 0; b < B; ++b)
                 for (int c = 0; c < C; ++c)
@@ -231,7 +272,7 @@ static void eval_projection(const void* x, int dtype, int64_t ld, const int32_t*
         for (int b = 0; b + 1 < B; ++b) {
             for (int c = 0; c < C; ++c)
                 l[c] += H[(int64_t)b * C + c];
-            float thr = lo + ((float)(b + 1) / scale);
+            float thr = bin_mode == OR_BINS_RANDOM ? t[b] : lo + ((float)(b + 1) / scale);
             consider(best, l, parent, C, n, b, thr, lo, scale);
         }
         free(H);
@@ -269,6 +310,7 @@ int or_find_splits(const void* x, int dtype, int64_t ld, const int32_t* y, int32
                    const int32_t* proj_offsets, const int32_t* nz_offsets,
                    const int32_t* nz_feature, const int8_t* nz_weight,
                    const int32_t* node_bins, int32_t bins, int32_t sort_threshold,
+                   int32_t bin_mode, uint64_t bin_seed,
                    or_split* out, int32_t* hist_out, int32_t n_threads)
 {
     int32_t P = proj_offsets[n_nodes];
@@ -297,11 +339,12 @@ int or_find_splits(const void* x, int dtype, int64_t ld, const int32_t* y, int32
         int32_t j0 = nz_offsets[q], z = nz_offsets[q + 1] - j0;
         int32_t* hrow = (hist_out && !sort_path) ? hist_out + (int64_t)q * bins * C : NULL;
         eval_projection(x, dtype, ld, y, C, sample_idx + s0, n, parent + (int64_t)v * C,
-                        nz_feature + j0, nz_weight + j0, z, B, sort_path, &cands[q], hrow, bins);
+                        nz_feature + j0, nz_weight + j0, z, B, sort_path, bin_mode, bin_seed, q,
+                        &cands[q], hrow, bins);
     }
     for (int32_t v = 0; v < n_nodes; ++v) {
         int32_t n = node_offsets[v + 1] - node_offsets[v];
-        int kind = n < T ? 1 : 0;
+        int kind = n < T ? 1 : (bin_mode == OR_BINS_RANDOM ? 2 : 0);
         int32_t bestq = -1;
         for (int32_t q = proj_offsets[v]; q < proj_offsets[v + 1]; ++q) {
             if (!cands[q].valid)
@@ -354,6 +397,8 @@ static int goes_left(const void* x, int dtype, int64_t ld, const int32_t* feat, 
     float v = or_project_value(x, dtype, ld, feat, w, z, row);
     if (s->kind == 0)
         return or_bin_index(v, s->lo, s->scale, B) <= s->bin;
+    if (s->kind == 2)
+        return v < s->threshold;   /* random-width: bin(v) <= bin iff v < t_{bin+1} */
     return v <= s->threshold;
 }
 
@@ -554,7 +599,7 @@ int64_t or_grow_forest(const void* x, int dtype, int64_t ld, int32_t d,
         if (level_nodes) level_nodes[level] = N;
         if (level_units) level_units[level] = (int64_t)off[N] * k;
         or_split* sp = (or_split*)malloc(sizeof(or_split) * (size_t)N);
-        or_find_splits(x, dtype, ld, y, C, N, off, sidx, po, no, nf, nw, NULL, bins, sort_threshold,
+        or_find_splits(x, dtype, ld, y, C, N, off, sidx, po, no, nf, nw, NULL, bins, sort_threshold, OR_BINS_EQUAL, 0,
                        sp, NULL, n_threads);
         int32_t* pidx = (int32_t*)malloc(sizeof(int32_t) * (size_t)(off[N] > 0 ? off[N] : 1));
         int32_t* coff = (int32_t*)malloc(sizeof(int32_t) * (size_t)(2 * N + 1));

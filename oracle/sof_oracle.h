@@ -35,11 +35,17 @@ extern "C" {
  * threshold above OR_SORT_LIMIT + 1 acts as OR_SORT_LIMIT + 1. */
 #define OR_SORT_LIMIT 8192
 
+/* Bin layouts of the histogram path. */
+#define OR_BINS_EQUAL  0
+#define OR_BINS_RANDOM 1
+
 typedef struct {
     int32_t proj;      /* node-local index of the winning projection, -1 = no split */
-    int32_t kind;      /* 0 = histogram path, 1 = sort path (the node's path even without a split) */
+    int32_t kind;      /* 0 = histogram path (equal width), 1 = sort path, 2 = histogram path
+                          (random width); the node's path even without a split */
     int32_t bin;       /* hist: left iff bin(v) <= bin; sort: sorted position, left = first bin+1 */
-    float   threshold; /* sort: left iff v <= threshold; hist: lo + (bin+1)/scale (informational) */
+    float   threshold; /* sort: left iff v <= threshold; random width: left iff v < threshold
+                          (= boundary bin+1); equal width: lo + (bin+1)/scale (informational) */
     float   lo;        /* minimum projected value of the winning projection */
     float   scale;     /* hist: B / (hi - lo) with the overflow guard; sort: 0 */
     int32_t n_left, n_right;
@@ -70,6 +76,11 @@ float or_project_value(const void* x, int dtype, int64_t ld, const int32_t* feat
 float or_bin_scale(int n_bins, float lo, float hi);
 int   or_bin_index(float v, float lo, float scale, int n_bins);
 
+/* Random-width boundaries t[0..n_bins-2] of projection q, and the bin of v
+ * (the number of boundaries <= v). */
+void or_rw_boundaries(uint64_t seed, int64_t q, int n_bins, float lo, float hi, float* t);
+int  or_rw_bin(const float* t, int n_bins, float v);
+
 /* Projected values of every (node, projection, sample), node blocks in node
  * order, each block laid out [projection][sample]. */
 void or_project(const void* x, int dtype, int64_t ld, int32_t n_nodes,
@@ -85,6 +96,7 @@ int or_find_splits(const void* x, int dtype, int64_t ld, const int32_t* y, int32
                    const int32_t* proj_offsets, const int32_t* nz_offsets,
                    const int32_t* nz_feature, const int8_t* nz_weight,
                    const int32_t* node_bins, int32_t bins, int32_t sort_threshold,
+                   int32_t bin_mode, uint64_t bin_seed,
                    or_split* out, int32_t* hist_out, int32_t n_threads);
 
 /* Stable partition of every node's samples by its split: left block (input

@@ -7,6 +7,7 @@ invariants that any correct split search satisfies.
 """
 from __future__ import annotations
 
+import bisect
 import math
 import os
 from fractions import Fraction
@@ -20,7 +21,7 @@ from tests import bruteforce as BF
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 
-def one_node(X, y, C, feats, weights, *, T=0, bins=256, idx=None, hist=False):
+def one_node(X, y, C, feats, weights, *, T=0, bins=256, idx=None, hist=False, bin_mode=0, bin_seed=0):
     """Run the oracle on a single node holding all rows of X (or idx)."""
     n_rows = X.shape[1]
     idx = np.arange(n_rows, dtype=np.int32) if idx is None else np.asarray(idx, np.int32)
@@ -31,7 +32,7 @@ def one_node(X, y, C, feats, weights, *, T=0, bins=256, idx=None, hist=False):
     nw = np.concatenate([np.asarray(w, np.int8) for w in weights])
     sp, H = O.find_splits(X, y, C, np.array([0, len(idx)], np.int32), idx,
                           np.array([0, k], np.int32), nz_off, nf, nw, bins=bins,
-                          sort_threshold=T, hist=hist)
+                          sort_threshold=T, hist=hist, bin_mode=bin_mode, bin_seed=bin_seed)
     return sp[0], H, (nz_off, nf, nw)
 
 
@@ -553,3 +554,116 @@ def test_growth_batched_equals_single_tree():
         single, _, _ = O.grow_forest(X, y, C, np.array([0, n], np.int64), roots[t], k=5, z=2, seed=4,
                                      bins=32, sort_threshold=20, first_tree=t)
         assert renumber_tree(nodes, t).tobytes() == single.tobytes()
+
+
+# --------------------------------------------------------------------------
+# random-width bins (bin boundaries at random-width intervals)
+# --------------------------------------------------------------------------
+
+def test_rw_boundaries_sorted_in_range_and_unbiased():
+    # The widths are i.i.d., so over many projections boundary i sits on
+    # average at i/B of [lo, hi]; a slip in the prefix index (G_{i+1} for G_i)
+    # moves every mean by 1/B, far outside the tolerance.
+    for B in (2, 3, 16, 256):
+        m = 3000
+        acc = np.zeros(B - 1)
+        for q in range(m):
+            t = O.rw_boundaries(7, q, B, 0.0, 1.0)
+            assert len(t) == B - 1
+            assert np.all(np.diff(t) >= 0) and t[0] >= 0.0
+            assert t[-1] <= np.nextafter(np.float32(1.0), np.float32(2.0))
+            acc += t
+        mean = acc / m
+        want = np.arange(1, B) / B
+        assert np.max(np.abs(mean - want)) < 0.4 / B, (B, np.max(np.abs(mean - want)))
+    a = O.rw_boundaries(1, 5, 64, -2.0, 3.0)
+    assert np.array_equal(a, O.rw_boundaries(1, 5, 64, -2.0, 3.0))
+    assert not np.array_equal(a, O.rw_boundaries(2, 5, 64, -2.0, 3.0))
+    assert not np.array_equal(a, O.rw_boundaries(1, 6, 64, -2.0, 3.0))
+
+
+def test_rw_bin_is_upper_bound():
+    rng = np.random.default_rng(77)
+    for trial in range(200):
+        B = int(rng.choice([2, 3, 5, 16, 64, 256]))
+        lo, hi = sorted((rng.normal(size=2) * rng.choice([1e-3, 1.0, 1e3])).astype(np.float32).tolist())
+        t = O.rw_boundaries(trial, 3 * trial, B, lo, hi)
+        probe = np.concatenate([rng.uniform(lo, hi, 40).astype(np.float32), t,
+                                np.nextafter(t, np.float32(-np.inf)), np.nextafter(t, np.float32(np.inf)),
+                                np.array([lo, hi], np.float32)])
+        tl = [float(x) for x in t]
+        for v in probe:
+            assert O.rw_bin(t, B, v) == bisect.bisect_right(tl, float(v))
+
+
+@pytest.mark.parametrize("seed", range(60))
+def test_rw_hist_path_matches_bruteforce(seed):
+    # integer projected values (exact in FP32); the bins come from the oracle's
+    # boundaries through bisect, the best split from exact rationals
+    rng = np.random.default_rng(5000 + seed)
+    n = int(rng.integers(2, 14))
+    C = int(rng.integers(2, 5))
+    d = 5
+    Xi = rng.integers(-int(rng.choice([4, 1000])), 1001, size=(d, n))
+    y = rng.integers(0, C, size=n).astype(np.int32)
+    k = int(rng.integers(1, 5))
+    B = int(rng.choice([2, 3, 4, 8, 16, 100, 256]))
+    bseed = int(rng.integers(0, 2**63))
+    feats, weights = random_projs(rng, k, d, 3)
+    vals = exact_values(Xi, feats, weights, range(n))
+    bins, bounds = [], []
+    for p, vs in enumerate(vals):
+        t = O.rw_boundaries(bseed, p, B, float(min(vs)), float(max(vs)))
+        bounds.append(t)
+        tl = [float(x) for x in t]
+        bins.append([bisect.bisect_right(tl, float(v)) for v in vs])
+    want = BF.best_bin_split(bins, y.tolist(), C, B)
+    sp, H, _ = one_node(Xi.astype(np.float32), y, C, feats, weights, T=0, bins=B, hist=True,
+                        bin_mode=O.BINS_RANDOM, bin_seed=bseed)
+    assert sp["kind"] == 2
+    for p in range(k):
+        for b in range(B):
+            for c in range(C):
+                assert H[p, b, c] == sum(1 for kk, yy in zip(bins[p], y) if kk == b and yy == c)
+    if want is None:
+        assert sp["proj"] == -1 and sp["gain"] == 0.0
+        return
+    g, p, b, n_left = want
+    assert (sp["proj"], sp["bin"], sp["n_left"]) == (p, b, n_left)
+    assert sp["threshold"] == bounds[p][b]
+    assert sum(1 for v in vals[p] if v < float(bounds[p][b])) == n_left
+    assert abs(Fraction(float(sp["gain"])) - g) <= g * Fraction(1, 2**50)
+
+
+def test_rw_partition_sends_values_below_the_threshold_left():
+    rng = np.random.default_rng(91)
+    d, n_rows = 10, 6000
+    X = rng.standard_normal((d, n_rows)).astype(np.float32)
+    y = rng.integers(0, 3, n_rows).astype(np.int32)
+    sizes = [0, 1, 2, 5, 64, 300, 1000, 2500]
+    offs = np.zeros(len(sizes) + 1, np.int32)
+    offs[1:] = np.cumsum(sizes)
+    idx = rng.permutation(n_rows)[:offs[-1]].astype(np.int32)
+    k = 4
+    po = (np.arange(len(sizes) + 1) * k).astype(np.int32)
+    feats, weights = random_projs(rng, k * len(sizes), d, 3)
+    zo = np.zeros(len(feats) + 1, np.int32)
+    zo[1:] = np.cumsum([len(f) for f in feats])
+    nf = np.concatenate([np.asarray(f, np.int32) for f in feats])
+    nw = np.concatenate([np.asarray(w, np.int8) for w in weights])
+    sp, _ = O.find_splits(X, y, 3, offs, idx, po, zo, nf, nw, bins=64, sort_threshold=0,
+                          bin_mode=O.BINS_RANDOM, bin_seed=123)
+    out, coff = O.partition(X, offs, idx, po, zo, nf, nw, sp, bins=64)
+    for v in range(len(sizes)):
+        a, b = offs[v], offs[v + 1]
+        assert sp[v]["kind"] == 2
+        if sp[v]["proj"] < 0:
+            assert coff[2 * v + 1] == b
+            continue
+        q = po[v] + sp[v]["proj"]
+        f, w = nf[zo[q]:zo[q + 1]], nw[zo[q]:zo[q + 1]]
+        vals = np.array([O.project_value(X, f, w, r) for r in idx[a:b]], np.float32)
+        left = idx[a:b][vals < sp[v]["threshold"]]
+        right = idx[a:b][~(vals < sp[v]["threshold"])]
+        assert coff[2 * v + 1] - a == sp[v]["n_left"] == left.size
+        assert np.array_equal(out[a:b], np.concatenate([left, right]))
