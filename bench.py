@@ -38,6 +38,7 @@ WORKLOADS = {
     "c3a": "batched frontier, 4096 log-normal nodes (median 300, 2..100000, ~4.0M samples) over a "
            "4.0M x 512 FP32 matrix, node rows contiguous, 3 classes, k=64, z=4, B=256",
     "c3b": "as c3a, each node's rows an ascending random subset of the matrix",
+    "c3a_rw": "as c3a with random-width bins (boundaries at random-width intervals, two-level routing)",
     "c2": "single root node, n=1048576, d=256 FP32, 2 classes, k=256, z=3, B=256, histogram path",
     "c5": "single root node, n=10M, d=128 FP16 on the 1/256 grid, 2 classes, k=128, z=1..8, B=256",
     "c5f32": "as c5 with the same values stored FP32",
@@ -57,6 +58,10 @@ def make_workload(name: str):
         return W.config3("a")
     if name == "c3b":
         return W.config3("b")
+    if name == "c3a_rw":
+        wl = W.config3("a")
+        wl.meta.update(bin_mode=1, bin_seed=20260302)
+        return wl
     if name == "c2":
         return W.config2()
     if name == "c5":
@@ -192,7 +197,9 @@ def cpu_baseline(wl, T, budget_units: float):
         t0 = time.perf_counter()
         ref, _ = O.find_splits(sample.X, sample.y, sample.n_classes, sample.node_offsets, sample.sample_idx,
                                sample.proj_offsets, sample.nz_offsets, sample.nz_feature, sample.nz_weight,
-                               bins=sample.bins, sort_threshold=T, node_bins=sample.node_bins, threads=nt)
+                               bins=sample.bins, sort_threshold=T, node_bins=sample.node_bins, threads=nt,
+                               bin_mode=int(wl.meta.get("bin_mode", 0)),
+                               bin_seed=int(wl.meta.get("bin_seed", 0)))
         O.partition(sample.X, sample.node_offsets, sample.sample_idx, sample.proj_offsets, sample.nz_offsets,
                     sample.nz_feature, sample.nz_weight, ref, bins=sample.bins, node_bins=sample.node_bins)
         return time.perf_counter() - t0
@@ -253,7 +260,8 @@ class PlainForm:
             oidx = torch.empty(max(n, 1), dtype=torch.int32, device=dv)
             coff = torch.empty(3, dtype=torch.int32, device=dv)
             d, fr, p = f.structs()
-            q = S.sof_params(S._ptr(nb), int(wl.bins), int(T))
+            q = S.sof_params(S._ptr(nb), int(wl.bins), int(T), int(wl.meta.get("bin_mode", 0)), 0,
+                             int(wl.meta.get("bin_seed", 0)))
             sz = ctypes.c_size_t(0)
             S._check(S.lib().sof_workspace_size(ctx.handle, ctypes.byref(d), ctypes.byref(fr), ctypes.byref(p),
                                                 ctypes.byref(q), ctypes.byref(sz)))
@@ -450,8 +458,11 @@ def main():
     stream = torch.cuda.current_stream()
     out = torch.empty((max(wl.n_nodes, 1), 10), dtype=torch.int32, device=dev_name)
 
+    bin_mode = int(wl.meta.get("bin_mode", 0))
+    bin_seed = int(wl.meta.get("bin_seed", 0))
+
     def step():
-        S.find_splits(ctx, dev, bins=wl.bins, sort_threshold=T, out=out)
+        S.find_splits(ctx, dev, bins=wl.bins, sort_threshold=T, out=out, bin_mode=bin_mode, bin_seed=bin_seed)
         S.partition(ctx, dev, out, bins=wl.bins)
 
     for _ in range(args.warmup):
@@ -502,7 +513,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "description": WORKLOADS[args.workload],
                    "nodes": wl.n_nodes, "samples": int(wl.n_samples), "units": int(wl.units),
-                   "sort_threshold": T, "bins": wl.bins, "step": "find_splits + partition"},
+                   "sort_threshold": T, "bins": wl.bins,
+                   "bin_layout": "random width" if bin_mode else "equal width",
+                   "step": "find_splits + partition"},
         "roofline": roof,
         "find_splits": {"ms": round(per["total"], 4), "algorithmic_bytes": sb["find"],
                         "achieved_GBs": round(find_gbs, 1), "frac": round(find_gbs / HBM_PEAK_GBS, 4),

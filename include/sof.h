@@ -76,8 +76,13 @@ extern "C" {
 #define SOF_WORKSPACE_ALIGN  256
 
 /* split kinds */
-#define SOF_SPLIT_HIST 0
-#define SOF_SPLIT_SORT 1
+#define SOF_SPLIT_HIST  0   /* histogram path, equal-width bins */
+#define SOF_SPLIT_SORT  1   /* sort path */
+#define SOF_SPLIT_RHIST 2   /* histogram path, random-width bins */
+
+/* bin layouts of the histogram path (sof_params.bin_mode) */
+#define SOF_BINS_EQUAL  0
+#define SOF_BINS_RANDOM 1
 
 typedef struct sof_ctx sof_ctx;
 typedef struct sof_forest sof_forest;
@@ -110,18 +115,31 @@ typedef struct {
     int32_t        max_proj_per_node; /* >= every node's projection count, <= 1024 */
 } sof_proj;
 
+/* Histogram bins.  SOF_BINS_EQUAL: B equal-width bins over [lo, hi] (the
+ * Method section's "few arithmetic operations" binning).  SOF_BINS_RANDOM:
+ * boundaries at random-width intervals (the Introduction's footnote; the
+ * paper gives no sampling rule, so this one is the library's): for the q-th
+ * projection of the call (q = proj_offsets[v] + p) the bin widths are
+ * g_j = 1 + (bits 63..48 of SplitMix64 output 256 q + j of the stream started
+ * at bin_seed), j = 0..B-1; with G_i = g_0 + ... + g_{i-1}, boundary i
+ * (i = 1..B-1) is lo + (G_i / G_B) * (hi - lo), each operation one FP32
+ * rounding, and a value's bin is the number of boundaries <= v. */
 typedef struct {
     const int32_t* node_bins;     /* device, n_nodes bin counts in [2, bins], or NULL */
     int32_t        bins;          /* 2..SOF_MAX_BINS: bin count when node_bins is NULL, else the maximum */
     int32_t        sort_threshold;/* nodes with n < min(T, SOF_SORT_LIMIT + 1) sort; 0 = all histogram */
+    int32_t        bin_mode;      /* SOF_BINS_EQUAL or SOF_BINS_RANDOM */
+    int32_t        pad;
+    uint64_t       bin_seed;      /* SOF_BINS_RANDOM: seed of the widths */
 } sof_params;
 
 /* Best split of one node (section 4.3: the projection and its split value). */
 typedef struct {
     int32_t proj;       /* node-local index of the winning projection, -1 = no split */
-    int32_t kind;       /* SOF_SPLIT_HIST or SOF_SPLIT_SORT: the node's path (also without a split) */
+    int32_t kind;       /* SOF_SPLIT_HIST, _SORT or _RHIST: the node's path (also without a split) */
     int32_t bin;        /* hist: left iff bin(v) <= bin; sort: sorted position, left = first bin+1; -1 */
-    float   threshold;  /* sort: left iff v <= threshold; hist: lo + (bin+1)/scale, informational */
+    float   threshold;  /* sort: left iff v <= threshold; random-width hist: left iff v < threshold
+                           (boundary bin+1); equal-width hist: lo + (bin+1)/scale, informational */
     float   lo;         /* min projected value of the winner */
     float   scale;      /* hist: bins / (hi - lo), FLT_MAX if that is not finite; sort: 0 */
     int32_t n_left;     /* no split: n_left = n, n_right = 0 */

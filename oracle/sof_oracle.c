@@ -159,14 +159,19 @@ void or_rw_boundaries(uint64_t seed, int64_t q, int n_bins, float lo, float hi, 
     }
 }
 
-/* Random-width bin of v: how many of the B-1 boundaries are <= v. */
+/* Random-width bin of v: how many of the B-1 (ascending) boundaries are <=
+ * v, i.e. std::upper_bound's index, by binary search. */
 int or_rw_bin(const float* t, int n_bins, float v)
 {
-    int b = 0;
-    for (int i = 0; i + 1 < n_bins; ++i)
-        if (t[i] <= v)
-            ++b;
-    return b;
+    int lo = 0, hi = n_bins - 1;
+    while (lo < hi) {
+        int mid = lo + (hi - lo) / 2;
+        if (t[mid] <= v)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
 }
 
 /* ------------------------------------------------------------------------ */

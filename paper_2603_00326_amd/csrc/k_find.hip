@@ -325,6 +325,113 @@ __device__ Cand scan_hist_fast(const LdsHistCM& h, int B, int C, int64_t n, floa
     return best;
 }
 
+// ---------------------------------------------------------------------------
+// Histogram bins of one projection.  Equal width: the closed-form index.
+// Random width (bin boundaries at random-width intervals, after the
+// Introduction's footnote; the sampling rule is this library's reading): the
+// B widths of the call's q-th projection are g_j = 1 + (bits 63..48 of
+// SplitMix64 output 256 q + j), G_i = g_0 + ... + g_{i-1} (exact integers,
+// G_B <= 2^24), boundary i = 1..B-1 is lo + (G_i / G_B) (hi - lo) with each
+// operation rounded once, and a value's bin is the number of boundaries <= v.
+//
+// Routing without a search over the boundaries: a wave builds, per
+// projection, a table over kRwCells equal-width cells of [lo, hi] with lut[c]
+// = the number of boundaries whose cell is below c.  The cell index is
+// monotone in the value, so a boundary in an earlier cell is < v and one in a
+// later cell is > v: bin(v) = lut[c(v)] + the boundaries of cell c(v) that are
+// <= v (usually none or one, found by a short binary search).
+
+struct EqualBins {
+    float lo, scale;
+    int B;
+    __device__ int operator()(float v) const { return bin_index(v, lo, scale, B); }
+};
+
+constexpr int kRwCells = 511;
+
+struct RwTable {
+    float t[256];                  // boundary i+1 at t[i] (i < B-1), +inf above
+    int32_t lut[kRwCells + 1];
+};
+
+__device__ __forceinline__ float rw_cell_scale(float lo, float hi) {
+    float s = __fdiv_rn((float)kRwCells, __fsub_rn(hi, lo));
+    return s <= FLT_MAX ? s : FLT_MAX;
+}
+__device__ __forceinline__ int rw_cell(float x, float lo, float sc) {
+    const float t = __fmul_rn(__fsub_rn(x, lo), sc);
+    return t < (float)kRwCells ? (int)t : kRwCells - 1;
+}
+__device__ __forceinline__ uint32_t rw_width(uint64_t seed, int64_t q, int j) {
+    return 1u + (uint32_t)(splitmix_at(seed, (uint64_t)q * 256u + (uint64_t)j) >> 48);
+}
+
+// Build projection q's table (one wave, every lane; lane l owns bins 4l..4l+3).
+__device__ void rw_build(RwTable& T, uint64_t seed, int64_t q, int B, float lo, float hi, float sc) {
+    const int lane = lane_id();
+    uint32_t g[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) g[i] = 4 * lane + i < B ? rw_width(seed, q, 4 * lane + i) : 0u;
+    const uint32_t s0 = g[0], s1 = s0 + g[1], s2 = s1 + g[2], s3 = s2 + g[3];
+    const uint32_t incl = wave_scan_u(s3);
+    const uint32_t ex = incl - s3;
+    const float tot = (float)(uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+    const float wd = __fsub_rn(hi, lo);
+    const uint32_t G[4] = {ex + s0, ex + s1, ex + s2, ex + s3};   // G_{j+1}, j = 4 lane + i
+    float tv[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        tv[i] = 4 * lane + i < B - 1 ? __fadd_rn(lo, __fmul_rn(__fdiv_rn((float)G[i], tot), wd)) : INFINITY;
+    *(float4*)&T.t[4 * lane] = make_float4(tv[0], tv[1], tv[2], tv[3]);
+    *(int4*)&T.lut[8 * lane] = make_int4(0, 0, 0, 0);
+    *(int4*)&T.lut[8 * lane + 4] = make_int4(0, 0, 0, 0);
+    wave_sync();
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        if (4 * lane + i < B - 1) atomicAdd(&T.lut[rw_cell(tv[i], lo, sc) + 1], 1);
+    wave_sync();
+    const int4 a = *(const int4*)&T.lut[8 * lane];
+    const int4 b = *(const int4*)&T.lut[8 * lane + 4];
+    const uint32_t p0 = a.x, p1 = p0 + a.y, p2 = p1 + a.z, p3 = p2 + a.w;
+    const uint32_t p4 = p3 + b.x, p5 = p4 + b.y, p6 = p5 + b.z, p7 = p6 + b.w;
+    const uint32_t e8 = wave_scan_u(p7) - p7;
+    *(int4*)&T.lut[8 * lane] = make_int4(e8 + p0, e8 + p1, e8 + p2, e8 + p3);
+    *(int4*)&T.lut[8 * lane + 4] = make_int4(e8 + p4, e8 + p5, e8 + p6, e8 + p7);
+    wave_sync();
+}
+
+struct RwBins {
+    const RwTable* T;
+    float lo, sc;
+    __device__ int operator()(float v) const {
+        const int c = rw_cell(v, lo, sc);
+        int a = T->lut[c], b = T->lut[c + 1];
+        while (a < b) {
+            const int m = (a + b) >> 1;
+            if (T->t[m] <= v) a = m + 1;
+            else b = m;
+        }
+        return a;
+    }
+};
+
+// Boundary b+1 of projection q (the random-width split threshold: bin(v) <= b
+// iff v < it), by one wave with uniform loop bounds.
+__device__ float rw_boundary(uint64_t seed, int64_t q, int B, float lo, float hi, int b) {
+    const int lane = lane_id();
+    uint32_t gb = 0, gt = 0;
+    for (int j0 = 0; j0 < 256; j0 += kWave) {
+        const int j = j0 + lane;
+        if (j < B) {
+            const uint32_t g = rw_width(seed, q, j);
+            gt += g;
+            if (j <= b) gb += g;
+        }
+    }
+    const uint32_t Gb = wave_sum_u(gb), GB = wave_sum_u(gt);
+    return __fadd_rn(lo, __fmul_rn(__fdiv_rn((float)Gb, (float)GB), __fsub_rn(hi, lo)));
+}
+
 // a better than b, ties to the lower projection
 __device__ __forceinline__ bool cand_better_proj(const Cand& a, const Cand& b) {
     if (a.D == 0) return false;
@@ -366,13 +473,18 @@ struct BlockShared {
     WaveScratch w[kWavesPerBlock];
 };
 
-size_t find_smem_main(int bins, int classes) {
-    return sizeof(BlockShared) + (size_t)kWavesPerBlock * bins_stride(bins) * classes * sizeof(int32_t);
+size_t find_smem_main(int bins, int classes, bool random_bins) {
+    return sizeof(BlockShared) + (size_t)kWavesPerBlock * bins_stride(bins) * classes * sizeof(int32_t) +
+           (random_bins ? (size_t)kWavesPerBlock * sizeof(RwTable) : 0);
 }
 
 __device__ __forceinline__ BlockShared& block_shared(char* smem) { return *(BlockShared*)smem; }
 __device__ __forceinline__ int32_t* wave_hist(char* smem, int w, int bins, int C) {
     return (int32_t*)(smem + sizeof(BlockShared)) + (size_t)w * bins_stride(bins) * C;
+}
+// the wave's random-width table (launches with random-width bins only)
+__device__ __forceinline__ RwTable& wave_rw(char* smem, int w, int bins, int C) {
+    return ((RwTable*)(smem + sizeof(BlockShared) + (size_t)kWavesPerBlock * bins_stride(bins) * C * sizeof(int32_t)))[w];
 }
 
 // block-wide min/max of per-thread values (all threads call)
@@ -549,7 +661,7 @@ __device__ __forceinline__ void stage_batch(const ProjHash& P, int v, int p0, in
 
 constexpr int kSmallR = kSmallMax / kWave;   // up to 8 samples per lane
 
-template <typename T, class PS, int R>
+template <typename T, class PS, int R, bool RW>
 __device__ void do_small_r(const FindArgs& A, const PS& P, int v, int64_t s0, int64_t n, char* smem) {
     BlockShared& S = block_shared(smem);
     const int w = threadIdx.x >> 6, lane = lane_id();
@@ -602,13 +714,24 @@ __device__ void do_small_r(const FindArgs& A, const PS& P, int v, int64_t s0, in
             const int Bs = bins_stride(Bm);
             for (int e = lane * 4; e < C * Bs; e += kWave * 4) *(int4*)(hist + e) = make_int4(0, 0, 0, 0);
             wave_sync();
+            if (RW) {
+                RwTable& tab = wave_rw(smem, w, Bm, C);
+                const float sc = rw_cell_scale(lo, hi);
+                rw_build(tab, A.bin_seed, proj_global(P, v, p), B, lo, hi, sc);
+                const RwBins bn{&tab, lo, sc};
 #pragma unroll
-            for (int r = 0; r < R; ++r)
-                if (lab[r] >= 0) atomicAdd(&hist[lab[r] * Bs + bin_index(val[r], lo, scale, B)], 1);
+                for (int r = 0; r < R; ++r)
+                    if (lab[r] >= 0) atomicAdd(&hist[lab[r] * Bs + bn(val[r])], 1);
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    if (lab[r] >= 0) atomicAdd(&hist[lab[r] * Bs + bin_index(val[r], lo, scale, B)], 1);
+            }
             wave_sync();
             LdsHistCM h{hist, Bs};
             write_hist_row(A, proj_global(P, v, p), h, B);
             c = scan_hist_fast(h, B, C, n, lo, scale, WS.pcs);
+            if (RW && c.D != 0) c.thr = rw_boundary(A.bin_seed, proj_global(P, v, p), B, lo, hi, c.pos);
             wave_sync();
         }
         c.proj = p;
@@ -626,20 +749,22 @@ __device__ void do_small_r(const FindArgs& A, const PS& P, int v, int64_t s0, in
         uint64_t SP = 0;
         for (int c = 0; c < C; ++c) SP += (uint64_t)WS.pc[c] * (uint64_t)WS.pc[c];
         b.SP = SP;
-        if (lane == 0) write_record((SplitRec*)A.out + v, b, sortp ? 1 : 0, (int32_t)n);
+        if (lane == 0)
+            write_record((SplitRec*)A.out + v, b, sortp ? SOF_SPLIT_SORT : (RW ? SOF_SPLIT_RHIST : SOF_SPLIT_HIST),
+                         (int32_t)n);
     }
 }
 
-template <typename T, class PS>
+template <typename T, class PS, bool RW>
 __device__ void do_small(const FindArgs& A, const PS& P, int v, char* smem) {
     int64_t s0, n;
     node_range(A, v, s0, n);
     if (n > kSmallMax) n = kSmallMax;   // the plan never queues larger nodes here
     const int nr = (int)((n + kWave - 1) / kWave);
-    if (nr <= 1) do_small_r<T, PS, 1>(A, P, v, s0, n, smem);
-    else if (nr <= 2) do_small_r<T, PS, 2>(A, P, v, s0, n, smem);
-    else if (nr <= 4) do_small_r<T, PS, 4>(A, P, v, s0, n, smem);
-    else do_small_r<T, PS, kSmallR>(A, P, v, s0, n, smem);
+    if (nr <= 1) do_small_r<T, PS, 1, RW>(A, P, v, s0, n, smem);
+    else if (nr <= 2) do_small_r<T, PS, 2, RW>(A, P, v, s0, n, smem);
+    else if (nr <= 4) do_small_r<T, PS, 4, RW>(A, P, v, s0, n, smem);
+    else do_small_r<T, PS, kSmallR, RW>(A, P, v, s0, n, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -654,7 +779,7 @@ constexpr int kMidR = kMidMax / kBlock;   // up to 32 samples per thread
 // histogram; finally wave j scans histogram j, so the group's scans run in
 // parallel.  Range slots glo/ghi are indexed by projection, so no slot is
 // rewritten while another wave may still read it.
-template <typename T, class PS, int R>
+template <typename T, class PS, int R, bool RW>
 __device__ void do_mid_r(const FindArgs& A, const PS& P, int4 D, int g, int64_t s0, int64_t n, char* smem) {
     BlockShared& S = block_shared(smem);
     const int tid = threadIdx.x, w = tid >> 6, lane = lane_id();
@@ -700,12 +825,27 @@ __device__ void do_mid_r(const FindArgs& A, const PS& P, int4 D, int g, int64_t 
         hi = fmaxf(fmaxf(S.ghi[j][0], S.ghi[j][1]), fmaxf(S.ghi[j][2], S.ghi[j][3]));
         const float scale = bin_scale(B, lo, hi);
         int32_t* hist = wave_hist(smem, j, Bm, C);
+        if (RW) {
+            // every wave builds projection j's table in its own slot (no block barrier)
+            RwTable& tab = wave_rw(smem, w, Bm, C);
+            const float sc = rw_cell_scale(lo, hi);
+            wave_sync();   // this wave's lookups of the previous projection are done
+            rw_build(tab, A.bin_seed, proj_global(P, v, p0 + j), B, lo, hi, sc);
+            const RwBins bn{&tab, lo, sc};
 #pragma unroll
-        for (int r = 0; r < R; ++r)
-            if (tid + (int64_t)r * kBlock < n) {
-                const int y = (int)((labp[r >> 3] >> (4 * (r & 7))) & 15u);
-                atomicAdd(&hist[y * Bs + bin_index(val[r], lo, scale, B)], 1);
-            }
+            for (int r = 0; r < R; ++r)
+                if (tid + (int64_t)r * kBlock < n) {
+                    const int y = (int)((labp[r >> 3] >> (4 * (r & 7))) & 15u);
+                    atomicAdd(&hist[y * Bs + bn(val[r])], 1);
+                }
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                if (tid + (int64_t)r * kBlock < n) {
+                    const int y = (int)((labp[r >> 3] >> (4 * (r & 7))) & 15u);
+                    atomicAdd(&hist[y * Bs + bin_index(val[r], lo, scale, B)], 1);
+                }
+        }
     }
     __syncthreads();
     if (w < np) {
@@ -715,6 +855,7 @@ __device__ void do_mid_r(const FindArgs& A, const PS& P, int4 D, int g, int64_t 
         LdsHistCM h{wave_hist(smem, w, Bm, C), Bs};
         write_hist_row(A, proj_global(P, v, p0 + w), h, B);
         Cand c = scan_hist_fast(h, B, C, n, lo, scale, S.w[w].pcs);
+        if (RW && c.D != 0) c.thr = rw_boundary(A.bin_seed, proj_global(P, v, p0 + w), B, lo, hi, c.pos);
         c.proj = p0 + w;
         if (lane == 0) ((Cand*)A.ws.slots)[D.y + p0 + w] = c;
     }
@@ -742,10 +883,10 @@ constexpr int kBR = 16;   // samples per lane per step of a chunk loop
 // Each step covers kWave * kBR samples; the next step's row ids are loaded
 // before this step's columns, and slots past the chunk's end repeat its last
 // sample (valid addresses, masked out of the result).
-template <typename T, class PS, bool kHist>
+template <typename T, class PS, bool kHist, class Bn>
 __device__ __forceinline__ void big_chunk(const FindArgs& A, const PS& P, const BigDesc& bd, int p,
                                           int ch, WaveScratch& WS, float& lo, float& hi,
-                                          int32_t* hist, float hlo, float hscale, int B) {
+                                          int32_t* hist, const Bn& bin) {
     const int lane = lane_id();
     const int C = A.n_classes;
     int64_t s0, n;
@@ -786,7 +927,7 @@ __device__ __forceinline__ void big_chunk(const FindArgs& A, const PS& P, const 
         for (int r = 0; r < kBR; ++r) {
             if (i0 + r * kWave + lane >= cn) continue;
             if (kHist) {
-                atomicAdd(&hist[bin_index(v[r], hlo, hscale, B) * C + lab[r]], 1);
+                atomicAdd(&hist[bin(v[r]) * C + lab[r]], 1);
             } else {
                 lo = fminf(lo, v[r]);
                 hi = fmaxf(hi, v[r]);
@@ -945,7 +1086,7 @@ __global__ __launch_bounds__(kBlock) void k_brange(FindArgs A, PS P) {
         int p, ch;
         if (!big_item(A, it, nbig, bd, p, ch)) continue;
         float lo, hi;
-        big_chunk<T, PS, false>(A, P, bd, p, ch, WS, lo, hi, nullptr, 0.f, 0.f, 0);
+        big_chunk<T, PS, false>(A, P, bd, p, ch, WS, lo, hi, nullptr, EqualBins{0.f, 0.f, 2});
         lo = wave_min(lo);
         hi = wave_max(hi);
         if (lane_id() == 0) W.crange[it] = make_float2(lo, hi);
@@ -978,7 +1119,7 @@ __global__ __launch_bounds__(kBlock) void k_bmerge(FindArgs A) {
     }
 }
 
-template <typename T, class PS>
+template <typename T, class PS, bool RW>
 __global__ __launch_bounds__(kBlock) void k_bhist(FindArgs A, PS P) {
     extern __shared__ __align__(16) char smem[];
     BlockShared& S = block_shared(smem);
@@ -1000,7 +1141,14 @@ __global__ __launch_bounds__(kBlock) void k_bhist(FindArgs A, PS P) {
         for (int e = lane; e < B * C; e += kWave) hist[e] = 0;
         wave_sync();
         float lo, hi;
-        big_chunk<T, PS, true>(A, P, bd, p, ch, WS, lo, hi, hist, r.x, scale, B);
+        if (RW) {
+            RwTable& tab = wave_rw(smem, w, Bm, C);
+            const float sc = rw_cell_scale(r.x, r.y);
+            rw_build(tab, A.bin_seed, proj_global(P, bd.node, p), B, r.x, r.y, sc);
+            big_chunk<T, PS, true>(A, P, bd, p, ch, WS, lo, hi, hist, RwBins{&tab, r.x, sc});
+        } else {
+            big_chunk<T, PS, true>(A, P, bd, p, ch, WS, lo, hi, hist, EqualBins{r.x, scale, B});
+        }
         wave_sync();
         int32_t* out = W.chist + (int64_t)it * Bm * C;
         for (int e = lane; e < B * C; e += kWave) out[e] = hist[e];
@@ -1010,7 +1158,7 @@ __global__ __launch_bounds__(kBlock) void k_bhist(FindArgs A, PS P) {
 
 // Per (big node, projection): sum the chunk histograms into the wave's LDS
 // histogram, then the boundary scan.
-template <class PS>
+template <class PS, bool RW>
 __global__ __launch_bounds__(kBlock) void k_bscan(FindArgs A, PS P) {
     extern __shared__ __align__(16) char smem[];
     const FindWs& W = A.ws;
@@ -1046,6 +1194,7 @@ __global__ __launch_bounds__(kBlock) void k_bscan(FindArgs A, PS P) {
         LdsHistCM h{hist, Bs};
         write_hist_row(A, proj_global(P, bd.node, p), h, B);
         Cand c = scan_hist_fast(h, B, C, n, r.x, scale, block_shared(smem).w[w].pcs);
+        if (RW && c.D != 0) c.thr = rw_boundary(A.bin_seed, proj_global(P, bd.node, p), B, r.x, r.y, c.pos);
         c.proj = p;
         if (lane == 0) ((Cand*)W.slots)[bd.slot + p] = c;
         wave_sync();
@@ -1055,7 +1204,7 @@ __global__ __launch_bounds__(kBlock) void k_bscan(FindArgs A, PS P) {
 // kLarge: nodes of kMidSplit+1 .. kMidMax samples (32 per thread); else
 // kSmallMax+1 .. kMidSplit (up to 16 per thread).  Separate kernels so that
 // each gets the register allocation of its own size class.
-template <typename T, class PS, bool kLarge>
+template <typename T, class PS, bool kLarge, bool RW>
 __global__ __launch_bounds__(kBlock, kLarge ? 1 : 4) void k_mid(FindArgs A, PS P) {
     extern __shared__ __align__(16) char smem[];
     BlockShared& S = block_shared(smem);
@@ -1075,18 +1224,18 @@ __global__ __launch_bounds__(kBlock, kLarge ? 1 : 4) void k_mid(FindArgs A, PS P
         node_range(A, D.x, s0, n);
         if (kLarge) {
             if (n > kMidMax) n = kMidMax;   // the plan never queues larger nodes here
-            do_mid_r<T, PS, kMidR>(A, P, D, e.y, s0, n, smem);
+            do_mid_r<T, PS, kMidR, RW>(A, P, D, e.y, s0, n, smem);
         } else {
             if (n > kMidSplit) n = kMidSplit;   // the plan never queues larger nodes here
             const int nr = (int)((n + kBlock - 1) / kBlock);
-            if (nr <= 4) do_mid_r<T, PS, 4>(A, P, D, e.y, s0, n, smem);
-            else if (nr <= 8) do_mid_r<T, PS, 8>(A, P, D, e.y, s0, n, smem);
-            else do_mid_r<T, PS, 16>(A, P, D, e.y, s0, n, smem);
+            if (nr <= 4) do_mid_r<T, PS, 4, RW>(A, P, D, e.y, s0, n, smem);
+            else if (nr <= 8) do_mid_r<T, PS, 8, RW>(A, P, D, e.y, s0, n, smem);
+            else do_mid_r<T, PS, 16, RW>(A, P, D, e.y, s0, n, smem);
         }
     }
 }
 
-template <typename T, class PS>
+template <typename T, class PS, bool RW>
 __global__ __launch_bounds__(kBlock, 4) void k_small(FindArgs A, PS P) {
     extern __shared__ __align__(16) char smem[];
     BlockShared& S = block_shared(smem);
@@ -1097,7 +1246,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_small(FindArgs A, PS P) {
         int it = block_dequeue(&W.hdr[H_Q_SMALL], &S.item);
         if (it >= ns) break;
         int v = W.small_items[it];
-        if (v >= 0 && v < N) do_small<T>(A, P, v, smem);
+        if (v >= 0 && v < N) do_small<T, PS, RW>(A, P, v, smem);
     }
 }
 
@@ -1111,16 +1260,17 @@ __global__ __launch_bounds__(kBlock) void k_reduce(FindArgs A) {
     const Cand* slots = (const Cand*)W.slots;
     const int gw = (blockIdx.x * kBlock + threadIdx.x) >> 6;
     const int nw = gridDim.x * kWavesPerBlock;
+    const int hist_kind = A.bin_mode == SOF_BINS_RANDOM ? SOF_SPLIT_RHIST : SOF_SPLIT_HIST;
     for (int d = gw; d < nmid + nsb + nbig + nmid2; d += nw) {
         int node, slot, k, kind;
         if (d >= nmid + nsb + nbig) {
-            int4 D = W.desc_mid2[d - nmid - nsb - nbig]; node = D.x; slot = D.y; k = D.w; kind = 0;
+            int4 D = W.desc_mid2[d - nmid - nsb - nbig]; node = D.x; slot = D.y; k = D.w; kind = hist_kind;
         } else if (d < nmid) {
-            int4 D = W.desc_mid[d]; node = D.x; slot = D.y; k = D.w; kind = 0;
+            int4 D = W.desc_mid[d]; node = D.x; slot = D.y; k = D.w; kind = hist_kind;
         } else if (d < nmid + nsb) {
             int4 D = W.desc_sb[d - nmid]; node = D.x; slot = D.y; k = D.w; kind = 1;
         } else {
-            BigDesc bd = big_desc(A, d - nmid - nsb); node = bd.node; slot = bd.slot; k = bd.k; kind = 0;
+            BigDesc bd = big_desc(A, d - nmid - nsb); node = bd.node; slot = bd.slot; k = bd.k; kind = hist_kind;
         }
         if (slot + (int64_t)k > W.cap_slots) continue;
         bool bv = false;
@@ -1342,7 +1492,7 @@ __global__ __launch_bounds__(kBlock) void k_sortblk(FindArgs A, PS P) {
 // ---------------------------------------------------------------------------
 // host side
 
-template <typename T, class PS>
+template <typename T, class PS, bool RW>
 static hipError_t launch_find_t(const FindArgs& a, const PS& p, const LaunchCfg& cfg, hipStream_t s,
                                 const hipEvent_t* ev) {
     const int Nc = a.n_nodes > 0 ? a.n_nodes : 1;
@@ -1362,15 +1512,15 @@ static hipError_t launch_find_t(const FindArgs& a, const PS& p, const LaunchCfg&
     mark();
     hipLaunchKernelGGL(k_bmerge, dim3(cfg.grid_light), dim3(kBlock), 0, s, a);
     mark();
-    hipLaunchKernelGGL((k_bhist<T, PS>), dim3(cfg.grid_bhist), dim3(kBlock), sm, s, a, p);
+    hipLaunchKernelGGL((k_bhist<T, PS, RW>), dim3(cfg.grid_bhist), dim3(kBlock), sm, s, a, p);
     mark();
-    hipLaunchKernelGGL((k_bscan<PS>), dim3(cfg.grid_bscan), dim3(kBlock), sm, s, a, p);
+    hipLaunchKernelGGL((k_bscan<PS, RW>), dim3(cfg.grid_bscan), dim3(kBlock), sm, s, a, p);
     mark();
-    hipLaunchKernelGGL((k_mid<T, PS, false>), dim3(cfg.grid_mid), dim3(kBlock), sm, s, a, p);
+    hipLaunchKernelGGL((k_mid<T, PS, false, RW>), dim3(cfg.grid_mid), dim3(kBlock), sm, s, a, p);
     mark();
-    hipLaunchKernelGGL((k_mid<T, PS, true>), dim3(cfg.grid_mid2), dim3(kBlock), sm, s, a, p);
+    hipLaunchKernelGGL((k_mid<T, PS, true, RW>), dim3(cfg.grid_mid2), dim3(kBlock), sm, s, a, p);
     mark();
-    hipLaunchKernelGGL((k_small<T, PS>), dim3(cfg.grid_small), dim3(kBlock), sm, s, a, p);
+    hipLaunchKernelGGL((k_small<T, PS, RW>), dim3(cfg.grid_small), dim3(kBlock), sm, s, a, p);
     mark();
     hipLaunchKernelGGL((k_sortblk<T, PS>), dim3(cfg.grid_sort), dim3(kBlock), cfg.smem_sort, s, a, p);
     mark();
@@ -1381,13 +1531,18 @@ static hipError_t launch_find_t(const FindArgs& a, const PS& p, const LaunchCfg&
 
 hipError_t launch_find_csr(const FindArgs& a, const ProjCSR& p, const LaunchCfg& cfg, hipStream_t s,
                            const hipEvent_t* ev) {
-    if (a.dtype == SOF_F16) return launch_find_t<_Float16>(a, p, cfg, s, ev);
-    return launch_find_t<float>(a, p, cfg, s, ev);
+    const bool rw = a.bin_mode == SOF_BINS_RANDOM;
+    if (a.dtype == SOF_F16)
+        return rw ? launch_find_t<_Float16, ProjCSR, true>(a, p, cfg, s, ev)
+                  : launch_find_t<_Float16, ProjCSR, false>(a, p, cfg, s, ev);
+    return rw ? launch_find_t<float, ProjCSR, true>(a, p, cfg, s, ev)
+              : launch_find_t<float, ProjCSR, false>(a, p, cfg, s, ev);
 }
+// forest growth uses equal-width bins
 hipError_t launch_find_hash(const FindArgs& a, const ProjHash& p, const LaunchCfg& cfg, hipStream_t s,
                             const hipEvent_t* ev) {
-    if (a.dtype == SOF_F16) return launch_find_t<_Float16>(a, p, cfg, s, ev);
-    return launch_find_t<float>(a, p, cfg, s, ev);
+    if (a.dtype == SOF_F16) return launch_find_t<_Float16, ProjHash, false>(a, p, cfg, s, ev);
+    return launch_find_t<float, ProjHash, false>(a, p, cfg, s, ev);
 }
 
 // resident blocks per CU of a kernel (at least 1)
@@ -1398,29 +1553,35 @@ static hipError_t occ(const void* f, size_t smem, int* out) {
     return e;
 }
 
-hipError_t find_occupancy(int bins, int classes, int n_cu, LaunchCfg* cfg) {
-    const size_t sm = find_smem_main(bins, classes), ss = find_smem_sort();
+template <bool RW>
+static hipError_t find_occupancy_t(int bins, int classes, int n_cu, LaunchCfg* cfg) {
+    const size_t sm = find_smem_main(bins, classes, RW), ss = find_smem_sort();
     int b = 0;
     hipError_t e;
     cfg->n_cu = n_cu;
     cfg->smem_main = sm;
     cfg->smem_sort = ss;
-    if ((e = occ((const void*)k_mid<float, ProjCSR, false>, sm, &b)) != hipSuccess) return e;
+    if ((e = occ((const void*)k_mid<float, ProjCSR, false, RW>, sm, &b)) != hipSuccess) return e;
     cfg->grid_mid = n_cu * b;
-    if ((e = occ((const void*)k_mid<float, ProjCSR, true>, sm, &b)) != hipSuccess) return e;
+    if ((e = occ((const void*)k_mid<float, ProjCSR, true, RW>, sm, &b)) != hipSuccess) return e;
     cfg->grid_mid2 = n_cu * b;
-    if ((e = occ((const void*)k_small<float, ProjCSR>, sm, &b)) != hipSuccess) return e;
+    if ((e = occ((const void*)k_small<float, ProjCSR, RW>, sm, &b)) != hipSuccess) return e;
     cfg->grid_small = n_cu * b;
     if ((e = occ((const void*)k_sortblk<float, ProjCSR>, ss, &b)) != hipSuccess) return e;
     cfg->grid_sort = n_cu * b;
     if ((e = occ((const void*)k_brange<float, ProjCSR>, sm, &b)) != hipSuccess) return e;
     cfg->grid_brange = n_cu * b;
-    if ((e = occ((const void*)k_bhist<float, ProjCSR>, sm, &b)) != hipSuccess) return e;
+    if ((e = occ((const void*)k_bhist<float, ProjCSR, RW>, sm, &b)) != hipSuccess) return e;
     cfg->grid_bhist = n_cu * b;
-    if ((e = occ((const void*)k_bscan<ProjCSR>, sm, &b)) != hipSuccess) return e;
+    if ((e = occ((const void*)k_bscan<ProjCSR, RW>, sm, &b)) != hipSuccess) return e;
     cfg->grid_bscan = n_cu * b;
     cfg->grid_light = n_cu * 4;
     return hipSuccess;
+}
+
+hipError_t find_occupancy(int bins, int classes, bool random_bins, int n_cu, LaunchCfg* cfg) {
+    return random_bins ? find_occupancy_t<true>(bins, classes, n_cu, cfg)
+                       : find_occupancy_t<false>(bins, classes, n_cu, cfg);
 }
 
 }  // namespace sof

@@ -2,8 +2,9 @@
 // (paper section 4: each node splits its samples between its children).
 //
 // The split rule is re-evaluated on recomputed projected values (the same FP32
-// CSR-order sums as the search): histogram splits send v left iff
-// bin(v) <= bin, sort splits iff v <= threshold.  Output per node: left
+// CSR-order sums as the search): equal-width histogram splits send v left iff
+// bin(v) <= bin, random-width ones iff v < threshold (the next boundary, which
+// is the same rule), sort splits iff v <= threshold.  Output per node: left
 // samples in input order, then right samples in input order.
 //
 //   k_pplan     per node: child offsets, tiny/small-node queues or chunk items
@@ -211,8 +212,9 @@ __device__ void ptiny_r(const PartArgs& A, const PS& P, int v, int64_t s0, int n
         const int i = lane + r * kWave;
         bool left = true;
         if (!all_left)
-            left = sp.kind == SOF_SPLIT_HIST ? bin_index(val[r], sp.lo, sp.scale, B) <= sp.bin
-                                             : val[r] <= sp.threshold;
+            left = sp.kind == SOF_SPLIT_HIST    ? bin_index(val[r], sp.lo, sp.scale, B) <= sp.bin
+                   : sp.kind == SOF_SPLIT_RHIST ? val[r] < sp.threshold
+                                                : val[r] <= sp.threshold;
         m[r] = __ballot(i < n && left);
         nl += __popcll(m[r]);
     }
@@ -314,8 +316,9 @@ __device__ void predicates_r(const PartArgs& A, const PS& P, int v, int64_t at, 
         const int64_t i = tid + (int64_t)r * kBlock;
         bool left = true;
         if (!all_left)
-            left = sp.kind == SOF_SPLIT_HIST ? bin_index(val[r], sp.lo, sp.scale, B) <= sp.bin
-                                             : val[r] <= sp.threshold;
+            left = sp.kind == SOF_SPLIT_HIST    ? bin_index(val[r], sp.lo, sp.scale, B) <= sp.bin
+                   : sp.kind == SOF_SPLIT_RHIST ? val[r] < sp.threshold
+                                                : val[r] <= sp.threshold;
         const uint64_t m = __ballot(i < cn && left);
         if (lane_id() == 0) {
             S.mask[r][w] = m;

@@ -93,6 +93,8 @@ struct FindArgs {
     const int32_t* n_nodes_dev; // device count (forest growth), or NULL
     const int32_t* node_bins;
     int32_t bins, sort_threshold;  // sort_threshold already clamped
+    int32_t bin_mode;           // SOF_BINS_EQUAL or SOF_BINS_RANDOM
+    uint64_t bin_seed;
     void* out;                  // SplitRec[n_nodes]
     int32_t* hist_out;
     FindWs ws;
@@ -122,8 +124,8 @@ hipError_t launch_find_csr(const FindArgs& a, const ProjCSR& p, const LaunchCfg&
                            const hipEvent_t* ev = nullptr);
 hipError_t launch_find_hash(const FindArgs& a, const ProjHash& p, const LaunchCfg& cfg, hipStream_t s,
                             const hipEvent_t* ev = nullptr);
-size_t find_smem_main(int bins, int classes);
+size_t find_smem_main(int bins, int classes, bool random_bins);
 size_t find_smem_sort();
-hipError_t find_occupancy(int bins, int classes, int n_cu, LaunchCfg* cfg);
+hipError_t find_occupancy(int bins, int classes, bool random_bins, int n_cu, LaunchCfg* cfg);
 
 }  // namespace sof

@@ -166,3 +166,34 @@ def test_repeat_runs_identical(ctx):
     for _ in range(4):
         _, b, Hb = run_gpu(ctx, wl)
         assert a.tobytes() == b.tobytes() and np.array_equal(Ha, Hb)
+
+
+# --------------------------------------------------------------------------
+# random-width bins: every size class, histograms, records and partition
+
+@pytest.mark.parametrize("T,C,B,dt", [(0, 3, 256, np.float32), (300, 5, 128, np.float32),
+                                      (0, 2, 2, np.float32), (64, 16, 256, np.float16)])
+def test_random_width_bins(ctx, T, C, B, dt):
+    import torch
+    from paper_2603_00326_amd import sof as S
+    seed = 0xC0FFEE + T + B
+    wl = W.random_frontier(71 + C, n_rows=90000, d=14, n_classes=C, sizes=EDGE_SIZES, k=5, z=(1, 6),
+                           bins=B, sort_threshold=T, layout="r", dtype=dt)
+    say(f"[gpu] random-width bins T={T} C={C} B={B} dtype={np.dtype(dt).name}")
+    dev = S.to_device(wl)
+    out, H = S.find_splits(ctx, dev, bins=B, sort_threshold=T, hist=True, bin_mode=S.SOF_BINS_RANDOM,
+                           bin_seed=seed)
+    out_idx, coff = S.partition(ctx, dev, out, bins=B)
+    torch.cuda.synchronize()
+    got = S.splits_to_numpy(out)[:wl.n_nodes]
+    ref, Href = O.find_splits_w(wl, hist=True, bin_mode=O.BINS_RANDOM, bin_seed=seed)
+    assert_splits_match(got, ref, "random-width")
+    n = np.diff(wl.node_offsets)
+    hist_nodes = n >= min(T, 8193)
+    assert np.all(got["kind"][hist_nodes] == S.SOF_SPLIT_RHIST)
+    bad = np.argwhere(H.cpu().numpy() != Href)
+    assert bad.size == 0, f"histogram differs at {bad[:5].tolist()}"
+    want_idx, want_coff = O.partition(wl.X, wl.node_offsets, wl.sample_idx, wl.proj_offsets, wl.nz_offsets,
+                                      wl.nz_feature, wl.nz_weight, ref, bins=B)
+    assert np.array_equal(coff.cpu().numpy(), want_coff)
+    assert np.array_equal(out_idx.cpu().numpy(), want_idx)

@@ -44,11 +44,11 @@ def sample_nodes(wl, seed, per_class=10):
     return sorted(int(v) for v in pick)
 
 
-def run_full(ctx, wl, T):
+def run_full(ctx, wl, T, bin_mode=0, bin_seed=0):
     import torch
     from paper_2603_00326_amd import sof as S
     dev = S.to_device(wl)
-    out, _ = S.find_splits(ctx, dev, bins=wl.bins, sort_threshold=T)
+    out, _ = S.find_splits(ctx, dev, bins=wl.bins, sort_threshold=T, bin_mode=bin_mode, bin_seed=bin_seed)
     out_idx, coff = S.partition(ctx, dev, out, bins=wl.bins)
     torch.cuda.synchronize()
     got = S.splits_to_numpy(out)[:wl.n_nodes]
@@ -74,10 +74,16 @@ def check_partition_properties(wl, got, out_idx, coff):
     assert np.array_equal(wl.sample_idx[a], out_idx[b]), "per-node permutation"
 
 
-def check_sampled(wl, T, got, out_idx, coff, nodes, tag):
+def check_sampled(wl, T, got, out_idx, coff, nodes, tag, bin_mode=0, bin_seed=0):
     sub = W.sub_frontier(wl, nodes)
     sub.sort_threshold = T
-    ref, _ = O.find_splits_w(sub)
+    if bin_mode:
+        # random-width boundaries are keyed by the projection's index in the
+        # call, so the oracle runs on the whole frontier and is sampled after
+        ref_all, _ = O.find_splits_w(wl, sort_threshold=T, bin_mode=bin_mode, bin_seed=bin_seed)
+        ref = ref_all[nodes]
+    else:
+        ref, _ = O.find_splits_w(sub)
     assert_splits_match(got[nodes], ref, tag)
     want_idx, want_coff = O.partition(sub.X, sub.node_offsets, sub.sample_idx, sub.proj_offsets,
                                       sub.nz_offsets, sub.nz_feature, sub.nz_weight, ref, bins=sub.bins,
@@ -131,3 +137,14 @@ def test_root_4096_rows_both_paths(ctx, T):
     got, out_idx, coff = run_full(ctx, wl, T)
     check_partition_properties(wl, got, out_idx, coff)
     check_sampled(wl, T, got, out_idx, coff, [0], f"c1 T={T}")
+
+
+def test_frontier_4096_nodes_random_width_bins(ctx):
+    wl = W.config3("a")
+    T = tuned_threshold(ctx, wl)
+    seed = 20260302
+    nodes = sample_nodes(wl, seed=23)
+    say(f"[gpu] full frontier random-width bins nodes={wl.n_nodes} samples={wl.n_samples} T={T}")
+    got, out_idx, coff = run_full(ctx, wl, T, bin_mode=1, bin_seed=seed)
+    check_partition_properties(wl, got, out_idx, coff)
+    check_sampled(wl, T, got, out_idx, coff, nodes, "c3a random-width", bin_mode=1, bin_seed=seed)
