@@ -86,6 +86,10 @@ def lib():
         L.or_grow_forest.argtypes = [P, ctypes.c_int, i64, i32, P, i32, i32, i32, P, P, i32, i32, u64,
                                      i32, i32, i32, i32, P, i64, P, P]
         L.or_grow_forest.restype = i64
+        L.or_leaf_of.argtypes = [P, ctypes.c_int, i64, P, i32, i32]
+        L.or_leaf_of.restype = i32
+        L.or_predict.argtypes = [P, ctypes.c_int, i64, P, P, i32, i32, i32, P, P]
+        L.or_predict.restype = None
         _lib = L
     return _lib
 
@@ -236,3 +240,23 @@ def grow_forest(X, y, n_classes, root_offsets, root_idx, *, k, z, seed, bins=256
         raise RuntimeError("node capacity too small")
     levels = int(np.count_nonzero(ln))
     return nodes[:n].copy(), ln[:levels].copy(), lu[:levels].copy()
+
+
+def leaf_of(X, nodes, root: int, row: int) -> int:
+    """Index of the leaf that row reaches from node root."""
+    X, dt = _xinfo(X)
+    nodes = np.ascontiguousarray(nodes, dtype=TREE_NODE_DTYPE)
+    return int(lib().or_leaf_of(_p(X), dt, X.shape[1], _p(nodes), int(root), int(row)))
+
+
+def predict(X, nodes, roots, n_classes: int):
+    """Forest prediction for every row of X: (votes (n_rows, C) int32, pred (n_rows,) int32)."""
+    X, dt = _xinfo(X)
+    nodes = np.ascontiguousarray(nodes, dtype=TREE_NODE_DTYPE)
+    roots = _c(roots, np.int32)
+    n = X.shape[1]
+    votes = np.zeros((n, n_classes), np.int32)
+    pred = np.zeros(n, np.int32)
+    lib().or_predict(_p(X), dt, X.shape[1], _p(nodes), _p(roots), len(roots), int(n_classes), n, _p(votes),
+                     _p(pred))
+    return votes, pred

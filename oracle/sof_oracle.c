@@ -665,3 +665,44 @@ int64_t or_grow_forest(const void* x, int dtype, int64_t ld, int32_t d,
     free(front);
     return n_nodes;
 }
+
+/* ------------------------------------------------------------------------ */
+/* prediction (the forest's trees each vote the label of the leaf a row      */
+/* reaches; the majority class wins, ties to the lowest class)               */
+/* ------------------------------------------------------------------------ */
+
+static int node_goes_left(const void* x, int dtype, int64_t ld, const or_tree_node* t, int32_t row)
+{
+    float v = or_project_value(x, dtype, ld, t->feature, t->weight, t->nnz, row);
+    if (t->kind == 0)
+        return or_bin_index(v, t->lo, t->scale, t->n_bins) <= t->bin;
+    if (t->kind == 2)
+        return v < t->threshold;
+    return v <= t->threshold;
+}
+
+int32_t or_leaf_of(const void* x, int dtype, int64_t ld, const or_tree_node* nodes, int32_t root,
+                   int32_t row)
+{
+    int32_t i = root;
+    while (!nodes[i].is_leaf)
+        i = node_goes_left(x, dtype, ld, &nodes[i], row) ? nodes[i].left : nodes[i].right;
+    return i;
+}
+
+void or_predict(const void* x, int dtype, int64_t ld, const or_tree_node* nodes, const int32_t* roots,
+                int32_t n_trees, int32_t C, int32_t n_rows, int32_t* votes, int32_t* pred)
+{
+    for (int32_t r = 0; r < n_rows; ++r) {
+        int32_t* vr = votes + (int64_t)r * C;
+        for (int c = 0; c < C; ++c)
+            vr[c] = 0;
+        for (int32_t t = 0; t < n_trees; ++t)
+            vr[nodes[or_leaf_of(x, dtype, ld, nodes, roots[t], r)].label] += 1;
+        int32_t best = 0;
+        for (int c = 1; c < C; ++c)
+            if (vr[c] > vr[best])
+                best = c;
+        pred[r] = best;
+    }
+}

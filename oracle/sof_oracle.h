@@ -127,7 +127,17 @@ int64_t or_grow_forest(const void* x, int dtype, int64_t ld, int32_t n_features,
                        or_tree_node* nodes, int64_t cap,
                        int64_t* level_nodes, int64_t* level_units);
 
+/* Leaf a row reaches from a root, and forest prediction: per row, every tree
+ * votes its leaf's label; pred = the class with most votes (lowest on ties).
+ * Internal nodes send a row left when bin(v) <= bin (kind 0), v <= threshold
+ * (kind 1) or v < threshold (kind 2), v being the node's projection. */
+int32_t or_leaf_of(const void* x, int dtype, int64_t ld, const or_tree_node* nodes, int32_t root,
+                   int32_t row);
+void or_predict(const void* x, int dtype, int64_t ld, const or_tree_node* nodes, const int32_t* roots,
+                int32_t n_trees, int32_t n_classes, int32_t n_rows, int32_t* votes, int32_t* pred);
+
 #ifdef __cplusplus
 }
 #endif
+
 #endif

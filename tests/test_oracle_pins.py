@@ -667,3 +667,57 @@ def test_rw_partition_sends_values_below_the_threshold_left():
         right = idx[a:b][~(vals < sp[v]["threshold"])]
         assert coff[2 * v + 1] - a == sp[v]["n_left"] == left.size
         assert np.array_equal(out[a:b], np.concatenate([left, right]))
+
+
+# --------------------------------------------------------------------------
+# forest prediction
+# --------------------------------------------------------------------------
+
+def _small_forest(seed, n=1500, d=10, C=3, trees=3, T=40, max_depth=64):
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((d, n)).astype(np.float32)
+    y = rng.integers(0, C, n).astype(np.int32)
+    roots = [np.sort(np.random.default_rng(seed * 10 + t).integers(0, n, n)).astype(np.int32)
+             for t in range(trees)]
+    ro = np.arange(trees + 1, dtype=np.int64) * n
+    nodes, _, _ = O.grow_forest(X, y, C, ro, np.concatenate(roots), k=6, z=3, seed=seed, bins=64,
+                                sort_threshold=T, max_depth=max_depth)
+    root_ids = np.array([int(np.nonzero((nodes["depth"] == 0) & (nodes["tree"] == t))[0][0])
+                         for t in range(trees)], np.int32)
+    return X, y, C, roots, nodes, root_ids
+
+
+def test_predict_routes_in_bag_samples_to_their_leaves():
+    # the traversal rule must agree with the partition that grew the tree: the
+    # in-bag samples of every tree reach each leaf exactly n_samples times
+    X, y, C, roots, nodes, root_ids = _small_forest(11)
+    for t, r in enumerate(root_ids):
+        counts = {}
+        for row in roots[t]:
+            leaf = O.leaf_of(X, nodes, int(r), int(row))
+            assert nodes[leaf]["is_leaf"] == 1 and nodes[leaf]["tree"] == t
+            counts[leaf] = counts.get(leaf, 0) + 1
+        leaves = np.nonzero((nodes["tree"] == t) & (nodes["is_leaf"] == 1))[0]
+        for leaf in leaves:
+            assert counts.get(int(leaf), 0) == nodes[leaf]["n_samples"], (t, leaf)
+
+
+def test_predict_pure_tree_fits_in_bag_labels():
+    X, y, C, roots, nodes, root_ids = _small_forest(12, trees=1, T=100)
+    leaves = nodes[nodes["is_leaf"] == 1]
+    votes, pred = O.predict(X, nodes, root_ids, C)
+    inbag = np.unique(roots[0])
+    # continuous features: every leaf of a tree grown to purity is pure
+    assert np.array_equal(pred[inbag], y[inbag])
+    assert np.all(votes.sum(axis=1) == 1) and leaves.size > 1
+
+
+def test_predict_votes_and_majority():
+    X, y, C, roots, nodes, root_ids = _small_forest(13, trees=5)
+    votes, pred = O.predict(X, nodes, root_ids, C)
+    assert np.all(votes.sum(axis=1) == 5)
+    assert np.array_equal(pred, np.argmax(votes, axis=1))
+    for t in range(5):
+        one_v, one_p = O.predict(X, nodes, root_ids[t:t + 1], C)
+        labels = np.array([nodes[O.leaf_of(X, nodes, int(root_ids[t]), r)]["label"] for r in range(0, 1500, 7)])
+        assert np.array_equal(one_p[0:1500:7], labels)
