@@ -267,6 +267,23 @@ int sof_forest_frontier_stats(sof_forest* forest, int64_t* n_nodes, int64_t* n_s
 int sof_forest_export(sof_forest* forest, sof_tree_node* host_nodes, int64_t cap, int64_t* n,
                       void* stream);
 
+/* Forest prediction (the trees of section 2 vote): for every row r < n_rows
+ * of data (labels unused, may be NULL), walk each tree from its root node;
+ * an internal node sends the row left when its rule holds on the row's
+ * projection v (the node's features and +/-1 weights, FP32 adds in order
+ * from +0): kind SOF_SPLIT_HIST bin(v) <= bin with the node's lo, scale and
+ * n_bins; SOF_SPLIT_SORT v <= threshold; SOF_SPLIT_RHIST v < threshold.  The
+ * leaf's label gets one vote.  nodes: device array of n_nodes records in
+ * sof_forest_export's layout (8-byte aligned); roots: device array of n_trees
+ * root indices (a forest's roots are nodes 0 .. n_trees-1); votes (optional,
+ * device, n_rows * n_classes int32) and pred (device, n_rows int32: the class
+ * with most votes, the lowest on ties).  A child index outside [0, n_nodes)
+ * ends the walk without a vote.  Asynchronous on stream; allocates nothing.
+ * Errors: SOF_ERR_INVALID_ARG, SOF_ERR_UNSUPPORTED (dtype, classes),
+ * SOF_ERR_HIP. */
+int sof_predict(sof_ctx* ctx, const sof_data* data, const sof_tree_node* nodes, int64_t n_nodes,
+                const int32_t* roots, int32_t n_trees, int32_t* votes, int32_t* pred, void* stream);
+
 /* Crossover microbenchmark (section 4.1: run once before training, a search
  * for the node size where histograms overtake sorting): times the sort and
  * histogram paths on synthetic frontiers of equal nodes of growing size, on

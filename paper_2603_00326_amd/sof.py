@@ -32,7 +32,7 @@ EXPORTED = [
     "sof_version", "sof_last_error", "sof_create", "sof_destroy", "sof_workspace_size",
     "sof_project", "sof_find_splits", "sof_partition", "sof_forest_create", "sof_forest_destroy",
     "sof_grow_level", "sof_forest_frontier_size", "sof_forest_frontier_stats", "sof_forest_export",
-    "sof_autotune",
+    "sof_autotune", "sof_predict",
     "sof_timing_enable", "sof_timing_read",
 ]
 
@@ -129,6 +129,7 @@ def lib():
             L.sof_forest_export.argtypes = [P, P, i64, ctypes.POINTER(i64), P]
         L.sof_timing_enable.argtypes = [P, ctypes.c_int]
         L.sof_timing_read.argtypes = [P, P, ctypes.POINTER(i32)]
+        L.sof_predict.argtypes = [P, ctypes.POINTER(sof_data), P, i64, P, i32, P, P, P]
         if hasattr(L, "sof_autotune"):
             L.sof_autotune.argtypes = [P, i32, i32, i32, i32, i32, ctypes.POINTER(sof_tune), P]
         _lib = L
@@ -351,6 +352,29 @@ def autotune(ctx: Context, n_classes: int, k: int, z: int, bins: int = 256, *, d
             "hist_us": [round(float(t.hist_us[i]), 5) for i in range(n)]}
 
 
+def nodes_to_device(nodes: np.ndarray, device="cuda:0"):
+    """Tree node records (TREE_NODE_DTYPE) as a device byte tensor."""
+    import torch
+    raw = np.ascontiguousarray(nodes, dtype=TREE_NODE_DTYPE).view(np.uint8).reshape(-1)
+    return torch.from_numpy(raw.copy()).to(device)
+
+
+def predict(ctx: Context, X, nodes, roots, n_classes: int, *, votes=True, stream=None):
+    """Forest prediction for every row of X (torch (d, n) FP32/FP16 on the
+    device).  nodes: device byte tensor of records (nodes_to_device), roots:
+    device int32 tensor of root indices.  Returns (votes (n, C) or None, pred (n,))."""
+    import torch
+    dtype = SOF_F16 if str(X.dtype) == "torch.float16" else SOF_F32
+    n = int(X.shape[1])
+    d = sof_data(_ptr(X), None, int(X.stride(0)), n, int(X.shape[0]), int(n_classes), dtype)
+    V = torch.empty((n, n_classes), dtype=torch.int32, device=X.device) if votes else None
+    pred = torch.empty(max(n, 1), dtype=torch.int32, device=X.device)
+    n_nodes = int(nodes.numel()) // TREE_NODE_DTYPE.itemsize
+    _check(lib().sof_predict(ctx.handle, ctypes.byref(d), _ptr(nodes), n_nodes, _ptr(roots), int(roots.numel()),
+                             _ptr(V), _ptr(pred), _stream(stream)))
+    return V, pred[:n]
+
+
 class Forest:
     """Level-wise growth of several trees to purity on the device."""
 
@@ -406,6 +430,13 @@ class Forest:
         _check(lib().sof_forest_export(self.handle, out.ctypes.data, int(self.max_nodes), ctypes.byref(n),
                                        _stream(stream)))
         return out[:n.value].copy()
+
+    def predict(self, Xq, *, votes=True, stream=None):
+        """Predict rows of Xq (device (d, n) tensor, the training layout) with this forest."""
+        import torch
+        nodes = nodes_to_device(self.export(stream), Xq.device)
+        roots = torch.arange(self.n_trees, dtype=torch.int32, device=Xq.device)
+        return predict(self.ctx, Xq, nodes, roots, self.data.n_classes, votes=votes, stream=stream)
 
     def grow(self, use_graph: bool = True, stream=None, max_levels: int = 65):
         """Grow until the frontier is empty; returns the frontier size before each level."""

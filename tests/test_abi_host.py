@@ -39,7 +39,7 @@ def test_header_declares_the_boundary():
     names = header_functions()
     for must in ("sof_create", "sof_destroy", "sof_workspace_size", "sof_project", "sof_find_splits",
                  "sof_partition", "sof_forest_create", "sof_grow_level", "sof_forest_frontier_size",
-                 "sof_forest_export", "sof_autotune", "sof_last_error"):
+                 "sof_forest_export", "sof_autotune", "sof_predict", "sof_last_error"):
         assert must in names
 
 
@@ -80,9 +80,9 @@ def proj(S, **kw):
 
 
 def params(S, **kw):
-    q = dict(node_bins=None, bins=256, sort_threshold=64)
+    q = dict(node_bins=None, bins=256, sort_threshold=64, bin_mode=0, bin_seed=0)
     q.update(kw)
-    return S.sof_params(q["node_bins"], q["bins"], q["sort_threshold"])
+    return S.sof_params(q["node_bins"], q["bins"], q["sort_threshold"], q["bin_mode"], 0, q["bin_seed"])
 
 
 def ws_size(S, L, d=None, f=None, p=None, q=None):
@@ -129,6 +129,8 @@ def test_workspace_size_of_valid_arguments(S, L):
     ("params", dict(bins=1), UNSUPPORTED),
     ("params", dict(bins=257), UNSUPPORTED),
     ("params", dict(sort_threshold=-1), INVALID),
+    ("params", dict(bin_mode=2), UNSUPPORTED),
+    ("params", dict(bin_mode=-1), UNSUPPORTED),
 ])
 def test_workspace_size_rejects(S, L, part, kw, code):
     args = {"d": None, "f": None, "p": None, "q": None}
@@ -156,6 +158,7 @@ def test_null_context_rejected_everywhere(S, L):
     assert L.sof_forest_export(None, None, 0, by(n), None) == INVALID
     t = S.sof_tune()
     assert L.sof_autotune(None, S.SOF_F32, 2, 64, 3, 256, by(t), None) == INVALID
+    assert L.sof_predict(None, by(d), FAKE, 10, FAKE, 1, None, FAKE, None) == INVALID
     assert L.sof_timing_enable(None, 1) == INVALID
     assert L.sof_destroy(None) == OK
 
