@@ -45,6 +45,8 @@ WORKLOADS = {
     "c1": "single root node, n=4096, d=64 FP32, 2 classes, k=64, z=3, B=256",
     "c4": "full training: 8 trees grown to purity level by level from bootstrap roots of a 2M x 1024 FP32 "
           "matrix (90% zeros), 4 classes, k=128, z=3 from the device sampler, B=256, max depth 64",
+    "accuracy": "held-out accuracy of 32-tree forests grown with exact splits, histograms and the dynamic "
+                "switch on config 1's rule (4096 training rows, 100000 test rows, d=64, 10% label noise)",
 }
 
 
@@ -327,8 +329,23 @@ def run_growth(args, S, ctx):
         torch.cuda.synchronize()
         wall = time.perf_counter() - t_start
         nodes = f.export() if timed else None
+        pred = None
+        if timed:
+            nd = S.nodes_to_device(nodes, dev_name)
+            rt = torch.arange(len(ro) - 1, dtype=torch.int32, device=dev_name)
+            S.predict(ctx, Xd, nd, rt, C, votes=False)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            _, P = S.predict(ctx, Xd, nd, rt, C, votes=False)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            pred = {"rows": int(X.shape[1]), "trees": len(ro) - 1, "ms": round(ms, 3),
+                    "row_trees_per_s": X.shape[1] * (len(ro) - 1) / (ms * 1e-3),
+                    "training_accuracy": float((P.cpu().numpy() == y).mean())}
         f.close()
-        return wall, levels, [a.elapsed_time(b) for a, b in evs], nodes
+        return wall, levels, [a.elapsed_time(b) for a, b in evs], (nodes, pred)
 
     for _ in range(args.warmup):
         grow_once(False)
@@ -337,7 +354,7 @@ def run_growth(args, S, ctx):
         wall, levels, lms, nodes = grow_once(True)
         walls.append(wall)
         last = (levels, lms, nodes)
-    levels, lms, nodes = last
+    levels, lms, (nodes, pred_info) = last
     units = sum(ns * k for _, _, ns in levels)
     ms_per_step = float(np.mean(walls)) * 1e3
     # algorithmic bytes per level: the split search reads each sample's index,
@@ -372,6 +389,7 @@ def run_growth(args, S, ctx):
                      "ms_per_launch": round(tot_ms / max(len(levels), 1), 5)},
         "levels": rows,
         "level_ms_sum": round(tot_ms, 3),
+        "predict": pred_info,
     }
     if tune:
         result["autotune"] = tune
@@ -393,6 +411,50 @@ def run_growth(args, S, ctx):
                                   "seconds": round(el, 3),
                                   "gpu_same_levels": gpu_top}
     print(json.dumps(result), flush=True)
+
+
+# ---------------------------------------------------------------------------
+# accuracy of exact, histogram and dynamic forests (the paper finds the three
+# statistically indistinguishable)
+
+def run_accuracy(args, S, ctx):
+    import torch
+    from paper_2603_00326_amd import workloads as W
+    X, y, Xt, yt = W.accuracy_data()
+    C, trees, k, z, bins, n = 2, 32, 64, 3, 256, X.shape[1]
+    dev_name = "cuda:0"
+    Xd, yd, Xtd = (torch.from_numpy(a).to(dev_name) for a in (X, y, Xt))
+    ri = np.concatenate([np.sort(np.random.default_rng(1000 + t).integers(0, n, n)) for t in range(trees)])
+    rid = torch.from_numpy(ri.astype(np.int32)).to(dev_name)
+    ro = np.arange(trees + 1, dtype=np.int64) * n
+    tune = S.autotune(ctx, C, k, z, bins, dtype=np.float32)
+    out = {}
+    # dynamic: the threshold this GPU's autotuner picks, and the paper's CPU breakeven (~1200 samples)
+    for name, T in (("exact", 2**31 - 1), ("histogram", 0), ("dynamic", int(tune["sort_threshold"])),
+                    ("dynamic_T1200", 1200)):
+        f = S.Forest(ctx, Xd, yd, C, ro, rid, k=k, z=z, seed=11, bins=bins, sort_threshold=T, max_depth=64)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        f.grow()
+        torch.cuda.synchronize()
+        grow_ms = (time.perf_counter() - t0) * 1e3
+        _, P = f.predict(Xtd, votes=False)
+        nodes = len(f.export())
+        f.close()
+        acc = float((P.cpu().numpy() == yt).mean())
+        out[name] = {"sort_threshold": T, "accuracy": round(acc, 5),
+                     "stderr": round(float(np.sqrt(acc * (1 - acc) / len(yt))), 5),
+                     "nodes": nodes, "grow_ms": round(grow_ms, 2)}
+        log(f"[bench] {name}: T={T} accuracy {acc:.4f} ({nodes} nodes, {grow_ms:.1f} ms)")
+    accs = [v["accuracy"] for v in out.values()]
+    print(json.dumps({
+        "metric": "held-out accuracy, exact vs histogram vs dynamic splits",
+        "value": out["dynamic"]["accuracy"], "unit": "fraction correct", "n_gpus": 1,
+        "higher_is_better": True, "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "accuracy", "description": WORKLOADS["accuracy"], "trees": trees, "k": k,
+                   "z": z, "bins": bins, "train_rows": n, "test_rows": int(len(yt)),
+                   "bayes_accuracy": 0.9},
+        "forests": out, "max_difference": round(max(accs) - min(accs), 5)}), flush=True)
 
 
 # ---------------------------------------------------------------------------
@@ -437,6 +499,9 @@ def main():
 
     if args.workload == "c4":
         run_growth(args, S, S.Context(0))
+        return
+    if args.workload == "accuracy":
+        run_accuracy(args, S, S.Context(0))
         return
 
     t0 = time.perf_counter()

@@ -207,6 +207,18 @@ def config1(sort: bool = False, seed: int = 0) -> Workload:
                     meta=dict(config=1, k=k, z=z, d=d))
 
 
+def accuracy_data(seed: int = 7, n_train: int = 4096, n_test: int = 100_000, d: int = 64):
+    """Training and held-out rows from config 1's rule: d N(0,1) features,
+    y = [x0 + x2 - x5 > 0] with 10% of labels flipped (both sets)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for n in (n_train, n_test):
+        X = rng.standard_normal((d, n), dtype=np.float32)
+        s = X[0].astype(np.float64) + X[2].astype(np.float64) - X[5].astype(np.float64)
+        out += [X, _flip_labels(rng, (s > 0).astype(np.int32), 0.10, 2)]
+    return tuple(out)
+
+
 def config2(seed: int = 1, n: int = 1 << 20) -> Workload:
     """Root node at scale: n=2^20, d=256 (128 N(0,1) + 128 Bernoulli(0.1)),
     2 classes from a random 6-feature oblique rule with 5% flips, k=256, z=3."""
