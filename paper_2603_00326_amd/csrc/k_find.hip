@@ -18,9 +18,10 @@
 //              one block per node, one wave per projection
 //   k_sortblk  sort nodes of 65..8192 samples: bitonic sort in LDS
 //   k_reduce   best projection per node for nodes with per-projection slots
-// Partial results of big nodes go to distinct workspace entries with plain
-// stores and are combined by the next kernel; no global atomics take part in
-// the arithmetic, and no kernel waits on another block.
+// Partial ranges of big nodes go to distinct workspace entries and are merged
+// by the next kernel; their chunk histograms are added into per-projection
+// histograms with integer atomics (order-free, so the sums are exact).  No
+// kernel waits on another block.
 #include "sof_device.h"
 #include "sof_internal.h"
 
@@ -77,6 +78,12 @@ __device__ __forceinline__ int proj_count(const ProjCSR& P, int v) {
 __device__ __forceinline__ int proj_global(const ProjCSR& P, int v, int p) {
     return (int)clamp64(P.proj_offsets[v], 0, P.n_proj) + p;
 }
+__device__ __forceinline__ int proj_nnz(const ProjCSR& P, int v, int p) {
+    const int q = proj_global(P, v, p);
+    const int64_t j0 = clamp64(P.nz_offsets[q], 0, P.n_nz);
+    const int64_t j1 = clamp64(P.nz_offsets[q + 1], j0, P.n_nz);
+    return j1 - j0 > SOF_MAX_NNZ ? SOF_MAX_NNZ : (int)(j1 - j0);
+}
 // Stage the nonzeros of node-local projection p into per-wave LDS (called by
 // a whole wave).  Returns z.
 __device__ __forceinline__ int proj_stage(const ProjCSR& P, int v, int p, int d, int32_t* lf,
@@ -112,6 +119,7 @@ __device__ __forceinline__ uint64_t draw_counter(int tree, int level, int pos, i
 }
 
 __device__ __forceinline__ int proj_count(const ProjHash& P, int) { return P.k; }
+__device__ __forceinline__ int proj_nnz(const ProjHash& P, int, int) { return P.z; }
 __device__ __forceinline__ int proj_global(const ProjHash& P, int v, int p) { return v * P.k + p; }
 // z distinct features by Floyd's sampling (Bentley and Floyd, CACM 1987):
 // draw j (j = 0..z-1) proposes t uniform in [0, d-z+j] by multiply-shift of
@@ -869,7 +877,7 @@ __device__ void do_mid_r(const FindArgs& A, const PS& P, int4 D, int g, int64_t 
 // stored at that number.
 
 struct BigDesc {
-    int node, slot, item_a, item_c, bigslot, k, nchunk, pad;
+    int node, slot, item_a, item_c, bigslot, k, nchunk, vc;   // vc: value-cache base in kVcUnit units, or -1
 };
 __device__ __forceinline__ BigDesc big_desc(const FindArgs& A, int d) {
     int4 a = A.ws.desc_big[2 * d], b = A.ws.desc_big[2 * d + 1];
@@ -886,7 +894,7 @@ constexpr int kBR = 16;   // samples per lane per step of a chunk loop
 template <typename T, class PS, bool kHist, class Bn>
 __device__ __forceinline__ void big_chunk(const FindArgs& A, const PS& P, const BigDesc& bd, int p,
                                           int ch, WaveScratch& WS, float& lo, float& hi,
-                                          int32_t* hist, const Bn& bin) {
+                                          int32_t* hist, const Bn& bin, float* vcw = nullptr) {
     const int lane = lane_id();
     const int C = A.n_classes;
     int64_t s0, n;
@@ -923,6 +931,11 @@ __device__ __forceinline__ void big_chunk(const FindArgs& A, const PS& P, const 
         }
         float v[kBR];
         gather_rows<T, kBR>(A, WS.lf, WS.ls, z, off, v);
+        if (!kHist && vcw) {
+#pragma unroll
+            for (int r = 0; r < kBR; ++r)
+                if (i0 + r * kWave + lane < cn) vcw[i0 + r * kWave + lane] = v[r];
+        }
 #pragma unroll
         for (int r = 0; r < kBR; ++r) {
             if (i0 + r * kWave + lane >= cn) continue;
@@ -934,6 +947,50 @@ __device__ __forceinline__ void big_chunk(const FindArgs& A, const PS& P, const 
             }
         }
     }
+}
+
+// Histogram pass of (projection, chunk) from the value cache: the range pass
+// stored the chunk's projected values, so only the row ids and labels are read
+// besides them (coalesced, R per lane per step, slots past the end repeat the
+// last sample and are masked out).
+template <class Bn>
+__device__ __forceinline__ void big_chunk_cached(const FindArgs& A, const BigDesc& bd, int ch, const float* vcr,
+                                                 int32_t* hist, const Bn& bin) {
+    const int lane = lane_id();
+    const int C = A.n_classes;
+    int64_t s0, n;
+    node_range(A, bd.node, s0, n);
+    const int64_t c0 = (int64_t)ch * kChunk;
+    const int cn = (int)clamp64(n - c0, 0, kChunk);
+    if (cn <= 0) return;
+    const int32_t* sidx = A.sample_idx + s0 + c0;
+    for (int i0 = 0; i0 < cn; i0 += kWave * kBR) {
+        int lab[kBR];
+        float v[kBR];
+#pragma unroll
+        for (int r = 0; r < kBR; ++r) {
+            const int i = i0 + r * kWave + lane;
+            const int j = i < cn ? i : cn - 1;
+            const int row = (uint32_t)sidx[j] < (uint32_t)A.n_rows ? sidx[j] : 0;
+            lab[r] = label_of(A, row);
+            v[r] = vcr[j];
+        }
+#pragma unroll
+        for (int r = 0; r < kBR; ++r)
+            if (i0 + r * kWave + lane < cn) atomicAdd(&hist[bin(v[r]) * C + lab[r]], 1);
+    }
+}
+
+// The value cache pays when re-gathering a projection costs more than
+// reading its stored value back (z elements of s_x bytes against 4).
+template <typename T>
+__device__ __forceinline__ bool use_vcache(const BigDesc& bd, int z) {
+    return bd.vc >= 0 && z * (int)sizeof(T) > 8;
+}
+__device__ __forceinline__ float* vcache_at(const FindArgs& A, const BigDesc& bd, int p, int ch) {
+    int64_t s0, n;
+    node_range(A, bd.node, s0, n);
+    return A.ws.vcache + (int64_t)bd.vc * kVcUnit + (int64_t)p * n + (int64_t)ch * kChunk;
 }
 
 // ---------------------------------------------------------------------------
@@ -981,6 +1038,8 @@ __global__ __launch_bounds__(kBlock) void k_plan(FindArgs A, PS P) {
         const int o_ic = wave_alloc(&W.hdr[H_IBIGC], cat == CAT_BIG ? k : 0);
         const int o_slot = wave_alloc(&W.hdr[H_SLOTS], slot_node ? k : 0);
         const int o_bslot = wave_alloc(&W.hdr[H_BIGSLOTS], cat == CAT_BIG ? k : 0);
+        const int vunits = cat == CAT_BIG ? (int)((n * (int64_t)k + kVcUnit - 1) / kVcUnit) : 0;
+        const int o_vc = wave_alloc(&W.hdr[H_VCACHE], vunits);
         bool over = false;
         if (slot_node && o_slot + (int64_t)k > W.cap_slots) over = true;
         if (cat == CAT_SMALL && o_small >= W.cap_small) over = true;
@@ -1013,7 +1072,8 @@ __global__ __launch_bounds__(kBlock) void k_plan(FindArgs A, PS P) {
         case CAT_SB: W.desc_sb[o_dsb] = make_int4(v, o_slot, o_isb, k); break;
         case CAT_BIG:
             W.desc_big[2 * o_dbig] = make_int4(v, o_slot, o_ia, o_ic);
-            W.desc_big[2 * o_dbig + 1] = make_int4(o_bslot, k, nch, 0);
+            W.desc_big[2 * o_dbig + 1] =
+                make_int4(o_bslot, k, nch, o_vc >= 0 && o_vc + (int64_t)vunits <= W.cap_vcache ? o_vc : -1);
             break;
         default: break;
         }
@@ -1086,7 +1146,8 @@ __global__ __launch_bounds__(kBlock) void k_brange(FindArgs A, PS P) {
         int p, ch;
         if (!big_item(A, it, nbig, bd, p, ch)) continue;
         float lo, hi;
-        big_chunk<T, PS, false>(A, P, bd, p, ch, WS, lo, hi, nullptr, EqualBins{0.f, 0.f, 2});
+        float* vcw = use_vcache<T>(bd, proj_nnz(P, bd.node, p)) ? vcache_at(A, bd, p, ch) : nullptr;
+        big_chunk<T, PS, false>(A, P, bd, p, ch, WS, lo, hi, nullptr, EqualBins{0.f, 0.f, 2}, vcw);
         lo = wave_min(lo);
         hi = wave_max(hi);
         if (lane_id() == 0) W.crange[it] = make_float2(lo, hi);
@@ -1114,8 +1175,12 @@ __global__ __launch_bounds__(kBlock) void k_bmerge(FindArgs A) {
         }
         lo = wave_min(lo);
         hi = wave_max(hi);
-        if (lane_id() == 0 && bd.bigslot + (int64_t)p < W.cap_bigslots)
-            W.brange[bd.bigslot + p] = make_float2(lo, hi);
+        if (bd.bigslot + (int64_t)p < W.cap_bigslots) {
+            if (lane_id() == 0) W.brange[bd.bigslot + p] = make_float2(lo, hi);
+            // the projection's histogram, filled by the histogram pass
+            int32_t* ph = W.phist + (int64_t)(bd.bigslot + p) * A.bins * A.n_classes;
+            for (int e = lane_id(); e < A.bins * A.n_classes; e += kWave) ph[e] = 0;
+        }
     }
 }
 
@@ -1141,23 +1206,29 @@ __global__ __launch_bounds__(kBlock) void k_bhist(FindArgs A, PS P) {
         for (int e = lane; e < B * C; e += kWave) hist[e] = 0;
         wave_sync();
         float lo, hi;
+        const float* vcr = use_vcache<T>(bd, proj_nnz(P, bd.node, p)) ? vcache_at(A, bd, p, ch) : nullptr;
         if (RW) {
             RwTable& tab = wave_rw(smem, w, Bm, C);
             const float sc = rw_cell_scale(r.x, r.y);
             rw_build(tab, A.bin_seed, proj_global(P, bd.node, p), B, r.x, r.y, sc);
-            big_chunk<T, PS, true>(A, P, bd, p, ch, WS, lo, hi, hist, RwBins{&tab, r.x, sc});
+            if (vcr) big_chunk_cached(A, bd, ch, vcr, hist, RwBins{&tab, r.x, sc});
+            else big_chunk<T, PS, true>(A, P, bd, p, ch, WS, lo, hi, hist, RwBins{&tab, r.x, sc});
         } else {
-            big_chunk<T, PS, true>(A, P, bd, p, ch, WS, lo, hi, hist, EqualBins{r.x, scale, B});
+            if (vcr) big_chunk_cached(A, bd, ch, vcr, hist, EqualBins{r.x, scale, B});
+            else big_chunk<T, PS, true>(A, P, bd, p, ch, WS, lo, hi, hist, EqualBins{r.x, scale, B});
         }
         wave_sync();
-        int32_t* out = W.chist + (int64_t)it * Bm * C;
-        for (int e = lane; e < B * C; e += kWave) out[e] = hist[e];
+        // add the chunk's counts into the projection's histogram (integer
+        // additions commute, so the sum does not depend on their order)
+        int32_t* ph = W.phist + (int64_t)(bd.bigslot + p) * Bm * C;
+        for (int e = lane; e < B * C; e += kWave)
+            if (hist[e]) atomicAdd(&ph[e], hist[e]);
         wave_sync();
     }
 }
 
-// Per (big node, projection): sum the chunk histograms into the wave's LDS
-// histogram, then the boundary scan.
+// Per (big node, projection): the projection's histogram (summed by the
+// histogram pass) into the wave's LDS histogram, then the boundary scan.
 template <class PS, bool RW>
 __global__ __launch_bounds__(kBlock) void k_bscan(FindArgs A, PS P) {
     extern __shared__ __align__(16) char smem[];
@@ -1175,18 +1246,14 @@ __global__ __launch_bounds__(kBlock) void k_bscan(FindArgs A, PS P) {
         if (p < 0 || p >= bd.k || bd.bigslot + (int64_t)p >= W.cap_bigslots ||
             bd.slot + (int64_t)p >= W.cap_slots)
             continue;
-        const int64_t base = (int64_t)bd.item_a + (int64_t)p * bd.nchunk;
-        if (base + bd.nchunk > W.cap_ibiga) continue;
         const int B = node_bins(A, bd.node);
         int64_t s0, n;
         node_range(A, bd.node, s0, n);
         const int Bs = bins_stride(Bm);
+        const int32_t* ph = W.phist + (int64_t)(bd.bigslot + p) * Bm * C;
         for (int e = lane; e < C * Bs; e += kWave) {
             const int c = e / Bs, b = e - c * Bs;
-            int32_t acc = 0;
-            if (b < B)
-                for (int ch = 0; ch < bd.nchunk; ++ch) acc += W.chist[(base + ch) * Bm * C + b * C + c];
-            hist[e] = acc;
+            hist[e] = b < B ? ph[b * C + c] : 0;
         }
         wave_sync();
         const float2 r = W.brange[bd.bigslot + p];

@@ -222,6 +222,10 @@ FindLayout sof::find_layout(int64_t N, int64_t S, int64_t P, int64_t K, int bins
     const int64_t nmid2 = mn(N, S / (kMidSplit + 1));
     c.cap_dmid2 = nmid2 + 1;
     c.cap_imid2 = mn(P, K * nmid2) + 1;
+    // every big node's n * k values, each node rounded up to whole units; off
+    // (0) beyond 2^30 units (a terabyte), where nodes fall back to re-gathering
+    c.cap_vcache = nbig > 0 ? (S * K) / kVcUnit + nbig + 1 : 0;
+    if (c.cap_vcache > (int64_t(1) << 30)) c.cap_vcache = 0;
     size_t o = 0;
     L.hdr = o; o = align_up(o + H_COUNT * sizeof(int32_t));
     L.small_items = o; o = align_up(o + c.cap_small * sizeof(int32_t));
@@ -237,7 +241,8 @@ FindLayout sof::find_layout(int64_t N, int64_t S, int64_t P, int64_t K, int bins
     L.slots = o; o = align_up(o + c.cap_slots * 80);
     L.crange = o; o = align_up(o + c.cap_ibiga * sizeof(float2));
     L.brange = o; o = align_up(o + c.cap_bigslots * sizeof(float2));
-    L.chist = o; o = align_up(o + (size_t)c.cap_ibiga * bins * classes * sizeof(int32_t));
+    L.phist = o; o = align_up(o + (size_t)c.cap_bigslots * bins * classes * sizeof(int32_t));
+    L.vcache = o; o = align_up(o + (size_t)c.cap_vcache * kVcUnit * sizeof(float));
     L.total = o;
     return L;
 }
@@ -259,7 +264,8 @@ void sof::find_bind(const FindLayout& L, void* ws, FindWs* w) {
     w->slots = (void*)(b + L.slots);
     w->crange = (float2*)(b + L.crange);
     w->brange = (float2*)(b + L.brange);
-    w->chist = (int32_t*)(b + L.chist);
+    w->phist = (int32_t*)(b + L.phist);
+    w->vcache = (float*)(b + L.vcache);
 }
 
 extern "C" int sof_workspace_size(const sof_ctx* ctx, const sof_data* data, const sof_frontier* fr,

@@ -18,6 +18,7 @@ constexpr int kMidSplit = 4096;      // mid nodes up to here: at most 16 samples
 constexpr int kMidMax = 8192;        // histogram nodes up to here: one block per (node, projection group)
 constexpr int kChunk = 8192;         // larger nodes: (node, projection, sample chunk) items
 constexpr int kSortMax = SOF_SORT_LIMIT;
+constexpr int kVcUnit = 256;         // allocation unit of the big-node value cache (floats)
 
 // header counters of the find-splits workspace
 enum {
@@ -33,6 +34,7 @@ enum {
     H_BIGSLOTS,    // big projection slots (merged range)
     H_DMID2,       // mid descriptors of nodes above kMidSplit samples
     H_IMID2,       // their items
+    H_VCACHE,      // projected-value cache of big nodes, in units of kVcUnit floats
     H_Q_MID = 16,  // dequeue counters
     H_Q_SMALL,
     H_Q_SB,
@@ -76,9 +78,10 @@ struct FindWs {
     void* slots;          // Cand[]
     float2* crange;       // per big item: (min, max) of the chunk
     float2* brange;       // per big slot: (min, max) over the node
-    int32_t* chist;       // per big item: [bins][classes] of the chunk
+    int32_t* phist;       // per big projection slot: [bins][classes] summed over the node's chunks
+    float* vcache;        // big nodes: projected values of the range pass, [projection][sample] per node
     int64_t cap_small, cap_dmid, cap_imid, cap_dsb, cap_isb, cap_dbig, cap_ibiga, cap_ibigc;
-    int64_t cap_slots, cap_bigslots, cap_dmid2, cap_imid2;
+    int64_t cap_slots, cap_bigslots, cap_dmid2, cap_imid2, cap_vcache;
 };
 
 struct FindArgs {
@@ -104,7 +107,7 @@ struct FindArgs {
 struct FindLayout {
     size_t hdr, small_items, desc_mid, desc_mid2, desc_sb, desc_big, items_mid, items_mid2, items_sb, items_biga,
         items_bigc;
-    size_t slots, crange, brange, chist, total;
+    size_t slots, crange, brange, phist, vcache, total;
     FindWs caps;
 };
 FindLayout find_layout(int64_t n_nodes, int64_t n_samples, int64_t n_proj, int64_t max_k, int bins,
