@@ -67,7 +67,11 @@ def lib():
         L.or_project.argtypes = [P, ctypes.c_int, i64, i32, P, P, P, P, P, P, P]
         L.or_project.restype = None
         L.or_find_splits.argtypes = [P, ctypes.c_int, i64, P, i32, i32, P, P, P, P, P, P, P, i32, i32,
-                                     i32, u64, P, P, i32]
+                                     i32, u64, i32, P, P, i32]
+        L.or_ln_int.argtypes = [i64]
+        L.or_ln_int.restype = ctypes.c_double
+        L.or_klnk.argtypes = [i64]
+        L.or_klnk.restype = ctypes.c_double
         L.or_rw_boundaries.argtypes = [u64, i64, ctypes.c_int, ctypes.c_float, ctypes.c_float, P]
         L.or_rw_boundaries.restype = None
         L.or_rw_bin.argtypes = [P, ctypes.c_int, ctypes.c_float]
@@ -143,6 +147,11 @@ def project(X, node_offsets, sample_idx, proj_offsets, nz_offsets, nz_feature, n
 
 
 BINS_EQUAL, BINS_RANDOM = 0, 1
+CRIT_GINI, CRIT_ENTROPY = 0, 1
+
+
+def ln_int(k: int) -> float:
+    return float(lib().or_ln_int(int(k)))
 
 
 def rw_boundaries(seed: int, q: int, n_bins: int, lo, hi) -> np.ndarray:
@@ -159,7 +168,7 @@ def rw_bin(t, n_bins: int, v) -> int:
 
 def find_splits(X, y, n_classes, node_offsets, sample_idx, proj_offsets, nz_offsets, nz_feature,
                 nz_weight, *, bins=256, sort_threshold=0, node_bins=None, hist=False, threads=0,
-                bin_mode=BINS_EQUAL, bin_seed=0):
+                bin_mode=BINS_EQUAL, bin_seed=0, criterion=CRIT_GINI):
     """Best split per node.  Returns (splits[N] of SPLIT_DTYPE, hist or None)."""
     X, dt = _xinfo(X)
     y = _c(y, np.int32)
@@ -172,7 +181,7 @@ def find_splits(X, y, n_classes, node_offsets, sample_idx, proj_offsets, nz_offs
     H = np.zeros((P, bins, n_classes), np.int32) if hist else None
     lib().or_find_splits(_p(X), dt, X.shape[1], _p(y), int(n_classes), N, _p(no), _p(si), _p(po), _p(zo),
                          _p(zf), _p(zw), _p(nb), int(bins), int(sort_threshold), int(bin_mode),
-                         int(bin_seed) & (2**64 - 1), _p(out), _p(H), int(threads))
+                         int(bin_seed) & (2**64 - 1), int(criterion), _p(out), _p(H), int(threads))
     return out, H
 
 

@@ -51,6 +51,16 @@
  *     The node splits iff the best candidate has a positive decrease,
  *     n*N > S_P*D with S_P = sum of squared parent counts; the reported gain
  *     is (n*N - S_P*D) / (n^2 * D) in binary64.
+ *  4'. Entropy criterion (information gain, YDF's own, Method step 3): with
+ *     f(k) = k ln k, maximising the gain H(P) - n_L/n H(L) - n_R/n H(R) is
+ *     maximising E = sum_c f(l_c) + sum_c f(r_c) - f(n_L) - f(n_R).  E is
+ *     evaluated in binary64 with a natural logarithm built from IEEE basic
+ *     operations only (or_ln_int below), the sums taken over c in ascending
+ *     order, so that an implementation performing the same operations gets the
+ *     same bits and the same argmax; a candidate replaces the incumbent only on
+ *     a strictly larger E.  The gain is ((f(n) - sum_c f(P_c)) + E) / n and
+ *     the node splits iff it exceeds 1e-12 (rounding stays below 1e-13 for
+ *     n <= 2^24).
  */
 #include "sof_oracle.h"
 
@@ -186,7 +196,73 @@ typedef struct {
     uint64_t D;
     int64_t nL, nR;
     uint64_t SL, SR;
+    double E, FL, FR;   /* entropy criterion: score, sum f(l_c), sum f(r_c) */
 } cand_t;
+
+/* Natural logarithm of an integer 1 <= k < 2^53 in binary64 by a fixed
+ * sequence of IEEE operations: k = m 2^e with m in [sqrt(2)/2, sqrt(2)) (exact
+ * halvings), then ln m = 2 atanh(s), s = (m - 1) / (m + 1), summed as
+ * 2 (s + s^3/3 + ... + s^25/25) (Abramowitz and Stegun 4.1.27); |s| <= 0.172,
+ * so the first omitted term is below 2^-60 of the sum. */
+double or_ln_int(int64_t k)
+{
+    int e = 0;
+    double m = (double)k;
+    while (m >= 2.0) {
+        m = m * 0.5;
+        ++e;
+    }
+    if (m > 1.4142135623730951) {
+        m = m * 0.5;
+        ++e;
+    }
+    double s = (m - 1.0) / (m + 1.0);
+    double s2 = s * s;
+    double t = s, sum = s;
+    for (int j = 1; j <= 12; ++j) {
+        t = t * s2;
+        sum = sum + t / (double)(2 * j + 1);
+    }
+    double a = (double)e * 0.69314718055994530942;
+    double b = 2.0 * sum;
+    return a + b;
+}
+
+/* f(k) = k ln k, f(0) = 0. */
+double or_klnk(int64_t k)
+{
+    if (k <= 0)
+        return 0.0;
+    return (double)k * or_ln_int(k);
+}
+
+static void consider_entropy(cand_t* best, const int64_t* l, const int64_t* parent, int C, int64_t n,
+                             int32_t pos, float thr, float lo, float scale)
+{
+    int64_t nL = 0;
+    double FL = 0.0, FR = 0.0;
+    for (int c = 0; c < C; ++c) {
+        nL += l[c];
+        FL = FL + or_klnk(l[c]);
+        FR = FR + or_klnk(parent[c] - l[c]);
+    }
+    int64_t nR = n - nL;
+    if (nL < 1 || nR < 1)
+        return;
+    double E = ((FL + FR) - or_klnk(nL)) - or_klnk(nR);
+    if (best->valid && !(E > best->E))
+        return;
+    best->valid = 1;
+    best->pos = pos;
+    best->thr = thr;
+    best->lo = lo;
+    best->scale = scale;
+    best->E = E;
+    best->FL = FL;
+    best->FR = FR;
+    best->nL = nL;
+    best->nR = nR;
+}
 
 /* N1/D1 > N2/D2 with both denominators positive. */
 static int q_greater(u128 N1, uint64_t D1, u128 N2, uint64_t D2)
@@ -194,8 +270,19 @@ static int q_greater(u128 N1, uint64_t D1, u128 N2, uint64_t D2)
     return N1 * (u128)D2 > N2 * (u128)D1;
 }
 
+static void consider_gini(cand_t* best, const int64_t* l, const int64_t* parent, int C, int64_t n,
+                          int32_t pos, float thr, float lo, float scale);
 static void consider(cand_t* best, const int64_t* l, const int64_t* parent, int C, int64_t n,
-                     int32_t pos, float thr, float lo, float scale)
+                     int32_t pos, float thr, float lo, float scale, int criterion)
+{
+    if (criterion == OR_CRIT_ENTROPY)
+        consider_entropy(best, l, parent, C, n, pos, thr, lo, scale);
+    else
+        consider_gini(best, l, parent, C, n, pos, thr, lo, scale);
+}
+
+static void consider_gini(cand_t* best, const int64_t* l, const int64_t* parent, int C, int64_t n,
+                          int32_t pos, float thr, float lo, float scale)
 {
     int64_t nL = 0;
     uint64_t SL = 0, SR = 0;
@@ -248,7 +335,7 @@ static int effective_threshold(int32_t T)
 static void eval_projection(const void* x, int dtype, int64_t ld, const int32_t* y, int C,
                             const int32_t* idx, int32_t n, const int64_t* parent,
                             const int32_t* feat, const int8_t* w, int z, int B, int sort_path,
-                            int bin_mode, uint64_t bin_seed, int64_t q,
+                            int bin_mode, uint64_t bin_seed, int64_t q, int criterion,
                             cand_t* best, int32_t* hist_row, int32_t bins_stride)
 {
     memset(best, 0, sizeof(*best));
@@ -278,7 +365,7 @@ static void eval_projection(const void* x, int dtype, int64_t ld, const int32_t*
             for (int c = 0; c < C; ++c)
                 l[c] += H[(int64_t)b * C + c];
             float thr = bin_mode == OR_BINS_RANDOM ? t[b] : lo + ((float)(b + 1) / scale);
-            consider(best, l, parent, C, n, b, thr, lo, scale);
+            consider(best, l, parent, C, n, b, thr, lo, scale, criterion);
         }
         free(H);
     } else {
@@ -291,7 +378,7 @@ static void eval_projection(const void* x, int dtype, int64_t ld, const int32_t*
         for (int32_t i = 0; i + 1 < n; ++i) {
             l[s[i].y] += 1;
             if (s[i].v < s[i + 1].v)
-                consider(best, l, parent, C, n, i, s[i].v, lo, 0.0f);
+                consider(best, l, parent, C, n, i, s[i].v, lo, 0.0f, criterion);
         }
         free(s);
         (void)bins_stride;
@@ -315,7 +402,7 @@ int or_find_splits(const void* x, int dtype, int64_t ld, const int32_t* y, int32
                    const int32_t* proj_offsets, const int32_t* nz_offsets,
                    const int32_t* nz_feature, const int8_t* nz_weight,
                    const int32_t* node_bins, int32_t bins, int32_t sort_threshold,
-                   int32_t bin_mode, uint64_t bin_seed,
+                   int32_t bin_mode, uint64_t bin_seed, int32_t criterion,
                    or_split* out, int32_t* hist_out, int32_t n_threads)
 {
     int32_t P = proj_offsets[n_nodes];
@@ -344,7 +431,7 @@ int or_find_splits(const void* x, int dtype, int64_t ld, const int32_t* y, int32
         int32_t j0 = nz_offsets[q], z = nz_offsets[q + 1] - j0;
         int32_t* hrow = (hist_out && !sort_path) ? hist_out + (int64_t)q * bins * C : NULL;
         eval_projection(x, dtype, ld, y, C, sample_idx + s0, n, parent + (int64_t)v * C,
-                        nz_feature + j0, nz_weight + j0, z, B, sort_path, bin_mode, bin_seed, q,
+                        nz_feature + j0, nz_weight + j0, z, B, sort_path, bin_mode, bin_seed, q, criterion,
                         &cands[q], hrow, bins);
     }
     for (int32_t v = 0; v < n_nodes; ++v) {
@@ -354,8 +441,38 @@ int or_find_splits(const void* x, int dtype, int64_t ld, const int32_t* y, int32
         for (int32_t q = proj_offsets[v]; q < proj_offsets[v + 1]; ++q) {
             if (!cands[q].valid)
                 continue;
-            if (bestq < 0 || q_greater(cands[q].N, cands[q].D, cands[bestq].N, cands[bestq].D))
+            if (bestq < 0 ||
+                (criterion == OR_CRIT_ENTROPY ? cands[q].E > cands[bestq].E
+                                              : q_greater(cands[q].N, cands[q].D, cands[bestq].N, cands[bestq].D)))
                 bestq = q;
+        }
+        if (criterion == OR_CRIT_ENTROPY) {
+            if (bestq < 0) {
+                no_split(&out[v], kind, n);
+                continue;
+            }
+            const cand_t* b = &cands[bestq];
+            double FP = 0.0;
+            for (int c = 0; c < C; ++c)
+                FP = FP + or_klnk(parent[(int64_t)v * C + c]);
+            double ig = ((or_klnk(n) - FP) + b->E) / (double)n;
+            if (!(ig > 1e-12)) {
+                no_split(&out[v], kind, n);
+                continue;
+            }
+            or_split* o = &out[v];
+            memset(o, 0, sizeof(*o));
+            o->proj = bestq - proj_offsets[v];
+            o->kind = kind;
+            o->bin = b->pos;
+            o->threshold = b->thr;
+            o->lo = b->lo;
+            o->scale = b->scale;
+            o->n_left = (int32_t)b->nL;
+            o->n_right = (int32_t)b->nR;
+            o->flags = (b->FL == or_klnk(b->nL) ? 1 : 0) | (b->FR == or_klnk(b->nR) ? 2 : 0);
+            o->gain = ig;
+            continue;
         }
         uint64_t SP = 0;
         for (int c = 0; c < C; ++c)
@@ -605,6 +722,7 @@ int64_t or_grow_forest(const void* x, int dtype, int64_t ld, int32_t d,
         if (level_units) level_units[level] = (int64_t)off[N] * k;
         or_split* sp = (or_split*)malloc(sizeof(or_split) * (size_t)N);
         or_find_splits(x, dtype, ld, y, C, N, off, sidx, po, no, nf, nw, NULL, bins, sort_threshold, OR_BINS_EQUAL, 0,
+                       OR_CRIT_GINI,
                        sp, NULL, n_threads);
         int32_t* pidx = (int32_t*)malloc(sizeof(int32_t) * (size_t)(off[N] > 0 ? off[N] : 1));
         int32_t* coff = (int32_t*)malloc(sizeof(int32_t) * (size_t)(2 * N + 1));

@@ -35,6 +35,10 @@ extern "C" {
  * threshold above OR_SORT_LIMIT + 1 acts as OR_SORT_LIMIT + 1. */
 #define OR_SORT_LIMIT 8192
 
+/* Split criteria. */
+#define OR_CRIT_GINI    0
+#define OR_CRIT_ENTROPY 1
+
 /* Bin layouts of the histogram path. */
 #define OR_BINS_EQUAL  0
 #define OR_BINS_RANDOM 1
@@ -96,8 +100,13 @@ int or_find_splits(const void* x, int dtype, int64_t ld, const int32_t* y, int32
                    const int32_t* proj_offsets, const int32_t* nz_offsets,
                    const int32_t* nz_feature, const int8_t* nz_weight,
                    const int32_t* node_bins, int32_t bins, int32_t sort_threshold,
-                   int32_t bin_mode, uint64_t bin_seed,
+                   int32_t bin_mode, uint64_t bin_seed, int32_t criterion,
                    or_split* out, int32_t* hist_out, int32_t n_threads);
+
+/* Natural logarithm of an integer k >= 1 by a fixed sequence of IEEE binary64
+ * operations, and f(k) = k ln k (the entropy criterion's building block). */
+double or_ln_int(int64_t k);
+double or_klnk(int64_t k);
 
 /* Stable partition of every node's samples by its split: left block (input
  * order) then right block (input order).  child_offsets has 2N+1 entries. */

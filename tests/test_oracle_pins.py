@@ -21,7 +21,8 @@ from tests import bruteforce as BF
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 
-def one_node(X, y, C, feats, weights, *, T=0, bins=256, idx=None, hist=False, bin_mode=0, bin_seed=0):
+def one_node(X, y, C, feats, weights, *, T=0, bins=256, idx=None, hist=False, bin_mode=0, bin_seed=0,
+             criterion=0):
     """Run the oracle on a single node holding all rows of X (or idx)."""
     n_rows = X.shape[1]
     idx = np.arange(n_rows, dtype=np.int32) if idx is None else np.asarray(idx, np.int32)
@@ -32,7 +33,8 @@ def one_node(X, y, C, feats, weights, *, T=0, bins=256, idx=None, hist=False, bi
     nw = np.concatenate([np.asarray(w, np.int8) for w in weights])
     sp, H = O.find_splits(X, y, C, np.array([0, len(idx)], np.int32), idx,
                           np.array([0, k], np.int32), nz_off, nf, nw, bins=bins,
-                          sort_threshold=T, hist=hist, bin_mode=bin_mode, bin_seed=bin_seed)
+                          sort_threshold=T, hist=hist, bin_mode=bin_mode, bin_seed=bin_seed,
+                          criterion=criterion)
     return sp[0], H, (nz_off, nf, nw)
 
 
@@ -721,3 +723,90 @@ def test_predict_votes_and_majority():
         one_v, one_p = O.predict(X, nodes, root_ids[t:t + 1], C)
         labels = np.array([nodes[O.leaf_of(X, nodes, int(root_ids[t]), r)]["label"] for r in range(0, 1500, 7)])
         assert np.array_equal(one_p[0:1500:7], labels)
+
+
+# --------------------------------------------------------------------------
+# entropy criterion
+# --------------------------------------------------------------------------
+
+def _ulp(x: float) -> float:
+    return math.ulp(x) if x else math.ulp(1.0)
+
+
+def test_ln_int_within_two_ulp_of_libm():
+    ks = list(range(1, 5000)) + [2**e + d for e in range(1, 31) for d in (-1, 0, 1)]
+    ks += [int(math.sqrt(2) * 2**e) + d for e in range(1, 30) for d in (-1, 0, 1)]
+    ks += list(np.random.default_rng(3).integers(1, 2**31 - 1, 2000))
+    for k in ks:
+        k = int(k)
+        if k < 1:
+            continue
+        got, want = O.ln_int(k), math.log(k)
+        assert abs(got - want) <= 2 * _ulp(want), (k, got, want)
+
+
+def _check_entropy_choice(sp, cands, n_tol=1e-12):
+    """The oracle's pick is a best candidate up to rounding, and the unique one
+    when it wins by a clear margin."""
+    best = max((g for g, *_ in cands), default=None)
+    if best is None or best <= n_tol:
+        assert sp["proj"] == -1 and sp["gain"] == 0.0
+        return
+    assert sp["proj"] >= 0
+    mine = [c for c in cands if (c[1], c[2]) == (sp["proj"], sp["bin"]) or
+            (isinstance(c[2], float) and (c[1], c[3]) == (sp["proj"], sp["n_left"]))]
+    assert mine, "the oracle's candidate is not one of the enumerated ones"
+    assert abs(sp["gain"] - best) <= 1e-12 * max(1.0, best)
+    assert mine[0][0] >= best - 1e-12
+    ordered = sorted(cands, key=lambda c: -c[0])
+    if len(ordered) == 1 or ordered[0][0] - ordered[1][0] > 1e-9:
+        g, p, t, n_left = ordered[0]
+        assert sp["proj"] == p and sp["n_left"] == n_left
+
+
+@pytest.mark.parametrize("seed", range(60))
+def test_entropy_hist_path_matches_bruteforce(seed):
+    rng = np.random.default_rng(7000 + seed)
+    n = int(rng.integers(2, 14))
+    C = int(rng.integers(2, 5))
+    d = 5
+    Xi = rng.integers(-1000, 1001, size=(d, n))
+    y = rng.integers(0, C, size=n).astype(np.int32)
+    k = int(rng.integers(1, 5))
+    B = int(rng.choice([2, 3, 8, 16, 100, 256]))
+    feats, weights = random_projs(rng, k, d, 3)
+    vals = exact_values(Xi, feats, weights, range(n))
+    bins = []
+    for vs in vals:
+        lo, hi = min(vs), max(vs)
+        row = []
+        for v in vs:
+            if hi == lo:
+                row.append(0)
+                continue
+            e = Fraction(v - lo) * B / (hi - lo)
+            if e < B and e != 0 and abs(e - round(e)) < Fraction(1, 10**5) * max(1, e):
+                pytest.skip("a sample sits on a bin edge within rounding")
+            row.append(min(math.floor(e), B - 1))
+        bins.append(row)
+    sp, _, _ = one_node(Xi.astype(np.float32), y, C, feats, weights, T=0, bins=B, criterion=O.CRIT_ENTROPY)
+    cands = BF.all_bin_gains(bins, y.tolist(), C, B)
+    _check_entropy_choice(sp, cands)
+    if sp["proj"] >= 0:
+        assert 0.0 < sp["gain"] <= BF.entropy(y.tolist(), C) + 1e-12
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_entropy_sort_path_matches_bruteforce(seed):
+    rng = np.random.default_rng(8000 + seed)
+    n = int(rng.integers(2, 14))
+    C = int(rng.integers(2, 5))
+    d = 5
+    Xi = rng.integers(-3, 4, size=(d, n))
+    y = rng.integers(0, C, size=n).astype(np.int32)
+    k = int(rng.integers(1, 5))
+    feats, weights = random_projs(rng, k, d, 3)
+    vals = exact_values(Xi, feats, weights, range(n))
+    sp, _, _ = one_node(Xi.astype(np.float32), y, C, feats, weights, T=1 << 30, criterion=O.CRIT_ENTROPY)
+    cands = [(g, p, float(t), nl) for g, p, t, nl in BF.all_threshold_gains(vals, y.tolist(), C)]
+    _check_entropy_choice(sp, cands)
