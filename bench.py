@@ -39,6 +39,7 @@ WORKLOADS = {
            "4.0M x 512 FP32 matrix, node rows contiguous, 3 classes, k=64, z=4, B=256",
     "c3b": "as c3a, each node's rows an ascending random subset of the matrix",
     "c3a_rw": "as c3a with random-width bins (boundaries at random-width intervals, two-level routing)",
+    "c3a_ent": "as c3a with the entropy criterion (information gain, binary64), histogram path at every node",
     "c2": "single root node, n=1048576, d=256 FP32, 2 classes, k=256, z=3, B=256, histogram path",
     "c5": "single root node, n=10M, d=128 FP16 on the 1/256 grid, 2 classes, k=128, z=1..8, B=256",
     "c5f32": "as c5 with the same values stored FP32",
@@ -63,6 +64,10 @@ def make_workload(name: str):
     if name == "c3a_rw":
         wl = W.config3("a")
         wl.meta.update(bin_mode=1, bin_seed=20260302)
+        return wl
+    if name == "c3a_ent":
+        wl = W.config3("a")
+        wl.meta.update(criterion=1)
         return wl
     if name == "c2":
         return W.config2()
@@ -201,7 +206,8 @@ def cpu_baseline(wl, T, budget_units: float):
                                sample.proj_offsets, sample.nz_offsets, sample.nz_feature, sample.nz_weight,
                                bins=sample.bins, sort_threshold=T, node_bins=sample.node_bins, threads=nt,
                                bin_mode=int(wl.meta.get("bin_mode", 0)),
-                               bin_seed=int(wl.meta.get("bin_seed", 0)))
+                               bin_seed=int(wl.meta.get("bin_seed", 0)),
+                               criterion=int(wl.meta.get("criterion", 0)))
         O.partition(sample.X, sample.node_offsets, sample.sample_idx, sample.proj_offsets, sample.nz_offsets,
                     sample.nz_feature, sample.nz_weight, ref, bins=sample.bins, node_bins=sample.node_bins)
         return time.perf_counter() - t0
@@ -262,8 +268,8 @@ class PlainForm:
             oidx = torch.empty(max(n, 1), dtype=torch.int32, device=dv)
             coff = torch.empty(3, dtype=torch.int32, device=dv)
             d, fr, p = f.structs()
-            q = S.sof_params(S._ptr(nb), int(wl.bins), int(T), int(wl.meta.get("bin_mode", 0)), 0,
-                             int(wl.meta.get("bin_seed", 0)))
+            q = S.sof_params(S._ptr(nb), int(wl.bins), int(T), int(wl.meta.get("bin_mode", 0)),
+                             int(wl.meta.get("criterion", 0)), int(wl.meta.get("bin_seed", 0)))
             sz = ctypes.c_size_t(0)
             S._check(S.lib().sof_workspace_size(ctx.handle, ctypes.byref(d), ctypes.byref(fr), ctypes.byref(p),
                                                 ctypes.byref(q), ctypes.byref(sz)))
@@ -514,6 +520,8 @@ def main():
 
     T = args.threshold
     tune = None
+    if wl.meta.get("criterion", 0):
+        T = 0   # the entropy criterion runs on the histogram path
     if T is None:
         tune = S.autotune(ctx, wl.n_classes, int(wl.meta.get("k", 64)), int(wl.meta.get("z", 3)), wl.bins,
                           dtype=wl.X.dtype)
@@ -525,9 +533,11 @@ def main():
 
     bin_mode = int(wl.meta.get("bin_mode", 0))
     bin_seed = int(wl.meta.get("bin_seed", 0))
+    criterion = int(wl.meta.get("criterion", 0))
 
     def step():
-        S.find_splits(ctx, dev, bins=wl.bins, sort_threshold=T, out=out, bin_mode=bin_mode, bin_seed=bin_seed)
+        S.find_splits(ctx, dev, bins=wl.bins, sort_threshold=T, out=out, bin_mode=bin_mode, bin_seed=bin_seed,
+                      criterion=criterion)
         S.partition(ctx, dev, out, bins=wl.bins)
 
     for _ in range(args.warmup):
@@ -580,6 +590,7 @@ def main():
                    "nodes": wl.n_nodes, "samples": int(wl.n_samples), "units": int(wl.units),
                    "sort_threshold": T, "bins": wl.bins,
                    "bin_layout": "random width" if bin_mode else "equal width",
+                   "criterion": "entropy" if criterion else "gini",
                    "step": "find_splits + partition"},
         "roofline": roof,
         "find_splits": {"ms": round(per["total"], 4), "algorithmic_bytes": sb["find"],

@@ -80,6 +80,10 @@ extern "C" {
 #define SOF_SPLIT_SORT  1   /* sort path */
 #define SOF_SPLIT_RHIST 2   /* histogram path, random-width bins */
 
+/* split criteria (sof_params.criterion) */
+#define SOF_CRIT_GINI    0
+#define SOF_CRIT_ENTROPY 1
+
 /* bin layouts of the histogram path (sof_params.bin_mode) */
 #define SOF_BINS_EQUAL  0
 #define SOF_BINS_RANDOM 1
@@ -129,9 +133,18 @@ typedef struct {
     int32_t        bins;          /* 2..SOF_MAX_BINS: bin count when node_bins is NULL, else the maximum */
     int32_t        sort_threshold;/* nodes with n < min(T, SOF_SORT_LIMIT + 1) sort; 0 = all histogram */
     int32_t        bin_mode;      /* SOF_BINS_EQUAL or SOF_BINS_RANDOM */
-    int32_t        pad;
+    int32_t        criterion;     /* SOF_CRIT_GINI, or SOF_CRIT_ENTROPY (histogram path only: sort_threshold 0) */
     uint64_t       bin_seed;      /* SOF_BINS_RANDOM: seed of the widths */
 } sof_params;
+
+/* Criteria.  SOF_CRIT_GINI: Gini decrease, argmax by exact 128-bit integer
+ * comparisons.  SOF_CRIT_ENTROPY (information gain, YDF's criterion in the
+ * Method section): each boundary's E = sum_c f(l_c) + sum_c f(r_c) - f(n_L)
+ * - f(n_R), f(k) = k ln k, in binary64 with a natural log built from IEEE
+ * basic operations (reduction to [sqrt(2)/2, sqrt(2)), 12 atanh-series terms),
+ * the sums over classes ascending; the largest E wins (lowest projection,
+ * then bin, on ties), the gain is ((f(n) - sum_c f(P_c)) + E) / n and the
+ * node splits iff it exceeds 1e-12. */
 
 /* Best split of one node (section 4.3: the projection and its split value). */
 typedef struct {

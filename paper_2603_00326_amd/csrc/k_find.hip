@@ -333,6 +333,69 @@ __device__ Cand scan_hist_fast(const LdsHistCM& h, int B, int C, int64_t n, floa
     return best;
 }
 
+// Entropy criterion over a class-major histogram (one wave; lane l owns bins
+// 4l..4l+3).  Every boundary b (0..B-2) with both sides non-empty gets
+// E = sum_c f(l_c) + sum_c f(r_c) - f(n_L) - f(n_R) in binary64, the sums over
+// c ascending, with f and the log of sof_device.h; the largest E wins, the
+// lowest boundary on ties.  The winner is returned with N = key(E), D = 1, so
+// the exact comparisons between projections order it by E; SL, SR, SP carry
+// the bits of sum f(l_c), sum f(r_c) and sum f(P_c) for the node record.
+__device__ Cand scan_hist_entropy(const LdsHistCM& h, int B, int C, int64_t n, float lo, float scale) {
+    const int lane = lane_id();
+    const int b0 = lane * 4;
+    double FL[4] = {0.0, 0.0, 0.0, 0.0}, FR[4] = {0.0, 0.0, 0.0, 0.0};
+    uint32_t nLi[4] = {0u, 0u, 0u, 0u};
+    double FP = 0.0;
+    for (int c = 0; c < C; ++c) {
+        uint4 q4 = make_uint4(0u, 0u, 0u, 0u);
+        if (b0 < B) q4 = h.load4(b0, c);
+        const uint32_t s0 = q4.x, s1 = s0 + q4.y, s2 = s1 + q4.z, s3 = s2 + q4.w;
+        const uint32_t incl = wave_scan_u(s3);
+        const uint32_t ex = incl - s3;
+        const uint32_t Pi = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+        FP = __dadd_rn(FP, klnk(Pi));
+        const uint32_t li[4] = {ex + s0, ex + s1, ex + s2, ex + s3};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            nLi[i] += li[i];
+            FL[i] = __dadd_rn(FL[i], klnk(li[i]));
+            FR[i] = __dadd_rn(FR[i], klnk(Pi - li[i]));
+        }
+    }
+    double bE = 0.0, bFL = 0.0, bFR = 0.0;
+    int bi = -1;
+    uint32_t bnL = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int64_t nL = nLi[i], nR = n - (int64_t)nLi[i];
+        if (b0 + i < B - 1 && nL >= 1 && nR >= 1) {
+            const double E = __dsub_rn(__dsub_rn(__dadd_rn(FL[i], FR[i]), klnk(nL)), klnk(nR));
+            if (bi < 0 || E > bE) { bE = E; bi = i; bFL = FL[i]; bFR = FR[i]; bnL = nLi[i]; }
+        }
+    }
+    Cand best;
+    cand_invalid(best);
+    best.SP = d_bits(FP);
+    best.lo = lo;
+    best.scale = scale;
+    const int win = wave_best_lane(bi >= 0, (u128)dkey(bE), 1ull, b0 + bi);
+    if (win < 0) return best;
+    const uint64_t kE = dkey(bE);
+    best.N = (u128)(((uint64_t)__builtin_amdgcn_readlane((int)(uint32_t)(kE >> 32), win) << 32) |
+                    (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)kE, win));
+    best.D = 1;
+    const uint64_t fl = d_bits(bFL), fr = d_bits(bFR);
+    best.SL = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(fl >> 32), win) << 32) |
+              (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)fl, win);
+    best.SR = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(fr >> 32), win) << 32) |
+              (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)fr, win);
+    best.pos = __builtin_amdgcn_readlane(b0 + bi, win);
+    best.nL = __builtin_amdgcn_readlane((int)bnL, win);
+    best.nR = (int32_t)(n - (int64_t)best.nL);
+    best.thr = hist_threshold(lo, scale, best.pos);
+    return best;
+}
+
 // ---------------------------------------------------------------------------
 // Histogram bins of one projection.  Equal width: the closed-form index.
 // Random width (bin boundaries at random-width intervals, after the
@@ -669,7 +732,7 @@ __device__ __forceinline__ void stage_batch(const ProjHash& P, int v, int p0, in
 
 constexpr int kSmallR = kSmallMax / kWave;   // up to 8 samples per lane
 
-template <typename T, class PS, int R, bool RW>
+template <typename T, class PS, int R, bool RW, bool ENT>
 __device__ void do_small_r(const FindArgs& A, const PS& P, int v, int64_t s0, int64_t n, char* smem) {
     BlockShared& S = block_shared(smem);
     const int w = threadIdx.x >> 6, lane = lane_id();
@@ -697,8 +760,12 @@ __device__ void do_small_r(const FindArgs& A, const PS& P, int v, int64_t s0, in
         if (lab[r] >= 0) atomicAdd(&WS.pc[lab[r]], 1);
     wave_sync();
 
-    Cand best;
-    cand_invalid(best);
+    // The wave's running best lives in its LDS slot and is replaced by a plain
+    // store: a conditional register copy of the 80-byte candidate was compiled
+    // for gfx950 into code that kept the old 128-bit N while taking the other
+    // fields of the new candidate.
+    if (lane == 0) cand_invalid(WS.best);
+    wave_sync();
     for (int pb = w; pb < k; pb += kWavesPerBlock * kSmallBatch) {
       stage_batch(P, v, pb, kWavesPerBlock, k, A.n_features, WS);
       for (int gi = 0; gi < kSmallBatch; ++gi) {
@@ -738,41 +805,44 @@ __device__ void do_small_r(const FindArgs& A, const PS& P, int v, int64_t s0, in
             wave_sync();
             LdsHistCM h{hist, Bs};
             write_hist_row(A, proj_global(P, v, p), h, B);
-            c = scan_hist_fast(h, B, C, n, lo, scale, WS.pcs);
+            if (ENT) c = scan_hist_entropy(h, B, C, n, lo, scale);
+            else c = scan_hist_fast(h, B, C, n, lo, scale, WS.pcs);
             if (RW && c.D != 0) c.thr = rw_boundary(A.bin_seed, proj_global(P, v, p), B, lo, hi, c.pos);
             wave_sync();
         }
         c.proj = p;
-        if (cand_better(c, best)) best = c;
+        const bool take = cand_better(c, WS.best);
+        wave_sync();
+        if (take && lane == 0) WS.best = c;
+        wave_sync();
       }
     }
-    if (lane == 0) WS.best = best;
     __syncthreads();
     if (w == 0) {
-        Cand b = S.w[0].best;
-        for (int ww = 1; ww < kWavesPerBlock; ++ww) {
-            const Cand& o = S.w[ww].best;
-            if (cand_better_proj(o, b)) b = o;
-        }
+        // the winning wave's index first, then one copy of its slot
+        int bw = 0;
+        for (int ww = 1; ww < kWavesPerBlock; ++ww)
+            if (cand_better_proj(S.w[ww].best, S.w[bw].best)) bw = ww;
+        Cand b = S.w[bw].best;
         uint64_t SP = 0;
         for (int c = 0; c < C; ++c) SP += (uint64_t)WS.pc[c] * (uint64_t)WS.pc[c];
-        b.SP = SP;
+        if (!ENT) b.SP = SP;
         if (lane == 0)
             write_record((SplitRec*)A.out + v, b, sortp ? SOF_SPLIT_SORT : (RW ? SOF_SPLIT_RHIST : SOF_SPLIT_HIST),
-                         (int32_t)n);
+                         (int32_t)n, ENT);
     }
 }
 
-template <typename T, class PS, bool RW>
+template <typename T, class PS, bool RW, bool ENT>
 __device__ void do_small(const FindArgs& A, const PS& P, int v, char* smem) {
     int64_t s0, n;
     node_range(A, v, s0, n);
     if (n > kSmallMax) n = kSmallMax;   // the plan never queues larger nodes here
     const int nr = (int)((n + kWave - 1) / kWave);
-    if (nr <= 1) do_small_r<T, PS, 1, RW>(A, P, v, s0, n, smem);
-    else if (nr <= 2) do_small_r<T, PS, 2, RW>(A, P, v, s0, n, smem);
-    else if (nr <= 4) do_small_r<T, PS, 4, RW>(A, P, v, s0, n, smem);
-    else do_small_r<T, PS, kSmallR, RW>(A, P, v, s0, n, smem);
+    if (nr <= 1) do_small_r<T, PS, 1, RW, ENT>(A, P, v, s0, n, smem);
+    else if (nr <= 2) do_small_r<T, PS, 2, RW, ENT>(A, P, v, s0, n, smem);
+    else if (nr <= 4) do_small_r<T, PS, 4, RW, ENT>(A, P, v, s0, n, smem);
+    else do_small_r<T, PS, kSmallR, RW, ENT>(A, P, v, s0, n, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -787,7 +857,7 @@ constexpr int kMidR = kMidMax / kBlock;   // up to 32 samples per thread
 // histogram; finally wave j scans histogram j, so the group's scans run in
 // parallel.  Range slots glo/ghi are indexed by projection, so no slot is
 // rewritten while another wave may still read it.
-template <typename T, class PS, int R, bool RW>
+template <typename T, class PS, int R, bool RW, bool ENT>
 __device__ void do_mid_r(const FindArgs& A, const PS& P, int4 D, int g, int64_t s0, int64_t n, char* smem) {
     BlockShared& S = block_shared(smem);
     const int tid = threadIdx.x, w = tid >> 6, lane = lane_id();
@@ -862,7 +932,7 @@ __device__ void do_mid_r(const FindArgs& A, const PS& P, int4 D, int g, int64_t 
         const float scale = bin_scale(B, lo, hi);
         LdsHistCM h{wave_hist(smem, w, Bm, C), Bs};
         write_hist_row(A, proj_global(P, v, p0 + w), h, B);
-        Cand c = scan_hist_fast(h, B, C, n, lo, scale, S.w[w].pcs);
+        Cand c = ENT ? scan_hist_entropy(h, B, C, n, lo, scale) : scan_hist_fast(h, B, C, n, lo, scale, S.w[w].pcs);
         if (RW && c.D != 0) c.thr = rw_boundary(A.bin_seed, proj_global(P, v, p0 + w), B, lo, hi, c.pos);
         c.proj = p0 + w;
         if (lane == 0) ((Cand*)A.ws.slots)[D.y + p0 + w] = c;
@@ -1229,7 +1299,7 @@ __global__ __launch_bounds__(kBlock) void k_bhist(FindArgs A, PS P) {
 
 // Per (big node, projection): the projection's histogram (summed by the
 // histogram pass) into the wave's LDS histogram, then the boundary scan.
-template <class PS, bool RW>
+template <class PS, bool RW, bool ENT>
 __global__ __launch_bounds__(kBlock) void k_bscan(FindArgs A, PS P) {
     extern __shared__ __align__(16) char smem[];
     const FindWs& W = A.ws;
@@ -1260,7 +1330,8 @@ __global__ __launch_bounds__(kBlock) void k_bscan(FindArgs A, PS P) {
         const float scale = bin_scale(B, r.x, r.y);
         LdsHistCM h{hist, Bs};
         write_hist_row(A, proj_global(P, bd.node, p), h, B);
-        Cand c = scan_hist_fast(h, B, C, n, r.x, scale, block_shared(smem).w[w].pcs);
+        Cand c = ENT ? scan_hist_entropy(h, B, C, n, r.x, scale)
+                     : scan_hist_fast(h, B, C, n, r.x, scale, block_shared(smem).w[w].pcs);
         if (RW && c.D != 0) c.thr = rw_boundary(A.bin_seed, proj_global(P, bd.node, p), B, r.x, r.y, c.pos);
         c.proj = p;
         if (lane == 0) ((Cand*)W.slots)[bd.slot + p] = c;
@@ -1271,7 +1342,7 @@ __global__ __launch_bounds__(kBlock) void k_bscan(FindArgs A, PS P) {
 // kLarge: nodes of kMidSplit+1 .. kMidMax samples (32 per thread); else
 // kSmallMax+1 .. kMidSplit (up to 16 per thread).  Separate kernels so that
 // each gets the register allocation of its own size class.
-template <typename T, class PS, bool kLarge, bool RW>
+template <typename T, class PS, bool kLarge, bool RW, bool ENT>
 __global__ __launch_bounds__(kBlock, kLarge ? 1 : 4) void k_mid(FindArgs A, PS P) {
     extern __shared__ __align__(16) char smem[];
     BlockShared& S = block_shared(smem);
@@ -1291,18 +1362,18 @@ __global__ __launch_bounds__(kBlock, kLarge ? 1 : 4) void k_mid(FindArgs A, PS P
         node_range(A, D.x, s0, n);
         if (kLarge) {
             if (n > kMidMax) n = kMidMax;   // the plan never queues larger nodes here
-            do_mid_r<T, PS, kMidR, RW>(A, P, D, e.y, s0, n, smem);
+            do_mid_r<T, PS, kMidR, RW, ENT>(A, P, D, e.y, s0, n, smem);
         } else {
             if (n > kMidSplit) n = kMidSplit;   // the plan never queues larger nodes here
             const int nr = (int)((n + kBlock - 1) / kBlock);
-            if (nr <= 4) do_mid_r<T, PS, 4, RW>(A, P, D, e.y, s0, n, smem);
-            else if (nr <= 8) do_mid_r<T, PS, 8, RW>(A, P, D, e.y, s0, n, smem);
-            else do_mid_r<T, PS, 16, RW>(A, P, D, e.y, s0, n, smem);
+            if (nr <= 4) do_mid_r<T, PS, 4, RW, ENT>(A, P, D, e.y, s0, n, smem);
+            else if (nr <= 8) do_mid_r<T, PS, 8, RW, ENT>(A, P, D, e.y, s0, n, smem);
+            else do_mid_r<T, PS, 16, RW, ENT>(A, P, D, e.y, s0, n, smem);
         }
     }
 }
 
-template <typename T, class PS, bool RW>
+template <typename T, class PS, bool RW, bool ENT>
 __global__ __launch_bounds__(kBlock, 4) void k_small(FindArgs A, PS P) {
     extern __shared__ __align__(16) char smem[];
     BlockShared& S = block_shared(smem);
@@ -1313,7 +1384,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_small(FindArgs A, PS P) {
         int it = block_dequeue(&W.hdr[H_Q_SMALL], &S.item);
         if (it >= ns) break;
         int v = W.small_items[it];
-        if (v >= 0 && v < N) do_small<T, PS, RW>(A, P, v, smem);
+        if (v >= 0 && v < N) do_small<T, PS, RW, ENT>(A, P, v, smem);
     }
 }
 
@@ -1354,7 +1425,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce(FindArgs A) {
         Cand b;
         if (win >= 0) b = slots[slot + __shfl(bp, win)];
         else cand_invalid(b);
-        if (lane == 0) write_record((SplitRec*)A.out + node, b, kind, (int32_t)n);
+        if (lane == 0) write_record((SplitRec*)A.out + node, b, kind, (int32_t)n, A.criterion == SOF_CRIT_ENTROPY);
     }
 }
 
@@ -1559,7 +1630,7 @@ __global__ __launch_bounds__(kBlock) void k_sortblk(FindArgs A, PS P) {
 // ---------------------------------------------------------------------------
 // host side
 
-template <typename T, class PS, bool RW>
+template <typename T, class PS, bool RW, bool ENT>
 static hipError_t launch_find_t(const FindArgs& a, const PS& p, const LaunchCfg& cfg, hipStream_t s,
                                 const hipEvent_t* ev) {
     const int Nc = a.n_nodes > 0 ? a.n_nodes : 1;
@@ -1581,13 +1652,13 @@ static hipError_t launch_find_t(const FindArgs& a, const PS& p, const LaunchCfg&
     mark();
     hipLaunchKernelGGL((k_bhist<T, PS, RW>), dim3(cfg.grid_bhist), dim3(kBlock), sm, s, a, p);
     mark();
-    hipLaunchKernelGGL((k_bscan<PS, RW>), dim3(cfg.grid_bscan), dim3(kBlock), sm, s, a, p);
+    hipLaunchKernelGGL((k_bscan<PS, RW, ENT>), dim3(cfg.grid_bscan), dim3(kBlock), sm, s, a, p);
     mark();
-    hipLaunchKernelGGL((k_mid<T, PS, false, RW>), dim3(cfg.grid_mid), dim3(kBlock), sm, s, a, p);
+    hipLaunchKernelGGL((k_mid<T, PS, false, RW, ENT>), dim3(cfg.grid_mid), dim3(kBlock), sm, s, a, p);
     mark();
-    hipLaunchKernelGGL((k_mid<T, PS, true, RW>), dim3(cfg.grid_mid2), dim3(kBlock), sm, s, a, p);
+    hipLaunchKernelGGL((k_mid<T, PS, true, RW, ENT>), dim3(cfg.grid_mid2), dim3(kBlock), sm, s, a, p);
     mark();
-    hipLaunchKernelGGL((k_small<T, PS, RW>), dim3(cfg.grid_small), dim3(kBlock), sm, s, a, p);
+    hipLaunchKernelGGL((k_small<T, PS, RW, ENT>), dim3(cfg.grid_small), dim3(kBlock), sm, s, a, p);
     mark();
     hipLaunchKernelGGL((k_sortblk<T, PS>), dim3(cfg.grid_sort), dim3(kBlock), cfg.smem_sort, s, a, p);
     mark();
@@ -1598,18 +1669,27 @@ static hipError_t launch_find_t(const FindArgs& a, const PS& p, const LaunchCfg&
 
 hipError_t launch_find_csr(const FindArgs& a, const ProjCSR& p, const LaunchCfg& cfg, hipStream_t s,
                            const hipEvent_t* ev) {
-    const bool rw = a.bin_mode == SOF_BINS_RANDOM;
-    if (a.dtype == SOF_F16)
-        return rw ? launch_find_t<_Float16, ProjCSR, true>(a, p, cfg, s, ev)
-                  : launch_find_t<_Float16, ProjCSR, false>(a, p, cfg, s, ev);
-    return rw ? launch_find_t<float, ProjCSR, true>(a, p, cfg, s, ev)
-              : launch_find_t<float, ProjCSR, false>(a, p, cfg, s, ev);
+    const int mode = (a.bin_mode == SOF_BINS_RANDOM ? 1 : 0) | (a.criterion == SOF_CRIT_ENTROPY ? 2 : 0);
+    if (a.dtype == SOF_F16) {
+        switch (mode) {
+        case 1: return launch_find_t<_Float16, ProjCSR, true, false>(a, p, cfg, s, ev);
+        case 2: return launch_find_t<_Float16, ProjCSR, false, true>(a, p, cfg, s, ev);
+        case 3: return launch_find_t<_Float16, ProjCSR, true, true>(a, p, cfg, s, ev);
+        default: return launch_find_t<_Float16, ProjCSR, false, false>(a, p, cfg, s, ev);
+        }
+    }
+    switch (mode) {
+    case 1: return launch_find_t<float, ProjCSR, true, false>(a, p, cfg, s, ev);
+    case 2: return launch_find_t<float, ProjCSR, false, true>(a, p, cfg, s, ev);
+    case 3: return launch_find_t<float, ProjCSR, true, true>(a, p, cfg, s, ev);
+    default: return launch_find_t<float, ProjCSR, false, false>(a, p, cfg, s, ev);
+    }
 }
 // forest growth uses equal-width bins
 hipError_t launch_find_hash(const FindArgs& a, const ProjHash& p, const LaunchCfg& cfg, hipStream_t s,
                             const hipEvent_t* ev) {
-    if (a.dtype == SOF_F16) return launch_find_t<_Float16, ProjHash, false>(a, p, cfg, s, ev);
-    return launch_find_t<float, ProjHash, false>(a, p, cfg, s, ev);
+    if (a.dtype == SOF_F16) return launch_find_t<_Float16, ProjHash, false, false>(a, p, cfg, s, ev);
+    return launch_find_t<float, ProjHash, false, false>(a, p, cfg, s, ev);
 }
 
 // resident blocks per CU of a kernel (at least 1)
@@ -1620,7 +1700,7 @@ static hipError_t occ(const void* f, size_t smem, int* out) {
     return e;
 }
 
-template <bool RW>
+template <bool RW, bool ENT>
 static hipError_t find_occupancy_t(int bins, int classes, int n_cu, LaunchCfg* cfg) {
     const size_t sm = find_smem_main(bins, classes, RW), ss = find_smem_sort();
     int b = 0;
@@ -1628,11 +1708,11 @@ static hipError_t find_occupancy_t(int bins, int classes, int n_cu, LaunchCfg* c
     cfg->n_cu = n_cu;
     cfg->smem_main = sm;
     cfg->smem_sort = ss;
-    if ((e = occ((const void*)k_mid<float, ProjCSR, false, RW>, sm, &b)) != hipSuccess) return e;
+    if ((e = occ((const void*)k_mid<float, ProjCSR, false, RW, ENT>, sm, &b)) != hipSuccess) return e;
     cfg->grid_mid = n_cu * b;
-    if ((e = occ((const void*)k_mid<float, ProjCSR, true, RW>, sm, &b)) != hipSuccess) return e;
+    if ((e = occ((const void*)k_mid<float, ProjCSR, true, RW, ENT>, sm, &b)) != hipSuccess) return e;
     cfg->grid_mid2 = n_cu * b;
-    if ((e = occ((const void*)k_small<float, ProjCSR, RW>, sm, &b)) != hipSuccess) return e;
+    if ((e = occ((const void*)k_small<float, ProjCSR, RW, ENT>, sm, &b)) != hipSuccess) return e;
     cfg->grid_small = n_cu * b;
     if ((e = occ((const void*)k_sortblk<float, ProjCSR>, ss, &b)) != hipSuccess) return e;
     cfg->grid_sort = n_cu * b;
@@ -1640,15 +1720,19 @@ static hipError_t find_occupancy_t(int bins, int classes, int n_cu, LaunchCfg* c
     cfg->grid_brange = n_cu * b;
     if ((e = occ((const void*)k_bhist<float, ProjCSR, RW>, sm, &b)) != hipSuccess) return e;
     cfg->grid_bhist = n_cu * b;
-    if ((e = occ((const void*)k_bscan<ProjCSR, RW>, sm, &b)) != hipSuccess) return e;
+    if ((e = occ((const void*)k_bscan<ProjCSR, RW, ENT>, sm, &b)) != hipSuccess) return e;
     cfg->grid_bscan = n_cu * b;
     cfg->grid_light = n_cu * 4;
     return hipSuccess;
 }
 
-hipError_t find_occupancy(int bins, int classes, bool random_bins, int n_cu, LaunchCfg* cfg) {
-    return random_bins ? find_occupancy_t<true>(bins, classes, n_cu, cfg)
-                       : find_occupancy_t<false>(bins, classes, n_cu, cfg);
+hipError_t find_occupancy(int bins, int classes, int mode, int n_cu, LaunchCfg* cfg) {
+    switch (mode & 3) {
+    case 1: return find_occupancy_t<true, false>(bins, classes, n_cu, cfg);
+    case 2: return find_occupancy_t<false, true>(bins, classes, n_cu, cfg);
+    case 3: return find_occupancy_t<true, true>(bins, classes, n_cu, cfg);
+    default: return find_occupancy_t<false, false>(bins, classes, n_cu, cfg);
+    }
 }
 
 }  // namespace sof

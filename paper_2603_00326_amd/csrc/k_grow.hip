@@ -607,7 +607,7 @@ extern "C" int sof_forest_create(sof_ctx* ctx, const sof_data* data, const sof_f
     if (maxroot > SOF_MAX_NODE_SAMPLES) { delete f; return fail(SOF_ERR_OVERFLOW, "root above 2^24 samples"); }
     f->cap_front = f->n_samples / 2 + desc->n_trees + 1;
     f->cap_nodes = 2 * f->n_samples + desc->n_trees + 2;
-    if ((rc = launch_cfg(ctx, desc->bins, data->n_classes, false, &f->cfg))) { delete f; return rc; }
+    if ((rc = launch_cfg(ctx, desc->bins, data->n_classes, 0, &f->cfg))) { delete f; return rc; }
     const int C = data->n_classes;
     const int64_t S = f->n_samples > 0 ? f->n_samples : 1, F = f->cap_front;
     f->flay = find_layout(F, S, F * desc->k, desc->k, desc->bins, C);

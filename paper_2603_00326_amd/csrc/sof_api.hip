@@ -113,16 +113,16 @@ static const hipEvent_t* timing_events(sof_ctx* ctx) {
     return ctx->tev[ctx->tev_used++].data();
 }
 
-int sof::launch_cfg(sof_ctx* ctx, int bins, int classes, bool random_bins, LaunchCfg* cfg) {
+int sof::launch_cfg(sof_ctx* ctx, int bins, int classes, int mode, LaunchCfg* cfg) {
     std::lock_guard<std::mutex> g(ctx->mu);
-    auto key = std::make_pair(2 * bins + (random_bins ? 1 : 0), classes);
+    auto key = std::make_pair(4 * bins + (mode & 3), classes);
     auto it = ctx->cfg.find(key);
     if (it != ctx->cfg.end()) {
         *cfg = it->second;
         return SOF_OK;
     }
     LaunchCfg c;
-    hipError_t e = find_occupancy(bins, classes, random_bins, ctx->n_cu, &c);
+    hipError_t e = find_occupancy(bins, classes, mode, ctx->n_cu, &c);
     if (e != hipSuccess) return hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
     if (c.smem_main > ctx->lds_per_block || c.smem_sort > ctx->lds_per_block)
         return fail(SOF_ERR_UNSUPPORTED, "LDS need %zu/%zu bytes exceeds %zu per block", c.smem_main,
@@ -191,6 +191,10 @@ int sof::check_params(const sof_params* q) {
     if (q->sort_threshold < 0) return fail(SOF_ERR_INVALID_ARG, "sort_threshold < 0");
     if (q->bin_mode != SOF_BINS_EQUAL && q->bin_mode != SOF_BINS_RANDOM)
         return fail(SOF_ERR_UNSUPPORTED, "bin_mode %d (expected SOF_BINS_EQUAL or SOF_BINS_RANDOM)", q->bin_mode);
+    if (q->criterion != SOF_CRIT_GINI && q->criterion != SOF_CRIT_ENTROPY)
+        return fail(SOF_ERR_UNSUPPORTED, "criterion %d (expected SOF_CRIT_GINI or SOF_CRIT_ENTROPY)", q->criterion);
+    if (q->criterion == SOF_CRIT_ENTROPY && q->sort_threshold != 0)
+        return fail(SOF_ERR_UNSUPPORTED, "the entropy criterion runs on the histogram path only (sort_threshold 0)");
     return SOF_OK;
 }
 
@@ -321,6 +325,7 @@ int sof::fill_find_args(const sof_data* data, const sof_frontier* fr, const sof_
     a->bins = params->bins;
     a->sort_threshold = clamp_threshold(params->sort_threshold);
     a->bin_mode = params->bin_mode;
+    a->criterion = params->criterion;
     a->bin_seed = params->bin_seed;
     a->out = out;
     a->hist_out = hist_out;
@@ -343,7 +348,9 @@ extern "C" int sof_find_splits(sof_ctx* ctx, const sof_data* data, const sof_fro
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     LaunchCfg cfg;
-    if ((rc = launch_cfg(ctx, params->bins, data->n_classes, params->bin_mode == SOF_BINS_RANDOM, &cfg)))
+    if ((rc = launch_cfg(ctx, params->bins, data->n_classes,
+                         (params->bin_mode == SOF_BINS_RANDOM ? 1 : 0) | (params->criterion == SOF_CRIT_ENTROPY ? 2 : 0),
+                         &cfg)))
         return rc;
     if (ctx->check && (rc = device_check(ctx, data, fr, proj, params, (hipStream_t)stream))) return rc;
     FindArgs a;

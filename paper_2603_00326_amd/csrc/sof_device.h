@@ -250,6 +250,46 @@ __device__ __forceinline__ float u128_to_float(u128 x) {
     return ldexpf((float)m, sh);
 }
 
+// ---------------------------------------------------------------------------
+// Entropy criterion helpers.  f(k) = k ln k in binary64, with the natural log
+// of an integer built from IEEE basic operations only (each correctly
+// rounded, so any implementation of the same sequence gets the same bits):
+// k = m 2^e with m in [sqrt(2)/2, sqrt(2)), ln m = 2 atanh(s) with
+// s = (m - 1) / (m + 1), summed as 2 (s + s^3/3 + ... + s^25/25)
+// (Abramowitz and Stegun 4.1.27; |s| <= 0.172, first omitted term below 2^-60
+// of the sum).
+__device__ __forceinline__ double ln_int(int64_t k) {
+    int e = 63 - __clzll((long long)k);          // k >= 1: m = k 2^-e in [1, 2), exact
+    double m = ldexp((double)k, -e);
+    if (m > 1.4142135623730951) {
+        m = __dmul_rn(m, 0.5);
+        ++e;
+    }
+    const double s = __ddiv_rn(__dsub_rn(m, 1.0), __dadd_rn(m, 1.0));
+    const double s2 = __dmul_rn(s, s);
+    double t = s, sum = s;
+#pragma unroll
+    for (int j = 1; j <= 12; ++j) {
+        t = __dmul_rn(t, s2);
+        sum = __dadd_rn(sum, __ddiv_rn(t, (double)(2 * j + 1)));
+    }
+    return __dadd_rn(__dmul_rn((double)e, 0.69314718055994530942), __dmul_rn(2.0, sum));
+}
+__device__ __forceinline__ double klnk(int64_t k) { return k <= 0 ? 0.0 : __dmul_rn((double)k, ln_int(k)); }
+
+// Order-preserving map of a (non-NaN) double to an unsigned key, and back:
+// an entropy candidate keeps key(E) in N and 1 in D, so the exact (N, D)
+// comparisons below order it by E.
+__device__ __forceinline__ uint64_t dkey(double x) {
+    const uint64_t b = (uint64_t)__double_as_longlong(x);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double dkey_inv(uint64_t k) {
+    return __longlong_as_double((long long)((k >> 63) ? (k & 0x7fffffffffffffffull) : ~k));
+}
+__device__ __forceinline__ double bits_d(uint64_t b) { return __longlong_as_double((long long)b); }
+__device__ __forceinline__ uint64_t d_bits(double x) { return (uint64_t)__double_as_longlong(x); }
+
 // The node record of the best candidate (n = node size).
 struct SplitRec {
     int32_t proj, kind, bin;
@@ -259,11 +299,19 @@ struct SplitRec {
 };
 static_assert(sizeof(SplitRec) == 40, "sof_split layout");
 
-__device__ __forceinline__ void write_record(SplitRec* out, const Cand& b, int kind, int32_t n) {
+// Gini: split iff n N > S_P D, gain (n N - S_P D) / (n^2 D).  Entropy (N =
+// key of E, SL / SR / SP = bits of sum f(l_c), sum f(r_c), sum f(P_c)): gain
+// ((f(n) - sum f(P_c)) + E) / n, split iff it exceeds 1e-12.
+__device__ __forceinline__ void write_record(SplitRec* out, const Cand& b, int kind, int32_t n,
+                                             bool entropy = false) {
     SplitRec r;
     bool split = false;
     u128 lhs = 0, rhs = 0;
-    if (b.D != 0) {
+    double ig = 0.0;
+    if (b.D != 0 && entropy) {
+        ig = __ddiv_rn(__dadd_rn(__dsub_rn(klnk(n), bits_d(b.SP)), dkey_inv((uint64_t)b.N)), (double)n);
+        split = ig > 1e-12;
+    } else if (b.D != 0) {
         lhs = (u128)(uint64_t)n * b.N;
         rhs = (u128)b.SP * (u128)b.D;
         split = lhs > rhs;
@@ -274,10 +322,15 @@ __device__ __forceinline__ void write_record(SplitRec* out, const Cand& b, int k
     } else {
         r.proj = b.proj; r.kind = kind; r.bin = b.pos; r.threshold = b.thr; r.lo = b.lo;
         r.scale = b.scale; r.n_left = b.nL; r.n_right = b.nR;
-        r.flags = (b.SL == (uint64_t)b.nL * (uint64_t)b.nL ? 1 : 0) |
-                  (b.SR == (uint64_t)b.nR * (uint64_t)b.nR ? 2 : 0);
-        u128 den = (u128)((uint64_t)n * (uint64_t)n) * (u128)b.D;
-        r.gain = __fdiv_rn(u128_to_float(lhs - rhs), u128_to_float(den));
+        if (entropy) {
+            r.flags = (bits_d(b.SL) == klnk(b.nL) ? 1 : 0) | (bits_d(b.SR) == klnk(b.nR) ? 2 : 0);
+            r.gain = (float)ig;
+        } else {
+            r.flags = (b.SL == (uint64_t)b.nL * (uint64_t)b.nL ? 1 : 0) |
+                      (b.SR == (uint64_t)b.nR * (uint64_t)b.nR ? 2 : 0);
+            u128 den = (u128)((uint64_t)n * (uint64_t)n) * (u128)b.D;
+            r.gain = __fdiv_rn(u128_to_float(lhs - rhs), u128_to_float(den));
+        }
     }
     *out = r;
 }

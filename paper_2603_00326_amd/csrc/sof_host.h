@@ -18,7 +18,7 @@ struct sof_ctx {
     size_t lds_per_block = 0;
     bool check = false;
     std::mutex mu;
-    std::map<std::pair<int, int>, sof::LaunchCfg> cfg;   // key (2 * bins + random_bins, classes)
+    std::map<std::pair<int, int>, sof::LaunchCfg> cfg;   // key (4 * bins + mode, classes)
     bool timing = false;                             // benchmark instrumentation
     std::vector<std::array<hipEvent_t, SOF_STAGE_COUNT + 1>> tev;  // one event set per recorded call
     size_t tev_used = 0;
@@ -36,7 +36,8 @@ int check_params(const sof_params* q);
 int check_ws_public(void* ws, size_t ws_bytes, size_t need);
 int clamp_threshold(int t);
 
-int launch_cfg(sof_ctx* ctx, int bins, int classes, bool random_bins, LaunchCfg* cfg);
+// mode: bit 0 random-width bins, bit 1 entropy criterion
+int launch_cfg(sof_ctx* ctx, int bins, int classes, int mode, LaunchCfg* cfg);
 int fill_find_args(const sof_data* data, const sof_frontier* fr, const sof_params* params,
                    sof_split* out, int32_t* hist_out, FindArgs* a);
 

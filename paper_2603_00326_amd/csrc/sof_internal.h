@@ -97,6 +97,7 @@ struct FindArgs {
     const int32_t* node_bins;
     int32_t bins, sort_threshold;  // sort_threshold already clamped
     int32_t bin_mode;           // SOF_BINS_EQUAL or SOF_BINS_RANDOM
+    int32_t criterion;          // SOF_CRIT_GINI or SOF_CRIT_ENTROPY
     uint64_t bin_seed;
     void* out;                  // SplitRec[n_nodes]
     int32_t* hist_out;
@@ -129,6 +130,7 @@ hipError_t launch_find_hash(const FindArgs& a, const ProjHash& p, const LaunchCf
                             const hipEvent_t* ev = nullptr);
 size_t find_smem_main(int bins, int classes, bool random_bins);
 size_t find_smem_sort();
-hipError_t find_occupancy(int bins, int classes, bool random_bins, int n_cu, LaunchCfg* cfg);
+// mode: bit 0 random-width bins, bit 1 entropy criterion
+hipError_t find_occupancy(int bins, int classes, int mode, int n_cu, LaunchCfg* cfg);
 
 }  // namespace sof

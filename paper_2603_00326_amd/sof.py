@@ -24,6 +24,7 @@ SOF_ERR_HIP = -5
 SOF_ERR_DEVICE = -6
 SOF_F32, SOF_F16 = 0, 1
 SOF_BINS_EQUAL, SOF_BINS_RANDOM = 0, 1
+SOF_CRIT_GINI, SOF_CRIT_ENTROPY = 0, 1
 SOF_SPLIT_HIST, SOF_SPLIT_SORT, SOF_SPLIT_RHIST = 0, 1, 2
 SORT_LIMIT = 8192
 INT32_MAX = 2**31 - 1
@@ -63,7 +64,7 @@ class sof_proj(ctypes.Structure):
 
 
 class sof_params(ctypes.Structure):
-    _fields_ = [("node_bins", P), ("bins", i32), ("sort_threshold", i32), ("bin_mode", i32), ("pad", i32),
+    _fields_ = [("node_bins", P), ("bins", i32), ("sort_threshold", i32), ("bin_mode", i32), ("criterion", i32),
                 ("bin_seed", u64)]
 
 
@@ -259,8 +260,8 @@ def to_device(wl, device="cuda:0", X=None) -> DeviceFrontier:
 
 
 def _params(dev: DeviceFrontier, bins: int, sort_threshold: int, bin_mode: int = SOF_BINS_EQUAL,
-            bin_seed: int = 0) -> sof_params:
-    return sof_params(_ptr(dev.node_bins), int(bins), int(sort_threshold), int(bin_mode), 0,
+            bin_seed: int = 0, criterion: int = SOF_CRIT_GINI) -> sof_params:
+    return sof_params(_ptr(dev.node_bins), int(bins), int(sort_threshold), int(bin_mode), int(criterion),
                       int(bin_seed) & (2**64 - 1))
 
 
@@ -274,12 +275,12 @@ def workspace_size(dev: DeviceFrontier, bins: int = 256, sort_threshold: int = 0
 
 
 def find_splits(ctx: Context, dev: DeviceFrontier, *, bins=256, sort_threshold=0, hist=False,
-                out=None, stream=None, bin_mode=SOF_BINS_EQUAL, bin_seed=0):
+                out=None, stream=None, bin_mode=SOF_BINS_EQUAL, bin_seed=0, criterion=SOF_CRIT_GINI):
     """Best split per node.  Returns (splits int32 tensor (N, 10) in sof_split
     layout, hist int32 tensor (P, bins, C) or None)."""
     import torch
     d, f, p = dev.structs()
-    q = _params(dev, bins, sort_threshold, bin_mode, bin_seed)
+    q = _params(dev, bins, sort_threshold, bin_mode, bin_seed, criterion)
     ws, wsb = ctx.workspace(workspace_size(dev, bins, sort_threshold, ctx))
     N = dev.n_nodes
     if out is None:

@@ -37,8 +37,9 @@ def assert_splits_match(gpu: np.ndarray, ref: np.ndarray, where: str = ""):
     zero = r == 0
     assert np.all(g[zero] == 0), f"{where}: gain should be exactly 0"
     rel = np.abs(g[~zero] - r[~zero]) / r[~zero]
-    if rel.size:
-        assert rel.max() <= GAIN_RTOL, f"{where}: gain rel err {rel.max():.3g}"
+    if rel.size and rel.max() > GAIN_RTOL:
+        i = int(np.nonzero(~zero)[0][int(np.argmax(rel))])
+        raise AssertionError(f"{where}: gain rel err {rel.max():.3g} at node {i}: gpu {gpu[i]} oracle {ref[i]}")
 
 
 def oracle_splits(wl, **kw):

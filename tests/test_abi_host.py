@@ -80,9 +80,10 @@ def proj(S, **kw):
 
 
 def params(S, **kw):
-    q = dict(node_bins=None, bins=256, sort_threshold=64, bin_mode=0, bin_seed=0)
+    q = dict(node_bins=None, bins=256, sort_threshold=64, bin_mode=0, bin_seed=0, criterion=0)
     q.update(kw)
-    return S.sof_params(q["node_bins"], q["bins"], q["sort_threshold"], q["bin_mode"], 0, q["bin_seed"])
+    return S.sof_params(q["node_bins"], q["bins"], q["sort_threshold"], q["bin_mode"], q["criterion"],
+                        q["bin_seed"])
 
 
 def ws_size(S, L, d=None, f=None, p=None, q=None):
@@ -131,6 +132,8 @@ def test_workspace_size_of_valid_arguments(S, L):
     ("params", dict(sort_threshold=-1), INVALID),
     ("params", dict(bin_mode=2), UNSUPPORTED),
     ("params", dict(bin_mode=-1), UNSUPPORTED),
+    ("params", dict(criterion=2), UNSUPPORTED),
+    ("params", dict(criterion=1, sort_threshold=64), UNSUPPORTED),
 ])
 def test_workspace_size_rejects(S, L, part, kw, code):
     args = {"d": None, "f": None, "p": None, "q": None}
@@ -177,3 +180,8 @@ def test_binding_fails_loudly_without_the_library(S, monkeypatch):
     monkeypatch.setattr(S, "_lib", None)
     with pytest.raises(RuntimeError, match="missing"):
         S.lib()
+
+
+def test_entropy_on_the_histogram_path_is_accepted(S, L):
+    rc, n = ws_size(S, L, q=params(S, criterion=1, sort_threshold=0))
+    assert rc == OK and n > 0

@@ -197,3 +197,28 @@ def test_random_width_bins(ctx, T, C, B, dt):
                                       wl.nz_feature, wl.nz_weight, ref, bins=B)
     assert np.array_equal(coff.cpu().numpy(), want_coff)
     assert np.array_equal(out_idx.cpu().numpy(), want_idx)
+
+
+# --------------------------------------------------------------------------
+# entropy criterion (histogram path): records bit-exact, gains within 1e-6
+
+@pytest.mark.parametrize("C,B,dt,bm", [(2, 256, np.float32, 0), (3, 7, np.float32, 0), (16, 256, np.float16, 0),
+                                        (4, 128, np.float32, 1)])
+def test_entropy_criterion(ctx, C, B, dt, bm):
+    import torch
+    from paper_2603_00326_amd import sof as S
+    wl = W.random_frontier(81 + C, n_rows=90000, d=14, n_classes=C, sizes=EDGE_SIZES, k=5, z=(1, 6),
+                           bins=B, sort_threshold=0, layout="r", dtype=dt)
+    say(f"[gpu] entropy C={C} B={B} dtype={np.dtype(dt).name} bin_mode={bm}")
+    dev = S.to_device(wl)
+    out, H = S.find_splits(ctx, dev, bins=B, sort_threshold=0, hist=True, bin_mode=bm, bin_seed=77,
+                           criterion=S.SOF_CRIT_ENTROPY)
+    out_idx, coff = S.partition(ctx, dev, out, bins=B)
+    torch.cuda.synchronize()
+    got = S.splits_to_numpy(out)[:wl.n_nodes]
+    ref, Href = O.find_splits_w(wl, hist=True, bin_mode=bm, bin_seed=77, criterion=O.CRIT_ENTROPY)
+    assert_splits_match(got, ref, "entropy")
+    assert np.array_equal(H.cpu().numpy(), Href)
+    want_idx, want_coff = O.partition(wl.X, wl.node_offsets, wl.sample_idx, wl.proj_offsets, wl.nz_offsets,
+                                      wl.nz_feature, wl.nz_weight, ref, bins=B)
+    assert np.array_equal(coff.cpu().numpy(), want_coff) and np.array_equal(out_idx.cpu().numpy(), want_idx)

@@ -44,11 +44,12 @@ def sample_nodes(wl, seed, per_class=10):
     return sorted(int(v) for v in pick)
 
 
-def run_full(ctx, wl, T, bin_mode=0, bin_seed=0):
+def run_full(ctx, wl, T, bin_mode=0, bin_seed=0, criterion=0):
     import torch
     from paper_2603_00326_amd import sof as S
     dev = S.to_device(wl)
-    out, _ = S.find_splits(ctx, dev, bins=wl.bins, sort_threshold=T, bin_mode=bin_mode, bin_seed=bin_seed)
+    out, _ = S.find_splits(ctx, dev, bins=wl.bins, sort_threshold=T, bin_mode=bin_mode, bin_seed=bin_seed,
+                           criterion=criterion)
     out_idx, coff = S.partition(ctx, dev, out, bins=wl.bins)
     torch.cuda.synchronize()
     got = S.splits_to_numpy(out)[:wl.n_nodes]
@@ -74,10 +75,12 @@ def check_partition_properties(wl, got, out_idx, coff):
     assert np.array_equal(wl.sample_idx[a], out_idx[b]), "per-node permutation"
 
 
-def check_sampled(wl, T, got, out_idx, coff, nodes, tag, bin_mode=0, bin_seed=0):
+def check_sampled(wl, T, got, out_idx, coff, nodes, tag, bin_mode=0, bin_seed=0, criterion=0):
     sub = W.sub_frontier(wl, nodes)
     sub.sort_threshold = T
-    if bin_mode:
+    if criterion:
+        ref, _ = O.find_splits_w(sub, criterion=criterion)
+    elif bin_mode:
         # random-width boundaries are keyed by the projection's index in the
         # call, so the oracle runs on the whole frontier and is sampled after
         ref_all, _ = O.find_splits_w(wl, sort_threshold=T, bin_mode=bin_mode, bin_seed=bin_seed)
@@ -148,3 +151,12 @@ def test_frontier_4096_nodes_random_width_bins(ctx):
     got, out_idx, coff = run_full(ctx, wl, T, bin_mode=1, bin_seed=seed)
     check_partition_properties(wl, got, out_idx, coff)
     check_sampled(wl, T, got, out_idx, coff, nodes, "c3a random-width", bin_mode=1, bin_seed=seed)
+
+
+def test_frontier_4096_nodes_entropy(ctx):
+    wl = W.config3("a")
+    nodes = sample_nodes(wl, seed=29)
+    say(f"[gpu] full frontier entropy criterion nodes={wl.n_nodes} samples={wl.n_samples} T=0")
+    got, out_idx, coff = run_full(ctx, wl, 0, criterion=1)
+    check_partition_properties(wl, got, out_idx, coff)
+    check_sampled(wl, 0, got, out_idx, coff, nodes, "c3a entropy", criterion=1)
