@@ -88,6 +88,12 @@ extern "C" {
 #define SOF_BINS_EQUAL  0
 #define SOF_BINS_RANDOM 1
 
+/* Projection sampler of tree growth (sof_forest_desc.sampler, .weights). */
+#define SOF_SAMPLER_FIXED   0   /* exactly z distinct features per projection */
+#define SOF_SAMPLER_DENSITY 1   /* each feature with probability z/d: Binomial(d, z/d) of them */
+#define SOF_WEIGHTS_SIGN    0   /* weights +1 / -1 */
+#define SOF_WEIGHTS_UNIFORM 1   /* weights uniform on (-1, 1), never 0, exact in FP32 */
+
 typedef struct sof_ctx sof_ctx;
 typedef struct sof_forest sof_forest;
 
@@ -113,11 +119,18 @@ typedef struct {
     const int32_t* proj_offsets;  /* device, n_nodes + 1 */
     const int32_t* nz_offsets;    /* device, n_proj + 1 */
     const int32_t* nz_feature;    /* device, n_nz */
-    const int8_t*  nz_weight;     /* device, n_nz, each -1 or +1 */
+    const int8_t*  nz_weight;     /* device, n_nz integer weights (usually -1 or +1); not read
+                                     when nz_value is given */
     int64_t        n_nz;          /* = nz_offsets[n_proj] */
     int32_t        n_proj;        /* = proj_offsets[n_nodes] */
     int32_t        max_proj_per_node; /* >= every node's projection count, <= 1024 */
+    const float*   nz_value;      /* device, n_nz finite FP32 weights, or NULL (then nz_weight) */
 } sof_proj;
+
+/* Projected value of a sample (Method, step 1): v = sum over the projection's
+ * nonzeros in CSR order of w_j * x[f_j][row], each product and each add one
+ * FP32 rounding (no fused multiply-add), starting from +0.  With weights
+ * +/-1 every product is exact. */
 
 /* Histogram bins.  SOF_BINS_EQUAL: B equal-width bins over [lo, hi] (the
  * Method section's "few arithmetic operations" binning).  SOF_BINS_RANDOM:
@@ -170,8 +183,8 @@ typedef struct {
     int32_t kind, bin;                          /* split rule (kind -1 for leaves) */
     float   threshold, lo, scale;
     int32_t n_bins, nnz, pad;
-    int32_t feature[16];                        /* the winning projection */
-    int8_t  weight[16];
+    int32_t feature[16];                        /* the winning projection: nnz features, ascending */
+    float   weight[16];                         /* ... and their weights (0 past nnz) */
     double  gain;
 } sof_tree_node;
 
@@ -182,12 +195,33 @@ typedef struct {
     int32_t        n_trees;
     int32_t        first_tree;    /* tree ids first_tree .. first_tree+n_trees-1 key the sampler */
     int32_t        k;             /* projections per node, 1..1024 */
-    int32_t        z;             /* nonzeros per projection, 1..15, <= n_features */
+    int32_t        z;             /* SOF_SAMPLER_FIXED: nonzeros per projection, 1..15, <= n_features;
+                                     SOF_SAMPLER_DENSITY: their mean, 1..16 (density z / n_features) */
     int32_t        bins;          /* 2..256 */
     int32_t        sort_threshold;
     int32_t        max_depth;     /* 0..64: nodes at this depth become leaves */
+    int32_t        sampler;       /* SOF_SAMPLER_FIXED or SOF_SAMPLER_DENSITY */
+    int32_t        weights;       /* SOF_WEIGHTS_SIGN or SOF_WEIGHTS_UNIFORM */
     int32_t        pad;
 } sof_forest_desc;
+
+/* The sampler (Method: the sparse projection matrix; appendix: Floyd's
+ * sampling).  Projection p of node (tree, level, pos) depends on those values
+ * and the seed only; each random number is the SplitMix64 output at counter
+ * ((((tree * 64 + level) << 24 + pos) << 10 + p) << 4) + draw of a stream
+ * started at seed, seed ^ 0x6A09E667F3BCC909 (the nonzero count) or
+ * seed ^ 0xBB67AE8584CAA73B (weights).
+ *   nonzero count: FIXED: z.  DENSITY: pi = z/d, q = 1 - pi, r = pi/q,
+ *     P(0) = q^d by binary powering (low bit first), P(k+1) = (P(k) *
+ *     ((d-k)/(k+1))) * r; the count is the least k with
+ *     u < P(0) + ... + P(k), u = (output >> 11) / 2^53, at most min(d, 16);
+ *     each operation one binary64 rounding.  (d if z >= d, at most 16.)
+ *   features: Floyd's algorithm, draw j = 0..z_p-1 proposes
+ *     t = ((output >> 32) * (d - z_p + j + 1)) >> 32 and takes d - z_p + j if
+ *     t is taken; stored ascending.
+ *   weights of the nonzero of rank s: SIGN: -1 iff bit s of draw 15 (FIXED)
+ *     or of the weight stream's draw 0 (DENSITY) is set; UNIFORM:
+ *     (2m + 1 - 2^24) / 2^24, m = weight-stream draw s >> 40. */
 
 typedef struct {
     int32_t sort_threshold;   /* chosen histogram/sort switch T */

@@ -29,9 +29,9 @@ TREE_NODE_DTYPE = np.dtype([
     ("tree", "<i4"), ("depth", "<i4"), ("parent", "<i4"), ("left", "<i4"), ("right", "<i4"),
     ("n_samples", "<i4"), ("label", "<i4"), ("is_leaf", "<i4"), ("kind", "<i4"), ("bin", "<i4"),
     ("threshold", "<f4"), ("lo", "<f4"), ("scale", "<f4"), ("n_bins", "<i4"), ("nnz", "<i4"),
-    ("pad", "<i4"), ("feature", "<i4", (16,)), ("weight", "i1", (16,)), ("gain", "<f8"),
+    ("pad", "<i4"), ("feature", "<i4", (16,)), ("weight", "<f4", (16,)), ("gain", "<f8"),
 ])
-assert TREE_NODE_DTYPE.itemsize == 152
+assert TREE_NODE_DTYPE.itemsize == 200
 
 
 def build(force: bool = True) -> str:
@@ -85,9 +85,13 @@ def lib():
         L.or_hash.restype = u64
         L.or_counter.argtypes = [i32, i32, i32, i32, i32]
         L.or_counter.restype = u64
-        L.or_sample_projection.argtypes = [u64, i32, i32, i32, i32, i32, i32, P, P]
-        L.or_sample_projection.restype = None
-        L.or_grow_forest.argtypes = [P, ctypes.c_int, i64, i32, P, i32, i32, i32, P, P, i32, i32, u64,
+        L.or_sample_projection.argtypes = [u64, i32, i32, i32, i32, i32, i32, i32, i32, P, P]
+        L.or_sample_projection.restype = i32
+        L.or_density_nnz.argtypes = [u64, i32, i32, i32, i32, i32, i32]
+        L.or_density_nnz.restype = i32
+        L.or_sample_weight.argtypes = [u64, i32, i32, i32, i32, i32, i32, i32]
+        L.or_sample_weight.restype = ctypes.c_float
+        L.or_grow_forest.argtypes = [P, ctypes.c_int, i64, i32, P, i32, i32, i32, P, P, i32, i32, i32, i32, u64,
                                      i32, i32, i32, i32, P, i64, P, P]
         L.or_grow_forest.restype = i64
         L.or_leaf_of.argtypes = [P, ctypes.c_int, i64, P, i32, i32]
@@ -130,14 +134,14 @@ def bin_index(v, lo, scale, n_bins: int) -> int:
 def project_value(X, feat, w, row) -> np.float32:
     X, dt = _xinfo(X)
     feat = _c(feat, np.int32)
-    w = _c(w, np.int8)
+    w = _c(w, np.float32)
     return np.float32(lib().or_project_value(_p(X), dt, X.shape[1], _p(feat), _p(w), len(feat), int(row)))
 
 
 def project(X, node_offsets, sample_idx, proj_offsets, nz_offsets, nz_feature, nz_weight):
     X, dt = _xinfo(X)
     no, si, po = _c(node_offsets, np.int32), _c(sample_idx, np.int32), _c(proj_offsets, np.int32)
-    zo, zf, zw = _c(nz_offsets, np.int32), _c(nz_feature, np.int32), _c(nz_weight, np.int8)
+    zo, zf, zw = _c(nz_offsets, np.int32), _c(nz_feature, np.int32), _c(nz_weight, np.float32)
     n = np.diff(no.astype(np.int64))
     k = np.diff(po.astype(np.int64))
     out = np.empty(int((n * k).sum()), np.float32)
@@ -173,7 +177,7 @@ def find_splits(X, y, n_classes, node_offsets, sample_idx, proj_offsets, nz_offs
     X, dt = _xinfo(X)
     y = _c(y, np.int32)
     no, si, po = _c(node_offsets, np.int32), _c(sample_idx, np.int32), _c(proj_offsets, np.int32)
-    zo, zf, zw = _c(nz_offsets, np.int32), _c(nz_feature, np.int32), _c(nz_weight, np.int8)
+    zo, zf, zw = _c(nz_offsets, np.int32), _c(nz_feature, np.int32), _c(nz_weight, np.float32)
     nb = _c(node_bins, np.int32)
     N = len(no) - 1
     P = int(po[-1])
@@ -198,7 +202,7 @@ def partition(X, node_offsets, sample_idx, proj_offsets, nz_offsets, nz_feature,
               *, bins=256, node_bins=None):
     X, dt = _xinfo(X)
     no, si, po = _c(node_offsets, np.int32), _c(sample_idx, np.int32), _c(proj_offsets, np.int32)
-    zo, zf, zw = _c(nz_offsets, np.int32), _c(nz_feature, np.int32), _c(nz_weight, np.int8)
+    zo, zf, zw = _c(nz_offsets, np.int32), _c(nz_feature, np.int32), _c(nz_weight, np.float32)
     nb = _c(node_bins, np.int32)
     sp = np.ascontiguousarray(splits, dtype=SPLIT_DTYPE)
     N = len(no) - 1
@@ -221,15 +225,30 @@ def counter(tree, level, pos, proj, draw) -> int:
     return int(lib().or_counter(tree, level, pos, proj, draw))
 
 
-def sample_projection(seed, tree, level, pos, proj, n_features, z):
+SAMPLER_FIXED, SAMPLER_DENSITY = 0, 1
+WEIGHTS_SIGN, WEIGHTS_UNIFORM = 0, 1
+SEED_NNZ, SEED_WEIGHT = 0x6A09E667F3BCC909, 0xBB67AE8584CAA73B   # streams of the density sampler
+
+
+def sample_projection(seed, tree, level, pos, proj, n_features, z, sampler=SAMPLER_FIXED, weights=WEIGHTS_SIGN):
+    """Features (ascending, int32) and FP32 weights of one drawn projection."""
     f = np.zeros(16, np.int32)
-    w = np.zeros(16, np.int8)
-    lib().or_sample_projection(seed & (2**64 - 1), tree, level, pos, proj, n_features, z, _p(f), _p(w))
-    return f[:z].copy(), w[:z].copy()
+    w = np.zeros(16, np.float32)
+    nz = lib().or_sample_projection(seed & (2**64 - 1), tree, level, pos, proj, n_features, sampler, z, weights,
+                                    _p(f), _p(w))
+    return f[:nz].copy(), w[:nz].copy()
+
+
+def density_nnz(seed, tree, level, pos, proj, n_features, z) -> int:
+    return int(lib().or_density_nnz(seed & (2**64 - 1), tree, level, pos, proj, n_features, z))
+
+
+def sample_weight(seed, sampler, weights, tree, level, pos, proj, rank) -> np.float32:
+    return np.float32(lib().or_sample_weight(seed & (2**64 - 1), sampler, weights, tree, level, pos, proj, rank))
 
 
 def grow_forest(X, y, n_classes, root_offsets, root_idx, *, k, z, seed, bins=256, sort_threshold=0,
-                max_depth=64, threads=0, cap=None, first_tree=0):
+                max_depth=64, threads=0, cap=None, first_tree=0, sampler=SAMPLER_FIXED, weights=WEIGHTS_SIGN):
     """Grow several trees level by level to purity.  Returns (nodes, level_nodes, level_units)."""
     X, dt = _xinfo(X)
     y = _c(y, np.int32)
@@ -243,7 +262,8 @@ def grow_forest(X, y, n_classes, root_offsets, root_idx, *, k, z, seed, bins=256
     lu = np.zeros(max_depth + 1, np.int64)
     n = lib().or_grow_forest(_p(X), dt, X.shape[1], X.shape[0], _p(y), int(n_classes), n_trees,
                              int(first_tree), _p(ro),
-                             _p(ri), int(k), int(z), seed & (2**64 - 1), int(bins), int(sort_threshold),
+                             _p(ri), int(k), int(z), int(sampler), int(weights), seed & (2**64 - 1), int(bins),
+                             int(sort_threshold),
                              int(max_depth), int(threads), _p(nodes), int(cap), _p(ln), _p(lu))
     if n < 0:
         raise RuntimeError("node capacity too small")

@@ -15,8 +15,9 @@
  *  1. Projection ("build the feature by combining the active samples of the
  *     data columns for the non-zero offsets and apply weights"): for sample r,
  *     acc = +0.0f, then acc = acc + (w_j * x[f_j][r]) for the nonzeros j in CSR
- *     order.  w_j is +/-1, so every product is exact.  FP16 storage is widened
- *     exactly first.
+ *     order, each product and each add one FP32 rounding (no fused
+ *     multiply-add).  With w_j = +/-1 every product is exact.  FP16 storage is
+ *     widened exactly first.
  *  2. Node range: lo = min, hi = max of the projected values of the node.
  *  3. Histogram ("assign samples to bins and count the class instances in
  *     each bin") with equal-width bins over [lo, hi] (the paper notes equal
@@ -105,11 +106,11 @@ static float load_x(const void* x, int dtype, int64_t ld, int32_t f, int32_t r)
 /* ------------------------------------------------------------------------ */
 
 float or_project_value(const void* x, int dtype, int64_t ld, const int32_t* feat,
-                       const int8_t* w, int z, int32_t row)
+                       const float* w, int z, int32_t row)
 {
     float acc = 0.0f;
     for (int j = 0; j < z; ++j) {
-        float term = (float)w[j] * load_x(x, dtype, ld, feat[j], row);
+        float term = w[j] * load_x(x, dtype, ld, feat[j], row);
         acc = acc + term;
     }
     return acc;
@@ -118,7 +119,7 @@ float or_project_value(const void* x, int dtype, int64_t ld, const int32_t* feat
 void or_project(const void* x, int dtype, int64_t ld, int32_t n_nodes,
                 const int32_t* node_offsets, const int32_t* sample_idx,
                 const int32_t* proj_offsets, const int32_t* nz_offsets,
-                const int32_t* nz_feature, const int8_t* nz_weight, float* out)
+                const int32_t* nz_feature, const float* nz_weight, float* out)
 {
     int64_t base = 0;
     for (int32_t v = 0; v < n_nodes; ++v) {
@@ -334,7 +335,7 @@ static int effective_threshold(int32_t T)
 /* Best candidate of projection q of node v (both paths). */
 static void eval_projection(const void* x, int dtype, int64_t ld, const int32_t* y, int C,
                             const int32_t* idx, int32_t n, const int64_t* parent,
-                            const int32_t* feat, const int8_t* w, int z, int B, int sort_path,
+                            const int32_t* feat, const float* w, int z, int B, int sort_path,
                             int bin_mode, uint64_t bin_seed, int64_t q, int criterion,
                             cand_t* best, int32_t* hist_row, int32_t bins_stride)
 {
@@ -400,7 +401,7 @@ static void no_split(or_split* o, int kind, int32_t n)
 int or_find_splits(const void* x, int dtype, int64_t ld, const int32_t* y, int32_t C,
                    int32_t n_nodes, const int32_t* node_offsets, const int32_t* sample_idx,
                    const int32_t* proj_offsets, const int32_t* nz_offsets,
-                   const int32_t* nz_feature, const int8_t* nz_weight,
+                   const int32_t* nz_feature, const float* nz_weight,
                    const int32_t* node_bins, int32_t bins, int32_t sort_threshold,
                    int32_t bin_mode, uint64_t bin_seed, int32_t criterion,
                    or_split* out, int32_t* hist_out, int32_t n_threads)
@@ -513,7 +514,7 @@ int or_find_splits(const void* x, int dtype, int64_t ld, const int32_t* y, int32
 /* partition (each node splits its samples between its two children)         */
 /* ------------------------------------------------------------------------ */
 
-static int goes_left(const void* x, int dtype, int64_t ld, const int32_t* feat, const int8_t* w,
+static int goes_left(const void* x, int dtype, int64_t ld, const int32_t* feat, const float* w,
                      int z, int32_t row, const or_split* s, int B)
 {
     float v = or_project_value(x, dtype, ld, feat, w, z, row);
@@ -527,7 +528,7 @@ static int goes_left(const void* x, int dtype, int64_t ld, const int32_t* feat, 
 void or_partition(const void* x, int dtype, int64_t ld, int32_t n_nodes,
                   const int32_t* node_offsets, const int32_t* sample_idx,
                   const int32_t* proj_offsets, const int32_t* nz_offsets,
-                  const int32_t* nz_feature, const int8_t* nz_weight,
+                  const int32_t* nz_feature, const float* nz_weight,
                   const int32_t* node_bins, int32_t bins, const or_split* splits,
                   int32_t* out_idx, int32_t* child_offsets)
 {
@@ -583,18 +584,74 @@ uint64_t or_counter(int32_t tree, int32_t level, int32_t pos, int32_t proj, int3
     return c;
 }
 
-/* z distinct features out of n_features by Floyd's algorithm (Bentley and
- * Floyd, "A sample of brilliance", CACM 1987): for j = d-z .. d-1 draw t
- * uniformly in [0, j]; take t unless already taken, else take j.  The uniform
- * draw is the multiply-shift ((r >> 32) * (j + 1)) >> 32.  Features come out
- * ascending; the sign of the s-th is bit s of draw 15 (set = -1). */
-void or_sample_projection(uint64_t seed, int32_t tree, int32_t level, int32_t pos, int32_t proj,
-                          int32_t d, int32_t z, int32_t* feat, int8_t* w)
+/* Nonzero count of a projection under the density law (Method: the sparse
+ * projection matrix; appendix on Floyd's sampling): each of the d features is
+ * kept independently with probability pi = z/d, so the count K follows
+ * Binomial(d, pi).  One uniform u in [0, 1) per projection (the top 53 bits
+ * of draw 0 of the count stream) replaces the d per-feature coin flips: K is
+ * the least k with u < F(k), F the binomial distribution function summed
+ * from P(0) = (1 - pi)^d (binary powering, low bit first) with the ratio
+ * P(k+1) / P(k) = ((d - k) / (k + 1)) * (pi / (1 - pi)).  K is capped at
+ * min(d, 16); if z >= d every feature is kept (then min(d, 16)). */
+int32_t or_density_nnz(uint64_t seed, int32_t tree, int32_t level, int32_t pos, int32_t proj, int32_t d,
+                       int32_t z)
 {
+    int32_t cap = d < 16 ? d : 16;
+    if (z >= d)
+        return cap;
+    double pi = (double)z / (double)d;
+    double q = 1.0 - pi;
+    double ratio = pi / q;
+    double p0 = 1.0, b = q;
+    for (int32_t e = d; e != 0; e >>= 1) {
+        if (e & 1)
+            p0 = p0 * b;
+        b = b * b;
+    }
+    uint64_t h = or_hash(seed ^ OR_SEED_NNZ, or_counter(tree, level, pos, proj, 0));
+    double u = (double)(h >> 11) / 9007199254740992.0; /* 2^53 */
+    double pk = p0, F = p0;
+    int32_t k = 0;
+    while (k < cap && u >= F) {
+        pk = pk * ((double)(d - k) / (double)(k + 1)) * ratio;
+        F = F + pk;
+        ++k;
+    }
+    return k;
+}
+
+/* Weight of the nonzero of rank s (features ascending).  Signs: bit s of
+ * draw 15 (fixed count) or of the weight stream's draw 0 (density law), set
+ * = -1.  Uniform: m = top 24 bits of the weight stream's draw s, weight
+ * (2m + 1 - 2^24) / 2^24, an odd multiple of 2^-24 in (-1, 1). */
+float or_sample_weight(uint64_t seed, int32_t sampler, int32_t weights, int32_t tree, int32_t level,
+                       int32_t pos, int32_t proj, int32_t s)
+{
+    if (weights == OR_WEIGHTS_UNIFORM) {
+        uint64_t h = or_hash(seed ^ OR_SEED_WEIGHT, or_counter(tree, level, pos, proj, s));
+        int32_t m = (int32_t)(h >> 40);
+        return (float)(2 * m + 1 - (1 << 24)) / 16777216.0f;
+    }
+    uint64_t signs = sampler == OR_SAMPLER_DENSITY
+                         ? or_hash(seed ^ OR_SEED_WEIGHT, or_counter(tree, level, pos, proj, 0))
+                         : or_hash(seed, or_counter(tree, level, pos, proj, 15));
+    return ((signs >> s) & 1u) ? -1.0f : 1.0f;
+}
+
+/* One projection: its count nz (z, or the density law above), then nz
+ * distinct features out of d by Floyd's algorithm (Bentley and Floyd, "A
+ * sample of brilliance", CACM 1987): for j = d-nz .. d-1 draw t uniformly in
+ * [0, j]; take t unless already taken, else take j.  The uniform draw is the
+ * multiply-shift ((r >> 32) * (j + 1)) >> 32 of draw j - (d - nz).  Features
+ * come out ascending with their weights.  Returns nz. */
+int32_t or_sample_projection(uint64_t seed, int32_t tree, int32_t level, int32_t pos, int32_t proj,
+                             int32_t d, int32_t sampler, int32_t z, int32_t weights, int32_t* feat, float* w)
+{
+    int32_t nz = sampler == OR_SAMPLER_DENSITY ? or_density_nnz(seed, tree, level, pos, proj, d, z) : z;
     int32_t chosen[16];
     int m = 0;
-    for (int32_t j = d - z; j < d; ++j) {
-        uint64_t r = or_hash(seed, or_counter(tree, level, pos, proj, j - (d - z)));
+    for (int32_t j = d - nz; j < d; ++j) {
+        uint64_t r = or_hash(seed, or_counter(tree, level, pos, proj, j - (d - nz)));
         int32_t t = (int32_t)(((r >> 32) * (uint64_t)(uint32_t)(j + 1)) >> 32);
         int taken = 0;
         for (int i = 0; i < m; ++i)
@@ -611,11 +668,11 @@ void or_sample_projection(uint64_t seed, int32_t tree, int32_t level, int32_t po
         }
         chosen[k + 1] = key;
     }
-    uint64_t signs = or_hash(seed, or_counter(tree, level, pos, proj, 15));
-    for (int s = 0; s < z; ++s) {
-        feat[s] = chosen[s];
-        w[s] = ((signs >> s) & 1u) ? (int8_t)-1 : (int8_t)1;
+    for (int s2 = 0; s2 < nz; ++s2) {
+        feat[s2] = chosen[s2];
+        w[s2] = or_sample_weight(seed, sampler, weights, tree, level, pos, proj, s2);
     }
+    return nz;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -663,8 +720,8 @@ static void init_node(or_tree_node* t, int32_t tree, int32_t depth, int32_t pare
 int64_t or_grow_forest(const void* x, int dtype, int64_t ld, int32_t d,
                        const int32_t* y, int32_t C, int32_t n_trees, int32_t first_tree,
                        const int64_t* root_offsets, const int32_t* root_idx,
-                       int32_t k, int32_t z, uint64_t seed, int32_t bins,
-                       int32_t sort_threshold, int32_t max_depth, int32_t n_threads,
+                       int32_t k, int32_t z, int32_t sampler, int32_t weights, uint64_t seed,
+                       int32_t bins, int32_t sort_threshold, int32_t max_depth, int32_t n_threads,
                        or_tree_node* nodes, int64_t cap,
                        int64_t* level_nodes, int64_t* level_units)
 {
@@ -702,22 +759,23 @@ int64_t or_grow_forest(const void* x, int dtype, int64_t ld, int32_t d,
             memcpy(sidx + off[v], front[v].idx, sizeof(int32_t) * (size_t)front[v].n);
         int32_t* po = (int32_t*)malloc(sizeof(int32_t) * (size_t)(N + 1));
         int32_t* no = (int32_t*)malloc(sizeof(int32_t) * ((size_t)N * k + 1));
-        int32_t* nf = (int32_t*)malloc(sizeof(int32_t) * ((size_t)N * k * z + 1));
-        int8_t* nw = (int8_t*)malloc((size_t)N * k * z + 1);
-        int32_t pos = 0;
+        int32_t* nf = (int32_t*)malloc(sizeof(int32_t) * ((size_t)N * k * 16 + 1));
+        float* nw = (float*)malloc(sizeof(float) * ((size_t)N * k * 16 + 1));
+        int32_t pos = 0, tot = 0;
         for (int32_t v = 0; v < N; ++v) {
             if (v > 0 && front[v].tree != front[v - 1].tree)
                 pos = 0;
             po[v] = v * k;
             for (int32_t p = 0; p < k; ++p) {
                 int64_t q = (int64_t)v * k + p;
-                no[q] = (int32_t)(q * z);
-                or_sample_projection(seed, front[v].tree, level, pos, p, d, z, nf + q * z, nw + q * z);
+                no[q] = tot;
+                tot += or_sample_projection(seed, front[v].tree, level, pos, p, d, sampler, z, weights, nf + tot,
+                                            nw + tot);
             }
             pos++;
         }
         po[N] = N * k;
-        no[(int64_t)N * k] = (int32_t)((int64_t)N * k * z);
+        no[(int64_t)N * k] = tot;
         if (level_nodes) level_nodes[level] = N;
         if (level_units) level_units[level] = (int64_t)off[N] * k;
         or_split* sp = (or_split*)malloc(sizeof(or_split) * (size_t)N);
@@ -747,10 +805,10 @@ int64_t or_grow_forest(const void* x, int dtype, int64_t ld, int32_t d,
             me->scale = sp[v].scale;
             me->gain = sp[v].gain;
             me->n_bins = bins;
-            me->nnz = z;
-            for (int j = 0; j < z; ++j) {
-                me->feature[j] = nf[q * z + j];
-                me->weight[j] = nw[q * z + j];
+            me->nnz = no[q + 1] - no[q];
+            for (int j = 0; j < me->nnz; ++j) {
+                me->feature[j] = nf[no[q] + j];
+                me->weight[j] = nw[no[q] + j];
             }
             for (int side = 0; side < 2; ++side) {
                 int32_t c0 = coff[2 * v + side];

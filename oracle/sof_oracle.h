@@ -43,6 +43,14 @@ extern "C" {
 #define OR_BINS_EQUAL  0
 #define OR_BINS_RANDOM 1
 
+/* projection sampler of growth: nonzero-count law and weight law */
+#define OR_SAMPLER_FIXED   0
+#define OR_SAMPLER_DENSITY 1
+#define OR_WEIGHTS_SIGN    0
+#define OR_WEIGHTS_UNIFORM 1
+#define OR_SEED_NNZ    0x6A09E667F3BCC909ULL
+#define OR_SEED_WEIGHT 0xBB67AE8584CAA73BULL
+
 typedef struct {
     int32_t proj;      /* node-local index of the winning projection, -1 = no split */
     int32_t kind;      /* 0 = histogram path (equal width), 1 = sort path, 2 = histogram path
@@ -65,7 +73,7 @@ typedef struct {
     float   threshold, lo, scale;
     int32_t n_bins, nnz, pad;
     int32_t feature[16];
-    int8_t  weight[16];
+    float   weight[16];
     double  gain;
 } or_tree_node;
 
@@ -74,7 +82,7 @@ float or_half_to_float(uint16_t h);
 
 /* Projected value of one row for one projection (CSR order, from +0.0f). */
 float or_project_value(const void* x, int dtype, int64_t ld, const int32_t* feat,
-                       const int8_t* w, int z, int32_t row);
+                       const float* w, int z, int32_t row);
 
 /* Equal-width bin parameters and bin index (see the header of the .c file). */
 float or_bin_scale(int n_bins, float lo, float hi);
@@ -90,7 +98,7 @@ int  or_rw_bin(const float* t, int n_bins, float v);
 void or_project(const void* x, int dtype, int64_t ld, int32_t n_nodes,
                 const int32_t* node_offsets, const int32_t* sample_idx,
                 const int32_t* proj_offsets, const int32_t* nz_offsets,
-                const int32_t* nz_feature, const int8_t* nz_weight, float* out);
+                const int32_t* nz_feature, const float* nz_weight, float* out);
 
 /* Best split of every frontier node.  hist_out (optional) receives
  * [projection][bins][n_classes] int32 counts for histogram-path nodes and zeros
@@ -98,7 +106,7 @@ void or_project(const void* x, int dtype, int64_t ld, int32_t n_nodes,
 int or_find_splits(const void* x, int dtype, int64_t ld, const int32_t* y, int32_t n_classes,
                    int32_t n_nodes, const int32_t* node_offsets, const int32_t* sample_idx,
                    const int32_t* proj_offsets, const int32_t* nz_offsets,
-                   const int32_t* nz_feature, const int8_t* nz_weight,
+                   const int32_t* nz_feature, const float* nz_weight,
                    const int32_t* node_bins, int32_t bins, int32_t sort_threshold,
                    int32_t bin_mode, uint64_t bin_seed, int32_t criterion,
                    or_split* out, int32_t* hist_out, int32_t n_threads);
@@ -113,7 +121,7 @@ double or_klnk(int64_t k);
 void or_partition(const void* x, int dtype, int64_t ld, int32_t n_nodes,
                   const int32_t* node_offsets, const int32_t* sample_idx,
                   const int32_t* proj_offsets, const int32_t* nz_offsets,
-                  const int32_t* nz_feature, const int8_t* nz_weight,
+                  const int32_t* nz_feature, const float* nz_weight,
                   const int32_t* node_bins, int32_t bins, const or_split* splits,
                   int32_t* out_idx, int32_t* child_offsets);
 
@@ -121,8 +129,13 @@ void or_partition(const void* x, int dtype, int64_t ld, int32_t n_nodes,
 uint64_t or_mix64(uint64_t z);
 uint64_t or_hash(uint64_t seed, uint64_t counter);
 uint64_t or_counter(int32_t tree, int32_t level, int32_t pos, int32_t proj, int32_t draw);
-void or_sample_projection(uint64_t seed, int32_t tree, int32_t level, int32_t pos, int32_t proj,
-                          int32_t n_features, int32_t z, int32_t* feat, int8_t* w);
+int32_t or_density_nnz(uint64_t seed, int32_t tree, int32_t level, int32_t pos, int32_t proj,
+                       int32_t n_features, int32_t z);
+float or_sample_weight(uint64_t seed, int32_t sampler, int32_t weights, int32_t tree, int32_t level,
+                       int32_t pos, int32_t proj, int32_t rank);
+int32_t or_sample_projection(uint64_t seed, int32_t tree, int32_t level, int32_t pos, int32_t proj,
+                             int32_t n_features, int32_t sampler, int32_t z, int32_t weights,
+                             int32_t* feat, float* w);
 
 /* Level-wise growth of several trees to purity (tree ids first_tree ..
  * first_tree + n_trees - 1 key the sampler).  Returns the number of nodes,
@@ -131,7 +144,8 @@ void or_sample_projection(uint64_t seed, int32_t tree, int32_t level, int32_t po
 int64_t or_grow_forest(const void* x, int dtype, int64_t ld, int32_t n_features,
                        const int32_t* y, int32_t n_classes, int32_t n_trees, int32_t first_tree,
                        const int64_t* root_offsets, const int32_t* root_idx,
-                       int32_t k, int32_t z, uint64_t seed, int32_t bins,
+                       int32_t k, int32_t z, int32_t sampler, int32_t weights, uint64_t seed,
+                       int32_t bins,
                        int32_t sort_threshold, int32_t max_depth, int32_t n_threads,
                        or_tree_node* nodes, int64_t cap,
                        int64_t* level_nodes, int64_t* level_units);

@@ -24,6 +24,7 @@
 // kernel waits on another block.
 #include "sof_device.h"
 #include "sof_internal.h"
+#include "sof_sampler.h"
 
 namespace sof {
 
@@ -78,7 +79,7 @@ __device__ __forceinline__ int proj_count(const ProjCSR& P, int v) {
 __device__ __forceinline__ int proj_global(const ProjCSR& P, int v, int p) {
     return (int)clamp64(P.proj_offsets[v], 0, P.n_proj) + p;
 }
-__device__ __forceinline__ int proj_nnz(const ProjCSR& P, int v, int p) {
+__device__ __forceinline__ int proj_nnz(const ProjCSR& P, int v, int p, int) {
     const int q = proj_global(P, v, p);
     const int64_t j0 = clamp64(P.nz_offsets[q], 0, P.n_nz);
     const int64_t j1 = clamp64(P.nz_offsets[q + 1], j0, P.n_nz);
@@ -97,7 +98,7 @@ __device__ __forceinline__ int proj_stage(const ProjCSR& P, int v, int p, int d,
     if (lane < z) {
         uint32_t f = (uint32_t)P.nz_feature[j0 + lane];
         lf[lane] = f < (uint32_t)d ? (int)f : 0;
-        ls[lane] = P.nz_weight[j0 + lane] < 0 ? 0x80000000u : 0u;
+        ls[lane] = csr_weight_bits(P, j0 + lane);
     }
     wave_sync();
     return z;
@@ -111,46 +112,27 @@ __device__ __forceinline__ uint64_t splitmix_at(uint64_t seed, uint64_t c) {
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
     return z ^ (z >> 31);
 }
-__device__ __forceinline__ uint64_t draw_counter(int tree, int level, int pos, int p, int draw) {
-    uint64_t c = (uint64_t)tree * 64u + (uint64_t)level;
-    c = (c << 24) + (uint64_t)pos;
-    c = (c << 10) + (uint64_t)p;
-    return (c << 4) + (uint64_t)draw;
-}
-
 __device__ __forceinline__ int proj_count(const ProjHash& P, int) { return P.k; }
-__device__ __forceinline__ int proj_nnz(const ProjHash& P, int, int) { return P.z; }
+__device__ __forceinline__ SampSpec samp_spec(const ProjHash& P, int d) {
+    return SampSpec{P.seed, d, P.z, P.mode, P.wmode};
+}
 __device__ __forceinline__ int proj_global(const ProjHash& P, int v, int p) { return v * P.k + p; }
-// z distinct features by Floyd's sampling (Bentley and Floyd, CACM 1987):
-// draw j (j = 0..z-1) proposes t uniform in [0, d-z+j] by multiply-shift of
-// the hash's top 32 bits; a proposal already taken is replaced by d-z+j.
-// Features are stored ascending; sign of the s-th = bit s of draw 15.
+__device__ __forceinline__ int proj_nnz(const ProjHash& P, int v, int p, int d) {
+    return samp_nnz(samp_spec(P, d), P.tree_of[v], *P.level, P.pos_of[v], p);
+}
+// The drawn projection staged into per-wave LDS, features ascending (called
+// by a whole wave).  Returns z.
 __device__ __forceinline__ int proj_stage(const ProjHash& P, int v, int p, int d, int32_t* lf,
                                           uint32_t* ls) {
     const int lane = lane_id();
-    const int z = P.z;
+    const SampSpec sp = samp_spec(P, d);
     const int tree = P.tree_of[v], pos = P.pos_of[v], level = *P.level;
-    uint32_t t = 0;
-    if (lane < z) {
-        uint32_t top = (uint32_t)(d - z + lane) + 1u;
-        uint64_t r = splitmix_at(P.seed, draw_counter(tree, level, pos, p, lane));
-        t = (uint32_t)(((r >> 32) * (uint64_t)top) >> 32);
-    }
-    int mine = (int)t;
-    for (int j = 0; j < z; ++j) {
-        int cj = __shfl((int)t, j);
-        bool taken = __ballot(lane < j && mine == cj) != 0ull;
-        if (lane == j) mine = taken ? d - z + j : cj;
-    }
-    int rank = 0;
-    for (int i = 0; i < z; ++i) {
-        int ci = __shfl(mine, i);
-        rank += (ci < mine) ? 1 : 0;
-    }
-    uint64_t sg = splitmix_at(P.seed, draw_counter(tree, level, pos, p, 15));
+    const int z = __builtin_amdgcn_readfirstlane(samp_nnz(sp, tree, level, pos, p));
+    int mine, rank;
+    samp_wave(sp, z, tree, level, pos, p, mine, rank);
     if (lane < z) {
         lf[rank] = mine;
-        ls[rank] = ((sg >> rank) & 1ull) ? 0x80000000u : 0u;
+        ls[rank] = samp_weight_bits(sp, tree, level, pos, p, rank);
     }
     wave_sync();
     return z;
@@ -673,7 +655,7 @@ __device__ __forceinline__ void gather_rows(const FindArgs& A, const int32_t* lf
         for (int t = 0; t < FB; ++t) {
             if (t >= nf) break;
 #pragma unroll
-            for (int r = 0; r < R; ++r) val[r] = __fadd_rn(val[r], signed_term(x[t][r], sg[t]));
+            for (int r = 0; r < R; ++r) val[r] = __fadd_rn(val[r], weighted_term(x[t][r], sg[t]));
         }
     }
 }
@@ -711,7 +693,7 @@ __device__ __forceinline__ void stage_batch(const ProjCSR& P, int v, int p0, int
         if (t < cg) {
             const uint32_t f = (uint32_t)P.nz_feature[ag + t];
             WS.blf[e] = f < (uint32_t)d ? (int)f : 0;
-            WS.bls[e] = P.nz_weight[ag + t] < 0 ? 0x80000000u : 0u;
+            WS.bls[e] = csr_weight_bits(P, ag + t);
         }
     }
     wave_sync();
@@ -1216,7 +1198,7 @@ __global__ __launch_bounds__(kBlock) void k_brange(FindArgs A, PS P) {
         int p, ch;
         if (!big_item(A, it, nbig, bd, p, ch)) continue;
         float lo, hi;
-        float* vcw = use_vcache<T>(bd, proj_nnz(P, bd.node, p)) ? vcache_at(A, bd, p, ch) : nullptr;
+        float* vcw = use_vcache<T>(bd, proj_nnz(P, bd.node, p, A.n_features)) ? vcache_at(A, bd, p, ch) : nullptr;
         big_chunk<T, PS, false>(A, P, bd, p, ch, WS, lo, hi, nullptr, EqualBins{0.f, 0.f, 2}, vcw);
         lo = wave_min(lo);
         hi = wave_max(hi);
@@ -1276,7 +1258,7 @@ __global__ __launch_bounds__(kBlock) void k_bhist(FindArgs A, PS P) {
         for (int e = lane; e < B * C; e += kWave) hist[e] = 0;
         wave_sync();
         float lo, hi;
-        const float* vcr = use_vcache<T>(bd, proj_nnz(P, bd.node, p)) ? vcache_at(A, bd, p, ch) : nullptr;
+        const float* vcr = use_vcache<T>(bd, proj_nnz(P, bd.node, p, A.n_features)) ? vcache_at(A, bd, p, ch) : nullptr;
         if (RW) {
             RwTable& tab = wave_rw(smem, w, Bm, C);
             const float sc = rw_cell_scale(r.x, r.y);
@@ -1490,7 +1472,7 @@ __device__ void do_sortblock(const FindArgs& A, const PS& P, int4 D, int p, char
             float acc = 0.f;
             for (int j = 0; j < zn; ++j) {
                 const T* col = (const T*)A.x + (int64_t)S.lf[j] * A.ld;
-                acc = __fadd_rn(acc, signed_term(ldx(col, row), S.ls[j]));
+                acc = __fadd_rn(acc, weighted_term(ldx(col, row), S.ls[j]));
             }
             atomicAdd(&S.pc[y], 1);
             key = ((uint64_t)fkey(acc) << 32) | (uint32_t)y;

@@ -22,6 +22,7 @@
 #include "sof_device.h"
 #include "sof_host.h"
 #include "sof_internal.h"
+#include "sof_sampler.h"
 
 namespace sof {
 
@@ -30,6 +31,7 @@ enum { G_NFRONT = 0, G_LEVEL = 1, G_NNODES = 2, G_NEXTN = 3, G_NSAMP = 4, G_COUN
 struct GrowArgs {
     const int32_t* y;
     int32_t n_rows, n_classes, n_trees, k, z, n_features, max_depth, bins;
+    int32_t sampler, weights;     // SOF_SAMPLER_*, SOF_WEIGHTS_*
     uint64_t seed;
     int32_t* cnt;                 // G_* counters
     const int32_t* f_off;         // current frontier
@@ -61,40 +63,17 @@ __device__ __forceinline__ int gN(const GrowArgs& g) {
     return n < 0 ? 0 : (n > g.cap_front ? (int)g.cap_front : n);
 }
 
-__device__ __forceinline__ uint64_t g_splitmix(uint64_t seed, uint64_t c) {
-    uint64_t z = seed + c * 0x9E3779B97F4A7C15ull;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return z ^ (z >> 31);
-}
-__device__ __forceinline__ uint64_t g_counter(int tree, int level, int pos, int p, int draw) {
-    uint64_t c = (uint64_t)tree * 64u + (uint64_t)level;
-    c = (c << 24) + (uint64_t)pos;
-    c = (c << 10) + (uint64_t)p;
-    return (c << 4) + (uint64_t)draw;
-}
-// The sampler of the search, one thread: Floyd's distinct draws, ascending,
-// signs from draw 15.
-__device__ void g_sample(uint64_t seed, int tree, int level, int pos, int p, int d, int z, int32_t* f,
-                         int8_t* w) {
-    int32_t c[16];
-    for (int j = 0; j < z; ++j) {
-        uint32_t top = (uint32_t)(d - z + j) + 1u;
-        uint64_t r = g_splitmix(seed, g_counter(tree, level, pos, p, j));
-        int t = (int)(((r >> 32) * (uint64_t)top) >> 32);
-        bool taken = false;
-        for (int i = 0; i < j; ++i) taken |= c[i] == t;
-        c[j] = taken ? d - z + j : t;
-    }
-    for (int i = 1; i < z; ++i) {
-        int key = c[i], m = i - 1;
-        while (m >= 0 && c[m] > key) { c[m + 1] = c[m]; --m; }
-        c[m + 1] = key;
-    }
-    uint64_t sg = g_splitmix(seed, g_counter(tree, level, pos, p, 15));
-    for (int s = 0; s < 16; ++s) {
-        f[s] = s < z ? c[s] : 0;
-        w[s] = s < z ? (((sg >> s) & 1ull) ? (int8_t)-1 : (int8_t)1) : (int8_t)0;
+// The winning projection of a node into its record: features ascending,
+// FP32 weights, zeros past nnz.
+__device__ void g_sample(const GrowArgs& g, int tree, int level, int pos, int p, sof_tree_node& nd) {
+    const SampSpec sp{g.seed, g.n_features, g.z, g.sampler, g.weights};
+    int32_t f[SOF_MAX_NNZ];
+    uint32_t w[SOF_MAX_NNZ];
+    const int z = samp_thread(sp, tree, level, pos, p, f, w);
+    nd.nnz = z;
+    for (int q = 0; q < SOF_MAX_NNZ; ++q) {
+        nd.feature[q] = q < z ? f[q] : 0;
+        nd.weight[q] = q < z ? __uint_as_float(w[q]) : 0.f;
     }
 }
 
@@ -304,10 +283,9 @@ __global__ __launch_bounds__(256) void k_gwrite(GrowArgs g) {
         nd.scale = s.scale;
         nd.gain = (double)s.gain;
         nd.n_bins = g.bins;
-        nd.nnz = g.z;
         nd.left = (int32_t)lid;
         nd.right = (int32_t)(lid + 1);
-        g_sample(g.seed, tree, level, g.f_pos[v], s.proj, g.n_features, g.z, nd.feature, nd.weight);
+        g_sample(g, tree, level, g.f_pos[v], s.proj, nd);
         int64_t next = a & 0xffffffffll;
         int64_t nbase = g.scan_b[v];
         const int32_t nc[2] = {s.n_left, s.n_right};
@@ -332,7 +310,7 @@ __global__ __launch_bounds__(256) void k_gwrite(GrowArgs g) {
             ch.n_bins = 0;
             ch.nnz = 0;
             ch.pad = 0;
-            for (int q = 0; q < 16; ++q) { ch.feature[q] = 0; ch.weight[q] = 0; }
+            for (int q = 0; q < 16; ++q) { ch.feature[q] = 0; ch.weight[q] = 0.f; }
             ch.gain = 0.0;
             if (!leaf && next < g.cap_front) {
                 g.n_off[next] = (int32_t)nbase;
@@ -471,6 +449,8 @@ static GrowArgs grow_args(sof_forest* f) {
     g.max_depth = f->desc.max_depth;
     g.bins = f->desc.bins;
     g.seed = f->desc.seed;
+    g.sampler = f->desc.sampler;
+    g.weights = f->desc.weights;
     g.cnt = f->b.cnt;
     g.f_off = f->b.off[c];
     g.f_idx = f->b.idx[c];
@@ -523,7 +503,8 @@ static hipError_t level_launch(sof_forest* f, hipStream_t s) {
     a.out = f->b.splits;
     a.hist_out = nullptr;
     find_bind(f->flay, f->b.ws_find, &a.ws);
-    ProjHash ph{f->b.tree[c], f->b.pos[c], f->b.cnt + G_LEVEL, f->desc.seed, f->desc.k, f->desc.z};
+    ProjHash ph{f->b.tree[c], f->b.pos[c], f->b.cnt + G_LEVEL, f->desc.seed, f->desc.k, f->desc.z,
+                f->desc.sampler, f->desc.weights};
     hipError_t e = launch_find_hash(a, ph, f->cfg, s);
     if (e != hipSuccess) return e;
     PartArgs pa;
@@ -583,8 +564,14 @@ extern "C" int sof_forest_create(sof_ctx* ctx, const sof_data* data, const sof_f
     if (desc->first_tree < 0 || (int64_t)desc->first_tree + desc->n_trees > (1 << 20))
         return fail(SOF_ERR_INVALID_ARG, "tree ids out of range");
     if (desc->k < 1 || desc->k > 1024) return fail(SOF_ERR_INVALID_ARG, "k %d outside [1, 1024]", desc->k);
-    if (desc->z < 1 || desc->z > 15 || desc->z > data->n_features)
+    if (desc->sampler != SOF_SAMPLER_FIXED && desc->sampler != SOF_SAMPLER_DENSITY)
+        return fail(SOF_ERR_UNSUPPORTED, "sampler %d", desc->sampler);
+    if (desc->weights != SOF_WEIGHTS_SIGN && desc->weights != SOF_WEIGHTS_UNIFORM)
+        return fail(SOF_ERR_UNSUPPORTED, "weights %d", desc->weights);
+    if (desc->sampler == SOF_SAMPLER_FIXED && (desc->z < 1 || desc->z > 15 || desc->z > data->n_features))
         return fail(SOF_ERR_INVALID_ARG, "z %d outside [1, min(15, n_features)]", desc->z);
+    if (desc->sampler == SOF_SAMPLER_DENSITY && (desc->z < 1 || desc->z > SOF_MAX_NNZ))
+        return fail(SOF_ERR_INVALID_ARG, "mean nonzeros z %d outside [1, %d]", desc->z, SOF_MAX_NNZ);
     if (desc->bins < 2 || desc->bins > SOF_MAX_BINS) return fail(SOF_ERR_UNSUPPORTED, "bins %d", desc->bins);
     if (desc->sort_threshold < 0) return fail(SOF_ERR_INVALID_ARG, "sort_threshold < 0");
     if (desc->max_depth < 0 || desc->max_depth > 64) return fail(SOF_ERR_INVALID_ARG, "max_depth %d", desc->max_depth);

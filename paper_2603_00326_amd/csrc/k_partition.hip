@@ -17,6 +17,7 @@
 #include "sof_device.h"
 #include "sof_host.h"
 #include "sof_internal.h"
+#include "sof_sampler.h"
 
 namespace sof {
 
@@ -71,47 +72,23 @@ __device__ __forceinline__ int pstage(const ProjCSR& P, int v, int p, int d, int
     if (lane < z) {
         uint32_t f = (uint32_t)P.nz_feature[j0 + lane];
         lf[lane] = f < (uint32_t)d ? (int)f : 0;
-        ls[lane] = P.nz_weight[j0 + lane] < 0 ? 0x80000000u : 0u;
+        ls[lane] = csr_weight_bits(P, j0 + lane);
     }
     wave_sync_p();
     return z;
 }
 
-__device__ __forceinline__ uint64_t smix(uint64_t seed, uint64_t c) {
-    uint64_t z = seed + c * 0x9E3779B97F4A7C15ull;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return z ^ (z >> 31);
-}
-__device__ __forceinline__ uint64_t pcounter(int tree, int level, int pos, int p, int draw) {
-    uint64_t c = (uint64_t)tree * 64u + (uint64_t)level;
-    c = (c << 24) + (uint64_t)pos;
-    c = (c << 10) + (uint64_t)p;
-    return (c << 4) + (uint64_t)draw;
-}
 __device__ __forceinline__ int pcount(const ProjHash& P, int) { return P.k; }
 __device__ __forceinline__ int pstage(const ProjHash& P, int v, int p, int d, int32_t* lf, uint32_t* ls) {
     const int lane = lane_id();
-    const int z = P.z;
+    const SampSpec sp{P.seed, d, P.z, P.mode, P.wmode};
     const int tree = P.tree_of[v], pos = P.pos_of[v], level = *P.level;
-    uint32_t t = 0;
-    if (lane < z) {
-        uint32_t top = (uint32_t)(d - z + lane) + 1u;
-        uint64_t r = smix(P.seed, pcounter(tree, level, pos, p, lane));
-        t = (uint32_t)(((r >> 32) * (uint64_t)top) >> 32);
-    }
-    int mine = (int)t;
-    for (int j = 0; j < z; ++j) {
-        int cj = __shfl((int)t, j);
-        bool taken = __ballot(lane < j && mine == cj) != 0ull;
-        if (lane == j) mine = taken ? d - z + j : cj;
-    }
-    int rank = 0;
-    for (int i = 0; i < z; ++i) rank += (__shfl(mine, i) < mine) ? 1 : 0;
-    uint64_t sg = smix(P.seed, pcounter(tree, level, pos, p, 15));
+    const int z = __builtin_amdgcn_readfirstlane(samp_nnz(sp, tree, level, pos, p));
+    int mine, rank;
+    samp_wave(sp, z, tree, level, pos, p, mine, rank);
     if (lane < z) {
         lf[rank] = mine;
-        ls[rank] = ((sg >> rank) & 1ull) ? 0x80000000u : 0u;
+        ls[rank] = samp_weight_bits(sp, tree, level, pos, p, rank);
     }
     wave_sync_p();
     return z;
@@ -131,36 +108,24 @@ __device__ __forceinline__ int preg(const ProjCSR& P, int v, int p, int d, int& 
     if (lane < z) {
         uint32_t f = (uint32_t)P.nz_feature[j0 + lane];
         fj = f < (uint32_t)d ? (int)f : 0;
-        sj = P.nz_weight[j0 + lane] < 0 ? 0x80000000u : 0u;
+        sj = csr_weight_bits(P, j0 + lane);
     }
     return z;
 }
 __device__ __forceinline__ int preg(const ProjHash& P, int v, int p, int d, int& fj, uint32_t& sj) {
     const int lane = lane_id();
-    const int z = P.z;
+    const SampSpec sp{P.seed, d, P.z, P.mode, P.wmode};
     const int tree = P.tree_of[v], pos = P.pos_of[v], level = *P.level;
-    uint32_t t = 0;
-    if (lane < z) {
-        uint32_t top = (uint32_t)(d - z + lane) + 1u;
-        uint64_t r = smix(P.seed, pcounter(tree, level, pos, p, lane));
-        t = (uint32_t)(((r >> 32) * (uint64_t)top) >> 32);
-    }
-    int mine = (int)t;
-    for (int j = 0; j < z; ++j) {
-        int cj = __shfl((int)t, j);
-        bool taken = __ballot(lane < j && mine == cj) != 0ull;
-        if (lane == j) mine = taken ? d - z + j : cj;
-    }
-    int rank = 0;
-    for (int i = 0; i < z; ++i) rank += (__shfl(mine, i) < mine) ? 1 : 0;
+    const int z = __builtin_amdgcn_readfirstlane(samp_nnz(sp, tree, level, pos, p));
+    int mine, rank;
+    samp_wave(sp, z, tree, level, pos, p, mine, rank);
     // lane j takes the draw of rank j
     fj = 0;
     for (int i = 0; i < z; ++i) {
         const int ri = __shfl(rank, i), mi = __shfl(mine, i);
         if (ri == lane) fj = mi;
     }
-    const uint64_t sg = smix(P.seed, pcounter(tree, level, pos, p, 15));
-    sj = (lane < z && ((sg >> lane) & 1ull)) ? 0x80000000u : 0u;
+    sj = lane < z ? samp_weight_bits(sp, tree, level, pos, p, lane) : 0u;
     return z;
 }
 
@@ -203,7 +168,7 @@ __device__ void ptiny_r(const PartArgs& A, const PS& P, int v, int64_t s0, int n
 #pragma unroll
         for (int r = 0; r < R; ++r) x[r] = ldx((const T*)((const char*)col + off[r]), 0);
 #pragma unroll
-        for (int r = 0; r < R; ++r) val[r] = __fadd_rn(val[r], signed_term(x[r], sg));
+        for (int r = 0; r < R; ++r) val[r] = __fadd_rn(val[r], weighted_term(x[r], sg));
     }
     uint64_t m[R];
     int nl = 0;
@@ -309,7 +274,7 @@ __device__ void predicates_r(const PartArgs& A, const PS& P, int v, int64_t at, 
 #pragma unroll
         for (int r = 0; r < R; ++r) x[r] = ldx((const T*)((const char*)col + off[r]), 0);
 #pragma unroll
-        for (int r = 0; r < R; ++r) val[r] = __fadd_rn(val[r], signed_term(x[r], sg));
+        for (int r = 0; r < R; ++r) val[r] = __fadd_rn(val[r], weighted_term(x[r], sg));
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -595,7 +560,7 @@ extern "C" int sof_partition(sof_ctx* ctx, const sof_data* data, const sof_front
     a.child_offsets = child_offsets;
     part_bind(fr->n_nodes, fr->n_samples, ws, &a);
     ProjCSR p{proj->proj_offsets, proj->nz_offsets, proj->nz_feature, proj->nz_weight, proj->n_proj,
-              proj->n_nz};
+              proj->n_nz, proj->nz_value};
     e = launch_partition_csr(a, p, ctx->n_cu, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "partition launch");
     return SOF_OK;

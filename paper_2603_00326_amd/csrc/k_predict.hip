@@ -2,14 +2,15 @@
 // the leaf a row reaches, the class with most votes wins (lowest on ties).
 // The forests the paper trains (section 2) are grown to purity; an internal
 // node sends a row left when its rule holds on the row's projection v (the
-// node's own features and +/-1 weights, FP32 adds in CSR order from +0):
+// node's own features and FP32 weights, one rounding per product and per add
+// in feature order from +0):
 // equal-width bins bin(v) <= bin, sort splits v <= threshold, random-width
 // bins v < threshold.
 //
-// One thread per query row walks the trees in turn.  A node record (152
-// bytes, 8-byte aligned) is read as eighteen 8-byte loads issued together
-// (header, feature ids, weights), then the node's column gathers, so a level
-// costs two dependent round trips.  Every index taken from a record is
+// One thread per query row walks the trees in turn.  A node record (200
+// bytes, 8-byte aligned) is read as twenty-four 8-byte loads issued together
+// (header, feature ids, weights; not the gain), then the node's column
+// gathers, so a level costs two dependent round trips.  Every index taken from a record is
 // checked, and a walk stops after 130 steps (a tree is at most 65 levels
 // deep), so damaged records cannot run away.
 #include <hip/hip_runtime.h>
@@ -21,7 +22,7 @@
 
 namespace sof {
 
-static_assert(sizeof(sof_tree_node) == 152, "sof_tree_node layout");
+static_assert(sizeof(sof_tree_node) == 200, "sof_tree_node layout");
 
 struct PredArgs {
     const void* x;
@@ -36,22 +37,24 @@ struct PredArgs {
 
 constexpr int kPredictSteps = 130;
 
-// q: the record as 18 int2 (8k = byte offset): 0 tree, depth; 1 parent, left;
-// 2 right, n_samples; 3 label, is_leaf; 4 kind, bin; 5 threshold, lo;
-// 6 scale, n_bins; 7 nnz, pad; 8..15 feature ids; 16, 17 weights (int8 x 16)
+constexpr int kRecWords = 24;
+
+// q: the record as int2 words (8k = byte offset): 0 tree, depth; 1 parent,
+// left; 2 right, n_samples; 3 label, is_leaf; 4 kind, bin; 5 threshold, lo;
+// 6 scale, n_bins; 7 nnz, pad; 8..15 feature ids; 16..23 weights (FP32 x 16)
 template <typename T>
 __device__ __forceinline__ float node_value(const PredArgs& a, const int2* q, int nnz, int32_t row) {
     const int32_t f[16] = {q[8].x, q[8].y, q[9].x, q[9].y, q[10].x, q[10].y, q[11].x, q[11].y,
                            q[12].x, q[12].y, q[13].x, q[13].y, q[14].x, q[14].y, q[15].x, q[15].y};
-    const uint32_t wb[4] = {(uint32_t)q[16].x, (uint32_t)q[16].y, (uint32_t)q[17].x, (uint32_t)q[17].y};
+    const int32_t wb[16] = {q[16].x, q[16].y, q[17].x, q[17].y, q[18].x, q[18].y, q[19].x, q[19].y,
+                            q[20].x, q[20].y, q[21].x, q[21].y, q[22].x, q[22].y, q[23].x, q[23].y};
     float acc = 0.f;
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
         if (j >= nnz) break;
         const uint32_t fj = (uint32_t)f[j] < (uint32_t)a.n_features ? (uint32_t)f[j] : 0u;
-        const int8_t w = (int8_t)((wb[j >> 2] >> (8 * (j & 3))) & 0xffu);
         const float x = ldx((const T*)a.x + (int64_t)fj * a.ld, row);
-        acc = __fadd_rn(acc, w < 0 ? -x : x);
+        acc = __fadd_rn(acc, weighted_term(x, (uint32_t)wb[j]));
     }
     return acc;
 }
@@ -69,9 +72,9 @@ __global__ __launch_bounds__(256) void k_predict(PredArgs a) {
             for (int step = 0; step < kPredictSteps; ++step) {
                 if (i < 0 || i >= a.n_nodes) break;
                 const int2* rec = (const int2*)(a.nodes + i);
-                int2 q[18];
+                int2 q[kRecWords];
 #pragma unroll
-                for (int u = 0; u < 18; ++u) q[u] = rec[u];
+                for (int u = 0; u < kRecWords; ++u) q[u] = rec[u];
                 if (q[3].y) {
                     label = q[3].x;
                     break;

@@ -75,7 +75,7 @@ __global__ __launch_bounds__(256) void k_project(FindArgs A, ProjCSR P, const in
             for (int j = 0; j < s_z; ++j) {
                 uint32_t f = (uint32_t)P.nz_feature[j0 + j];
                 lf[j] = f < (uint32_t)A.n_features ? (int)f : 0;
-                ls[j] = P.nz_weight[j0 + j] < 0 ? 0x80000000u : 0u;
+                ls[j] = csr_weight_bits(P, j0 + j);
             }
         }
         __syncthreads();
@@ -92,7 +92,7 @@ __global__ __launch_bounds__(256) void k_project(FindArgs A, ProjCSR P, const in
             float acc = 0.f;
             for (int j = 0; j < z; ++j) {
                 const T* col = (const T*)A.x + (int64_t)lf[j] * A.ld;
-                acc = __fadd_rn(acc, signed_term(ldx(col, row), ls[j]));
+                acc = __fadd_rn(acc, weighted_term(ldx(col, row), ls[j]));
             }
             dst[i] = acc;
         }
@@ -149,8 +149,7 @@ __global__ void k_check(sof_data D, sof_frontier F, sof_proj P, sof_params Q, in
                 for (int32_t j = o; j < o1; ++j) {
                     int32_t f = P.nz_feature[j];
                     if ((uint32_t)f >= (uint32_t)D.n_features) bad |= CK_FEATURE;
-                    int8_t w = P.nz_weight[j];
-                    if (w != 1 && w != -1) bad |= CK_WEIGHT;
+                    if (P.nz_value && !__builtin_isfinite(P.nz_value[j])) bad |= CK_WEIGHT;
                     for (int32_t j2 = o; j2 < j; ++j2)
                         if (P.nz_feature[j2] == f) bad |= CK_DISTINCT;
                 }
@@ -181,7 +180,7 @@ int device_check(sof_ctx* ctx, const sof_data* data, const sof_frontier* fr, con
         const char* names[] = {"node_offsets", "node size above max_node_samples", "sample_idx out of range",
                                "proj_offsets", "projections per node above max_proj_per_node",
                                "nz_offsets", "nonzeros per projection above 16", "feature id out of range",
-                               "repeated feature in a projection", "weight not +/-1", "label out of range",
+                               "repeated feature in a projection", "weight not finite", "label out of range",
                                "node_bins out of range"};
         for (int b = 0; b < 12; ++b)
             if (got & (1 << b)) { if (!what.empty()) what += ", "; what += names[b]; }
@@ -226,7 +225,8 @@ extern "C" int sof_project(sof_ctx* ctx, const sof_data* data, const sof_frontie
     sof_params q{nullptr, 256, 0};
     FindArgs a;
     fill_find_args(data, fr, &q, nullptr, nullptr, &a);
-    ProjCSR p{proj->proj_offsets, proj->nz_offsets, proj->nz_feature, proj->nz_weight, proj->n_proj, proj->n_nz};
+    ProjCSR p{proj->proj_offsets, proj->nz_offsets, proj->nz_feature, proj->nz_weight, proj->n_proj, proj->n_nz,
+              proj->nz_value};
     e = launch_project(a, p, out, ws, ctx->n_cu, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "project launch");
     return SOF_OK;

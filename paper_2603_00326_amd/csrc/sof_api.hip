@@ -178,8 +178,8 @@ int sof::check_proj(const sof_proj* p, const sof_data* d) {
         return fail(SOF_ERR_INVALID_ARG, "max_proj_per_node %d above n_proj %d", p->max_proj_per_node,
                     p->n_proj);
     if (!p->proj_offsets || !p->nz_offsets) return fail(SOF_ERR_INVALID_ARG, "proj offsets NULL");
-    if (p->n_nz > 0 && (!p->nz_feature || !p->nz_weight))
-        return fail(SOF_ERR_INVALID_ARG, "nz_feature or nz_weight is NULL");
+    if (p->n_nz > 0 && (!p->nz_feature || (!p->nz_weight && !p->nz_value)))
+        return fail(SOF_ERR_INVALID_ARG, "nz_feature is NULL, or both nz_weight and nz_value are");
     (void)d;
     return SOF_OK;
 }
@@ -357,7 +357,7 @@ extern "C" int sof_find_splits(sof_ctx* ctx, const sof_data* data, const sof_fro
     fill_find_args(data, fr, params, out, hist_out, &a);
     find_bind(L, ws, &a.ws);
     ProjCSR p{proj->proj_offsets, proj->nz_offsets, proj->nz_feature, proj->nz_weight, proj->n_proj,
-              proj->n_nz};
+              proj->n_nz, proj->nz_value};
     e = launch_find_csr(a, p, cfg, (hipStream_t)stream, timing_events(ctx));
     if (e != hipSuccess) return hip_fail(e, "find_splits launch");
     return SOF_OK;

@@ -41,9 +41,9 @@ __device__ __forceinline__ float kfloat(uint32_t k) {
 __device__ __forceinline__ float ldx(const float* col, int32_t r) { return col[r]; }
 __device__ __forceinline__ float ldx(const _Float16* col, int32_t r) { return (float)col[r]; }
 
-// +x or -x (exact) by flipping the sign bit
-__device__ __forceinline__ float signed_term(float x, uint32_t sgn) {
-    return __uint_as_float(__float_as_uint(x) ^ sgn);
+// w * x, one FP32 rounding (exact for w = +/-1); w given as FP32 bits
+__device__ __forceinline__ float weighted_term(float x, uint32_t wbits) {
+    return __fmul_rn(x, __uint_as_float(wbits));
 }
 
 // ---------------------------------------------------------------------------

@@ -50,7 +50,13 @@ struct ProjCSR {
     const int8_t* nz_weight;
     int32_t n_proj;
     int64_t n_nz;
+    const float* nz_value;   // FP32 weights, or NULL: the integer weights nz_weight
 };
+
+// FP32 bits of the weight of nonzero j
+__device__ __forceinline__ uint32_t csr_weight_bits(const ProjCSR& P, int64_t j) {
+    return P.nz_value ? __float_as_uint(P.nz_value[j]) : __float_as_uint((float)P.nz_weight[j]);
+}
 
 // Projections drawn on the fly from a counter-based hash (forest growth):
 // node v of the frontier belongs to tree tree_of[v] at position pos_of[v] of
@@ -61,6 +67,7 @@ struct ProjHash {
     const int32_t* level;
     uint64_t seed;
     int32_t k, z;
+    int32_t mode, wmode;     // SOF_SAMPLER_*, SOF_WEIGHTS_*
 };
 
 struct FindWs {

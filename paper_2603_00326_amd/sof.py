@@ -26,6 +26,8 @@ SOF_F32, SOF_F16 = 0, 1
 SOF_BINS_EQUAL, SOF_BINS_RANDOM = 0, 1
 SOF_CRIT_GINI, SOF_CRIT_ENTROPY = 0, 1
 SOF_SPLIT_HIST, SOF_SPLIT_SORT, SOF_SPLIT_RHIST = 0, 1, 2
+SOF_SAMPLER_FIXED, SOF_SAMPLER_DENSITY = 0, 1
+SOF_WEIGHTS_SIGN, SOF_WEIGHTS_UNIFORM = 0, 1
 SORT_LIMIT = 8192
 INT32_MAX = 2**31 - 1
 
@@ -60,7 +62,7 @@ class sof_frontier(ctypes.Structure):
 
 class sof_proj(ctypes.Structure):
     _fields_ = [("proj_offsets", P), ("nz_offsets", P), ("nz_feature", P), ("nz_weight", P),
-                ("n_nz", i64), ("n_proj", i32), ("max_proj_per_node", i32)]
+                ("n_nz", i64), ("n_proj", i32), ("max_proj_per_node", i32), ("nz_value", P)]
 
 
 class sof_params(ctypes.Structure):
@@ -71,7 +73,7 @@ class sof_params(ctypes.Structure):
 class sof_forest_desc(ctypes.Structure):
     _fields_ = [("root_offsets", P), ("root_idx", P), ("seed", u64), ("n_trees", i32),
                 ("first_tree", i32), ("k", i32), ("z", i32), ("bins", i32), ("sort_threshold", i32),
-                ("max_depth", i32), ("pad", i32)]
+                ("max_depth", i32), ("sampler", i32), ("weights", i32), ("pad", i32)]
 
 
 class sof_tune(ctypes.Structure):
@@ -90,9 +92,9 @@ TREE_NODE_DTYPE = np.dtype([
     ("tree", "<i4"), ("depth", "<i4"), ("parent", "<i4"), ("left", "<i4"), ("right", "<i4"),
     ("n_samples", "<i4"), ("label", "<i4"), ("is_leaf", "<i4"), ("kind", "<i4"), ("bin", "<i4"),
     ("threshold", "<f4"), ("lo", "<f4"), ("scale", "<f4"), ("n_bins", "<i4"), ("nnz", "<i4"),
-    ("pad", "<i4"), ("feature", "<i4", (16,)), ("weight", "i1", (16,)), ("gain", "<f8"),
+    ("pad", "<i4"), ("feature", "<i4", (16,)), ("weight", "<f4", (16,)), ("gain", "<f8"),
 ])
-assert TREE_NODE_DTYPE.itemsize == 152
+assert TREE_NODE_DTYPE.itemsize == 200
 
 _lib = None
 
@@ -220,6 +222,7 @@ class DeviceFrontier:
     nz_feature: object
     nz_weight: object
     node_bins: object = None
+    nz_value: object = None      # FP32 weights (then nz_weight is None)
     max_node_samples: int = 0
     max_proj_per_node: int = 0
 
@@ -236,7 +239,7 @@ class DeviceFrontier:
                          self.n_nodes, int(self.max_node_samples))
         p = sof_proj(_ptr(self.proj_offsets), _ptr(self.nz_offsets), _ptr(self.nz_feature),
                      _ptr(self.nz_weight), int(self.nz_feature.numel()), int(self.nz_offsets.numel() - 1),
-                     int(self.max_proj_per_node))
+                     int(self.max_proj_per_node), _ptr(self.nz_value))
         return d, f, p
 
 
@@ -250,11 +253,13 @@ def to_device(wl, device="cuda:0", X=None) -> DeviceFrontier:
     n = np.diff(wl.node_offsets.astype(np.int64))
     k = np.diff(wl.proj_offsets.astype(np.int64))
     Xd = X if X is not None else torch.from_numpy(np.ascontiguousarray(wl.X)).to(device)
+    fw = np.asarray(wl.nz_weight).dtype.kind == "f"
     return DeviceFrontier(
         X=Xd, y=t(wl.y, np.int32), n_classes=int(wl.n_classes),
         node_offsets=t(wl.node_offsets, np.int32), sample_idx=t(wl.sample_idx, np.int32),
         proj_offsets=t(wl.proj_offsets, np.int32), nz_offsets=t(wl.nz_offsets, np.int32),
-        nz_feature=t(wl.nz_feature, np.int32), nz_weight=t(wl.nz_weight, np.int8),
+        nz_feature=t(wl.nz_feature, np.int32), nz_weight=None if fw else t(wl.nz_weight, np.int8),
+        nz_value=t(wl.nz_weight, np.float32) if fw else None,
         node_bins=None if wl.node_bins is None else t(wl.node_bins, np.int32),
         max_node_samples=int(n.max()) if n.size else 0, max_proj_per_node=int(k.max()) if k.size else 0)
 
@@ -381,7 +386,7 @@ class Forest:
 
     def __init__(self, ctx: Context, X, y, n_classes: int, root_offsets, root_idx, *, k: int, z: int,
                  seed: int, bins: int = 256, sort_threshold: int = 0, max_depth: int = 64,
-                 first_tree: int = 0):
+                 first_tree: int = 0, sampler: int = 0, weights: int = 0):
         self.ctx = ctx
         self._keep = (X, y, root_idx)
         dtype = SOF_F16 if str(X.dtype) == "torch.float16" else SOF_F32
@@ -392,7 +397,7 @@ class Forest:
         self.n_trees = len(ro) - 1
         self.desc = sof_forest_desc(ro.ctypes.data, _ptr(root_idx), int(seed) & (2**64 - 1), self.n_trees,
                                     int(first_tree), int(k), int(z), int(bins), int(sort_threshold),
-                                    int(max_depth), 0)
+                                    int(max_depth), int(sampler), int(weights), 0)
         h = P()
         _check(lib().sof_forest_create(ctx.handle, ctypes.byref(self.data), ctypes.byref(self.desc),
                                        ctypes.byref(h)))

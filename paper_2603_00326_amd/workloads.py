@@ -15,7 +15,7 @@ Layout conventions (the C ABI uses the same ones):
 * Projections are CSR: ``proj_offsets`` (int32, N+1) maps a node to its range
   of projections, ``nz_offsets`` (int32, P+1) maps a projection to its range of
   nonzeros, ``nz_feature`` (int32, ascending within a projection, distinct) and
-  ``nz_weight`` (int8, +/-1).
+  ``nz_weight`` (int8 +/-1, or FP32 weights: ``with_float_weights``).
 
 The paper measures on HIGGS, SUSY, Epsilon and Trunk; none is available here,
 so these generators stand in for them with dense real-valued column stores of
@@ -47,7 +47,7 @@ class Workload:
     proj_offsets: np.ndarray      # (N+1,) int32
     nz_offsets: np.ndarray        # (P+1,) int32
     nz_feature: np.ndarray        # (nnz,) int32
-    nz_weight: np.ndarray         # (nnz,) int8
+    nz_weight: np.ndarray         # (nnz,) int8 +/-1, or FP32 weights
     bins: int = 256
     sort_threshold: int = 0
     node_bins: np.ndarray | None = None   # (N,) int32 or None
@@ -150,6 +150,8 @@ def random_projections(rng: np.random.Generator, n_nodes: int, k: int, d: int,
     cand = rng.integers(0, d, size=(P, max(zmax * 2, 1)), dtype=np.int32)
     for q in range(P):
         zq = int(zs[q])
+        if zq == 0:
+            continue
         row = cand[q]
         seen = []
         for c in row:
@@ -166,6 +168,19 @@ def random_projections(rng: np.random.Generator, n_nodes: int, k: int, d: int,
     nz_weight = rng.choice(np.array([-1, 1], dtype=np.int8), size=nnz)
     proj_offsets = (np.arange(n_nodes + 1, dtype=np.int64) * k).astype(np.int32)
     return proj_offsets, nz_offsets, nz_feature, nz_weight
+
+
+def uniform_weights(rng: np.random.Generator, n: int) -> np.ndarray:
+    """n FP32 weights (2m + 1 - 2^24) / 2^24, m uniform on 0..2^24-1: symmetric
+    on (-1, 1), never 0, each exactly representable."""
+    m = rng.integers(0, 1 << 24, size=n, dtype=np.int64)
+    return ((2 * m + 1 - (1 << 24)).astype(np.float64) / float(1 << 24)).astype(np.float32)
+
+
+def with_float_weights(wl: "Workload", seed: int) -> "Workload":
+    """The same workload with FP32 weights from uniform_weights in place of +/-1."""
+    wl.nz_weight = uniform_weights(np.random.default_rng(seed), len(wl.nz_feature))
+    return wl
 
 
 def _random_projections_fast(rng, n_nodes, k, d, z):

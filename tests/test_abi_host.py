@@ -73,10 +73,10 @@ def frontier(S, **kw):
 
 def proj(S, **kw):
     p = dict(proj_offsets=FAKE, nz_offsets=FAKE, nz_feature=FAKE, nz_weight=FAKE, n_nz=64, n_proj=32,
-             max_proj_per_node=8)
+             max_proj_per_node=8, nz_value=None)
     p.update(kw)
     return S.sof_proj(p["proj_offsets"], p["nz_offsets"], p["nz_feature"], p["nz_weight"], p["n_nz"],
-                      p["n_proj"], p["max_proj_per_node"])
+                      p["n_proj"], p["max_proj_per_node"], p["nz_value"])
 
 
 def params(S, **kw):
@@ -126,6 +126,7 @@ def test_workspace_size_of_valid_arguments(S, L):
     ("proj", dict(max_proj_per_node=33), INVALID),
     ("proj", dict(proj_offsets=None), INVALID),
     ("proj", dict(nz_feature=None), INVALID),
+    ("proj", dict(nz_weight=None), INVALID),
     ("proj", dict(n_nz=1 << 31), OVERFLOW),
     ("params", dict(bins=1), UNSUPPORTED),
     ("params", dict(bins=257), UNSUPPORTED),
@@ -185,3 +186,43 @@ def test_binding_fails_loudly_without_the_library(S, monkeypatch):
 def test_entropy_on_the_histogram_path_is_accepted(S, L):
     rc, n = ws_size(S, L, q=params(S, criterion=1, sort_threshold=0))
     assert rc == OK and n > 0
+
+
+def test_fp32_weights_replace_integer_weights(S, L):
+    rc, n = ws_size(S, L, p=proj(S, nz_weight=None, nz_value=FAKE))
+    assert rc == OK and n > 0
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """Sizes and field offsets of every ABI struct as the C compiler lays them
+    out from sof.h equal the Python binding's."""
+    import subprocess
+    from paper_2603_00326_amd import sof
+    structs = {"sof_data": sof.sof_data, "sof_frontier": sof.sof_frontier, "sof_proj": sof.sof_proj,
+               "sof_params": sof.sof_params, "sof_forest_desc": sof.sof_forest_desc, "sof_tune": sof.sof_tune}
+    lines = []
+    for name, cls in structs.items():
+        lines.append(f'printf("{name} size %zu\\n", sizeof({name}));')
+        for fname, *_ in cls._fields_:
+            lines.append(f'printf("{name} {fname} %zu\\n", offsetof({name}, {fname}));')
+    for fname in sof.TREE_NODE_DTYPE.names:
+        lines.append(f'printf("sof_tree_node {fname} %zu\\n", offsetof(sof_tree_node, {fname}));')
+    lines.append('printf("sof_tree_node size %zu\\n", sizeof(sof_tree_node));')
+    lines.append('printf("sof_split size %zu\\n", sizeof(sof_split));')
+    src = tmp_path / "lay.c"
+    src.write_text("#include <stddef.h>\n#include <stdio.h>\n#include \"sof.h\"\nint main(void) {\n" +
+                   "\n".join(lines) + "\nreturn 0;\n}\n")
+    exe = tmp_path / "lay"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = {}
+    for ln in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        a, b, c = ln.split()
+        got[(a, b)] = int(c)
+    for name, cls in structs.items():
+        assert got[(name, "size")] == ctypes.sizeof(cls), name
+        for fname, *_ in cls._fields_:
+            assert got[(name, fname)] == getattr(cls, fname).offset, (name, fname)
+    for fname in sof.TREE_NODE_DTYPE.names:
+        assert got[("sof_tree_node", fname)] == sof.TREE_NODE_DTYPE.fields[fname][1], fname
+    assert got[("sof_tree_node", "size")] == sof.TREE_NODE_DTYPE.itemsize == 200
+    assert got[("sof_split", "size")] == sof.SPLIT_DTYPE.itemsize

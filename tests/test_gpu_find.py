@@ -222,3 +222,27 @@ def test_entropy_criterion(ctx, C, B, dt, bm):
     want_idx, want_coff = O.partition(wl.X, wl.node_offsets, wl.sample_idx, wl.proj_offsets, wl.nz_offsets,
                                       wl.nz_feature, wl.nz_weight, ref, bins=B)
     assert np.array_equal(coff.cpu().numpy(), want_coff) and np.array_equal(out_idx.cpu().numpy(), want_idx)
+
+
+# --------------------------------------------------------------------------
+# FP32 weights (the paper's random weights) and projections with no nonzeros:
+# search, histograms, partition and projection bit-exact on every path
+
+@pytest.mark.parametrize("T,dt", [(0, np.float32), (300, np.float16), (2**31 - 1, np.float32)])
+def test_fp32_weights_all_paths(ctx, T, dt):
+    import torch
+    from paper_2603_00326_amd import sof as S
+    wl = W.random_frontier(91, n_rows=60000, d=24, n_classes=3, sizes=EDGE_SIZES, k=6, z=(0, 6), bins=256,
+                           sort_threshold=T, layout="b", dtype=dt)
+    W.with_float_weights(wl, 92)
+    assert (np.diff(wl.nz_offsets) == 0).any()
+    dev, got, ref = check_case(ctx, wl, f"fp32 weights T={T}")
+    out_idx, coff = S.partition(ctx, dev, S.splits_from_numpy(ref), bins=wl.bins)
+    pj = S.project(ctx, dev)
+    torch.cuda.synchronize()
+    want_idx, want_coff = O.partition(wl.X, wl.node_offsets, wl.sample_idx, wl.proj_offsets, wl.nz_offsets,
+                                      wl.nz_feature, wl.nz_weight, ref, bins=wl.bins)
+    assert np.array_equal(coff.cpu().numpy(), want_coff) and np.array_equal(out_idx.cpu().numpy(), want_idx)
+    want = O.project(wl.X, wl.node_offsets, wl.sample_idx, wl.proj_offsets, wl.nz_offsets, wl.nz_feature,
+                     wl.nz_weight)
+    assert np.array_equal(pj.cpu().numpy().view(np.uint32), want.view(np.uint32))

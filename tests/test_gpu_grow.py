@@ -20,11 +20,11 @@ def ctx():
 
 
 def grow_case(ctx, *, seed, d, n, C, trees, k, z, bins, T, max_depth=64, graph=True, dtype=np.float32,
-              stats=False):
+              stats=False, sampler=0, weights=0):
     import torch
     from paper_2603_00326_amd import sof as S
     say(f"[gpu] grow seed={seed} d={d} n={n} C={C} trees={trees} k={k} z={z} B={bins} T={T} "
-        f"max_depth={max_depth} graph={graph} dtype={np.dtype(dtype).name}")
+        f"max_depth={max_depth} graph={graph} dtype={np.dtype(dtype).name} sampler={sampler} weights={weights}")
     rng = np.random.default_rng(seed)
     X = rng.standard_normal((d, n)).astype(np.float32)
     if dtype == np.float16:
@@ -35,10 +35,12 @@ def grow_case(ctx, *, seed, d, n, C, trees, k, z, bins, T, max_depth=64, graph=T
     ro = np.arange(trees + 1, dtype=np.int64) * n
     ri = np.concatenate(roots)
     ref, ref_levels, ref_units = O.grow_forest(X, y, C, ro, ri, k=k, z=z, seed=seed + 7, bins=bins,
-                                               sort_threshold=T, max_depth=max_depth)
+                                               sort_threshold=T, max_depth=max_depth, sampler=sampler,
+                                               weights=weights)
     Xd = torch.from_numpy(X.astype(dtype)).to("cuda:0")
     f = S.Forest(ctx, Xd, torch.from_numpy(y).to("cuda:0"), C, ro, torch.from_numpy(ri).to("cuda:0"),
-                 k=k, z=z, seed=seed + 7, bins=bins, sort_threshold=T, max_depth=max_depth)
+                 k=k, z=z, seed=seed + 7, bins=bins, sort_threshold=T, max_depth=max_depth, sampler=sampler,
+                 weights=weights)
     if stats:
         sizes, units = [], []
         while True:
@@ -93,3 +95,16 @@ def test_grow_sort_only_four_classes(ctx):
 
 def test_grow_fp16_storage_equals_oracle(ctx):
     grow_case(ctx, seed=6, d=16, n=2000, C=3, trees=2, k=8, z=4, bins=256, T=100, dtype=np.float16)
+
+
+# The paper's sampler: each feature enters a projection with probability z/d
+# (so some projections are empty), FP32 weights uniform on (-1, 1) or +/-1.
+@pytest.mark.parametrize("weights", [1, 0])
+def test_grow_density_sampler(ctx, weights):
+    grow_case(ctx, seed=61, d=40, n=3000, C=3, trees=3, k=8, z=2, bins=128, T=300, graph=True,
+              sampler=1, weights=weights)
+
+
+def test_grow_density_sampler_fp16_no_graph(ctx):
+    grow_case(ctx, seed=62, d=24, n=2500, C=2, trees=2, k=6, z=3, bins=256, T=0, graph=False,
+              dtype=np.float16, sampler=1, weights=1)

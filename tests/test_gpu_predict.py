@@ -118,3 +118,20 @@ def test_predict_random_tree_every_rule(ctx, dt):
         t["tree"] = int(np.searchsorted(offs, o))
     nodes = np.concatenate(trees)
     check(ctx, X, nodes, offs[:-1], C, f"random trees {np.dtype(dt).name}")
+
+
+def test_predict_density_sampler_forest(ctx):
+    # FP32 weights in the records: every internal node's projection rounds
+    # each product, as the oracle's traversal does
+    rng = np.random.default_rng(7)
+    d, n, C, trees = 30, 3000, 3, 3
+    X = rng.standard_normal((d, n)).astype(np.float32)
+    y = rng.integers(0, C, n).astype(np.int32)
+    roots = [np.sort(np.random.default_rng(80 + t).integers(0, n, n)).astype(np.int32) for t in range(trees)]
+    ro = np.arange(trees + 1, dtype=np.int64) * n
+    nodes, _, _ = O.grow_forest(X, y, C, ro, np.concatenate(roots), k=8, z=2, seed=11, bins=128,
+                                sort_threshold=200, max_depth=64, sampler=O.SAMPLER_DENSITY,
+                                weights=O.WEIGHTS_UNIFORM)
+    assert len(set(nodes["nnz"][nodes["is_leaf"] == 0].tolist())) > 1
+    Xq = rng.standard_normal((d, 20000)).astype(np.float32)
+    check(ctx, Xq, nodes, np.arange(trees), C, "density-sampler forest, new rows")

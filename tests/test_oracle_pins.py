@@ -163,6 +163,123 @@ def test_sampler_sign_balance():
 
 
 # --------------------------------------------------------------------------
+# the density sampler (each feature kept with probability z/d) and FP32
+# weights
+# --------------------------------------------------------------------------
+
+def _exact_binom_cdf(d, z, cap):
+    """F(0), ..., F(cap-1) of Binomial(d, z/d) as exact rationals."""
+    pi = Fraction(z, d)
+    out, F = [], Fraction(0)
+    for k in range(cap):
+        F += math.comb(d, k) * pi**k * (1 - pi)**(d - k)
+        out.append(F)
+    return out
+
+
+@pytest.mark.parametrize("d,z", [(64, 2), (1024, 2), (1024, 3), (10, 4), (20, 16), (300, 7)])
+def test_density_count_is_the_exact_binomial_inversion(d, z):
+    # The count is the least k with u < F(k), at most min(d, 16).  F is exact
+    # here, so the oracle's binary64 recurrence may differ from it only where
+    # u lies within a rounding margin of some F(k) (never, in practice).
+    cap = min(d, 16)
+    Fk = _exact_binom_cdf(d, z, cap)
+    seed = 0xC0FFEE
+    for pos in range(1500):
+        h = O.hash64(seed ^ O.SEED_NNZ, O.counter(1, 2, pos, 3, 0))
+        u = Fraction(h >> 11, 2**53)
+        want = next((k for k in range(cap) if u < Fk[k]), cap)
+        got = O.density_nnz(seed, 1, 2, pos, 3, d, z)
+        if got != want:
+            assert min(abs(u - F) for F in Fk) < Fraction(1, 2**40), (d, z, pos, got, want)
+
+
+def test_density_count_law_is_binomial():
+    from scipy import stats
+    d, z, n = 48, 2, 20000
+    got = np.array([O.density_nnz(11, 0, 0, pos, 0, d, z) for pos in range(n)])
+    assert abs(got.mean() - z) < 0.05
+    obs = np.bincount(got, minlength=17)[:17].astype(float)
+    pmf = stats.binom.pmf(np.arange(17), d, z / d)
+    pmf[16] += stats.binom.sf(16, d, z / d)
+    exp = n * pmf
+    keep = exp >= 5
+    o = np.append(obs[keep], obs[~keep].sum())
+    e = np.append(exp[keep], exp[~keep].sum())
+    chi2 = ((o - e) ** 2 / e).sum()
+    assert stats.chi2.sf(chi2, len(o) - 1) > 1e-3
+
+
+def test_density_count_cap_and_full_density():
+    assert O.density_nnz(1, 0, 0, 0, 0, 5, 5) == 5        # z >= d: every feature
+    assert O.density_nnz(1, 0, 0, 0, 0, 40, 40) == 16     # ... at most 16
+    assert O.density_nnz(1, 0, 0, 0, 0, 3, 7) == 3
+    got = [O.density_nnz(2, 0, 0, pos, 0, 20, 16) for pos in range(2000)]
+    assert max(got) == 16 and min(got) >= 6               # Binomial(20, 0.8), capped
+
+
+def test_density_projection_features_and_uniform_weights():
+    from scipy import stats
+    d = 30
+    counts = np.zeros(d)
+    ws, sizes = [], []
+    for pos in range(6000):
+        f, w = O.sample_projection(77, 0, 3, pos, 1, d, 2, O.SAMPLER_DENSITY, O.WEIGHTS_UNIFORM)
+        assert f.size == w.size == O.density_nnz(77, 0, 3, pos, 1, d, 2)
+        assert np.all(np.diff(f) > 0)
+        if f.size:
+            assert f.min() >= 0 and f.max() < d
+        counts[f] += 1
+        ws.append(w)
+        sizes.append(f.size)
+    assert 0 in sizes and max(sizes) >= 6
+    # every feature equally likely (chi-square, d - 1 dof)
+    assert stats.chisquare(counts).pvalue > 1e-3
+    w = np.concatenate(ws).astype(np.float64)
+    m = w * 2**24
+    assert np.all(m == np.round(m)) and np.all(np.abs(m) % 2 == 1) and np.all(np.abs(w) < 1)
+    assert stats.kstest(w, stats.uniform(loc=-1, scale=2).cdf).pvalue > 1e-3
+
+
+def test_density_signs_are_balanced_and_fixed_law_keeps_its_stream():
+    neg = tot = 0
+    for pos in range(4000):
+        _, w = O.sample_projection(5, 0, 1, pos, 7, 64, 3, O.SAMPLER_DENSITY, O.WEIGHTS_SIGN)
+        assert set(w.tolist()) <= {-1.0, 1.0}
+        neg += int((w < 0).sum())
+        tot += w.size
+    assert abs(neg / tot - 0.5) < 0.03
+    # the fixed law with sign weights draws its signs from bit s of draw 15
+    f, w = O.sample_projection(99, 1, 4, 17, 3, 1024, 3)
+    bits = O.hash64(99, O.counter(1, 4, 17, 3, 15))
+    assert [(-1.0 if (bits >> s) & 1 else 1.0) for s in range(3)] == w.tolist()
+
+
+def test_projection_with_fp32_weights():
+    from paper_2603_00326_amd import workloads as W
+    rng = np.random.default_rng(8)
+    X = rng.standard_normal((12, 500)).astype(np.float32)
+    for _ in range(300):
+        z = int(rng.integers(0, 9))
+        f = np.sort(rng.choice(12, z, replace=False)).astype(np.int32)
+        w = W.uniform_weights(rng, z)
+        r = int(rng.integers(0, 500))
+        v = O.project_value(X, f, w, r)
+        if z == 0:
+            assert v == 0
+            continue
+        # scaling by a power of two and negation commute with every rounding
+        assert O.project_value(X, f, w * np.float32(4), r) == v * 4
+        assert O.project_value(X, f, -w, r) == -v
+        if z == 1:
+            assert v == np.float32(w[0]) * X[f[0], r]
+        # within the error bound of z products and z adds in FP32
+        terms = [Fraction(float(w[j])) * Fraction(float(X[f[j], r])) for j in range(z)]
+        bound = Fraction(2 * z, 2**24) * sum(abs(t) for t in terms)
+        assert abs(Fraction(float(v)) - sum(terms)) <= bound
+
+
+# --------------------------------------------------------------------------
 # bins
 # --------------------------------------------------------------------------
 
@@ -503,7 +620,12 @@ def _route(nodes, X, r, root):
     return i
 
 
-def test_growth_to_purity_small():
+SAMPLERS = [(O.SAMPLER_FIXED, O.WEIGHTS_SIGN), (O.SAMPLER_DENSITY, O.WEIGHTS_UNIFORM),
+            (O.SAMPLER_DENSITY, O.WEIGHTS_SIGN)]
+
+
+@pytest.mark.parametrize("sampler,weights", SAMPLERS)
+def test_growth_to_purity_small(sampler, weights):
     rng = np.random.default_rng(51)
     d, n, C = 10, 400, 3
     X = rng.standard_normal((d, n)).astype(np.float32)
@@ -511,7 +633,8 @@ def test_growth_to_purity_small():
     roots = [np.sort(np.random.default_rng(t).integers(0, n, n)).astype(np.int32) for t in range(3)]
     ro = np.array([0, n, 2 * n, 3 * n], np.int64)
     ri = np.concatenate(roots)
-    nodes, ln, lu = O.grow_forest(X, y, C, ro, ri, k=6, z=2, seed=9, bins=64, sort_threshold=50)
+    nodes, ln, lu = O.grow_forest(X, y, C, ro, ri, k=6, z=2, seed=9, bins=64, sort_threshold=50,
+                                  sampler=sampler, weights=weights)
     assert ln[0] == 3
     for t in range(3):
         for r in roots[t]:
@@ -520,6 +643,19 @@ def test_growth_to_purity_small():
     leaves = nodes[nodes["is_leaf"] == 1]
     internal = nodes[nodes["is_leaf"] == 0]
     assert np.all(internal["gain"] > 0)
+    # an internal node's projection has 1..16 distinct ascending features and
+    # nonzero weights of its law; nothing past nnz
+    for nd in internal:
+        z = int(nd["nnz"])
+        assert 1 <= z <= 16 and np.all(np.diff(nd["feature"][:z]) > 0)
+        w = nd["weight"][:z].astype(np.float64)
+        if weights == O.WEIGHTS_SIGN:
+            assert set(w.tolist()) <= {-1.0, 1.0}
+        else:
+            assert np.all((np.abs(w) < 1) & (w != 0))
+        assert not nd["feature"][z:].any() and not nd["weight"][z:].any()
+    if sampler == O.SAMPLER_DENSITY:
+        assert len(set(internal["nnz"].tolist())) > 1
     # every sample of each tree lands in exactly one leaf: leaf sizes sum to n
     for t in range(3):
         assert leaves[leaves["tree"] == t]["n_samples"].sum() == n
@@ -543,7 +679,8 @@ def renumber_tree(nodes, t):
     return out
 
 
-def test_growth_batched_equals_single_tree():
+@pytest.mark.parametrize("sampler,weights", SAMPLERS)
+def test_growth_batched_equals_single_tree(sampler, weights):
     rng = np.random.default_rng(52)
     d, n, C = 8, 300, 2
     X = rng.standard_normal((d, n)).astype(np.float32)
@@ -551,10 +688,10 @@ def test_growth_batched_equals_single_tree():
     roots = [np.sort(np.random.default_rng(100 + t).integers(0, n, n)).astype(np.int32) for t in range(3)]
     ro = np.array([0, n, 2 * n, 3 * n], np.int64)
     nodes, _, _ = O.grow_forest(X, y, C, ro, np.concatenate(roots), k=5, z=2, seed=4, bins=32,
-                                sort_threshold=20)
+                                sort_threshold=20, sampler=sampler, weights=weights)
     for t in range(3):
         single, _, _ = O.grow_forest(X, y, C, np.array([0, n], np.int64), roots[t], k=5, z=2, seed=4,
-                                     bins=32, sort_threshold=20, first_tree=t)
+                                     bins=32, sort_threshold=20, first_tree=t, sampler=sampler, weights=weights)
         assert renumber_tree(nodes, t).tobytes() == single.tobytes()
 
 
