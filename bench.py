@@ -46,6 +46,9 @@ WORKLOADS = {
     "c1": "single root node, n=4096, d=64 FP32, 2 classes, k=64, z=3, B=256",
     "c4": "full training: 8 trees grown to purity level by level from bootstrap roots of a 2M x 1024 FP32 "
           "matrix (90% zeros), 4 classes, k=128, z=3 from the device sampler, B=256, max depth 64",
+    "c4p": "as c4 with the paper's projection sampler: k = 1.5 sqrt(d) = 48 projections per node, each "
+           "feature kept with probability 2/d (3 sqrt(d) nonzeros per node on average, Binomial counts, "
+           "empty projections included), FP32 weights uniform on (-1, 1)",
     "accuracy": "held-out accuracy of 32-tree forests grown with exact splits, histograms and the dynamic "
                 "switch on config 1's rule (4096 training rows, 100000 test rows, d=64, 10% label noise)",
 }
@@ -301,6 +304,10 @@ def run_growth(args, S, ctx):
     t0 = time.perf_counter()
     X, y, C, ro, ri = W.config4_data()
     k, z, bins, max_depth, seed = 128, 3, 256, 64, 4
+    sampler, weights = S.SOF_SAMPLER_FIXED, S.SOF_WEIGHTS_SIGN
+    if args.workload == "c4p":
+        k, z = 48, 2          # 1.5 sqrt(1024) projections, 3 sqrt(1024) / k nonzeros each on average
+        sampler, weights = S.SOF_SAMPLER_DENSITY, S.SOF_WEIGHTS_UNIFORM
     log(f"[bench] c4 data {X.shape[1]} x {X.shape[0]}, {len(ro) - 1} trees, {ri.size} root samples "
         f"(generated in {time.perf_counter() - t0:.1f}s)")
     dev_name = "cuda:0"
@@ -318,7 +325,7 @@ def run_growth(args, S, ctx):
 
     def grow_once(timed):
         f = S.Forest(ctx, Xd, yd, C, ro, rid, k=k, z=z, seed=seed, bins=bins, sort_threshold=T,
-                     max_depth=max_depth)
+                     max_depth=max_depth, sampler=sampler, weights=weights)
         torch.cuda.synchronize()
         levels, evs = [], []
         t_start = time.perf_counter()
@@ -365,7 +372,8 @@ def run_growth(args, S, ctx):
     ms_per_step = float(np.mean(walls)) * 1e3
     # algorithmic bytes per level: the split search reads each sample's index,
     # label and k*z feature values; the partition re-reads z values and moves
-    # two indices per sample of every split node
+    # two indices per sample of every split node (z: the law's mean count for
+    # the density sampler)
     internal = nodes[nodes["is_leaf"] == 0]
     rows, tot_b, tot_ms = [], 0.0, 0.0
     for (depth, nn, ns), ms in zip(levels, lms):
@@ -384,8 +392,9 @@ def run_growth(args, S, ctx):
         "ms_per_step": round(ms_per_step, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "c4", "description": WORKLOADS["c4"], "trees": len(ro) - 1,
-                   "root_samples": int(ri.size), "k": k, "z": z, "bins": bins, "sort_threshold": T,
+        "config": {"workload": args.workload, "description": WORKLOADS[args.workload], "trees": len(ro) - 1,
+                   "root_samples": int(ri.size), "k": k, "z": z, "sampler": int(sampler), "weights": int(weights),
+                   "bins": bins, "sort_threshold": T,
                    "max_depth": max_depth, "levels": len(levels), "nodes": int(len(nodes)),
                    "units": int(units), "step": "grow every tree to purity (one forest)"},
         "roofline": {"bound": "hbm", "kernel": "grow_level (every kernel of a level, summed over levels)",
@@ -407,7 +416,7 @@ def run_growth(args, S, ctx):
         log(f"[bench] CPU oracle baseline: tree 0 of the forest to depth {D}")
         t0 = time.perf_counter()
         _, _, lu = O.grow_forest(X, y, C, ro[:2], ri[:int(ro[1])], k=k, z=z, seed=seed, bins=bins,
-                                 sort_threshold=T, max_depth=D, threads=threads)
+                                 sort_threshold=T, max_depth=D, threads=threads, sampler=sampler, weights=weights)
         el = time.perf_counter() - t0
         top = [i for i, r in enumerate(rows) if r["depth"] < D]
         gpu_top = sum(rows[i]["units"] for i in top) / (sum(lms[i] for i in top) * 1e-3) if top else None
@@ -503,7 +512,7 @@ def main():
         print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "launches": 3}))
         return
 
-    if args.workload == "c4":
+    if args.workload in ("c4", "c4p"):
         run_growth(args, S, S.Context(0))
         return
     if args.workload == "accuracy":

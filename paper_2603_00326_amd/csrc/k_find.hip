@@ -318,11 +318,14 @@ __device__ Cand scan_hist_fast(const LdsHistCM& h, int B, int C, int64_t n, floa
 // Entropy criterion over a class-major histogram (one wave; lane l owns bins
 // 4l..4l+3).  Every boundary b (0..B-2) with both sides non-empty gets
 // E = sum_c f(l_c) + sum_c f(r_c) - f(n_L) - f(n_R) in binary64, the sums over
-// c ascending, with f and the log of sof_device.h; the largest E wins, the
+// c ascending, with f and the log of sof_device.h (read from the call's table
+// of f for counts below its size, which the same function filled, so the
+// values are identical either way); the largest E wins, the
 // lowest boundary on ties.  The winner is returned with N = key(E), D = 1, so
 // the exact comparisons between projections order it by E; SL, SR, SP carry
 // the bits of sum f(l_c), sum f(r_c) and sum f(P_c) for the node record.
-__device__ Cand scan_hist_entropy(const LdsHistCM& h, int B, int C, int64_t n, float lo, float scale) {
+__device__ Cand scan_hist_entropy(const LdsHistCM& h, int B, int C, int64_t n, float lo, float scale,
+                                  const double* tab, int64_t ntab) {
     const int lane = lane_id();
     const int b0 = lane * 4;
     double FL[4] = {0.0, 0.0, 0.0, 0.0}, FR[4] = {0.0, 0.0, 0.0, 0.0};
@@ -335,13 +338,13 @@ __device__ Cand scan_hist_entropy(const LdsHistCM& h, int B, int C, int64_t n, f
         const uint32_t incl = wave_scan_u(s3);
         const uint32_t ex = incl - s3;
         const uint32_t Pi = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
-        FP = __dadd_rn(FP, klnk(Pi));
+        FP = __dadd_rn(FP, klnk_tab(tab, ntab, Pi));
         const uint32_t li[4] = {ex + s0, ex + s1, ex + s2, ex + s3};
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             nLi[i] += li[i];
-            FL[i] = __dadd_rn(FL[i], klnk(li[i]));
-            FR[i] = __dadd_rn(FR[i], klnk(Pi - li[i]));
+            FL[i] = __dadd_rn(FL[i], klnk_tab(tab, ntab, li[i]));
+            FR[i] = __dadd_rn(FR[i], klnk_tab(tab, ntab, Pi - li[i]));
         }
     }
     double bE = 0.0, bFL = 0.0, bFR = 0.0;
@@ -351,7 +354,8 @@ __device__ Cand scan_hist_entropy(const LdsHistCM& h, int B, int C, int64_t n, f
     for (int i = 0; i < 4; ++i) {
         const int64_t nL = nLi[i], nR = n - (int64_t)nLi[i];
         if (b0 + i < B - 1 && nL >= 1 && nR >= 1) {
-            const double E = __dsub_rn(__dsub_rn(__dadd_rn(FL[i], FR[i]), klnk(nL)), klnk(nR));
+            const double E = __dsub_rn(__dsub_rn(__dadd_rn(FL[i], FR[i]), klnk_tab(tab, ntab, nL)),
+                                       klnk_tab(tab, ntab, nR));
             if (bi < 0 || E > bE) { bE = E; bi = i; bFL = FL[i]; bFR = FR[i]; bnL = nLi[i]; }
         }
     }
@@ -787,7 +791,7 @@ __device__ void do_small_r(const FindArgs& A, const PS& P, int v, int64_t s0, in
             wave_sync();
             LdsHistCM h{hist, Bs};
             write_hist_row(A, proj_global(P, v, p), h, B);
-            if (ENT) c = scan_hist_entropy(h, B, C, n, lo, scale);
+            if (ENT) c = scan_hist_entropy(h, B, C, n, lo, scale, A.ws.flnk, A.ws.cap_flnk);
             else c = scan_hist_fast(h, B, C, n, lo, scale, WS.pcs);
             if (RW && c.D != 0) c.thr = rw_boundary(A.bin_seed, proj_global(P, v, p), B, lo, hi, c.pos);
             wave_sync();
@@ -914,7 +918,8 @@ __device__ void do_mid_r(const FindArgs& A, const PS& P, int4 D, int g, int64_t 
         const float scale = bin_scale(B, lo, hi);
         LdsHistCM h{wave_hist(smem, w, Bm, C), Bs};
         write_hist_row(A, proj_global(P, v, p0 + w), h, B);
-        Cand c = ENT ? scan_hist_entropy(h, B, C, n, lo, scale) : scan_hist_fast(h, B, C, n, lo, scale, S.w[w].pcs);
+        Cand c = ENT ? scan_hist_entropy(h, B, C, n, lo, scale, A.ws.flnk, A.ws.cap_flnk)
+                     : scan_hist_fast(h, B, C, n, lo, scale, S.w[w].pcs);
         if (RW && c.D != 0) c.thr = rw_boundary(A.bin_seed, proj_global(P, v, p0 + w), B, lo, hi, c.pos);
         c.proj = p0 + w;
         if (lane == 0) ((Cand*)A.ws.slots)[D.y + p0 + w] = c;
@@ -1312,7 +1317,7 @@ __global__ __launch_bounds__(kBlock) void k_bscan(FindArgs A, PS P) {
         const float scale = bin_scale(B, r.x, r.y);
         LdsHistCM h{hist, Bs};
         write_hist_row(A, proj_global(P, bd.node, p), h, B);
-        Cand c = ENT ? scan_hist_entropy(h, B, C, n, r.x, scale)
+        Cand c = ENT ? scan_hist_entropy(h, B, C, n, r.x, scale, A.ws.flnk, A.ws.cap_flnk)
                      : scan_hist_fast(h, B, C, n, r.x, scale, block_shared(smem).w[w].pcs);
         if (RW && c.D != 0) c.thr = rw_boundary(A.bin_seed, proj_global(P, bd.node, p), B, r.x, r.y, c.pos);
         c.proj = p;
@@ -1612,6 +1617,12 @@ __global__ __launch_bounds__(kBlock) void k_sortblk(FindArgs A, PS P) {
 // ---------------------------------------------------------------------------
 // host side
 
+// the entropy criterion's table of k ln k, k = 0 .. n - 1
+__global__ __launch_bounds__(kBlock) void k_flnk(double* tab, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        tab[i] = klnk(i);
+}
+
 template <typename T, class PS, bool RW, bool ENT>
 static hipError_t launch_find_t(const FindArgs& a, const PS& p, const LaunchCfg& cfg, hipStream_t s,
                                 const hipEvent_t* ev) {
@@ -1624,6 +1635,11 @@ static hipError_t launch_find_t(const FindArgs& a, const PS& p, const LaunchCfg&
         if (ev) (void)hipEventRecord(ev[st++], s);
     };
     mark();
+    if (ENT && a.ws.cap_flnk > 0) {
+        int64_t g = (a.ws.cap_flnk + kBlock - 1) / kBlock;
+        if (g > 4 * cfg.n_cu) g = 4 * cfg.n_cu;
+        hipLaunchKernelGGL(k_flnk, dim3((unsigned)g), dim3(kBlock), 0, s, a.ws.flnk, a.ws.cap_flnk);
+    }
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, a.ws.hdr);
     hipLaunchKernelGGL((k_plan<PS>), dim3(grid_plan), dim3(kBlock), 0, s, a, p);
     hipLaunchKernelGGL(k_expand, dim3(cfg.grid_light), dim3(kBlock), 0, s, a);

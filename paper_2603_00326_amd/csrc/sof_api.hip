@@ -206,7 +206,8 @@ int sof::clamp_threshold(int t) { return t > SOF_SORT_LIMIT + 1 ? SOF_SORT_LIMIT
 static size_t align_up(size_t x) { return (x + SOF_WORKSPACE_ALIGN - 1) & ~(size_t)(SOF_WORKSPACE_ALIGN - 1); }
 static int64_t mn(int64_t a, int64_t b) { return a < b ? a : b; }
 
-FindLayout sof::find_layout(int64_t N, int64_t S, int64_t P, int64_t K, int bins, int classes) {
+FindLayout sof::find_layout(int64_t N, int64_t S, int64_t P, int64_t K, int bins, int classes,
+                            int64_t flnk_entries) {
     FindLayout L;
     memset(&L, 0, sizeof(L));
     FindWs& c = L.caps;
@@ -230,6 +231,7 @@ FindLayout sof::find_layout(int64_t N, int64_t S, int64_t P, int64_t K, int bins
     // (0) beyond 2^30 units (a terabyte), where nodes fall back to re-gathering
     c.cap_vcache = nbig > 0 ? (S * K) / kVcUnit + nbig + 1 : 0;
     if (c.cap_vcache > (int64_t(1) << 30)) c.cap_vcache = 0;
+    c.cap_flnk = flnk_entries;
     size_t o = 0;
     L.hdr = o; o = align_up(o + H_COUNT * sizeof(int32_t));
     L.small_items = o; o = align_up(o + c.cap_small * sizeof(int32_t));
@@ -247,6 +249,7 @@ FindLayout sof::find_layout(int64_t N, int64_t S, int64_t P, int64_t K, int bins
     L.brange = o; o = align_up(o + c.cap_bigslots * sizeof(float2));
     L.phist = o; o = align_up(o + (size_t)c.cap_bigslots * bins * classes * sizeof(int32_t));
     L.vcache = o; o = align_up(o + (size_t)c.cap_vcache * kVcUnit * sizeof(float));
+    L.flnk = o; o = align_up(o + (size_t)c.cap_flnk * sizeof(double));
     L.total = o;
     return L;
 }
@@ -270,6 +273,7 @@ void sof::find_bind(const FindLayout& L, void* ws, FindWs* w) {
     w->brange = (float2*)(b + L.brange);
     w->phist = (int32_t*)(b + L.phist);
     w->vcache = (float*)(b + L.vcache);
+    w->flnk = (double*)(b + L.flnk);
 }
 
 extern "C" int sof_workspace_size(const sof_ctx* ctx, const sof_data* data, const sof_frontier* fr,
@@ -281,7 +285,8 @@ extern "C" int sof_workspace_size(const sof_ctx* ctx, const sof_data* data, cons
         (rc = check_params(params)))
         return rc;
     FindLayout L = find_layout(fr->n_nodes, fr->n_samples, proj->n_proj, proj->max_proj_per_node,
-                               params->bins, data->n_classes);
+                               params->bins, data->n_classes,
+                               flnk_entries(params->criterion, fr->max_node_samples));
     size_t need = L.total;
     size_t part = part_workspace(fr->n_nodes, fr->n_samples);
     if (part > need) need = part;
@@ -342,7 +347,8 @@ extern "C" int sof_find_splits(sof_ctx* ctx, const sof_data* data, const sof_fro
         return rc;
     if (fr->n_nodes > 0 && !out) return fail(SOF_ERR_INVALID_ARG, "out is NULL");
     FindLayout L = find_layout(fr->n_nodes, fr->n_samples, proj->n_proj, proj->max_proj_per_node,
-                               params->bins, data->n_classes);
+                               params->bins, data->n_classes,
+                               flnk_entries(params->criterion, fr->max_node_samples));
     if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
     if (fr->n_nodes == 0) return SOF_OK;
     hipError_t e = hipSetDevice(ctx->device);

@@ -87,8 +87,9 @@ struct FindWs {
     float2* brange;       // per big slot: (min, max) over the node
     int32_t* phist;       // per big projection slot: [bins][classes] summed over the node's chunks
     float* vcache;        // big nodes: projected values of the range pass, [projection][sample] per node
+    double* flnk;         // entropy criterion: k ln k for k = 0 .. cap_flnk - 1
     int64_t cap_small, cap_dmid, cap_imid, cap_dsb, cap_isb, cap_dbig, cap_ibiga, cap_ibigc;
-    int64_t cap_slots, cap_bigslots, cap_dmid2, cap_imid2, cap_vcache;
+    int64_t cap_slots, cap_bigslots, cap_dmid2, cap_imid2, cap_vcache, cap_flnk;
 };
 
 struct FindArgs {
@@ -115,11 +116,19 @@ struct FindArgs {
 struct FindLayout {
     size_t hdr, small_items, desc_mid, desc_mid2, desc_sb, desc_big, items_mid, items_mid2, items_sb, items_biga,
         items_bigc;
-    size_t slots, crange, brange, phist, vcache, total;
+    size_t slots, crange, brange, phist, vcache, flnk, total;
     FindWs caps;
 };
+// flnk_entries: size of the entropy criterion's k ln k table (0 for Gini)
 FindLayout find_layout(int64_t n_nodes, int64_t n_samples, int64_t n_proj, int64_t max_k, int bins,
-                       int classes);
+                       int classes, int64_t flnk_entries = 0);
+// table entries for a call: counts reach the largest node's size; capped at
+// 2^20 (8 MiB), above which f is computed directly
+inline int64_t flnk_entries(int criterion, int64_t max_node_samples) {
+    if (criterion != SOF_CRIT_ENTROPY) return 0;
+    const int64_t n = max_node_samples + 1;
+    return n < (int64_t(1) << 20) ? n : (int64_t(1) << 20);
+}
 void find_bind(const FindLayout& L, void* ws, FindWs* out);
 
 struct LaunchCfg {

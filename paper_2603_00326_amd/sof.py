@@ -270,9 +270,10 @@ def _params(dev: DeviceFrontier, bins: int, sort_threshold: int, bin_mode: int =
                       int(bin_seed) & (2**64 - 1))
 
 
-def workspace_size(dev: DeviceFrontier, bins: int = 256, sort_threshold: int = 0, ctx=None) -> int:
+def workspace_size(dev: DeviceFrontier, bins: int = 256, sort_threshold: int = 0, ctx=None,
+                   criterion: int = SOF_CRIT_GINI) -> int:
     d, f, p = dev.structs()
-    q = _params(dev, bins, sort_threshold)
+    q = _params(dev, bins, sort_threshold, criterion=criterion)
     out = ctypes.c_size_t(0)
     _check(lib().sof_workspace_size(ctx.handle if ctx else None, ctypes.byref(d), ctypes.byref(f),
                                     ctypes.byref(p), ctypes.byref(q), ctypes.byref(out)))
@@ -286,7 +287,7 @@ def find_splits(ctx: Context, dev: DeviceFrontier, *, bins=256, sort_threshold=0
     import torch
     d, f, p = dev.structs()
     q = _params(dev, bins, sort_threshold, bin_mode, bin_seed, criterion)
-    ws, wsb = ctx.workspace(workspace_size(dev, bins, sort_threshold, ctx))
+    ws, wsb = ctx.workspace(workspace_size(dev, bins, sort_threshold, ctx, criterion))
     N = dev.n_nodes
     if out is None:
         out = torch.empty((max(N, 1), 10), dtype=torch.int32, device=dev.node_offsets.device)

@@ -186,6 +186,12 @@ def test_binding_fails_loudly_without_the_library(S, monkeypatch):
 def test_entropy_on_the_histogram_path_is_accepted(S, L):
     rc, n = ws_size(S, L, q=params(S, criterion=1, sort_threshold=0))
     assert rc == OK and n > 0
+    # the entropy workspace holds k ln k for k = 0 .. max_node_samples
+    f = frontier(S, n_nodes=40, n_samples=100000, max_node_samples=60000)
+    d = data(S, n_rows=100000, ld=100000)
+    rc0, g = ws_size(S, L, d=d, f=f, q=params(S, sort_threshold=0))
+    rc1, e = ws_size(S, L, d=d, f=f, q=params(S, criterion=1, sort_threshold=0))
+    assert rc0 == rc1 == OK and e >= g + 60001 * 8
 
 
 def test_fp32_weights_replace_integer_weights(S, L):

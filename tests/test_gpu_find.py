@@ -210,6 +210,7 @@ def test_entropy_criterion(ctx, C, B, dt, bm):
     wl = W.random_frontier(81 + C, n_rows=90000, d=14, n_classes=C, sizes=EDGE_SIZES, k=5, z=(1, 6),
                            bins=B, sort_threshold=0, layout="r", dtype=dt)
     say(f"[gpu] entropy C={C} B={B} dtype={np.dtype(dt).name} bin_mode={bm}")
+    ctx = S.Context(0)   # a fresh workspace, sized for this call alone
     dev = S.to_device(wl)
     out, H = S.find_splits(ctx, dev, bins=B, sort_threshold=0, hist=True, bin_mode=bm, bin_seed=77,
                            criterion=S.SOF_CRIT_ENTROPY)
