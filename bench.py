@@ -482,6 +482,9 @@ def main():
     ap.add_argument("--workload", default="c3a", choices=sorted(WORKLOADS))
     ap.add_argument("--threshold", type=int, default=None,
                     help="sort/histogram switch T (default: the autotuner's choice)")
+    ap.add_argument("--bins-switch", type=int, default=None,
+                    help="config 3: nodes below this size take half the bins (default: the autotuner's "
+                         "rule; 0 = full bins everywhere)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--plain", type=int, default=2,
                     help="steps of the per-node-launch form (0 skips it)")
@@ -529,13 +532,24 @@ def main():
 
     T = args.threshold
     tune = None
-    if wl.meta.get("criterion", 0):
-        T = 0   # the entropy criterion runs on the histogram path
-    if T is None:
+    per_node_bins = args.workload.startswith("c3")   # config 3: 128-256 bins per node
+    if T is None or (per_node_bins and args.bins_switch is None):
         tune = S.autotune(ctx, wl.n_classes, int(wl.meta.get("k", 64)), int(wl.meta.get("z", 3)), wl.bins,
                           dtype=wl.X.dtype)
-        T = int(tune["sort_threshold"])
+        if T is None:
+            T = int(tune["sort_threshold"])
+    if wl.meta.get("criterion", 0):
+        T = 0   # the entropy criterion runs on the histogram path
     log(f"[bench] sort threshold T={T}" + (f" (autotuned in {tune['ms']:.1f} ms)" if tune else ""))
+    bins_small, bins_switch = wl.bins, 0
+    if per_node_bins:
+        bins_small = tune["bins_small"] if tune else max(wl.bins // 2, 2)
+        bins_switch = args.bins_switch if args.bins_switch is not None else tune["bins_switch"]
+        if bins_switch > 0:
+            n_v = np.diff(wl.node_offsets.astype(np.int64))
+            wl.node_bins = np.where(n_v < bins_switch, bins_small, wl.bins).astype(np.int32)
+            dev.node_bins = torch.from_numpy(wl.node_bins).to(dev_name)
+        log(f"[bench] bins: {bins_small} below n={bins_switch}, else {wl.bins}")
 
     stream = torch.cuda.current_stream()
     out = torch.empty((max(wl.n_nodes, 1), 10), dtype=torch.int32, device=dev_name)
@@ -598,6 +612,8 @@ def main():
         "config": {"workload": args.workload, "description": WORKLOADS[args.workload],
                    "nodes": wl.n_nodes, "samples": int(wl.n_samples), "units": int(wl.units),
                    "sort_threshold": T, "bins": wl.bins,
+                   "bins_small": int(bins_small) if bins_switch > 0 else None,
+                   "bins_switch": int(bins_switch),
                    "bin_layout": "random width" if bin_mode else "equal width",
                    "criterion": "entropy" if criterion else "gini",
                    "step": "find_splits + partition"},

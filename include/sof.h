@@ -232,6 +232,7 @@ typedef struct {
     float   hist_us[32];      /* per measured size: histogram-path time per node-projection (us) */
     int32_t sizes[32];
     float   elapsed_ms;       /* wall time of the whole tuning run */
+    float   half_us[32];      /* per measured size: histogram path with bins_small bins (us) */
 } sof_tune;
 
 /* ---------------------------------------------------------------------- */

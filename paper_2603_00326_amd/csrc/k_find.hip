@@ -836,41 +836,94 @@ __device__ void do_small(const FindArgs& A, const PS& P, int v, char* smem) {
 
 constexpr int kMidR = kMidMax / kBlock;   // up to 32 samples per thread
 
-// One mid-node item: projections g*kMidGroup .. of node D.x, by one block.
+// A mid item carries everything its kernel needs to start: the node, its
+// candidate slot base, the projection group, the node's projection count, its
+// sample range and its first projection's index in the call (q0), so the
+// kernel's first load is the item itself.
+struct MidItem {
+    int v, slot, g, k, s0, n, q0;
+};
+
+// Two-phase staging of a projection's nonzeros, so that a caller can overlap
+// the CSR range loads with its own loads: stage_range reads the range of the
+// projection with index q in the call (CSR; nothing for drawn projections),
+// stage_fill stages the nonzeros into the wave's LDS (whole wave) and returns z.
+struct StageRange {
+    int64_t j0, j1;
+};
+__device__ __forceinline__ StageRange stage_range(const ProjCSR& P, int q) {
+    q = q < P.n_proj ? (q < 0 ? 0 : q) : P.n_proj - 1;
+    const int64_t j0 = clamp64(P.nz_offsets[q], 0, P.n_nz);
+    int64_t j1 = clamp64(P.nz_offsets[q + 1], j0, P.n_nz);
+    if (j1 - j0 > SOF_MAX_NNZ) j1 = j0 + SOF_MAX_NNZ;
+    return StageRange{j0, j1};
+}
+__device__ __forceinline__ StageRange stage_range(const ProjHash&, int) { return StageRange{0, 0}; }
+__device__ __forceinline__ int stage_fill(const ProjCSR& P, StageRange r, int, int, int d, int32_t* lf,
+                                          uint32_t* ls) {
+    const int z = (int)(r.j1 - r.j0);
+    const int lane = lane_id();
+    if (lane < z) {
+        const uint32_t f = (uint32_t)P.nz_feature[r.j0 + lane];
+        lf[lane] = f < (uint32_t)d ? (int)f : 0;
+        ls[lane] = csr_weight_bits(P, r.j0 + lane);
+    }
+    wave_sync();
+    return z;
+}
+__device__ __forceinline__ int stage_fill(const ProjHash& P, StageRange, int v, int p, int d, int32_t* lf,
+                                          uint32_t* ls) {
+    return proj_stage(P, v, p, d, lf, ls);
+}
+// index of node-local projection p in the call, given the node's first (q0)
+__device__ __forceinline__ int item_q(const ProjCSR&, int, int q0, int p) { return q0 + p; }
+__device__ __forceinline__ int item_q(const ProjHash& P, int v, int, int p) { return v * P.k + p; }
+
+// One mid-node item: projections g*kMidGroup .. of node m.v, by one block.
 // The node's row ids and labels are loaded once; wave j stages projection j's
 // nonzeros; then for each projection all threads gather its values, the block
 // reduces its range (one barrier) and counts it into that projection's own LDS
 // histogram; finally wave j scans histogram j, so the group's scans run in
 // parallel.  Range slots glo/ghi are indexed by projection, so no slot is
-// rewritten while another wave may still read it.
+// rewritten while another wave may still read it.  The row ids and the CSR
+// ranges are requested together, then the labels and the nonzeros, so the
+// item costs two dependent round trips before its first gather.
 template <typename T, class PS, int R, bool RW, bool ENT>
-__device__ void do_mid_r(const FindArgs& A, const PS& P, int4 D, int g, int64_t s0, int64_t n, char* smem) {
+__device__ void do_mid_r(const FindArgs& A, const PS& P, const MidItem& m, int64_t n, char* smem) {
     BlockShared& S = block_shared(smem);
     const int tid = threadIdx.x, w = tid >> 6, lane = lane_id();
     const int C = A.n_classes, Bm = A.bins;
-    const int v = D.x;
+    const int v = m.v;
+    const int64_t s0 = m.s0;
     const int B = node_bins(A, v);
-    const int p0 = g * kMidGroup;
-    const int np = D.w - p0 < kMidGroup ? D.w - p0 : kMidGroup;
-    if (w < np) {
-        const int z = proj_stage(P, v, p0 + w, A.n_features, S.w[w].lf, S.w[w].ls);
-        if (lane == 0) S.gz[w] = z;
+    const int p0 = m.g * kMidGroup;
+    const int np = m.k - p0 < kMidGroup ? m.k - p0 : kMidGroup;
+    uint32_t rid[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t i = tid + (int64_t)r * kBlock;
+        rid[r] = n > 0 ? (uint32_t)A.sample_idx[s0 + (i < n ? i : n - 1)] : 0u;
     }
-    const int Bs = bins_stride(Bm);
-    for (int j = 0; j < np; ++j) {
-        int32_t* hist = wave_hist(smem, j, Bm, C);
-        for (int e = tid * 4; e < C * Bs; e += kBlock * 4) *(int4*)(hist + e) = make_int4(0, 0, 0, 0);
-    }
+    StageRange sr{0, 0};
+    if (w < np) sr = stage_range(P, item_q(P, v, m.q0, p0 + w));
     uint32_t off[R];
     uint32_t labp[(R + 7) / 8];
 #pragma unroll
     for (int q = 0; q < (R + 7) / 8; ++q) labp[q] = 0;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const int64_t i = tid + (int64_t)r * kBlock;
-        const int row = n > 0 ? row_of(A, s0 + (i < n ? i : n - 1)) : 0;
+        const int row = rid[r] < (uint32_t)A.n_rows ? (int)rid[r] : 0;
         off[r] = (uint32_t)row * (uint32_t)sizeof(T);
         labp[r >> 3] |= (uint32_t)label_of(A, row) << (4 * (r & 7));
+    }
+    if (w < np) {
+        const int z = stage_fill(P, sr, v, p0 + w, A.n_features, S.w[w].lf, S.w[w].ls);
+        if (lane == 0) S.gz[w] = z;
+    }
+    const int Bs = bins_stride(Bm);
+    for (int j = 0; j < np; ++j) {
+        int32_t* hist = wave_hist(smem, j, Bm, C);
+        for (int e = tid * 4; e < C * Bs; e += kBlock * 4) *(int4*)(hist + e) = make_int4(0, 0, 0, 0);
     }
     __syncthreads();
     for (int j = 0; j < np; ++j) {
@@ -894,7 +947,7 @@ __device__ void do_mid_r(const FindArgs& A, const PS& P, int4 D, int g, int64_t 
             RwTable& tab = wave_rw(smem, w, Bm, C);
             const float sc = rw_cell_scale(lo, hi);
             wave_sync();   // this wave's lookups of the previous projection are done
-            rw_build(tab, A.bin_seed, proj_global(P, v, p0 + j), B, lo, hi, sc);
+            rw_build(tab, A.bin_seed, item_q(P, v, m.q0, p0 + j), B, lo, hi, sc);
             const RwBins bn{&tab, lo, sc};
 #pragma unroll
             for (int r = 0; r < R; ++r)
@@ -917,12 +970,12 @@ __device__ void do_mid_r(const FindArgs& A, const PS& P, int4 D, int g, int64_t 
         const float hi = fmaxf(fmaxf(S.ghi[w][0], S.ghi[w][1]), fmaxf(S.ghi[w][2], S.ghi[w][3]));
         const float scale = bin_scale(B, lo, hi);
         LdsHistCM h{wave_hist(smem, w, Bm, C), Bs};
-        write_hist_row(A, proj_global(P, v, p0 + w), h, B);
+        write_hist_row(A, item_q(P, v, m.q0, p0 + w), h, B);
         Cand c = ENT ? scan_hist_entropy(h, B, C, n, lo, scale, A.ws.flnk, A.ws.cap_flnk)
                      : scan_hist_fast(h, B, C, n, lo, scale, S.w[w].pcs);
-        if (RW && c.D != 0) c.thr = rw_boundary(A.bin_seed, proj_global(P, v, p0 + w), B, lo, hi, c.pos);
+        if (RW && c.D != 0) c.thr = rw_boundary(A.bin_seed, item_q(P, v, m.q0, p0 + w), B, lo, hi, c.pos);
         c.proj = p0 + w;
-        if (lane == 0) ((Cand*)A.ws.slots)[D.y + p0 + w] = c;
+        if (lane == 0) ((Cand*)A.ws.slots)[m.slot + p0 + w] = c;
     }
 }
 
@@ -1137,7 +1190,8 @@ __global__ __launch_bounds__(kBlock) void k_plan(FindArgs A, PS P) {
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_expand(FindArgs A) {
+template <class PS>
+__global__ __launch_bounds__(kBlock) void k_expand(FindArgs A, PS P) {
     const FindWs& W = A.ws;
     const int tid = threadIdx.x;
     const int nmid = count_of(A, H_DMID, W.cap_dmid);
@@ -1149,13 +1203,25 @@ __global__ __launch_bounds__(kBlock) void k_expand(FindArgs A) {
             const int e = d - nmid - nsb - nbig;
             const int4 D = W.desc_mid2[e];
             const int ng = (D.w + kMidGroup - 1) / kMidGroup;
+            int64_t s0 = 0, n = 0;
+            if (ng > 0) node_range(A, D.x, s0, n);
+            const int q0 = ng > 0 ? proj_global(P, D.x, 0) : 0;
             for (int g = tid; g < ng; g += kBlock)
-                if (D.z + (int64_t)g < W.cap_imid2) W.items_mid2[D.z + g] = make_int2(e, g);
+                if (D.z + (int64_t)g < W.cap_imid2) {
+                    W.items_mid2[2 * (D.z + g)] = make_int4(D.x, D.y, g, D.w);
+                    W.items_mid2[2 * (D.z + g) + 1] = make_int4((int)s0, (int)n, q0, 0);
+                }
         } else if (d < nmid) {
-            int4 D = W.desc_mid[d];
+            const int4 D = W.desc_mid[d];
             const int ng = (D.w + kMidGroup - 1) / kMidGroup;
+            int64_t s0 = 0, n = 0;
+            if (ng > 0) node_range(A, D.x, s0, n);
+            const int q0 = ng > 0 ? proj_global(P, D.x, 0) : 0;
             for (int g = tid; g < ng; g += kBlock)
-                if (D.z + (int64_t)g < W.cap_imid) W.items_mid[D.z + g] = make_int2(d, g);
+                if (D.z + (int64_t)g < W.cap_imid) {
+                    W.items_mid[2 * (D.z + g)] = make_int4(D.x, D.y, g, D.w);
+                    W.items_mid[2 * (D.z + g) + 1] = make_int4((int)s0, (int)n, q0, 0);
+                }
         } else if (d < nmid + nsb) {
             int e = d - nmid;
             int4 D = W.desc_sb[e];
@@ -1335,27 +1401,26 @@ __global__ __launch_bounds__(kBlock, kLarge ? 1 : 4) void k_mid(FindArgs A, PS P
     BlockShared& S = block_shared(smem);
     const FindWs& W = A.ws;
     const int nm = kLarge ? count_of(A, H_IMID2, W.cap_imid2) : count_of(A, H_IMID, W.cap_imid);
-    const int nmd = kLarge ? count_of(A, H_DMID2, W.cap_dmid2) : count_of(A, H_DMID, W.cap_dmid);
-    const int2* items = kLarge ? W.items_mid2 : W.items_mid;
-    const int4* desc = kLarge ? W.desc_mid2 : W.desc_mid;
+    const int4* items = kLarge ? W.items_mid2 : W.items_mid;
+    const int N = n_nodes_of(A);
     for (;;) {
         int it = block_dequeue(&W.hdr[kLarge ? H_Q_MID2 : H_Q_MID], &S.item);
         if (it >= nm) break;
-        int2 e = items[it];
-        if (e.x < 0 || e.x >= nmd) continue;
-        int4 D = desc[e.x];
-        if (e.y < 0 || e.y * kMidGroup >= D.w) continue;
-        int64_t s0, n;
-        node_range(A, D.x, s0, n);
+        const int4 a = items[2 * it], b = items[2 * it + 1];
+        const MidItem m{a.x, a.y, a.z, a.w, b.x, b.y, b.z};
+        if (m.v < 0 || m.v >= N || m.g < 0 || m.g * kMidGroup >= m.k || m.s0 < 0 || m.n < 0 ||
+            (int64_t)m.s0 + m.n > A.n_samples || m.slot < 0 || (int64_t)m.slot + m.k > W.cap_slots)
+            continue;
+        int64_t n = m.n;
         if (kLarge) {
             if (n > kMidMax) n = kMidMax;   // the plan never queues larger nodes here
-            do_mid_r<T, PS, kMidR, RW, ENT>(A, P, D, e.y, s0, n, smem);
+            do_mid_r<T, PS, kMidR, RW, ENT>(A, P, m, n, smem);
         } else {
             if (n > kMidSplit) n = kMidSplit;   // the plan never queues larger nodes here
             const int nr = (int)((n + kBlock - 1) / kBlock);
-            if (nr <= 4) do_mid_r<T, PS, 4, RW, ENT>(A, P, D, e.y, s0, n, smem);
-            else if (nr <= 8) do_mid_r<T, PS, 8, RW, ENT>(A, P, D, e.y, s0, n, smem);
-            else do_mid_r<T, PS, 16, RW, ENT>(A, P, D, e.y, s0, n, smem);
+            if (nr <= 4) do_mid_r<T, PS, 4, RW, ENT>(A, P, m, n, smem);
+            else if (nr <= 8) do_mid_r<T, PS, 8, RW, ENT>(A, P, m, n, smem);
+            else do_mid_r<T, PS, 16, RW, ENT>(A, P, m, n, smem);
         }
     }
 }
@@ -1642,7 +1707,7 @@ static hipError_t launch_find_t(const FindArgs& a, const PS& p, const LaunchCfg&
     }
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, a.ws.hdr);
     hipLaunchKernelGGL((k_plan<PS>), dim3(grid_plan), dim3(kBlock), 0, s, a, p);
-    hipLaunchKernelGGL(k_expand, dim3(cfg.grid_light), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((k_expand<PS>), dim3(cfg.grid_light), dim3(kBlock), 0, s, a, p);
     mark();
     hipLaunchKernelGGL((k_brange<T, PS>), dim3(cfg.grid_brange), dim3(kBlock), sm, s, a, p);
     mark();

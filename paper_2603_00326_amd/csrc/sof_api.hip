@@ -239,8 +239,8 @@ FindLayout sof::find_layout(int64_t N, int64_t S, int64_t P, int64_t K, int bins
     L.desc_mid2 = o; o = align_up(o + c.cap_dmid2 * sizeof(int4));
     L.desc_sb = o; o = align_up(o + c.cap_dsb * sizeof(int4));
     L.desc_big = o; o = align_up(o + 2 * c.cap_dbig * sizeof(int4));
-    L.items_mid = o; o = align_up(o + c.cap_imid * sizeof(int2));
-    L.items_mid2 = o; o = align_up(o + c.cap_imid2 * sizeof(int2));
+    L.items_mid = o; o = align_up(o + c.cap_imid * 2 * sizeof(int4));
+    L.items_mid2 = o; o = align_up(o + c.cap_imid2 * 2 * sizeof(int4));
     L.items_sb = o; o = align_up(o + c.cap_isb * sizeof(int2));
     L.items_biga = o; o = align_up(o + c.cap_ibiga * sizeof(int2));
     L.items_bigc = o; o = align_up(o + c.cap_ibigc * sizeof(int2));
@@ -263,8 +263,8 @@ void sof::find_bind(const FindLayout& L, void* ws, FindWs* w) {
     w->desc_mid2 = (int4*)(b + L.desc_mid2);
     w->desc_sb = (int4*)(b + L.desc_sb);
     w->desc_big = (int4*)(b + L.desc_big);
-    w->items_mid = (int2*)(b + L.items_mid);
-    w->items_mid2 = (int2*)(b + L.items_mid2);
+    w->items_mid = (int4*)(b + L.items_mid);
+    w->items_mid2 = (int4*)(b + L.items_mid2);
     w->items_sb = (int2*)(b + L.items_sb);
     w->items_biga = (int2*)(b + L.items_biga);
     w->items_bigc = (int2*)(b + L.items_bigc);

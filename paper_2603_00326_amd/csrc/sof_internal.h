@@ -77,8 +77,8 @@ struct FindWs {
     int4* desc_mid2;
     int4* desc_sb;
     int4* desc_big;       // two int4 per big node
-    int2* items_mid;
-    int2* items_mid2;
+    int4* items_mid;      // two int4 per mid item: (node, slot, group, k), (s0, n, q0, 0)
+    int4* items_mid2;
     int2* items_sb;
     int2* items_biga;
     int2* items_bigc;

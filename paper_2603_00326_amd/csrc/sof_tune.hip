@@ -158,7 +158,7 @@ extern "C" int sof_autotune(sof_ctx* ctx, int32_t dtype, int32_t n_classes, int3
         (void)hipEventDestroy(ev0);
         return hip_fail(e, "hipEventCreate");
     }
-    float half_us[32];
+    float* half_us = out->half_us;
     int rc = SOF_OK;
     const int half_bins = bins / 2 >= SOF_MIN_BINS ? bins / 2 : SOF_MIN_BINS;
     for (int i = 0; i < n_sizes && rc == SOF_OK; ++i) {
@@ -201,13 +201,15 @@ extern "C" int sof_autotune(sof_ctx* ctx, int32_t dtype, int32_t n_classes, int3
         else break;
     }
     out->sort_threshold = T;
-    // bins switch: first size where full bins cost at most 10% more than half bins
-    int sw = 0;
-    for (int i = 0; i < n_sizes; ++i)
-        if (out->hist_us[i] <= 1.1f * half_us[i]) {
-            sw = kSizes[i];
-            break;
-        }
+    // bins switch: smallest size from which full bins cost at most 10% more than
+    // half bins at every larger measured size (half bins below it); if the
+    // largest size already fails, every measured size takes half bins
+    int sw = kSizes[n_sizes - 1] + 1;
+    for (int i = n_sizes - 1; i >= 0; --i) {
+        if (out->hist_us[i] <= 1.1f * half_us[i]) sw = kSizes[i];
+        else break;
+    }
+    if (sw == kSizes[0]) sw = 0;
     out->bins_small = half_bins;
     out->bins_switch = sw;
     out->elapsed_ms =

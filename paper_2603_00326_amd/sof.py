@@ -79,7 +79,7 @@ class sof_forest_desc(ctypes.Structure):
 class sof_tune(ctypes.Structure):
     _fields_ = [("sort_threshold", i32), ("bins_small", i32), ("bins_switch", i32), ("n_points", i32),
                 ("sort_us", ctypes.c_float * 32), ("hist_us", ctypes.c_float * 32),
-                ("sizes", i32 * 32), ("elapsed_ms", ctypes.c_float)]
+                ("sizes", i32 * 32), ("elapsed_ms", ctypes.c_float), ("half_us", ctypes.c_float * 32)]
 
 
 SPLIT_DTYPE = np.dtype([
@@ -356,7 +356,8 @@ def autotune(ctx: Context, n_classes: int, k: int, z: int, bins: int = 256, *, d
             "bins_switch": int(t.bins_switch), "ms": float(t.elapsed_ms),
             "sizes": [int(t.sizes[i]) for i in range(n)],
             "sort_us": [round(float(t.sort_us[i]), 5) for i in range(n)],
-            "hist_us": [round(float(t.hist_us[i]), 5) for i in range(n)]}
+            "hist_us": [round(float(t.hist_us[i]), 5) for i in range(n)],
+            "half_us": [round(float(t.half_us[i]), 5) for i in range(n)]}
 
 
 def nodes_to_device(nodes: np.ndarray, device="cuda:0"):

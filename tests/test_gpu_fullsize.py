@@ -25,11 +25,24 @@ def ctx():
     return S.Context(0)
 
 
-def tuned_threshold(ctx, wl):
+def tune(ctx, wl):
     from paper_2603_00326_amd import sof as S
-    t = S.autotune(ctx, wl.n_classes, int(wl.meta.get("k", 64)), int(wl.meta.get("z", 3)), wl.bins,
-                   dtype=wl.X.dtype)
-    return int(t["sort_threshold"])
+    return S.autotune(ctx, wl.n_classes, int(wl.meta.get("k", 64)), int(wl.meta.get("z", 3)), wl.bins,
+                      dtype=wl.X.dtype)
+
+
+def tuned_threshold(ctx, wl):
+    return int(tune(ctx, wl)["sort_threshold"])
+
+
+def tuned_config3(ctx, wl):
+    """The benchmark's configuration of a config-3 frontier: the autotuned
+    switch, and half the bins below the autotuned size (128-256 bins)."""
+    t = tune(ctx, wl)
+    if t["bins_switch"] > 0:
+        n = np.diff(wl.node_offsets.astype(np.int64))
+        wl.node_bins = np.where(n < t["bins_switch"], t["bins_small"], wl.bins).astype(np.int32)
+    return int(t["sort_threshold"]), t
 
 
 def sample_nodes(wl, seed, per_class=10):
@@ -100,10 +113,11 @@ def check_sampled(wl, T, got, out_idx, coff, nodes, tag, bin_mode=0, bin_seed=0,
 @pytest.mark.parametrize("layout", ["a", "b"])
 def test_frontier_4096_lognormal_nodes(ctx, layout):
     wl = W.config3(layout)
-    for T in sorted({tuned_threshold(ctx, wl), 48}):
+    T0, t = tuned_config3(ctx, wl)
+    for T in sorted({T0, 48}):
         nodes = sample_nodes(wl, seed=17)
         say(f"[gpu] full frontier layout={layout} nodes={wl.n_nodes} samples={wl.n_samples} T={T} "
-            f"sampled={len(nodes)}")
+            f"bins {t['bins_small']} below n={t['bins_switch']} sampled={len(nodes)}")
         got, out_idx, coff = run_full(ctx, wl, T)
         check_partition_properties(wl, got, out_idx, coff)
         check_sampled(wl, T, got, out_idx, coff, nodes, f"c3{layout} T={T}")
@@ -144,7 +158,7 @@ def test_root_4096_rows_both_paths(ctx, T):
 
 def test_frontier_4096_nodes_random_width_bins(ctx):
     wl = W.config3("a")
-    T = tuned_threshold(ctx, wl)
+    T, _ = tuned_config3(ctx, wl)
     seed = 20260302
     nodes = sample_nodes(wl, seed=23)
     say(f"[gpu] full frontier random-width bins nodes={wl.n_nodes} samples={wl.n_samples} T={T}")
@@ -155,6 +169,7 @@ def test_frontier_4096_nodes_random_width_bins(ctx):
 
 def test_frontier_4096_nodes_entropy(ctx):
     wl = W.config3("a")
+    tuned_config3(ctx, wl)
     nodes = sample_nodes(wl, seed=29)
     say(f"[gpu] full frontier entropy criterion nodes={wl.n_nodes} samples={wl.n_samples} T=0")
     got, out_idx, coff = run_full(ctx, wl, 0, criterion=1)
