@@ -138,6 +138,10 @@ __device__ __forceinline__ int proj_stage(const ProjHash& P, int v, int p, int d
     return z;
 }
 
+// index of node-local projection p in the call, given the node's first (q0)
+__device__ __forceinline__ int item_q(const ProjCSR&, int, int q0, int p) { return q0 + p; }
+__device__ __forceinline__ int item_q(const ProjHash& P, int v, int, int p) { return v * P.k + p; }
+
 // ---------------------------------------------------------------------------
 // allocation helpers
 
@@ -673,21 +677,35 @@ __device__ __forceinline__ void gather_rows(const FindArgs& A, const int32_t* lf
 
 constexpr int kSmallBatch = 8;
 
-__device__ __forceinline__ void stage_batch(const ProjCSR& P, int v, int p0, int pstep, int k, int d,
-                                            WaveScratch& WS) {
+// The CSR ranges of a batch (lane g < kSmallBatch: projection p0 + pstep g,
+// index q0 + p in the call), requested before the caller's other loads;
+// batch_fill then stages the nonzeros.
+struct BatchRange {
+    int64_t a;
+    int cnt;
+};
+__device__ __forceinline__ BatchRange batch_range(const ProjCSR& P, int q0, int p0, int pstep, int k) {
     const int lane = lane_id();
-    int64_t a = 0;
-    int cnt = 0;
+    BatchRange r{0, 0};
     if (lane < kSmallBatch) {
         const int p = p0 + pstep * lane;
         if (p < k) {
-            const int q = proj_global(P, v, p);
-            a = clamp64(P.nz_offsets[q], 0, P.n_nz);
-            const int64_t b = clamp64(P.nz_offsets[q + 1], a, P.n_nz);
-            cnt = (int)(b - a > SOF_MAX_NNZ ? SOF_MAX_NNZ : b - a);
+            int q = q0 + p;
+            q = q < P.n_proj ? (q < 0 ? 0 : q) : P.n_proj - 1;
+            r.a = clamp64(P.nz_offsets[q], 0, P.n_nz);
+            const int64_t b = clamp64(P.nz_offsets[q + 1], r.a, P.n_nz);
+            r.cnt = (int)(b - r.a > SOF_MAX_NNZ ? SOF_MAX_NNZ : b - r.a);
         }
-        WS.bz[lane] = cnt;
     }
+    return r;
+}
+__device__ __forceinline__ BatchRange batch_range(const ProjHash&, int, int, int, int) { return BatchRange{0, 0}; }
+__device__ __forceinline__ void batch_fill(const ProjCSR& P, BatchRange r, int, int, int, int, int d,
+                                           WaveScratch& WS) {
+    const int lane = lane_id();
+    const int64_t a = r.a;
+    const int cnt = r.cnt;
+    if (lane < kSmallBatch) WS.bz[lane] = cnt;
 #pragma unroll
     for (int i = 0; i < kSmallBatch * SOF_MAX_NNZ / kWave; ++i) {
         const int e = lane + kWave * i;
@@ -702,8 +720,8 @@ __device__ __forceinline__ void stage_batch(const ProjCSR& P, int v, int p0, int
     }
     wave_sync();
 }
-__device__ __forceinline__ void stage_batch(const ProjHash& P, int v, int p0, int pstep, int k, int d,
-                                            WaveScratch& WS) {
+__device__ __forceinline__ void batch_fill(const ProjHash& P, BatchRange, int v, int p0, int pstep, int k, int d,
+                                           WaveScratch& WS) {
     for (int g = 0; g < kSmallBatch; ++g) {
         const int p = p0 + pstep * g;
         int z = 0;
@@ -719,26 +737,37 @@ __device__ __forceinline__ void stage_batch(const ProjHash& P, int v, int p0, in
 constexpr int kSmallR = kSmallMax / kWave;   // up to 8 samples per lane
 
 template <typename T, class PS, int R, bool RW, bool ENT>
-__device__ void do_small_r(const FindArgs& A, const PS& P, int v, int64_t s0, int64_t n, char* smem) {
+__device__ void do_small_r(const FindArgs& A, const PS& P, int v, int64_t s0, int64_t n, int k, int q0,
+                           char* smem) {
     BlockShared& S = block_shared(smem);
     const int w = threadIdx.x >> 6, lane = lane_id();
     const int C = A.n_classes, Bm = A.bins;
-    const int k = proj_count(P, v);
     const int B = node_bins(A, v);
     const bool sortp = n < A.sort_threshold;
     WaveScratch& WS = S.w[w];
     int32_t* hist = wave_hist(smem, w, Bm, C);
 
+    // row ids and the first batch's CSR ranges together, then labels and the
+    // batch's nonzeros
+    uint32_t rid[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t i = lane + (int64_t)r * kWave;
+        rid[r] = n > 0 ? (uint32_t)A.sample_idx[s0 + (i < n ? i : n - 1)] : 0u;
+    }
+    BatchRange br{0, 0};
+    if (w < k) br = batch_range(P, q0, w, kWavesPerBlock, k);
     uint32_t off[R];
     int lab[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int64_t i = lane + (int64_t)r * kWave;
-        const int row = n > 0 ? row_of(A, s0 + (i < n ? i : n - 1)) : 0;
+        const int row = rid[r] < (uint32_t)A.n_rows ? (int)rid[r] : 0;
         off[r] = (uint32_t)row * (uint32_t)sizeof(T);
         const int y = label_of(A, row);
         lab[r] = i < n ? y : -1;
     }
+    if (w < k) batch_fill(P, br, v, w, kWavesPerBlock, k, A.n_features, WS);
     if (lane < 16) WS.pc[lane] = 0;
     wave_sync();
 #pragma unroll
@@ -753,7 +782,7 @@ __device__ void do_small_r(const FindArgs& A, const PS& P, int v, int64_t s0, in
     if (lane == 0) cand_invalid(WS.best);
     wave_sync();
     for (int pb = w; pb < k; pb += kWavesPerBlock * kSmallBatch) {
-      stage_batch(P, v, pb, kWavesPerBlock, k, A.n_features, WS);
+      if (pb != w) batch_fill(P, batch_range(P, q0, pb, kWavesPerBlock, k), v, pb, kWavesPerBlock, k, A.n_features, WS);
       for (int gi = 0; gi < kSmallBatch; ++gi) {
         const int p = pb + kWavesPerBlock * gi;
         if (p >= k) break;
@@ -769,7 +798,7 @@ __device__ void do_small_r(const FindArgs& A, const PS& P, int v, int64_t s0, in
         Cand c;
         if (sortp) {
             c = scan_sort_small(WS, val[0], lab[0], n, C);
-            write_zero_row(A, proj_global(P, v, p));
+            write_zero_row(A, item_q(P, v, q0, p));
         } else {
             const float scale = bin_scale(B, lo, hi);
             const int Bs = bins_stride(Bm);
@@ -778,7 +807,7 @@ __device__ void do_small_r(const FindArgs& A, const PS& P, int v, int64_t s0, in
             if (RW) {
                 RwTable& tab = wave_rw(smem, w, Bm, C);
                 const float sc = rw_cell_scale(lo, hi);
-                rw_build(tab, A.bin_seed, proj_global(P, v, p), B, lo, hi, sc);
+                rw_build(tab, A.bin_seed, item_q(P, v, q0, p), B, lo, hi, sc);
                 const RwBins bn{&tab, lo, sc};
 #pragma unroll
                 for (int r = 0; r < R; ++r)
@@ -790,10 +819,10 @@ __device__ void do_small_r(const FindArgs& A, const PS& P, int v, int64_t s0, in
             }
             wave_sync();
             LdsHistCM h{hist, Bs};
-            write_hist_row(A, proj_global(P, v, p), h, B);
+            write_hist_row(A, item_q(P, v, q0, p), h, B);
             if (ENT) c = scan_hist_entropy(h, B, C, n, lo, scale, A.ws.flnk, A.ws.cap_flnk);
             else c = scan_hist_fast(h, B, C, n, lo, scale, WS.pcs);
-            if (RW && c.D != 0) c.thr = rw_boundary(A.bin_seed, proj_global(P, v, p), B, lo, hi, c.pos);
+            if (RW && c.D != 0) c.thr = rw_boundary(A.bin_seed, item_q(P, v, q0, p), B, lo, hi, c.pos);
             wave_sync();
         }
         c.proj = p;
@@ -819,16 +848,19 @@ __device__ void do_small_r(const FindArgs& A, const PS& P, int v, int64_t s0, in
     }
 }
 
+// item: (node, s0, n | k << 16, q0) as the plan wrote it
 template <typename T, class PS, bool RW, bool ENT>
-__device__ void do_small(const FindArgs& A, const PS& P, int v, char* smem) {
-    int64_t s0, n;
-    node_range(A, v, s0, n);
+__device__ void do_small(const FindArgs& A, const PS& P, int4 it, char* smem) {
+    const int v = it.x;
+    const int64_t s0 = it.y;
+    int64_t n = it.z & 0xffff;
+    const int k = (int)((uint32_t)it.z >> 16), q0 = it.w;
     if (n > kSmallMax) n = kSmallMax;   // the plan never queues larger nodes here
     const int nr = (int)((n + kWave - 1) / kWave);
-    if (nr <= 1) do_small_r<T, PS, 1, RW, ENT>(A, P, v, s0, n, smem);
-    else if (nr <= 2) do_small_r<T, PS, 2, RW, ENT>(A, P, v, s0, n, smem);
-    else if (nr <= 4) do_small_r<T, PS, 4, RW, ENT>(A, P, v, s0, n, smem);
-    else do_small_r<T, PS, kSmallR, RW, ENT>(A, P, v, s0, n, smem);
+    if (nr <= 1) do_small_r<T, PS, 1, RW, ENT>(A, P, v, s0, n, k, q0, smem);
+    else if (nr <= 2) do_small_r<T, PS, 2, RW, ENT>(A, P, v, s0, n, k, q0, smem);
+    else if (nr <= 4) do_small_r<T, PS, 4, RW, ENT>(A, P, v, s0, n, k, q0, smem);
+    else do_small_r<T, PS, kSmallR, RW, ENT>(A, P, v, s0, n, k, q0, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -875,9 +907,6 @@ __device__ __forceinline__ int stage_fill(const ProjHash& P, StageRange, int v, 
                                           uint32_t* ls) {
     return proj_stage(P, v, p, d, lf, ls);
 }
-// index of node-local projection p in the call, given the node's first (q0)
-__device__ __forceinline__ int item_q(const ProjCSR&, int, int q0, int p) { return q0 + p; }
-__device__ __forceinline__ int item_q(const ProjHash& P, int v, int, int p) { return v * P.k + p; }
 
 // One mid-node item: projections g*kMidGroup .. of node m.v, by one block.
 // The node's row ids and labels are loaded once; wave j stages projection j's
@@ -1176,7 +1205,9 @@ __global__ __launch_bounds__(kBlock) void k_plan(FindArgs A, PS P) {
         }
         switch (cat) {
         case CAT_NOSPLIT: write_nosplit(A, v, sortp ? 1 : 0, n); break;
-        case CAT_SMALL: W.small_items[o_small] = v; break;
+        case CAT_SMALL:
+            W.small_items[o_small] = make_int4(v, (int)s0, (int)n | (k << 16), proj_global(P, v, 0));
+            break;
         case CAT_MID: W.desc_mid[o_dmid] = make_int4(v, o_slot, o_imid, k); break;
         case CAT_MID2: W.desc_mid2[o_dmid2] = make_int4(v, o_slot, o_imid2, k); break;
         case CAT_SB: W.desc_sb[o_dsb] = make_int4(v, o_slot, o_isb, k); break;
@@ -1435,8 +1466,10 @@ __global__ __launch_bounds__(kBlock, 4) void k_small(FindArgs A, PS P) {
     for (;;) {
         int it = block_dequeue(&W.hdr[H_Q_SMALL], &S.item);
         if (it >= ns) break;
-        int v = W.small_items[it];
-        if (v >= 0 && v < N) do_small<T, PS, RW, ENT>(A, P, v, smem);
+        const int4 e = W.small_items[it];
+        const int64_t n = e.z & 0xffff;
+        if (e.x >= 0 && e.x < N && e.y >= 0 && (int64_t)e.y + n <= A.n_samples)
+            do_small<T, PS, RW, ENT>(A, P, e, smem);
     }
 }
 

@@ -234,7 +234,7 @@ FindLayout sof::find_layout(int64_t N, int64_t S, int64_t P, int64_t K, int bins
     c.cap_flnk = flnk_entries;
     size_t o = 0;
     L.hdr = o; o = align_up(o + H_COUNT * sizeof(int32_t));
-    L.small_items = o; o = align_up(o + c.cap_small * sizeof(int32_t));
+    L.small_items = o; o = align_up(o + c.cap_small * sizeof(int4));
     L.desc_mid = o; o = align_up(o + c.cap_dmid * sizeof(int4));
     L.desc_mid2 = o; o = align_up(o + c.cap_dmid2 * sizeof(int4));
     L.desc_sb = o; o = align_up(o + c.cap_dsb * sizeof(int4));
@@ -258,7 +258,7 @@ void sof::find_bind(const FindLayout& L, void* ws, FindWs* w) {
     char* b = (char*)ws;
     *w = L.caps;
     w->hdr = (int32_t*)(b + L.hdr);
-    w->small_items = (int32_t*)(b + L.small_items);
+    w->small_items = (int4*)(b + L.small_items);
     w->desc_mid = (int4*)(b + L.desc_mid);
     w->desc_mid2 = (int4*)(b + L.desc_mid2);
     w->desc_sb = (int4*)(b + L.desc_sb);

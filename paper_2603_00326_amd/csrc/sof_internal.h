@@ -72,7 +72,7 @@ struct ProjHash {
 
 struct FindWs {
     int32_t* hdr;
-    int32_t* small_items;
+    int4* small_items;    // per small node: (node, s0, n | k << 16, q0)
     int4* desc_mid;
     int4* desc_mid2;
     int4* desc_sb;
