@@ -175,3 +175,22 @@ def test_frontier_4096_nodes_entropy(ctx):
     got, out_idx, coff = run_full(ctx, wl, 0, criterion=1)
     check_partition_properties(wl, got, out_idx, coff)
     check_sampled(wl, 0, got, out_idx, coff, nodes, "c3a entropy", criterion=1)
+
+
+@pytest.mark.parametrize("criterion", [0, 1])
+def test_root_at_the_maximum_node_size(ctx, criterion):
+    """One root of exactly 2^24 samples, the largest node the exact 128-bit
+    comparisons admit (2^24 + 1 is rejected on the host), FP16 storage,
+    random labels (near-ties everywhere), Gini and entropy (whose class
+    counts here exceed the k ln k table and are computed directly)."""
+    n = 1 << 24
+    wl = W.random_frontier(71, n_rows=n, d=6, n_classes=2, sizes=[n], k=4, z=(1, 3), bins=256,
+                           sort_threshold=0, layout="a", dtype=np.float16)
+    say(f"[gpu] root n=2^24 FP16 criterion={criterion}")
+    got, out_idx, coff = run_full(ctx, wl, 0, criterion=criterion)
+    ref, _ = O.find_splits_w(wl, criterion=criterion)
+    assert_splits_match(got, ref, f"n=2^24 criterion={criterion}")
+    check_partition_properties(wl, got, out_idx, coff)
+    want_idx, want_coff = O.partition(wl.X, wl.node_offsets, wl.sample_idx, wl.proj_offsets, wl.nz_offsets,
+                                      wl.nz_feature, wl.nz_weight, ref, bins=wl.bins)
+    assert np.array_equal(coff, want_coff) and np.array_equal(out_idx, want_idx)
