@@ -51,10 +51,6 @@ __device__ __forceinline__ void prange(const PartArgs& A, int v, int64_t& s0, in
     n = b - a;
 }
 
-__device__ __forceinline__ int prow(const PartArgs& A, int64_t at) {
-    uint32_t r = (uint32_t)A.sample_idx[at];
-    return r < (uint32_t)A.n_rows ? (int)r : 0;
-}
 
 // projection sources (same contracts as in the search)
 __device__ __forceinline__ int pcount(const ProjCSR& P, int v) {
@@ -245,6 +241,13 @@ __device__ void predicates_r(const PartArgs& A, const PS& P, int v, int64_t at, 
     const SplitRec sp = ((const SplitRec*)A.splits)[v];
     const int k = pcount(P, v);
     const bool all_left = sp.proj < 0 || sp.proj >= k;
+    // the row ids are requested before the split's projection is staged
+    uint32_t rid[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t i = tid + (int64_t)r * kBlock;
+        rid[r] = cn > 0 ? (uint32_t)A.sample_idx[at + (i < cn ? i : cn - 1)] : 0u;
+    }
     if (w == 0) {
         int z = all_left ? 0 : pstage(P, v, sp.proj, A.n_features, S.lf, S.ls);
         if (lane_id() == 0) S.z = z;
@@ -259,22 +262,35 @@ __device__ void predicates_r(const PartArgs& A, const PS& P, int v, int64_t at, 
     uint32_t off[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const int64_t i = tid + (int64_t)r * kBlock;
-        const int row = cn > 0 ? prow(A, at + (i < cn ? i : cn - 1)) : 0;
+        const int row = rid[r] < (uint32_t)A.n_rows ? (int)rid[r] : 0;
         off[r] = (uint32_t)row * (uint32_t)sizeof(T);
     }
+    // FB columns per round trip (all loads of a round at valid addresses; a
+    // round's spare slots re-read its first column and are not added); the
+    // adds stay in CSR order
+    constexpr int FB = R <= 8 ? 4 : (R <= 16 ? 2 : 1);
     float val[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) val[r] = 0.f;
-    for (int j = 0; j < z; ++j) {
-        const int f = __builtin_amdgcn_readfirstlane(S.lf[j]);
-        const uint32_t sg = __builtin_amdgcn_readfirstlane(S.ls[j]);
-        const T* col = (const T*)A.x + (int64_t)f * A.ld;
-        float x[R];
+    for (int j = 0; j < z; j += FB) {
+        const int nf = z - j < FB ? z - j : FB;
+        float x[FB][R];
+        uint32_t sg[FB];
 #pragma unroll
-        for (int r = 0; r < R; ++r) x[r] = ldx((const T*)((const char*)col + off[r]), 0);
+        for (int t = 0; t < FB; ++t) {
+            const int jt = t < nf ? j + t : j;
+            const int f = __builtin_amdgcn_readfirstlane(S.lf[jt]);
+            sg[t] = __builtin_amdgcn_readfirstlane(S.ls[jt]);
+            const T* col = (const T*)A.x + (int64_t)f * A.ld;
 #pragma unroll
-        for (int r = 0; r < R; ++r) val[r] = __fadd_rn(val[r], weighted_term(x[r], sg));
+            for (int r = 0; r < R; ++r) x[t][r] = ldx((const T*)((const char*)col + off[r]), 0);
+        }
+#pragma unroll
+        for (int t = 0; t < FB; ++t) {
+            if (t >= nf) break;
+#pragma unroll
+            for (int r = 0; r < R; ++r) val[r] = __fadd_rn(val[r], weighted_term(x[t][r], sg[t]));
+        }
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
