@@ -955,10 +955,51 @@ __device__ void do_mid_r(const FindArgs& A, const PS& P, const MidItem& m, int64
         for (int e = tid * 4; e < C * Bs; e += kBlock * 4) *(int4*)(hist + e) = make_int4(0, 0, 0, 0);
     }
     __syncthreads();
+    // Software pipeline over the group's projections: the first FB columns of
+    // projection j + 1 are requested as soon as projection j's values are
+    // complete, so their latency overlaps j's range barrier and histogram
+    // (block barriers here wait for LDS only).  Adds stay in CSR order.
+    constexpr int FB = R <= 8 ? 4 : (R <= 16 ? 2 : 1);
+    float xa[FB][R];
+    uint32_t sga[FB];
+    int za = 0;
+    auto request = [&](int j) {
+        za = __builtin_amdgcn_readfirstlane(S.gz[j]);
+        if (za > 0) {
+#pragma unroll
+            for (int t = 0; t < FB; ++t) {
+                const int jt = t < za ? t : 0;
+                const int f = __builtin_amdgcn_readfirstlane(S.w[j].lf[jt]);
+                sga[t] = __builtin_amdgcn_readfirstlane(S.w[j].ls[jt]);
+                const T* col = (const T*)A.x + (int64_t)f * A.ld;
+#pragma unroll
+                for (int r = 0; r < R; ++r) xa[t][r] = ldx_off(col, off[r]);
+            }
+        }
+    };
+    if (np > 0) request(0);
     for (int j = 0; j < np; ++j) {
-        const int z = __builtin_amdgcn_readfirstlane(S.gz[j]);
+        const int z = za;
         float val[R];
-        gather_rows<T, R, (R <= 8 ? 4 : (R <= 16 ? 2 : 1))>(A, S.w[j].lf, S.w[j].ls, z, off, val);
+#pragma unroll
+        for (int r = 0; r < R; ++r) val[r] = 0.f;
+#pragma unroll
+        for (int t = 0; t < FB; ++t) {
+            if (t >= z) break;
+#pragma unroll
+            for (int r = 0; r < R; ++r) val[r] = __fadd_rn(val[r], weighted_term(xa[t][r], sga[t]));
+        }
+        for (int c = FB; c < z; ++c) {   // columns beyond the first FB, one round trip each
+            const int f = __builtin_amdgcn_readfirstlane(S.w[j].lf[c]);
+            const uint32_t sg = __builtin_amdgcn_readfirstlane(S.w[j].ls[c]);
+            const T* col = (const T*)A.x + (int64_t)f * A.ld;
+            float x[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) x[r] = ldx_off(col, off[r]);
+#pragma unroll
+            for (int r = 0; r < R; ++r) val[r] = __fadd_rn(val[r], weighted_term(x[r], sg));
+        }
+        if (j + 1 < np) request(j + 1);
         float lo = INFINITY, hi = -INFINITY;
 #pragma unroll
         for (int r = 0; r < R; ++r)
