@@ -7,15 +7,20 @@
  * switch between histograms and sorting; section 4.3 for the data resident on
  * the device and a call that returns the best projection and its split).  For
  * every node of a frontier and each of its sparse projections the library
- *   1. forms the projected value of every active sample, a +/-1 weighted sum
- *      of a few feature columns accumulated in FP32 in CSR order from +0.0f;
- *   2. builds per-class counts over equal-width bins spanning the node's
- *      [min, max] of that projection (histogram path), or sorts the projected
- *      values when the node has fewer than the sort threshold samples;
+ *   1. forms the projected value of every active sample, a weighted sum of a
+ *      few feature columns (+/-1, integer or FP32 weights) accumulated in FP32
+ *      in CSR order from +0.0f;
+ *   2. builds per-class counts over equal-width (or random-width) bins
+ *      spanning the node's [min, max] of that projection (histogram path), or
+ *      sorts the projected values when the node has fewer than the sort
+ *      threshold samples;
  *   3. scans the bin (or sorted-sample) boundaries for the largest Gini
- *      impurity decrease, compared exactly in integers, and keeps the best over
+ *      impurity decrease, compared exactly in integers (or the largest
+ *      information gain, SOF_CRIT_ENTROPY), and keeps the best over
  *      projections (ties: lowest projection, then lowest bin or position);
  * and then stably partitions each node's sample indices between its children.
+ * Forests grow level by level on the device (sof_grow_level), drawing their
+ * projections with a counter-based sampler, and predict (sof_predict).
  *
  * Conventions shared by every call:
  *  - Array pointers inside sof_data / sof_frontier / sof_proj / sof_params and
@@ -339,8 +344,9 @@ int sof_predict(sof_ctx* ctx, const sof_data* data, const sof_tree_node* nodes, 
  * count, projections per node (capped at 64 for timing), nonzeros per
  * projection and bin count.  Picks the sort threshold (the smallest measured
  * size from which the histogram path is never slower) and a bin-count switch
- * for small nodes (below the first size where full bins cost at most 10% more
- * than half bins, half the bins).  Allocates its own device buffers, frees
+ * for small nodes (half the bins below the smallest measured size from which
+ * full bins cost at most 10% more than half bins at every larger size; 0 when
+ * that holds everywhere).  Allocates its own device buffers, frees
  * them, and synchronises `stream`.  Errors: SOF_ERR_INVALID_ARG (NULL, k or
  * nnz out of range), SOF_ERR_UNSUPPORTED (dtype, classes, bins), SOF_ERR_HIP. */
 int sof_autotune(sof_ctx* ctx, int32_t dtype, int32_t n_classes, int32_t k, int32_t nnz, int32_t bins,

@@ -6,8 +6,11 @@
 // Launch sequence on one stream.  Every kernel reads its work counts from
 // device memory, so the sequence is graph-capturable:
 //   k_reset    zero the queue counters
-//   k_plan     classify nodes by path and size, allocate queue entries
-//   k_expand   write the (descriptor, sub-item) entries of every queue
+//   k_plan     classify nodes by path and size, allocate queue entries; a
+//              small node's item carries its sample range, projection count
+//              and first projection index
+//   k_expand   write the items of the per-projection and per-group queues
+//              (a mid item is self-contained, like a small one)
 //   k_brange   big nodes: range of every (projection, chunk); one wave each
 //   k_bmerge   big nodes: range of every projection over its chunks
 //   k_bhist    big nodes: histogram of every (projection, chunk); one wave each
@@ -670,10 +673,11 @@ __device__ __forceinline__ void gather_rows(const FindArgs& A, const int32_t* lf
 
 // ---------------------------------------------------------------------------
 // Small nodes stage the nonzeros of a batch of kSmallBatch projections
-// (p0, p0 + pstep, ...; those >= k get none) into the wave's scratch with one
-// round of loads: lane g reads projection g's CSR range, then every lane
-// fetches two of the batch's 128 (projection, nonzero) slots.  Every index is
-// clamped into its array.
+// (p0, p0 + pstep, ...; those >= k get none) into the wave's scratch in two
+// phases: batch_range (lane g reads projection g's CSR range) and batch_fill
+// (every lane fetches two of the batch's 128 (projection, nonzero) slots), so
+// a caller can issue its own loads between them.  Every index is clamped into
+// its array.
 
 constexpr int kSmallBatch = 8;
 
