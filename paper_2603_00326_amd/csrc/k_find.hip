@@ -1251,7 +1251,10 @@ __global__ __launch_bounds__(kBlock) void k_plan(FindArgs A, PS P) {
         switch (cat) {
         case CAT_NOSPLIT: write_nosplit(A, v, sortp ? 1 : 0, n); break;
         case CAT_SMALL:
-            W.small_items[o_small] = make_int4(v, (int)s0, (int)n | (k << 16), proj_global(P, v, 0));
+            // k <= max_proj_per_node <= 1024 by contract; clamped so the pack stays defined
+            W.small_items[o_small] =
+                make_int4(v, (int)s0, (int)((uint32_t)n | ((uint32_t)(k < 0x7fff ? k : 0x7fff) << 16)),
+                          proj_global(P, v, 0));
             break;
         case CAT_MID: W.desc_mid[o_dmid] = make_int4(v, o_slot, o_imid, k); break;
         case CAT_MID2: W.desc_mid2[o_dmid2] = make_int4(v, o_slot, o_imid2, k); break;
