@@ -537,9 +537,13 @@ struct BlockShared {
     WaveScratch w[kWavesPerBlock];
 };
 
-size_t find_smem_main(int bins, int classes, bool random_bins) {
+// entropy launches: k ln k for k = 0 .. kSmallMax in LDS (small nodes' counts)
+constexpr int kFlnkLds = kSmallMax + 1;
+
+size_t find_smem_main(int bins, int classes, bool random_bins, bool entropy) {
     return sizeof(BlockShared) + (size_t)kWavesPerBlock * bins_stride(bins) * classes * sizeof(int32_t) +
-           (random_bins ? (size_t)kWavesPerBlock * sizeof(RwTable) : 0);
+           (random_bins ? (size_t)kWavesPerBlock * sizeof(RwTable) : 0) +
+           (entropy ? (size_t)kFlnkLds * sizeof(double) : 0);
 }
 
 __device__ __forceinline__ BlockShared& block_shared(char* smem) { return *(BlockShared*)smem; }
@@ -549,6 +553,12 @@ __device__ __forceinline__ int32_t* wave_hist(char* smem, int w, int bins, int C
 // the wave's random-width table (launches with random-width bins only)
 __device__ __forceinline__ RwTable& wave_rw(char* smem, int w, int bins, int C) {
     return ((RwTable*)(smem + sizeof(BlockShared) + (size_t)kWavesPerBlock * bins_stride(bins) * C * sizeof(int32_t)))[w];
+}
+static_assert(sizeof(BlockShared) % 8 == 0 && sizeof(RwTable) % 8 == 0, "the k ln k copy is 8-byte aligned");
+// the block's copy of k ln k, k = 0 .. kSmallMax (entropy launches only)
+__device__ __forceinline__ double* block_flnk(char* smem, int bins, int C, bool rw) {
+    return (double*)(smem + sizeof(BlockShared) + (size_t)kWavesPerBlock * bins_stride(bins) * C * sizeof(int32_t) +
+                     (rw ? (size_t)kWavesPerBlock * sizeof(RwTable) : 0));
 }
 
 // block-wide min/max of per-thread values (all threads call)
@@ -824,7 +834,7 @@ __device__ void do_small_r(const FindArgs& A, const PS& P, int v, int64_t s0, in
             wave_sync();
             LdsHistCM h{hist, Bs};
             write_hist_row(A, item_q(P, v, q0, p), h, B);
-            if (ENT) c = scan_hist_entropy(h, B, C, n, lo, scale, A.ws.flnk, A.ws.cap_flnk);
+            if (ENT) c = scan_hist_entropy(h, B, C, n, lo, scale, block_flnk(smem, Bm, C, RW), kFlnkLds);
             else c = scan_hist_fast(h, B, C, n, lo, scale, WS.pcs);
             if (RW && c.D != 0) c.thr = rw_boundary(A.bin_seed, item_q(P, v, q0, p), B, lo, hi, c.pos);
             wave_sync();
@@ -1511,6 +1521,10 @@ __global__ __launch_bounds__(kBlock, 4) void k_small(FindArgs A, PS P) {
     const FindWs& W = A.ws;
     const int ns = count_of(A, H_SMALL, W.cap_small);
     const int N = n_nodes_of(A);
+    if (ENT) {   // node counts here are at most kSmallMax: the block keeps their k ln k in LDS
+        double* t = block_flnk(smem, A.bins, A.n_classes, RW);
+        for (int i = threadIdx.x; i < kFlnkLds; i += kBlock) t[i] = i < W.cap_flnk ? W.flnk[i] : klnk(i);
+    }   // the first dequeue's barrier publishes it
     for (;;) {
         int it = block_dequeue(&W.hdr[H_Q_SMALL], &S.item);
         if (it >= ns) break;
@@ -1846,7 +1860,7 @@ static hipError_t occ(const void* f, size_t smem, int* out) {
 
 template <bool RW, bool ENT>
 static hipError_t find_occupancy_t(int bins, int classes, int n_cu, LaunchCfg* cfg) {
-    const size_t sm = find_smem_main(bins, classes, RW), ss = find_smem_sort();
+    const size_t sm = find_smem_main(bins, classes, RW, ENT), ss = find_smem_sort();
     int b = 0;
     hipError_t e;
     cfg->n_cu = n_cu;

@@ -144,7 +144,7 @@ hipError_t launch_find_csr(const FindArgs& a, const ProjCSR& p, const LaunchCfg&
                            const hipEvent_t* ev = nullptr);
 hipError_t launch_find_hash(const FindArgs& a, const ProjHash& p, const LaunchCfg& cfg, hipStream_t s,
                             const hipEvent_t* ev = nullptr);
-size_t find_smem_main(int bins, int classes, bool random_bins);
+size_t find_smem_main(int bins, int classes, bool random_bins, bool entropy);
 size_t find_smem_sort();
 // mode: bit 0 random-width bins, bit 1 entropy criterion
 hipError_t find_occupancy(int bins, int classes, int mode, int n_cu, LaunchCfg* cfg);
