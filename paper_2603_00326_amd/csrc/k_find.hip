@@ -331,8 +331,21 @@ __device__ Cand scan_hist_fast(const LdsHistCM& h, int B, int C, int64_t n, floa
 // lowest boundary on ties.  The winner is returned with N = key(E), D = 1, so
 // the exact comparisons between projections order it by E; SL, SR, SP carry
 // the bits of sum f(l_c), sum f(r_c) and sum f(P_c) for the node record.
+// k ln k for the entropy scans: the block's LDS copy of its first nl entries,
+// then the call's table (ng entries), then the function itself -- the same
+// bits from any of the three
+struct Flnk {
+    const double* lds;
+    int64_t nl;
+    const double* glob;
+    int64_t ng;
+};
+__device__ __forceinline__ double flnk_at(const Flnk& t, int64_t k) {
+    return k < t.nl ? t.lds[k] : (k < t.ng ? t.glob[k] : klnk(k));
+}
+
 __device__ Cand scan_hist_entropy(const LdsHistCM& h, int B, int C, int64_t n, float lo, float scale,
-                                  const double* tab, int64_t ntab) {
+                                  const Flnk& tab) {
     const int lane = lane_id();
     const int b0 = lane * 4;
     double FL[4] = {0.0, 0.0, 0.0, 0.0}, FR[4] = {0.0, 0.0, 0.0, 0.0};
@@ -345,13 +358,13 @@ __device__ Cand scan_hist_entropy(const LdsHistCM& h, int B, int C, int64_t n, f
         const uint32_t incl = wave_scan_u(s3);
         const uint32_t ex = incl - s3;
         const uint32_t Pi = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
-        FP = __dadd_rn(FP, klnk_tab(tab, ntab, Pi));
+        FP = __dadd_rn(FP, flnk_at(tab, Pi));
         const uint32_t li[4] = {ex + s0, ex + s1, ex + s2, ex + s3};
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             nLi[i] += li[i];
-            FL[i] = __dadd_rn(FL[i], klnk_tab(tab, ntab, li[i]));
-            FR[i] = __dadd_rn(FR[i], klnk_tab(tab, ntab, Pi - li[i]));
+            FL[i] = __dadd_rn(FL[i], flnk_at(tab, li[i]));
+            FR[i] = __dadd_rn(FR[i], flnk_at(tab, Pi - li[i]));
         }
     }
     double bE = 0.0, bFL = 0.0, bFR = 0.0;
@@ -361,8 +374,8 @@ __device__ Cand scan_hist_entropy(const LdsHistCM& h, int B, int C, int64_t n, f
     for (int i = 0; i < 4; ++i) {
         const int64_t nL = nLi[i], nR = n - (int64_t)nLi[i];
         if (b0 + i < B - 1 && nL >= 1 && nR >= 1) {
-            const double E = __dsub_rn(__dsub_rn(__dadd_rn(FL[i], FR[i]), klnk_tab(tab, ntab, nL)),
-                                       klnk_tab(tab, ntab, nR));
+            const double E = __dsub_rn(__dsub_rn(__dadd_rn(FL[i], FR[i]), flnk_at(tab, nL)),
+                                       flnk_at(tab, nR));
             if (bi < 0 || E > bE) { bE = E; bi = i; bFL = FL[i]; bFR = FR[i]; bnL = nLi[i]; }
         }
     }
@@ -537,8 +550,9 @@ struct BlockShared {
     WaveScratch w[kWavesPerBlock];
 };
 
-// entropy launches: k ln k for k = 0 .. kSmallMax in LDS (small nodes' counts)
-constexpr int kFlnkLds = kSmallMax + 1;
+// entropy launches: k ln k for k = 0 .. 1024 in LDS (every count of a small
+// node, the common counts of a mid node)
+constexpr int kFlnkLds = 1025;
 
 size_t find_smem_main(int bins, int classes, bool random_bins, bool entropy) {
     return sizeof(BlockShared) + (size_t)kWavesPerBlock * bins_stride(bins) * classes * sizeof(int32_t) +
@@ -555,10 +569,15 @@ __device__ __forceinline__ RwTable& wave_rw(char* smem, int w, int bins, int C) 
     return ((RwTable*)(smem + sizeof(BlockShared) + (size_t)kWavesPerBlock * bins_stride(bins) * C * sizeof(int32_t)))[w];
 }
 static_assert(sizeof(BlockShared) % 8 == 0 && sizeof(RwTable) % 8 == 0, "the k ln k copy is 8-byte aligned");
-// the block's copy of k ln k, k = 0 .. kSmallMax (entropy launches only)
+// the block's copy of k ln k, k = 0 .. kFlnkLds - 1 (entropy launches only)
 __device__ __forceinline__ double* block_flnk(char* smem, int bins, int C, bool rw) {
     return (double*)(smem + sizeof(BlockShared) + (size_t)kWavesPerBlock * bins_stride(bins) * C * sizeof(int32_t) +
                      (rw ? (size_t)kWavesPerBlock * sizeof(RwTable) : 0));
+}
+template <bool RW>
+__device__ __forceinline__ void fill_flnk(const FindArgs& A, char* smem) {
+    double* t = block_flnk(smem, A.bins, A.n_classes, RW);
+    for (int i = threadIdx.x; i < kFlnkLds; i += kBlock) t[i] = i < A.ws.cap_flnk ? A.ws.flnk[i] : klnk(i);
 }
 
 // block-wide min/max of per-thread values (all threads call)
@@ -834,7 +853,7 @@ __device__ void do_small_r(const FindArgs& A, const PS& P, int v, int64_t s0, in
             wave_sync();
             LdsHistCM h{hist, Bs};
             write_hist_row(A, item_q(P, v, q0, p), h, B);
-            if (ENT) c = scan_hist_entropy(h, B, C, n, lo, scale, block_flnk(smem, Bm, C, RW), kFlnkLds);
+            if (ENT) c = scan_hist_entropy(h, B, C, n, lo, scale, Flnk{block_flnk(smem, Bm, C, RW), kFlnkLds, nullptr, 0});
             else c = scan_hist_fast(h, B, C, n, lo, scale, WS.pcs);
             if (RW && c.D != 0) c.thr = rw_boundary(A.bin_seed, item_q(P, v, q0, p), B, lo, hi, c.pos);
             wave_sync();
@@ -1055,7 +1074,10 @@ __device__ void do_mid_r(const FindArgs& A, const PS& P, const MidItem& m, int64
         const float scale = bin_scale(B, lo, hi);
         LdsHistCM h{wave_hist(smem, w, Bm, C), Bs};
         write_hist_row(A, item_q(P, v, m.q0, p0 + w), h, B);
-        Cand c = ENT ? scan_hist_entropy(h, B, C, n, lo, scale, A.ws.flnk, A.ws.cap_flnk)
+        // the large instance (counts up to 8192, most above the LDS copy) reads the call's table only
+        Cand c = ENT ? scan_hist_entropy(h, B, C, n, lo, scale,
+                                         R <= 16 ? Flnk{block_flnk(smem, Bm, C, RW), kFlnkLds, A.ws.flnk, A.ws.cap_flnk}
+                                                 : Flnk{nullptr, 0, A.ws.flnk, A.ws.cap_flnk})
                      : scan_hist_fast(h, B, C, n, lo, scale, S.w[w].pcs);
         if (RW && c.D != 0) c.thr = rw_boundary(A.bin_seed, item_q(P, v, m.q0, p0 + w), B, lo, hi, c.pos);
         c.proj = p0 + w;
@@ -1472,7 +1494,7 @@ __global__ __launch_bounds__(kBlock) void k_bscan(FindArgs A, PS P) {
         const float scale = bin_scale(B, r.x, r.y);
         LdsHistCM h{hist, Bs};
         write_hist_row(A, proj_global(P, bd.node, p), h, B);
-        Cand c = ENT ? scan_hist_entropy(h, B, C, n, r.x, scale, A.ws.flnk, A.ws.cap_flnk)
+        Cand c = ENT ? scan_hist_entropy(h, B, C, n, r.x, scale, Flnk{nullptr, 0, A.ws.flnk, A.ws.cap_flnk})
                      : scan_hist_fast(h, B, C, n, r.x, scale, block_shared(smem).w[w].pcs);
         if (RW && c.D != 0) c.thr = rw_boundary(A.bin_seed, proj_global(P, bd.node, p), B, r.x, r.y, c.pos);
         c.proj = p;
@@ -1492,6 +1514,7 @@ __global__ __launch_bounds__(kBlock, kLarge ? 1 : 4) void k_mid(FindArgs A, PS P
     const int nm = kLarge ? count_of(A, H_IMID2, W.cap_imid2) : count_of(A, H_IMID, W.cap_imid);
     const int4* items = kLarge ? W.items_mid2 : W.items_mid;
     const int N = n_nodes_of(A);
+    if (ENT && !kLarge) fill_flnk<RW>(A, smem);   // the first dequeue's barrier publishes it
     for (;;) {
         int it = block_dequeue(&W.hdr[kLarge ? H_Q_MID2 : H_Q_MID], &S.item);
         if (it >= nm) break;
@@ -1521,10 +1544,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_small(FindArgs A, PS P) {
     const FindWs& W = A.ws;
     const int ns = count_of(A, H_SMALL, W.cap_small);
     const int N = n_nodes_of(A);
-    if (ENT) {   // node counts here are at most kSmallMax: the block keeps their k ln k in LDS
-        double* t = block_flnk(smem, A.bins, A.n_classes, RW);
-        for (int i = threadIdx.x; i < kFlnkLds; i += kBlock) t[i] = i < W.cap_flnk ? W.flnk[i] : klnk(i);
-    }   // the first dequeue's barrier publishes it
+    if (ENT) fill_flnk<RW>(A, smem);   // the first dequeue's barrier publishes it
     for (;;) {
         int it = block_dequeue(&W.hdr[H_Q_SMALL], &S.item);
         if (it >= ns) break;

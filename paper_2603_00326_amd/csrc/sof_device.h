@@ -276,11 +276,6 @@ __device__ __forceinline__ double ln_int(int64_t k) {
     return __dadd_rn(__dmul_rn((double)e, 0.69314718055994530942), __dmul_rn(2.0, sum));
 }
 __device__ __forceinline__ double klnk(int64_t k) { return k <= 0 ? 0.0 : __dmul_rn((double)k, ln_int(k)); }
-// f(k) read from a table of f(0), ..., f(n_tab - 1) made by klnk itself (so
-// bit-identical), computed directly above it
-__device__ __forceinline__ double klnk_tab(const double* tab, int64_t n_tab, int64_t k) {
-    return k < n_tab ? tab[k] : klnk(k);
-}
 
 // Order-preserving map of a (non-NaN) double to an unsigned key, and back:
 // an entropy candidate keeps key(E) in N and 1 in D, so the exact (N, D)
