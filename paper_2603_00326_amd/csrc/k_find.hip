@@ -1100,17 +1100,19 @@ __device__ __forceinline__ BigDesc big_desc(const FindArgs& A, int d) {
     return BigDesc{a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
 }
 
-constexpr int kBR = 16;   // samples per lane per step of a chunk loop
+constexpr int kBR = 16;      // samples per lane per step of a range-pass chunk loop
+constexpr int kBRHist = 8;   // ... of a histogram-pass chunk loop (fewer registers, more waves)
 
 // Range (pass 1) or class histogram (pass 2) of projection p over chunk ch
 // of a big node, by one wave.  Pass 2 counts into the wave's LDS histogram.
-// Each step covers kWave * kBR samples; the next step's row ids are loaded
+// Each step covers kWave * kR samples; the next step's row ids are loaded
 // before this step's columns, and slots past the chunk's end repeat its last
 // sample (valid addresses, masked out of the result).
 template <typename T, class PS, bool kHist, class Bn>
 __device__ __forceinline__ void big_chunk(const FindArgs& A, const PS& P, const BigDesc& bd, int p,
                                           int ch, WaveScratch& WS, float& lo, float& hi,
                                           int32_t* hist, const Bn& bin, float* vcw = nullptr) {
+    constexpr int kR = kHist ? kBRHist : kBR;
     const int lane = lane_id();
     const int C = A.n_classes;
     int64_t s0, n;
@@ -1122,38 +1124,38 @@ __device__ __forceinline__ void big_chunk(const FindArgs& A, const PS& P, const 
     hi = -INFINITY;
     if (cn <= 0) return;
     const int32_t* sidx = A.sample_idx + s0 + c0;
-    int nxt[kBR];
+    int nxt[kR];
 #pragma unroll
-    for (int r = 0; r < kBR; ++r) {
+    for (int r = 0; r < kR; ++r) {
         const int i = r * kWave + lane;
         nxt[r] = sidx[i < cn ? i : cn - 1];
     }
-    for (int i0 = 0; i0 < cn; i0 += kWave * kBR) {
-        uint32_t off[kBR];
-        int lab[kBR];
+    for (int i0 = 0; i0 < cn; i0 += kWave * kR) {
+        uint32_t off[kR];
+        int lab[kR];
 #pragma unroll
-        for (int r = 0; r < kBR; ++r) {
+        for (int r = 0; r < kR; ++r) {
             const int row = (uint32_t)nxt[r] < (uint32_t)A.n_rows ? nxt[r] : 0;
             off[r] = (uint32_t)row * (uint32_t)sizeof(T);
             lab[r] = kHist ? label_of(A, row) : 0;
         }
-        const int i1 = i0 + kWave * kBR;
+        const int i1 = i0 + kWave * kR;
         if (i1 < cn) {
 #pragma unroll
-            for (int r = 0; r < kBR; ++r) {
+            for (int r = 0; r < kR; ++r) {
                 const int i = i1 + r * kWave + lane;
                 nxt[r] = sidx[i < cn ? i : cn - 1];
             }
         }
-        float v[kBR];
-        gather_rows<T, kBR>(A, WS.lf, WS.ls, z, off, v);
+        float v[kR];
+        gather_rows<T, kR>(A, WS.lf, WS.ls, z, off, v);
         if (!kHist && vcw) {
 #pragma unroll
-            for (int r = 0; r < kBR; ++r)
+            for (int r = 0; r < kR; ++r)
                 if (i0 + r * kWave + lane < cn) vcw[i0 + r * kWave + lane] = v[r];
         }
 #pragma unroll
-        for (int r = 0; r < kBR; ++r) {
+        for (int r = 0; r < kR; ++r) {
             if (i0 + r * kWave + lane >= cn) continue;
             if (kHist) {
                 atomicAdd(&hist[bin(v[r]) * C + lab[r]], 1);
@@ -1180,11 +1182,11 @@ __device__ __forceinline__ void big_chunk_cached(const FindArgs& A, const BigDes
     const int cn = (int)clamp64(n - c0, 0, kChunk);
     if (cn <= 0) return;
     const int32_t* sidx = A.sample_idx + s0 + c0;
-    for (int i0 = 0; i0 < cn; i0 += kWave * kBR) {
-        int lab[kBR];
-        float v[kBR];
+    for (int i0 = 0; i0 < cn; i0 += kWave * kBRHist) {
+        int lab[kBRHist];
+        float v[kBRHist];
 #pragma unroll
-        for (int r = 0; r < kBR; ++r) {
+        for (int r = 0; r < kBRHist; ++r) {
             const int i = i0 + r * kWave + lane;
             const int j = i < cn ? i : cn - 1;
             const int row = (uint32_t)sidx[j] < (uint32_t)A.n_rows ? sidx[j] : 0;
@@ -1192,7 +1194,7 @@ __device__ __forceinline__ void big_chunk_cached(const FindArgs& A, const BigDes
             v[r] = vcr[j];
         }
 #pragma unroll
-        for (int r = 0; r < kBR; ++r)
+        for (int r = 0; r < kBRHist; ++r)
             if (i0 + r * kWave + lane < cn) atomicAdd(&hist[bin(v[r]) * C + lab[r]], 1);
     }
 }
