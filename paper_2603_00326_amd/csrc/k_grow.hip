@@ -32,6 +32,7 @@ struct GrowArgs {
     const int32_t* y;
     int32_t n_rows, n_classes, n_trees, k, z, n_features, max_depth, bins;
     int32_t sampler, weights;     // SOF_SAMPLER_*, SOF_WEIGHTS_*
+    int32_t first_tree;           // f_tree / n_tree hold tree ids first_tree .. first_tree + n_trees - 1
     uint64_t seed;
     int32_t* cnt;                 // G_* counters
     const int32_t* f_off;         // current frontier
@@ -39,7 +40,7 @@ struct GrowArgs {
     const int32_t* f_node;
     const int32_t* f_tree;
     const int32_t* f_pos;
-    const int32_t* f_tstart;      // n_trees + 1
+    const int32_t* f_tstart;      // n_trees + 1, indexed by tree id - first_tree
     int32_t* n_off;               // next frontier
     int32_t* n_idx;
     int32_t* n_node;
@@ -328,17 +329,19 @@ __global__ __launch_bounds__(256) void k_gwrite(GrowArgs g) {
 __global__ __launch_bounds__(256) void k_gnext(GrowArgs g) {
     const int N = gN(g);
     const int64_t nn = g.scan_a[N] & 0xffffffffll;
-    if (blockIdx.x == 0 && threadIdx.x <= g.n_trees) {
-        const int t = threadIdx.x;
-        int ts = g.f_tstart[t];
-        ts = ts < 0 ? 0 : (ts > N ? N : ts);
-        g.n_tstart[t] = (int32_t)(g.scan_a[ts] & 0xffffffffll);
-    }
+    if (blockIdx.x == 0)
+        for (int t = threadIdx.x; t <= g.n_trees; t += blockDim.x) {
+            int ts = g.f_tstart[t];
+            ts = ts < 0 ? 0 : (ts > N ? N : ts);
+            g.n_tstart[t] = (int32_t)(g.scan_a[ts] & 0xffffffffll);
+        }
     if (blockIdx.x == 0 && threadIdx.x == 0) g.n_off[nn] = (int32_t)g.scan_b[N];
     // positions: the index of each next node within its tree's run; runs are
     // contiguous and ordered by tree, so pos = j - (first j of that tree)
     for (int64_t j = blockIdx.x * 256 + threadIdx.x; j < nn; j += gridDim.x * 256) {
-        const int t = g.n_tree[j];
+        // local index of the node's tree (tree ids start at first_tree)
+        int t = g.n_tree[j] - g.first_tree;
+        t = t < 0 ? 0 : (t >= g.n_trees ? g.n_trees - 1 : t);
         // first next index of tree t = scan_a low part at the tree's first current node
         int ts = g.f_tstart[t];
         ts = ts < 0 ? 0 : (ts > N ? N : ts);
@@ -451,6 +454,7 @@ static GrowArgs grow_args(sof_forest* f) {
     g.seed = f->desc.seed;
     g.sampler = f->desc.sampler;
     g.weights = f->desc.weights;
+    g.first_tree = f->desc.first_tree;
     g.cnt = f->b.cnt;
     g.f_off = f->b.off[c];
     g.f_idx = f->b.idx[c];

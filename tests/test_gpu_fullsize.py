@@ -1,10 +1,10 @@
 """Parity at the benchmark's full sizes, in the launch configuration the
 benchmark times (one batched call over the whole frontier, the autotuned sort
-threshold, then the partition of every node): sampled nodes of every size
-class against the oracle node by node, and over every node the properties
-that hold at any size (each node's output block is a permutation of its
-samples, split into a left block of the measured size that matches the
-split's left count)."""
+threshold, then the partition of every node): every node's split record and
+the whole partition against the oracle run over the same frontier, plus the
+properties that hold at any size (each node's output block is a permutation
+of its samples, split into a left block of the measured size that matches
+the split's left count)."""
 from __future__ import annotations
 
 import numpy as np
@@ -15,9 +15,6 @@ from paper_2603_00326_amd import workloads as W
 from tests.gpu_helpers import assert_splits_match, say
 
 pytestmark = pytest.mark.gpu
-
-CLASS_EDGES = [(0, 64), (65, 512), (513, 4096), (4097, 8192), (8193, 1 << 30)]
-
 
 @pytest.fixture(scope="module")
 def ctx():
@@ -43,18 +40,6 @@ def tuned_config3(ctx, wl):
         n = np.diff(wl.node_offsets.astype(np.int64))
         wl.node_bins = np.where(n < t["bins_switch"], t["bins_small"], wl.bins).astype(np.int32)
     return int(t["sort_threshold"]), t
-
-
-def sample_nodes(wl, seed, per_class=10):
-    """The three largest nodes plus up to per_class nodes of each size class."""
-    rng = np.random.default_rng(seed)
-    n = np.diff(wl.node_offsets.astype(np.int64))
-    pick = set(np.argsort(n, kind="stable")[-3:].tolist())
-    for lo, hi in CLASS_EDGES:
-        cand = np.nonzero((n >= lo) & (n <= hi))[0]
-        if cand.size:
-            pick.update(rng.choice(cand, size=min(per_class, cand.size), replace=False).tolist())
-    return sorted(int(v) for v in pick)
 
 
 def run_full(ctx, wl, T, bin_mode=0, bin_seed=0, criterion=0):
@@ -88,26 +73,17 @@ def check_partition_properties(wl, got, out_idx, coff):
     assert np.array_equal(wl.sample_idx[a], out_idx[b]), "per-node permutation"
 
 
-def check_sampled(wl, T, got, out_idx, coff, nodes, tag, bin_mode=0, bin_seed=0, criterion=0):
-    sub = W.sub_frontier(wl, nodes)
-    sub.sort_threshold = T
-    if criterion:
-        ref, _ = O.find_splits_w(sub, criterion=criterion)
-    elif bin_mode:
-        # random-width boundaries are keyed by the projection's index in the
-        # call, so the oracle runs on the whole frontier and is sampled after
-        ref_all, _ = O.find_splits_w(wl, sort_threshold=T, bin_mode=bin_mode, bin_seed=bin_seed)
-        ref = ref_all[nodes]
-    else:
-        ref, _ = O.find_splits_w(sub)
-    assert_splits_match(got[nodes], ref, tag)
-    want_idx, want_coff = O.partition(sub.X, sub.node_offsets, sub.sample_idx, sub.proj_offsets,
-                                      sub.nz_offsets, sub.nz_feature, sub.nz_weight, ref, bins=sub.bins,
-                                      node_bins=sub.node_bins)
-    no, so = wl.node_offsets.astype(np.int64), sub.node_offsets.astype(np.int64)
-    for i, v in enumerate(nodes):
-        assert np.array_equal(out_idx[no[v]:no[v + 1]], want_idx[so[i]:so[i + 1]]), f"{tag}: node {v} order"
-        assert coff[2 * v + 1] - no[v] == want_coff[2 * i + 1] - so[i], f"{tag}: node {v} left size"
+def check_all(wl, T, got, out_idx, coff, tag, bin_mode=0, bin_seed=0, criterion=0):
+    """Every node's record and the whole partition against the oracle run
+    over the same frontier."""
+    ref, _ = O.find_splits_w(wl, sort_threshold=T, bin_mode=bin_mode, bin_seed=bin_seed, criterion=criterion)
+    assert_splits_match(got, ref, tag)
+    want_idx, want_coff = O.partition(wl.X, wl.node_offsets, wl.sample_idx, wl.proj_offsets, wl.nz_offsets,
+                                      wl.nz_feature, wl.nz_weight, ref, bins=wl.bins, node_bins=wl.node_bins)
+    bad = np.nonzero(coff != want_coff)[0]
+    assert bad.size == 0, f"{tag}: child offset {bad[0]} differs: {coff[bad[0]]} vs {want_coff[bad[0]]}"
+    bad = np.nonzero(out_idx != want_idx)[0]
+    assert bad.size == 0, f"{tag}: partition differs at position {bad[0]} ({bad.size} positions)"
 
 
 @pytest.mark.parametrize("layout", ["a", "b"])
@@ -115,12 +91,11 @@ def test_frontier_4096_lognormal_nodes(ctx, layout):
     wl = W.config3(layout)
     T0, t = tuned_config3(ctx, wl)
     for T in sorted({T0, 48}):
-        nodes = sample_nodes(wl, seed=17)
         say(f"[gpu] full frontier layout={layout} nodes={wl.n_nodes} samples={wl.n_samples} T={T} "
-            f"bins {t['bins_small']} below n={t['bins_switch']} sampled={len(nodes)}")
+            f"bins {t['bins_small']} below n={t['bins_switch']}")
         got, out_idx, coff = run_full(ctx, wl, T)
         check_partition_properties(wl, got, out_idx, coff)
-        check_sampled(wl, T, got, out_idx, coff, nodes, f"c3{layout} T={T}")
+        check_all(wl, T, got, out_idx, coff, f"c3{layout} T={T}")
 
 
 def test_root_1m_rows_256_projections(ctx):
@@ -129,7 +104,7 @@ def test_root_1m_rows_256_projections(ctx):
     say(f"[gpu] root n={wl.n_samples} k={wl.n_proj} T={T}")
     got, out_idx, coff = run_full(ctx, wl, T)
     check_partition_properties(wl, got, out_idx, coff)
-    check_sampled(wl, T, got, out_idx, coff, [0], "c2")
+    check_all(wl, T, got, out_idx, coff, "c2")
 
 
 def test_root_10m_rows_fp16_equals_fp32_and_oracle(ctx):
@@ -138,7 +113,7 @@ def test_root_10m_rows_fp16_equals_fp32_and_oracle(ctx):
     say(f"[gpu] root n={w16.n_samples} FP16 T={T}")
     g16, i16, c16 = run_full(ctx, w16, T)
     check_partition_properties(w16, g16, i16, c16)
-    check_sampled(w16, T, g16, i16, c16, [0], "c5 fp16")
+    check_all(w16, T, g16, i16, c16, "c5 fp16")
     del w16
     w32 = W.config5(fp16=False)
     say(f"[gpu] root n={w32.n_samples} FP32 T={T}")
@@ -153,28 +128,26 @@ def test_root_4096_rows_both_paths(ctx, T):
     say(f"[gpu] root n={wl.n_samples} T={T}")
     got, out_idx, coff = run_full(ctx, wl, T)
     check_partition_properties(wl, got, out_idx, coff)
-    check_sampled(wl, T, got, out_idx, coff, [0], f"c1 T={T}")
+    check_all(wl, T, got, out_idx, coff, f"c1 T={T}")
 
 
 def test_frontier_4096_nodes_random_width_bins(ctx):
     wl = W.config3("a")
     T, _ = tuned_config3(ctx, wl)
     seed = 20260302
-    nodes = sample_nodes(wl, seed=23)
     say(f"[gpu] full frontier random-width bins nodes={wl.n_nodes} samples={wl.n_samples} T={T}")
     got, out_idx, coff = run_full(ctx, wl, T, bin_mode=1, bin_seed=seed)
     check_partition_properties(wl, got, out_idx, coff)
-    check_sampled(wl, T, got, out_idx, coff, nodes, "c3a random-width", bin_mode=1, bin_seed=seed)
+    check_all(wl, T, got, out_idx, coff, "c3a random-width", bin_mode=1, bin_seed=seed)
 
 
 def test_frontier_4096_nodes_entropy(ctx):
     wl = W.config3("a")
     tuned_config3(ctx, wl)
-    nodes = sample_nodes(wl, seed=29)
     say(f"[gpu] full frontier entropy criterion nodes={wl.n_nodes} samples={wl.n_samples} T=0")
     got, out_idx, coff = run_full(ctx, wl, 0, criterion=1)
     check_partition_properties(wl, got, out_idx, coff)
-    check_sampled(wl, 0, got, out_idx, coff, nodes, "c3a entropy", criterion=1)
+    check_all(wl, 0, got, out_idx, coff, "c3a entropy", criterion=1)
 
 
 @pytest.mark.parametrize("criterion", [0, 1])

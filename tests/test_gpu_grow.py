@@ -20,11 +20,12 @@ def ctx():
 
 
 def grow_case(ctx, *, seed, d, n, C, trees, k, z, bins, T, max_depth=64, graph=True, dtype=np.float32,
-              stats=False, sampler=0, weights=0):
+              stats=False, sampler=0, weights=0, first_tree=0):
     import torch
     from paper_2603_00326_amd import sof as S
     say(f"[gpu] grow seed={seed} d={d} n={n} C={C} trees={trees} k={k} z={z} B={bins} T={T} "
-        f"max_depth={max_depth} graph={graph} dtype={np.dtype(dtype).name} sampler={sampler} weights={weights}")
+        f"max_depth={max_depth} graph={graph} dtype={np.dtype(dtype).name} sampler={sampler} weights={weights} "
+        f"first_tree={first_tree}")
     rng = np.random.default_rng(seed)
     X = rng.standard_normal((d, n)).astype(np.float32)
     if dtype == np.float16:
@@ -36,11 +37,11 @@ def grow_case(ctx, *, seed, d, n, C, trees, k, z, bins, T, max_depth=64, graph=T
     ri = np.concatenate(roots)
     ref, ref_levels, ref_units = O.grow_forest(X, y, C, ro, ri, k=k, z=z, seed=seed + 7, bins=bins,
                                                sort_threshold=T, max_depth=max_depth, sampler=sampler,
-                                               weights=weights)
+                                               weights=weights, first_tree=first_tree)
     Xd = torch.from_numpy(X.astype(dtype)).to("cuda:0")
     f = S.Forest(ctx, Xd, torch.from_numpy(y).to("cuda:0"), C, ro, torch.from_numpy(ri).to("cuda:0"),
                  k=k, z=z, seed=seed + 7, bins=bins, sort_threshold=T, max_depth=max_depth, sampler=sampler,
-                 weights=weights)
+                 weights=weights, first_tree=first_tree)
     if stats:
         sizes, units = [], []
         while True:
@@ -108,3 +109,71 @@ def test_grow_density_sampler(ctx, weights):
 def test_grow_density_sampler_fp16_no_graph(ctx):
     grow_case(ctx, seed=62, d=24, n=2500, C=2, trees=2, k=6, z=3, bins=256, T=0, graph=False,
               dtype=np.float16, sampler=1, weights=1)
+
+
+def test_grow_tree_ids_from_first_tree(ctx):
+    """Tree ids first_tree .. first_tree + n_trees - 1 key the sampler; the
+    per-tree frontier bookkeeping is indexed by the local tree index."""
+    grow_case(ctx, seed=53, d=12, n=600, C=3, trees=3, k=6, z=2, bins=64, T=40, first_tree=1000)
+
+
+def test_grow_many_trees(ctx):
+    """More trees than a block has threads (257+): every tree's start in the
+    next frontier is written at every level."""
+    grow_case(ctx, seed=54, d=8, n=60, C=2, trees=300, k=3, z=2, bins=32, T=20, first_tree=7)
+
+
+# Roots above 8192 samples, so that the big-node passes (range, value cache,
+# histogram, scan), the larger mid-node instance and the chunked partition all
+# run under drawn projections.
+@pytest.mark.parametrize("sampler,z,dtype", [(0, 3, np.float32), (1, 2, np.float32), (0, 5, np.float16)])
+def test_grow_big_roots(ctx, sampler, z, dtype):
+    grow_case(ctx, seed=55 + z, d=64, n=40000, C=3, trees=2, k=8, z=z, bins=256, T=200, max_depth=8,
+              dtype=dtype, sampler=sampler, weights=sampler)
+
+
+def tree_nodes(nodes, tree):
+    """Nodes of one tree in the forest's order, with their parent/child ids
+    renumbered to positions within that tree."""
+    keep = np.nonzero(nodes["tree"] == tree)[0]
+    pos = np.full(len(nodes), -1, np.int64)
+    pos[keep] = np.arange(keep.size)
+    t = nodes[keep].copy()
+    for f in ("parent", "left", "right"):
+        v = t[f].astype(np.int64)
+        t[f] = np.where(v >= 0, pos[np.clip(v, 0, len(nodes) - 1)], -1)
+    return t
+
+
+def test_full_training_tree0_against_oracle(ctx):
+    """The full-training workload (8 trees from 2M-row bootstrap roots of a
+    2M x 1024 matrix, k = 128 drawn projections of 3 nonzeros, 256 bins,
+    autotuned switch), grown to depth 20 on the GPU; tree 0 against the
+    oracle's growth of that tree alone, record by record."""
+    import torch
+    from paper_2603_00326_amd import sof as S
+    from paper_2603_00326_amd import workloads as W
+    X, y, C, ro, ri = W.config4_data()
+    k, z, bins, seed, depth = 128, 3, 256, 4, 20
+    T = int(S.autotune(ctx, C, k, z, bins, dtype=X.dtype)["sort_threshold"])
+    say(f"[gpu] full training 8 trees x {X.shape[1]} rows, d={X.shape[0]}, k={k}, T={T}, depth {depth}")
+    Xd = torch.from_numpy(X).to("cuda:0")
+    f = S.Forest(ctx, Xd, torch.from_numpy(y).to("cuda:0"), C, ro, torch.from_numpy(ri).to("cuda:0"),
+                 k=k, z=z, seed=seed, bins=bins, sort_threshold=T, max_depth=depth)
+    f.grow(use_graph=True)
+    got = tree_nodes(f.export(), 0)
+    f.close()
+    del Xd
+    torch.cuda.empty_cache()
+    ref, _, _ = O.grow_forest(X, y, C, ro[:2], ri[:int(ro[1])], k=k, z=z, seed=seed, bins=bins,
+                              sort_threshold=T, max_depth=depth)
+    say(f"[gpu] tree 0: {len(got)} GPU nodes, {len(ref)} oracle nodes")
+    assert len(got) == len(ref)
+    for fld in ref.dtype.names:
+        if fld == "gain":
+            g, r = got["gain"], ref["gain"]
+            assert np.all((r == 0) == (g == 0)), "gain zero pattern"
+            assert np.all(np.abs(g - r) <= 1e-6 * np.abs(r)), "gain beyond 1e-6 relative"
+        else:
+            bad = np.nonzero(np.any((got[fld] != ref[fld]).reshape(len(ref), -1), axis=1))[0]
+            assert bad.size == 0, f"field {fld} differs at node {bad[0]}: {got[bad[0]]} vs {ref[bad[0]]}"

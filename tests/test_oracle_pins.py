@@ -127,6 +127,53 @@ def test_splitmix64_published_vectors():
         assert O.hash64(0, int(c)) == int(val, 16)
 
 
+def test_sampler_counter_worked_by_hand():
+    """The sampler's counter, c = ((((tree * 64 + level) * 2^24 + pos) * 2^10
+    + proj) * 2^4 + draw), against integers worked out by hand: one field at
+    a time (each lands at its own bit offset: draw 0, proj 4, pos 14, level
+    38, tree 44), every field at its maximum (2^46 - 1), and a mixed case with
+    a tree above 0 and the sign draw 15."""
+    assert O.counter(0, 0, 0, 0, 15) == 15
+    assert O.counter(0, 0, 0, 1, 0) == 16
+    assert O.counter(0, 0, 1, 0, 0) == 16_384
+    assert O.counter(0, 1, 0, 0, 0) == 274_877_906_944
+    assert O.counter(1, 0, 0, 0, 0) == 17_592_186_044_416
+    assert O.counter(3, 63, 16_777_215, 1023, 15) == 70_368_744_177_663
+    # 133 * 2^38 = 36,558,761,623,552; 1000 * 2^14 = 16,384,000; 17 * 16 = 272
+    assert O.counter(2, 5, 1000, 17, 15) == 36_558_778_007_839
+    # a draw for tree 1 never collides with one of tree 0 at the largest level,
+    # position, projection and draw
+    assert O.counter(1, 0, 0, 0, 0) == O.counter(0, 63, 16_777_215, 1023, 15) + 1
+
+
+def test_project_layout_against_a_plain_loop():
+    """Blocks in node order, each [projection][sample] in frontier sample
+    order, against a plain float32 loop over (node, projection, sample) on a
+    frontier of uneven nodes (one empty) with uneven projection counts."""
+    rng = np.random.default_rng(31)
+    d, n_rows = 7, 50
+    X = rng.standard_normal((d, n_rows)).astype(np.float32)
+    sizes, ks = [5, 0, 3, 9], [2, 3, 1, 4]
+    no = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int32)
+    si = rng.integers(0, n_rows, size=int(no[-1])).astype(np.int32)
+    po = np.concatenate([[0], np.cumsum(ks)]).astype(np.int32)
+    feats, weights = random_projs(rng, int(po[-1]), d, 4)
+    zo = np.concatenate([[0], np.cumsum([len(f) for f in feats])]).astype(np.int32)
+    nf = np.concatenate([np.asarray(f, np.int32) for f in feats])
+    nw = np.concatenate([np.asarray(w, np.int8) for w in weights])
+    want = []
+    for v in range(len(sizes)):
+        for q in range(po[v], po[v + 1]):
+            for i in range(no[v], no[v + 1]):
+                acc = np.float32(0.0)
+                for f, w in zip(feats[q], weights[q]):
+                    acc = np.float32(acc + np.float32(w) * X[f, si[i]])
+                want.append(acc)
+    got = O.project(X, no, si, po, zo, nf, nw)
+    assert got.shape == (sum(n * k for n, k in zip(sizes, ks)),)
+    assert np.array_equal(got.view(np.uint32), np.array(want, np.float32).view(np.uint32))
+
+
 def test_sampler_distinct_sorted_in_range_and_uniform():
     rng_counts = {}
     d, z = 5, 2
