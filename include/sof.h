@@ -79,6 +79,7 @@ extern "C" {
 #define SOF_MAX_NODE_SAMPLES (1 << 24)   /* exact 128-bit comparisons need n <= 2^24 */
 #define SOF_SORT_LIMIT       8192        /* largest node that can take the sort path */
 #define SOF_WORKSPACE_ALIGN  256
+#define SOF_STATIC_SCRATCH_BYTES (64 << 20)  /* per-device scratch of sof_find_splits_noalloc */
 
 /* split kinds */
 #define SOF_SPLIT_HIST  0   /* histogram path, equal-width bins */
@@ -277,6 +278,23 @@ int sof_project(sof_ctx* ctx, const sof_data* data, const sof_frontier* frontier
 int sof_find_splits(sof_ctx* ctx, const sof_data* data, const sof_frontier* frontier,
                     const sof_proj* proj, const sof_params* params, sof_split* out,
                     int32_t* hist_out, void* ws, size_t ws_bytes, void* stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): sof_find_splits
+ * with its workspace in a static per-device array of SOF_STATIC_SCRATCH_BYTES
+ * (64 MiB, allocated with the library's code object on every device it runs
+ * on and held until the process ends; its address is taken by sof_create).
+ * Same arguments, outputs and errors as sof_find_splits, without ws; calls
+ * no hipMalloc, hipFree or allocating routine.  Differences: big nodes
+ * (above 8192 samples) re-gather their columns instead of caching projected
+ * values, SOF_CHECK content checks are skipped, and sizes whose workspace
+ * exceeds the array fail with SOF_ERR_WORKSPACE before any launch.  Every
+ * call on a device uses the same array, so calls that overlap in time on
+ * one device (two streams, two threads) race and must be serialised by the
+ * caller; a call needs no clearing from the previous one. */
+int sof_find_splits_noalloc(sof_ctx* ctx, const sof_data* data, const sof_frontier* frontier,
+                            const sof_proj* proj, const sof_params* params, sof_split* out,
+                            int32_t* hist_out, void* stream);
 
 /* Stable partition (section 4: each node splits its samples between its
  * children): out_idx (same size as sample_idx, must not alias it) receives,

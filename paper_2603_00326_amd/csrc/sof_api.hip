@@ -40,6 +40,41 @@ extern "C" const char* sof_last_error(void) { return g_err.c_str(); }
 extern "C" const char* sof_version(void) { return "sof 0.1 gfx950"; }
 
 // ---------------------------------------------------------------------------
+// static scratch of sof_find_splits_noalloc
+//
+// One array per device, loaded with the code object and held until the
+// process ends.  In host code its name is only a stand-in for the device
+// symbol: the device address comes from hipGetSymbolAddress, taken once per
+// device (sof_create) with that device current, and only that address is
+// passed to kernels.
+
+static __device__ __align__(256) unsigned char scratch[SOF_STATIC_SCRATCH_BYTES];
+
+static std::mutex g_scratch_mu;
+static std::map<int, void*> g_scratch_ptr;   // device -> address of its scratch
+
+static int scratch_address(int device, void** out) {
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    auto it = g_scratch_ptr.find(device);
+    if (it != g_scratch_ptr.end()) {
+        *out = it->second;
+        return SOF_OK;
+    }
+    int prev = 0;
+    hipError_t e = hipGetDevice(&prev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (prev != device && (e = hipSetDevice(device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (prev != device) (void)hipSetDevice(prev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress (static scratch)");
+    if (!ptr) return fail(SOF_ERR_HIP, "hipGetSymbolAddress returned NULL for the static scratch");
+    g_scratch_ptr[device] = ptr;
+    *out = ptr;
+    return SOF_OK;
+}
+
+// ---------------------------------------------------------------------------
 // context
 
 extern "C" int sof_create(int device, sof_ctx** out) {
@@ -56,8 +91,12 @@ extern "C" int sof_create(int device, sof_ctx** out) {
     if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
         return fail(SOF_ERR_UNSUPPORTED, "sof_create: device is %s, this library is built for gfx950",
                     prop.gcnArchName);
+    void* sp = nullptr;
+    int rc = scratch_address(device, &sp);
+    if (rc) return rc;
     sof_ctx* c = new sof_ctx();
     c->device = device;
+    c->scratch = sp;
     c->n_cu = prop.multiProcessorCount;
     c->lds_per_block = (size_t)prop.sharedMemPerBlock;
     const char* chk = getenv("SOF_CHECK");
@@ -207,7 +246,7 @@ static size_t align_up(size_t x) { return (x + SOF_WORKSPACE_ALIGN - 1) & ~(size
 static int64_t mn(int64_t a, int64_t b) { return a < b ? a : b; }
 
 FindLayout sof::find_layout(int64_t N, int64_t S, int64_t P, int64_t K, int bins, int classes,
-                            int64_t flnk_entries) {
+                            int64_t flnk_entries, bool vcache) {
     FindLayout L;
     memset(&L, 0, sizeof(L));
     FindWs& c = L.caps;
@@ -230,7 +269,7 @@ FindLayout sof::find_layout(int64_t N, int64_t S, int64_t P, int64_t K, int bins
     // every big node's n * k values, each node rounded up to whole units; off
     // (0) beyond 2^30 units (a terabyte), where nodes fall back to re-gathering
     c.cap_vcache = nbig > 0 ? (S * K) / kVcUnit + nbig + 1 : 0;
-    if (c.cap_vcache > (int64_t(1) << 30)) c.cap_vcache = 0;
+    if (c.cap_vcache > (int64_t(1) << 30) || !vcache) c.cap_vcache = 0;
     c.cap_flnk = flnk_entries;
     size_t o = 0;
     L.hdr = o; o = align_up(o + H_COUNT * sizeof(int32_t));
@@ -365,6 +404,48 @@ extern "C" int sof_find_splits(sof_ctx* ctx, const sof_data* data, const sof_fro
     ProjCSR p{proj->proj_offsets, proj->nz_offsets, proj->nz_feature, proj->nz_weight, proj->n_proj,
               proj->n_nz, proj->nz_value};
     e = launch_find_csr(a, p, cfg, (hipStream_t)stream, timing_events(ctx));
+    if (e != hipSuccess) return hip_fail(e, "find_splits launch");
+    return SOF_OK;
+}
+
+// The same launch sequence as sof_find_splits, with the workspace in the
+// device's static scratch array instead of a caller buffer: no allocation,
+// no projected-value cache (big nodes re-gather their columns), and no
+// SOF_CHECK content checks (they allocate a flag).  The sequence clears the
+// queue counters itself and overwrites everything else it reads, so stale
+// contents of an earlier call do no harm; calls that overlap on one device
+// share the array and race.
+extern "C" int sof_find_splits_noalloc(sof_ctx* ctx, const sof_data* data, const sof_frontier* fr,
+                                       const sof_proj* proj, const sof_params* params, sof_split* out,
+                                       int32_t* hist_out, void* stream) {
+    if (!ctx) return fail(SOF_ERR_INVALID_ARG, "ctx is NULL");
+    int rc;
+    if ((rc = check_data(data)) || (rc = check_frontier(fr)) || (rc = check_proj(proj, data)) ||
+        (rc = check_params(params)))
+        return rc;
+    if (fr->n_nodes > 0 && !out) return fail(SOF_ERR_INVALID_ARG, "out is NULL");
+    FindLayout L = find_layout(fr->n_nodes, fr->n_samples, proj->n_proj, proj->max_proj_per_node,
+                               params->bins, data->n_classes,
+                               flnk_entries(params->criterion, fr->max_node_samples), false);
+    if (L.total > (size_t)SOF_STATIC_SCRATCH_BYTES)
+        return fail(SOF_ERR_WORKSPACE,
+                    "sof_find_splits_noalloc: these sizes need %zu bytes of scratch, above the static %zu",
+                    L.total, (size_t)SOF_STATIC_SCRATCH_BYTES);
+    if (!ctx->scratch) return fail(SOF_ERR_HIP, "sof_find_splits_noalloc: no static scratch on this device");
+    if (fr->n_nodes == 0) return SOF_OK;
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    LaunchCfg cfg;
+    if ((rc = launch_cfg(ctx, params->bins, data->n_classes,
+                         (params->bin_mode == SOF_BINS_RANDOM ? 1 : 0) | (params->criterion == SOF_CRIT_ENTROPY ? 2 : 0),
+                         &cfg)))
+        return rc;
+    FindArgs a;
+    fill_find_args(data, fr, params, out, hist_out, &a);
+    find_bind(L, ctx->scratch, &a.ws);
+    ProjCSR p{proj->proj_offsets, proj->nz_offsets, proj->nz_feature, proj->nz_weight, proj->n_proj,
+              proj->n_nz, proj->nz_value};
+    e = launch_find_csr(a, p, cfg, (hipStream_t)stream, nullptr);
     if (e != hipSuccess) return hip_fail(e, "find_splits launch");
     return SOF_OK;
 }

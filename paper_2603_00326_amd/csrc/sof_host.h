@@ -22,6 +22,7 @@ struct sof_ctx {
     bool timing = false;                             // benchmark instrumentation
     std::vector<std::array<hipEvent_t, SOF_STAGE_COUNT + 1>> tev;  // one event set per recorded call
     size_t tev_used = 0;
+    void* scratch = nullptr;   // device address of this device's static scratch array
 };
 
 namespace sof {

@@ -120,8 +120,10 @@ struct FindLayout {
     FindWs caps;
 };
 // flnk_entries: size of the entropy criterion's k ln k table (0 for Gini)
+// vcache = false lays out no projected-value cache (big nodes then re-gather
+// their columns in the histogram pass)
 FindLayout find_layout(int64_t n_nodes, int64_t n_samples, int64_t n_proj, int64_t max_k, int bins,
-                       int classes, int64_t flnk_entries = 0);
+                       int classes, int64_t flnk_entries = 0, bool vcache = true);
 // table entries for a call: counts reach the largest node's size; capped at
 // 2^20 (8 MiB), above which f is computed directly
 inline int64_t flnk_entries(int criterion, int64_t max_node_samples) {

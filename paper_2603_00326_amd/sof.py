@@ -36,7 +36,7 @@ EXPORTED = [
     "sof_project", "sof_find_splits", "sof_partition", "sof_forest_create", "sof_forest_destroy",
     "sof_grow_level", "sof_forest_frontier_size", "sof_forest_frontier_stats", "sof_forest_export",
     "sof_autotune", "sof_predict",
-    "sof_timing_enable", "sof_timing_read",
+    "sof_timing_enable", "sof_timing_read", "sof_find_splits_noalloc",
 ]
 
 
@@ -118,6 +118,8 @@ def lib():
         L.sof_find_splits.argtypes = [P, ctypes.POINTER(sof_data), ctypes.POINTER(sof_frontier),
                                       ctypes.POINTER(sof_proj), ctypes.POINTER(sof_params), P, P, P,
                                       ctypes.c_size_t, P]
+        L.sof_find_splits_noalloc.argtypes = [P, ctypes.POINTER(sof_data), ctypes.POINTER(sof_frontier),
+                                              ctypes.POINTER(sof_proj), ctypes.POINTER(sof_params), P, P, P]
         L.sof_partition.argtypes = [P, ctypes.POINTER(sof_data), ctypes.POINTER(sof_frontier),
                                     ctypes.POINTER(sof_proj), ctypes.POINTER(sof_params), P, P, P, P,
                                     ctypes.c_size_t, P]
@@ -297,6 +299,26 @@ def find_splits(ctx: Context, dev: DeviceFrontier, *, bins=256, sort_threshold=0
                         device=dev.node_offsets.device)
     _check(lib().sof_find_splits(ctx.handle, ctypes.byref(d), ctypes.byref(f), ctypes.byref(p),
                                  ctypes.byref(q), _ptr(out), _ptr(H), ws, wsb, _stream(stream)))
+    return out, H
+
+
+def find_splits_noalloc(ctx: Context, dev: DeviceFrontier, *, bins=256, sort_threshold=0, hist=False,
+                        out=None, stream=None, bin_mode=SOF_BINS_EQUAL, bin_seed=0, criterion=SOF_CRIT_GINI):
+    """find_splits through sof_find_splits_noalloc: the library's static
+    per-device scratch instead of a workspace.  Pass preallocated out (and
+    hist) tensors to allocate nothing at all."""
+    import torch
+    d, f, p = dev.structs()
+    q = _params(dev, bins, sort_threshold, bin_mode, bin_seed, criterion)
+    N = dev.n_nodes
+    if out is None:
+        out = torch.empty((max(N, 1), 10), dtype=torch.int32, device=dev.node_offsets.device)
+    H = hist if hist is not False and hist is not True else None
+    if hist is True:
+        H = torch.empty((int(dev.nz_offsets.numel() - 1), bins, dev.n_classes), dtype=torch.int32,
+                        device=dev.node_offsets.device)
+    _check(lib().sof_find_splits_noalloc(ctx.handle, ctypes.byref(d), ctypes.byref(f), ctypes.byref(p),
+                                         ctypes.byref(q), _ptr(out), _ptr(H), _stream(stream)))
     return out, H
 
 
