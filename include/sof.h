@@ -251,7 +251,10 @@ const char* sof_last_error(void);
 
 /* Create a context on HIP device `device`: checks the architecture (gfx950),
  * sizes the persistent launches from the device's compute-unit count and
- * occupancy.  Allocates host memory only.  Errors: SOF_ERR_INVALID_ARG (null
+ * occupancy, creates the two auxiliary streams (default priority) and three
+ * events that the batched search forks its size classes onto, and takes the
+ * device address of the static scratch of sof_find_splits_noalloc.  Allocates
+ * no device memory.  Errors: SOF_ERR_INVALID_ARG (null
  * out), SOF_ERR_HIP, SOF_ERR_UNSUPPORTED (not gfx950). */
 int sof_create(int device, sof_ctx** out);
 int sof_destroy(sof_ctx* ctx);
@@ -385,13 +388,19 @@ enum {
     SOF_STAGE_REDUCE,     /* best projection per node */
     SOF_STAGE_COUNT
 };
-/* While enabled, every sof_find_splits call records HIP events on its own
- * stream between the stages (events are created on first use, so enabling
- * is not for graph capture).  sof_timing_read waits for the recorded events
- * and writes summed milliseconds since the last read: ms[s] for stage s and
- * ms[SOF_STAGE_COUNT] for the whole sequence (ms holds SOF_STAGE_COUNT + 1
- * floats), and the number of calls.  Errors: SOF_ERR_INVALID_ARG for NULL
- * arguments, SOF_ERR_HIP if an event query fails. */
+/* The size classes run concurrently after the plan (the big-node stages on
+ * one auxiliary stream of the context, MID2 then SORT on another, MID then
+ * SMALL on the caller's stream), and REDUCE after all of them.  While timing
+ * is enabled, every sof_find_splits call records HIP events before and after
+ * each stage on the stream that runs it, and around the whole sequence
+ * (events are created on first use, so enabling is not for graph capture).
+ * sof_timing_read waits for the recorded events and writes summed
+ * milliseconds since the last read: ms[s] for stage s (from its start to its
+ * end on its stream, so concurrent stages overlap and their sum exceeds the
+ * whole) and ms[SOF_STAGE_COUNT] for the whole sequence (ms holds
+ * SOF_STAGE_COUNT + 1 floats), and the number of calls.  Errors:
+ * SOF_ERR_INVALID_ARG for NULL arguments, SOF_ERR_HIP if an event query
+ * fails. */
 int sof_timing_enable(sof_ctx* ctx, int enable);
 int sof_timing_read(sof_ctx* ctx, float* ms, int32_t* calls);
 

@@ -3,8 +3,11 @@
 // sorting; section 6 names batching many nodes into one GPU launch as the
 // next step, which is what this launch sequence does).
 //
-// Launch sequence on one stream.  Every kernel reads its work counts from
-// device memory, so the sequence is graph-capturable:
+// Launch sequence.  Every kernel reads its work counts from device memory,
+// so the sequence is graph-capturable.  The plan runs on the caller's stream;
+// then the big-node chain, the large mid nodes with the sort blocks, and the
+// mid and small nodes run on three streams at once (the size classes are
+// independent), and k_reduce runs after they join:
 //   k_reset    zero the queue counters
 //   k_plan     classify nodes by path and size, allocate queue entries; a
 //              small node's item carries its sample range, projection count
@@ -147,16 +150,6 @@ __device__ __forceinline__ int item_q(const ProjHash& P, int v, int, int p) { re
 
 // ---------------------------------------------------------------------------
 // allocation helpers
-
-// Wave-aggregated atomic allocation: returns this lane's base for cnt entries.
-__device__ __forceinline__ int wave_alloc(int32_t* ctr, int cnt) {
-    uint32_t incl = wave_incl_scan((uint32_t)cnt);
-    uint32_t total = __shfl(incl, 63);
-    int base = 0;
-    if (lane_id() == 63 && total) base = atomicAdd(ctr, (int)total);
-    base = __shfl(base, 63);
-    return base + (int)(incl - (uint32_t)cnt);
-}
 
 __device__ __forceinline__ int block_dequeue(int32_t* ctr, int* s_item) {
     __syncthreads();
@@ -1243,21 +1236,19 @@ __global__ __launch_bounds__(kBlock) void k_plan(FindArgs A, PS P) {
         }
         const int nch = (int)((n + kChunk - 1) / kChunk);
         const bool slot_node = cat == CAT_MID || cat == CAT_MID2 || cat == CAT_SB || cat == CAT_BIG;
-        const int o_small = wave_alloc(&W.hdr[H_SMALL], cat == CAT_SMALL);
-        const int o_dmid = wave_alloc(&W.hdr[H_DMID], cat == CAT_MID);
         const int gmid = (k + kMidGroup - 1) / kMidGroup;
-        const int o_imid = wave_alloc(&W.hdr[H_IMID], cat == CAT_MID ? gmid : 0);
-        const int o_dmid2 = wave_alloc(&W.hdr[H_DMID2], cat == CAT_MID2);
-        const int o_imid2 = wave_alloc(&W.hdr[H_IMID2], cat == CAT_MID2 ? gmid : 0);
-        const int o_dsb = wave_alloc(&W.hdr[H_DSB], cat == CAT_SB);
-        const int o_isb = wave_alloc(&W.hdr[H_ISB], cat == CAT_SB ? k : 0);
-        const int o_dbig = wave_alloc(&W.hdr[H_DBIG], cat == CAT_BIG);
-        const int o_ia = wave_alloc(&W.hdr[H_IBIGA], cat == CAT_BIG ? k * nch : 0);
-        const int o_ic = wave_alloc(&W.hdr[H_IBIGC], cat == CAT_BIG ? k : 0);
-        const int o_slot = wave_alloc(&W.hdr[H_SLOTS], slot_node ? k : 0);
-        const int o_bslot = wave_alloc(&W.hdr[H_BIGSLOTS], cat == CAT_BIG ? k : 0);
         const int vunits = cat == CAT_BIG ? (int)((n * (int64_t)k + kVcUnit - 1) / kVcUnit) : 0;
-        const int o_vc = wave_alloc(&W.hdr[H_VCACHE], vunits);
+        const int ctr[13] = {H_SMALL, H_DMID, H_IMID, H_DMID2, H_IMID2, H_DSB, H_ISB,
+                             H_DBIG, H_IBIGA, H_IBIGC, H_SLOTS, H_BIGSLOTS, H_VCACHE};
+        const int cnt[13] = {cat == CAT_SMALL, cat == CAT_MID, cat == CAT_MID ? gmid : 0,
+                             cat == CAT_MID2, cat == CAT_MID2 ? gmid : 0, cat == CAT_SB, cat == CAT_SB ? k : 0,
+                             cat == CAT_BIG, cat == CAT_BIG ? k * nch : 0, cat == CAT_BIG ? k : 0,
+                             slot_node ? k : 0, cat == CAT_BIG ? k : 0, vunits};
+        int ob[13];
+        wave_alloc_n<13>(W.hdr, ctr, cnt, ob);
+        const int o_small = ob[0], o_dmid = ob[1], o_imid = ob[2], o_dmid2 = ob[3], o_imid2 = ob[4];
+        const int o_dsb = ob[5], o_isb = ob[6], o_dbig = ob[7], o_ia = ob[8], o_ic = ob[9];
+        const int o_slot = ob[10], o_bslot = ob[11], o_vc = ob[12];
         bool over = false;
         if (slot_node && o_slot + (int64_t)k > W.cap_slots) over = true;
         if (cat == CAT_SMALL && o_small >= W.cap_small) over = true;
@@ -1303,8 +1294,12 @@ __global__ __launch_bounds__(kBlock) void k_plan(FindArgs A, PS P) {
     }
 }
 
+constexpr int kMaxProj = 1024;   // projections per node (the boundary's limit)
+
 template <class PS>
 __global__ __launch_bounds__(kBlock) void k_expand(FindArgs A, PS P) {
+    __shared__ int zcnt[SOF_MAX_NNZ + 1], zbase[SOF_MAX_NNZ + 1];
+    __shared__ int perm[kMaxProj];
     const FindWs& W = A.ws;
     const int tid = threadIdx.x;
     const int nmid = count_of(A, H_DMID, W.cap_dmid);
@@ -1341,21 +1336,72 @@ __global__ __launch_bounds__(kBlock) void k_expand(FindArgs A, PS P) {
             for (int p = tid; p < D.w; p += kBlock)
                 if (D.z + (int64_t)p < W.cap_isb) W.items_sb[D.z + p] = make_int2(e, p);
         } else {
+            // (projection, chunk) items with the projections ordered by
+            // nonzero count, most first: a round of grid-stride items then
+            // holds items of about equal cost, so the statically assigned
+            // rounds of the big-node kernels stay balanced when the counts
+            // vary.  Item t of the node stands for (p, ch) with
+            // t' = p * nchunk + ch (stored), wherever it sits; the range and
+            // histogram results are indexed by t' and merged order-free, so
+            // the order changes no result.
             int e = d - nmid - nsb;
             BigDesc bd = big_desc(A, e);
-            const int na = bd.k * bd.nchunk;
-            for (int t = tid; t < na; t += kBlock)
-                if (bd.item_a + (int64_t)t < W.cap_ibiga) W.items_biga[bd.item_a + t] = make_int2(e, t);
+            const int k = bd.k < kMaxProj ? bd.k : kMaxProj;
+            const int na = k * bd.nchunk;
+            if (tid <= SOF_MAX_NNZ) zcnt[tid] = 0;
+            __syncthreads();
+            int zr[kMaxProj / kBlock], slot[kMaxProj / kBlock];
+#pragma unroll
+            for (int i = 0; i < kMaxProj / kBlock; ++i) {
+                const int p = tid + i * kBlock;
+                zr[i] = p < k ? proj_nnz(P, bd.node, p, A.n_features) : 0;
+                slot[i] = p < k ? atomicAdd(&zcnt[zr[i]], 1) : 0;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                int b = 0;
+                for (int z = SOF_MAX_NNZ; z >= 0; --z) { zbase[z] = b; b += zcnt[z]; }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < kMaxProj / kBlock; ++i) {
+                const int p = tid + i * kBlock;
+                if (p < k) perm[zbase[zr[i]] + slot[i]] = p;
+            }
+            __syncthreads();
+            for (int t = tid; t < na; t += kBlock) {
+                const int pos = t / bd.nchunk, ch = t - pos * bd.nchunk;
+                if (bd.item_a + (int64_t)t < W.cap_ibiga)
+                    W.items_biga[bd.item_a + t] = make_int2(e, perm[pos] * bd.nchunk + ch);
+            }
             for (int p = tid; p < bd.k; p += kBlock)
                 if (bd.item_c + (int64_t)p < W.cap_ibigc) W.items_bigc[bd.item_c + p] = make_int2(e, p);
+            __syncthreads();   // zcnt and perm are reused by the block's next descriptor
         }
     }
 }
 
-// wave index over the grid and wave count, for kernels that hand one item to
-// each wave
-__device__ __forceinline__ int grid_wave() { return (int)((blockIdx.x * kBlock + threadIdx.x) >> 6); }
-__device__ __forceinline__ int grid_waves() { return (int)(gridDim.x * kWavesPerBlock); }
+// Per-wave items 0 .. n-1.  All but the last kDynRounds rounds of grid-stride
+// items are taken statically (no atomics, no barriers); the rest are claimed
+// dynamically, kWavesPerBlock consecutive items per block claim (one atomic,
+// wave w takes the w-th), so waves whose items cost more (more nonzeros) or
+// that became resident late (the size classes share the GPU) take fewer of
+// the tail.  body(it) runs on whole waves and contains no block barrier.
+constexpr int kDynRounds = 1;
+template <class F>
+__device__ __forceinline__ void for_wave_items(int n, int32_t* ctr, int* s_item, F&& body) {
+    const int w = threadIdx.x >> 6;
+    const int gw = (int)((blockIdx.x * kBlock + threadIdx.x) >> 6);
+    const int nw = (int)(gridDim.x * kWavesPerBlock);
+    const int fixed = n / nw - kDynRounds;
+    for (int r = 0; r < fixed; ++r) body(gw + r * nw);
+    const int base = (fixed > 0 ? fixed : 0) * nw;
+    for (;;) {
+        const int first = base + block_dequeue(ctr, s_item) * kWavesPerBlock;
+        if (first >= n) break;
+        if (first + w < n) body(first + w);
+    }
+}
 
 // big item it -> (descriptor, projection, chunk); false if out of range
 __device__ __forceinline__ bool big_item(const FindArgs& A, int it, int nbig, BigDesc& bd, int& p,
@@ -1377,30 +1423,31 @@ __global__ __launch_bounds__(kBlock) void k_brange(FindArgs A, PS P) {
     const int na = count_of(A, H_IBIGA, W.cap_ibiga);
     const int nbig = count_of(A, H_DBIG, W.cap_dbig);
     WaveScratch& WS = S.w[threadIdx.x >> 6];
-    for (int it = grid_wave(); it < na; it += grid_waves()) {
+    for_wave_items(na, &W.hdr[H_Q_BRANGE], &S.item, [&](int it) {
         BigDesc bd;
         int p, ch;
-        if (!big_item(A, it, nbig, bd, p, ch)) continue;
+        if (!big_item(A, it, nbig, bd, p, ch)) return;
         float lo, hi;
         float* vcw = use_vcache<T>(bd, proj_nnz(P, bd.node, p, A.n_features)) ? vcache_at(A, bd, p, ch) : nullptr;
         big_chunk<T, PS, false>(A, P, bd, p, ch, WS, lo, hi, nullptr, EqualBins{0.f, 0.f, 2}, vcw);
         lo = wave_min(lo);
         hi = wave_max(hi);
-        if (lane_id() == 0) W.crange[it] = make_float2(lo, hi);
-    }
+        if (lane_id() == 0) W.crange[bd.item_a + (int64_t)p * bd.nchunk + ch] = make_float2(lo, hi);
+    });
 }
 
 // range of every (big node, projection): min and max over its chunks
 __global__ __launch_bounds__(kBlock) void k_bmerge(FindArgs A) {
+    __shared__ int s_item;
     const FindWs& W = A.ws;
     const int nc = count_of(A, H_IBIGC, W.cap_ibigc);
     const int nbig = count_of(A, H_DBIG, W.cap_dbig);
-    for (int it = grid_wave(); it < nc; it += grid_waves()) {
+    for_wave_items(nc, &W.hdr[H_Q_BMERGE], &s_item, [&](int it) {
         const int2 e = W.items_bigc[it];
-        if (e.x < 0 || e.x >= nbig) continue;
+        if (e.x < 0 || e.x >= nbig) return;
         const BigDesc bd = big_desc(A, e.x);
         const int p = e.y;
-        if (p < 0 || p >= bd.k) continue;
+        if (p < 0 || p >= bd.k) return;
         float lo = INFINITY, hi = -INFINITY;
         const int64_t base = (int64_t)bd.item_a + (int64_t)p * bd.nchunk;
         for (int ch = lane_id(); ch < bd.nchunk; ch += kWave) {
@@ -1417,7 +1464,7 @@ __global__ __launch_bounds__(kBlock) void k_bmerge(FindArgs A) {
             int32_t* ph = W.phist + (int64_t)(bd.bigslot + p) * A.bins * A.n_classes;
             for (int e = lane_id(); e < A.bins * A.n_classes; e += kWave) ph[e] = 0;
         }
-    }
+    });
 }
 
 template <typename T, class PS, bool RW>
@@ -1431,11 +1478,11 @@ __global__ __launch_bounds__(kBlock) void k_bhist(FindArgs A, PS P) {
     const int C = A.n_classes, Bm = A.bins;
     WaveScratch& WS = S.w[w];
     int32_t* hist = wave_hist(smem, w, Bm, C);
-    for (int it = grid_wave(); it < na; it += grid_waves()) {
+    for_wave_items(na, &W.hdr[H_Q_BHIST], &S.item, [&](int it) {
         BigDesc bd;
         int p, ch;
-        if (!big_item(A, it, nbig, bd, p, ch)) continue;
-        if (bd.bigslot + (int64_t)p >= W.cap_bigslots) continue;
+        if (!big_item(A, it, nbig, bd, p, ch)) return;
+        if (bd.bigslot + (int64_t)p >= W.cap_bigslots) return;
         const int B = node_bins(A, bd.node);
         const float2 r = W.brange[bd.bigslot + p];
         const float scale = bin_scale(B, r.x, r.y);
@@ -1460,7 +1507,7 @@ __global__ __launch_bounds__(kBlock) void k_bhist(FindArgs A, PS P) {
         for (int e = lane; e < B * C; e += kWave)
             if (hist[e]) atomicAdd(&ph[e], hist[e]);
         wave_sync();
-    }
+    });
 }
 
 // Per (big node, projection): the projection's histogram (summed by the
@@ -1474,14 +1521,14 @@ __global__ __launch_bounds__(kBlock) void k_bscan(FindArgs A, PS P) {
     const int w = threadIdx.x >> 6, lane = lane_id();
     const int C = A.n_classes, Bm = A.bins;
     int32_t* hist = wave_hist(smem, w, Bm, C);
-    for (int it = grid_wave(); it < nc; it += grid_waves()) {
+    for_wave_items(nc, &W.hdr[H_Q_BSCAN], &block_shared(smem).item, [&](int it) {
         const int2 e = W.items_bigc[it];
-        if (e.x < 0 || e.x >= nbig) continue;
+        if (e.x < 0 || e.x >= nbig) return;
         const BigDesc bd = big_desc(A, e.x);
         const int p = e.y;
         if (p < 0 || p >= bd.k || bd.bigslot + (int64_t)p >= W.cap_bigslots ||
             bd.slot + (int64_t)p >= W.cap_slots)
-            continue;
+            return;
         const int B = node_bins(A, bd.node);
         int64_t s0, n;
         node_range(A, bd.node, s0, n);
@@ -1502,7 +1549,7 @@ __global__ __launch_bounds__(kBlock) void k_bscan(FindArgs A, PS P) {
         c.proj = p;
         if (lane == 0) ((Cand*)W.slots)[bd.slot + p] = c;
         wave_sync();
-    }
+    });
 }
 
 // kLarge: nodes of kMidSplit+1 .. kMidMax samples (32 per thread); else
@@ -1806,17 +1853,24 @@ __global__ __launch_bounds__(kBlock) void k_flnk(double* tab, int64_t n) {
 }
 
 template <typename T, class PS, bool RW, bool ENT>
-static hipError_t launch_find_t(const FindArgs& a, const PS& p, const LaunchCfg& cfg, hipStream_t s,
+static hipError_t launch_find_t(const FindArgs& a, const PS& p, const LaunchCfg& cfg, const FindStreams& st,
                                 const hipEvent_t* ev) {
     const int Nc = a.n_nodes > 0 ? a.n_nodes : 1;
     int grid_plan = (Nc + kBlock - 1) / kBlock;
     if (grid_plan > 4 * cfg.n_cu) grid_plan = 4 * cfg.n_cu;
     const size_t sm = cfg.smem_main;
-    int st = 0;
-    auto mark = [&]() {
-        if (ev) (void)hipEventRecord(ev[st++], s);
+    const hipStream_t s = st.main;
+    const bool fork = st.aux[0] && st.aux[1];
+    const hipStream_t sb = fork ? st.aux[0] : s;   // big-node chain
+    const hipStream_t sl = fork ? st.aux[1] : s;   // large mid nodes, then sort blocks
+    hipError_t e = hipSuccess;
+    auto rec = [&](int i, hipStream_t q) {
+        if (ev && e == hipSuccess) e = hipEventRecord(ev[i], q);
     };
-    mark();
+    auto beg = [&](int stage, hipStream_t q) { rec(2 * stage, q); };
+    auto end = [&](int stage, hipStream_t q) { rec(2 * stage + 1, q); };
+    rec(2 * SOF_STAGE_COUNT, s);
+    beg(SOF_STAGE_PLAN, s);
     if (ENT && a.ws.cap_flnk > 0) {
         int64_t g = (a.ws.cap_flnk + kBlock - 1) / kBlock;
         if (g > 4 * cfg.n_cu) g = 4 * cfg.n_cu;
@@ -1825,29 +1879,57 @@ static hipError_t launch_find_t(const FindArgs& a, const PS& p, const LaunchCfg&
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, a.ws.hdr);
     hipLaunchKernelGGL((k_plan<PS>), dim3(grid_plan), dim3(kBlock), 0, s, a, p);
     hipLaunchKernelGGL((k_expand<PS>), dim3(cfg.grid_light), dim3(kBlock), 0, s, a, p);
-    mark();
-    hipLaunchKernelGGL((k_brange<T, PS>), dim3(cfg.grid_brange), dim3(kBlock), sm, s, a, p);
-    mark();
-    hipLaunchKernelGGL(k_bmerge, dim3(cfg.grid_light), dim3(kBlock), 0, s, a);
-    mark();
-    hipLaunchKernelGGL((k_bhist<T, PS, RW>), dim3(cfg.grid_bhist), dim3(kBlock), sm, s, a, p);
-    mark();
-    hipLaunchKernelGGL((k_bscan<PS, RW, ENT>), dim3(cfg.grid_bscan), dim3(kBlock), sm, s, a, p);
-    mark();
+    end(SOF_STAGE_PLAN, s);
+    // The size classes are independent of each other: the big-node chain and
+    // the large mid nodes run on the context's streams beside the caller's,
+    // so each kernel's tail overlaps the others' work.
+    if (fork && e == hipSuccess) {
+        e = hipEventRecord(st.fork, s);
+        if (e == hipSuccess) e = hipStreamWaitEvent(sb, st.fork, 0);
+        if (e == hipSuccess) e = hipStreamWaitEvent(sl, st.fork, 0);
+    }
+    if (e != hipSuccess) return e;
+    beg(SOF_STAGE_BIG_RANGE, sb);
+    hipLaunchKernelGGL((k_brange<T, PS>), dim3(cfg.grid_brange), dim3(kBlock), sm, sb, a, p);
+    end(SOF_STAGE_BIG_RANGE, sb);
+    beg(SOF_STAGE_BIG_MERGE, sb);
+    hipLaunchKernelGGL(k_bmerge, dim3(cfg.grid_light), dim3(kBlock), 0, sb, a);
+    end(SOF_STAGE_BIG_MERGE, sb);
+    beg(SOF_STAGE_BIG_HIST, sb);
+    hipLaunchKernelGGL((k_bhist<T, PS, RW>), dim3(cfg.grid_bhist), dim3(kBlock), sm, sb, a, p);
+    end(SOF_STAGE_BIG_HIST, sb);
+    beg(SOF_STAGE_BIG_SCAN, sb);
+    hipLaunchKernelGGL((k_bscan<PS, RW, ENT>), dim3(cfg.grid_bscan), dim3(kBlock), sm, sb, a, p);
+    end(SOF_STAGE_BIG_SCAN, sb);
+    beg(SOF_STAGE_MID2, sl);
+    hipLaunchKernelGGL((k_mid<T, PS, true, RW, ENT>), dim3(cfg.grid_mid2), dim3(kBlock), sm, sl, a, p);
+    end(SOF_STAGE_MID2, sl);
+    beg(SOF_STAGE_SORT, sl);
+    hipLaunchKernelGGL((k_sortblk<T, PS>), dim3(cfg.grid_sort), dim3(kBlock), cfg.smem_sort, sl, a, p);
+    end(SOF_STAGE_SORT, sl);
+    beg(SOF_STAGE_MID, s);
     hipLaunchKernelGGL((k_mid<T, PS, false, RW, ENT>), dim3(cfg.grid_mid), dim3(kBlock), sm, s, a, p);
-    mark();
-    hipLaunchKernelGGL((k_mid<T, PS, true, RW, ENT>), dim3(cfg.grid_mid2), dim3(kBlock), sm, s, a, p);
-    mark();
+    end(SOF_STAGE_MID, s);
+    beg(SOF_STAGE_SMALL, s);
     hipLaunchKernelGGL((k_small<T, PS, RW, ENT>), dim3(cfg.grid_small), dim3(kBlock), sm, s, a, p);
-    mark();
-    hipLaunchKernelGGL((k_sortblk<T, PS>), dim3(cfg.grid_sort), dim3(kBlock), cfg.smem_sort, s, a, p);
-    mark();
+    end(SOF_STAGE_SMALL, s);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (fork && e == hipSuccess) {
+        e = hipEventRecord(st.join[0], sb);
+        if (e == hipSuccess) e = hipEventRecord(st.join[1], sl);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, st.join[0], 0);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, st.join[1], 0);
+    }
+    if (e != hipSuccess) return e;
+    beg(SOF_STAGE_REDUCE, s);
     hipLaunchKernelGGL(k_reduce, dim3(cfg.grid_light), dim3(kBlock), 0, s, a);
-    mark();
+    end(SOF_STAGE_REDUCE, s);
+    rec(2 * SOF_STAGE_COUNT + 1, s);
+    if (e != hipSuccess) return e;
     return hipGetLastError();
 }
 
-hipError_t launch_find_csr(const FindArgs& a, const ProjCSR& p, const LaunchCfg& cfg, hipStream_t s,
+hipError_t launch_find_csr(const FindArgs& a, const ProjCSR& p, const LaunchCfg& cfg, const FindStreams& s,
                            const hipEvent_t* ev) {
     const int mode = (a.bin_mode == SOF_BINS_RANDOM ? 1 : 0) | (a.criterion == SOF_CRIT_ENTROPY ? 2 : 0);
     if (a.dtype == SOF_F16) {
@@ -1866,7 +1948,7 @@ hipError_t launch_find_csr(const FindArgs& a, const ProjCSR& p, const LaunchCfg&
     }
 }
 // forest growth uses equal-width bins
-hipError_t launch_find_hash(const FindArgs& a, const ProjHash& p, const LaunchCfg& cfg, hipStream_t s,
+hipError_t launch_find_hash(const FindArgs& a, const ProjHash& p, const LaunchCfg& cfg, const FindStreams& s,
                             const hipEvent_t* ev) {
     if (a.dtype == SOF_F16) return launch_find_t<_Float16, ProjHash, false, false>(a, p, cfg, s, ev);
     return launch_find_t<float, ProjHash, false, false>(a, p, cfg, s, ev);

@@ -509,7 +509,7 @@ static hipError_t level_launch(sof_forest* f, hipStream_t s) {
     find_bind(f->flay, f->b.ws_find, &a.ws);
     ProjHash ph{f->b.tree[c], f->b.pos[c], f->b.cnt + G_LEVEL, f->desc.seed, f->desc.k, f->desc.z,
                 f->desc.sampler, f->desc.weights};
-    hipError_t e = launch_find_hash(a, ph, f->cfg, s);
+    hipError_t e = launch_find_hash(a, ph, f->cfg, find_streams(f->ctx, s));
     if (e != hipSuccess) return e;
     PartArgs pa;
     memset(&pa, 0, sizeof(pa));
@@ -701,7 +701,10 @@ extern "C" int sof_grow_level(sof_forest* f, int use_graph, void* stream) {
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     hipStream_t s = (hipStream_t)stream;
     if (!use_graph) {
-        e = level_launch(f, s);
+        {
+            std::lock_guard<std::mutex> g(f->ctx->launch_mu);
+            e = level_launch(f, s);
+        }
         if (e != hipSuccess) return hip_fail(e, "grow_level launch");
     } else {
         const int c = f->cur;
@@ -713,8 +716,12 @@ extern "C" int sof_grow_level(sof_forest* f, int use_graph, void* stream) {
             hipGraph_t graph = nullptr;
             e = hipStreamBeginCapture(f->cap_stream, hipStreamCaptureModeThreadLocal);
             if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-            hipError_t le = level_launch(f, f->cap_stream);
-            e = hipStreamEndCapture(f->cap_stream, &graph);
+            hipError_t le;
+            {
+                std::lock_guard<std::mutex> g(f->ctx->launch_mu);
+                le = level_launch(f, f->cap_stream);
+                e = hipStreamEndCapture(f->cap_stream, &graph);
+            }
             if (le != hipSuccess) return hip_fail(le, "grow_level capture");
             if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
             e = hipGraphInstantiate(&f->exec[c], graph, nullptr, nullptr, 0);

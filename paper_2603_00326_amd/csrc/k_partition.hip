@@ -9,9 +9,14 @@
 //
 //   k_pplan     per node: child offsets, tiny/small-node queues or chunk items
 //   k_ptiny     nodes <= 1024 samples: one wave per node, all in registers
-//   k_psmall    nodes <= 8192 samples: one block per node; chunk items of
-//               larger nodes: predicate bits and left counts (first pass)
-//   k_pscatter  chunk items: prefix over the node's earlier chunks, scatter
+//   k_psmall    nodes <= 2048 samples: one block per node, 8 samples per
+//               thread, scattered from registers; chunk items (2048 samples)
+//               of larger nodes: predicate bits and left counts (first pass)
+//   k_pchunkscan  one block: exclusive prefix of the chunk items' left counts
+//   k_pscatter  chunk items: left counts of the node's earlier chunks from
+//               that prefix, scatter
+// Every gather requests all (up to 4) columns of the split's projection in
+// one round trip.
 #include <cstring>
 
 #include "sof_device.h"
@@ -23,8 +28,8 @@ namespace sof {
 
 
 constexpr int kPartTiny = 1024;            // one wave per node up to here
-constexpr int kPartMax = 8192;             // one block per node up to here
-constexpr int kPR = kPartMax / kBlock;     // 32 samples per thread
+constexpr int kPartMax = 2048;             // one block per node up to here; chunk size above
+constexpr int kPR = kPartMax / kBlock;     // 8 samples per thread
 constexpr int kWordsPerChunk = kPartMax / kWave;
 
 enum { P_SMALL = 0, P_ITEMS, P_TINY, P_Q_SMALL = 8, P_Q_A, P_Q_B, P_Q_TINY, P_COUNT = 16 };
@@ -153,18 +158,31 @@ __device__ void ptiny_r(const PartArgs& A, const PS& P, int v, int64_t s0, int n
         const uint32_t row = (uint32_t)raw[r] < (uint32_t)A.n_rows ? (uint32_t)raw[r] : 0u;
         off[r] = row * (uint32_t)sizeof(T);
     }
+    // FB columns per round trip (a round's spare slots re-read its first
+    // column, a valid address, and are not added); adds in CSR order
+    constexpr int FB = R <= 8 ? 4 : 2;
     float val[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) val[r] = 0.f;
-    for (int j = 0; j < z; ++j) {
-        const int f = __builtin_amdgcn_readlane(fj, j);
-        const uint32_t sg = (uint32_t)__builtin_amdgcn_readlane((int)sj, j);
-        const T* col = (const T*)A.x + (int64_t)f * A.ld;
-        float x[R];
+    for (int j = 0; j < z; j += FB) {
+        const int nf = z - j < FB ? z - j : FB;
+        float x[FB][R];
+        uint32_t sg[FB];
 #pragma unroll
-        for (int r = 0; r < R; ++r) x[r] = ldx((const T*)((const char*)col + off[r]), 0);
+        for (int t = 0; t < FB; ++t) {
+            const int jt = t < nf ? j + t : j;
+            const int f = __builtin_amdgcn_readlane(fj, jt);
+            sg[t] = (uint32_t)__builtin_amdgcn_readlane((int)sj, jt);
+            const T* col = (const T*)A.x + (int64_t)f * A.ld;
 #pragma unroll
-        for (int r = 0; r < R; ++r) val[r] = __fadd_rn(val[r], weighted_term(x[r], sg));
+            for (int r = 0; r < R; ++r) x[t][r] = ldx((const T*)((const char*)col + off[r]), 0);
+        }
+#pragma unroll
+        for (int t = 0; t < FB; ++t) {
+            if (t >= nf) break;
+#pragma unroll
+            for (int r = 0; r < R; ++r) val[r] = __fadd_rn(val[r], weighted_term(x[t][r], sg[t]));
+        }
     }
     uint64_t m[R];
     int nl = 0;
@@ -236,13 +254,14 @@ struct PShared {
 // the loads of one column are issued together at valid addresses; their
 // predicate bits are cleared by the i < cn test.
 template <typename T, class PS, int R>
-__device__ void predicates_r(const PartArgs& A, const PS& P, int v, int64_t at, int64_t cn, PShared& S) {
+__device__ void predicates_r(const PartArgs& A, const PS& P, int v, int64_t at, int64_t cn, PShared& S,
+                             uint32_t (&rid)[R]) {
     const int tid = threadIdx.x, w = tid >> 6;
     const SplitRec sp = ((const SplitRec*)A.splits)[v];
     const int k = pcount(P, v);
     const bool all_left = sp.proj < 0 || sp.proj >= k;
-    // the row ids are requested before the split's projection is staged
-    uint32_t rid[R];
+    // the row ids (rid: as stored in sample_idx) are requested before the
+    // split's projection is staged
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int64_t i = tid + (int64_t)r * kBlock;
@@ -309,15 +328,18 @@ __device__ void predicates_r(const PartArgs& A, const PS& P, int v, int64_t at, 
     __syncthreads();
 }
 
+template <typename T, class PS, int R>
+__device__ void predicates_chunk_r(const PartArgs& A, const PS& P, int v, int64_t at, int64_t cn, PShared& S) {
+    uint32_t rid[R];
+    predicates_r<T, PS, R>(A, P, v, at, cn, S, rid);
+}
 template <typename T, class PS>
 __device__ void predicates(const PartArgs& A, const PS& P, int v, int64_t at, int64_t cn, PShared& S) {
     const int nr = (int)((cn + kBlock - 1) / kBlock);
-    if (nr <= 1) predicates_r<T, PS, 1>(A, P, v, at, cn, S);
-    else if (nr <= 2) predicates_r<T, PS, 2>(A, P, v, at, cn, S);
-    else if (nr <= 4) predicates_r<T, PS, 4>(A, P, v, at, cn, S);
-    else if (nr <= 8) predicates_r<T, PS, 8>(A, P, v, at, cn, S);
-    else if (nr <= 16) predicates_r<T, PS, 16>(A, P, v, at, cn, S);
-    else predicates_r<T, PS, kPR>(A, P, v, at, cn, S);
+    if (nr <= 1) predicates_chunk_r<T, PS, 1>(A, P, v, at, cn, S);
+    else if (nr <= 2) predicates_chunk_r<T, PS, 2>(A, P, v, at, cn, S);
+    else if (nr <= 4) predicates_chunk_r<T, PS, 4>(A, P, v, at, cn, S);
+    else predicates_chunk_r<T, PS, kPR>(A, P, v, at, cn, S);
 }
 
 // Exclusive prefix of S.cnt in (row, wave) order; returns the total.
@@ -359,27 +381,75 @@ __device__ void scatter(const PartArgs& A, PShared& S, int64_t at, int64_t cn, i
     }
 }
 
+// A whole node of n <= kPartMax samples by one block: predicate bits, the
+// block's prefix of left counts, then every sample goes from its register
+// straight to its destination.
+template <typename T, class PS, int R>
+__device__ void psmall_node_r(const PartArgs& A, const PS& P, int v, int64_t s0, int64_t n, PShared& S) {
+    uint32_t rid[R];
+    predicates_r<T, PS, R>(A, P, v, s0, n, S, rid);
+    const int nr = (int)((n + kBlock - 1) / kBlock);
+    const int nl = row_prefix(S, nr);
+    const int tid = threadIdx.x, w = tid >> 6, lane = lane_id();
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t i = tid + (int64_t)r * kBlock;
+        if (i >= n) continue;
+        const uint64_t m = S.mask[r][w];
+        const int lpre = S.pre[r][w];
+        const int64_t before = (int64_t)r * kBlock + w * kWave;   // samples before this wave's first
+        const int64_t dst = ((m >> lane) & 1ull) ? s0 + lpre + __popcll(m & below)
+                                                 : s0 + nl + (before - lpre) + __popcll(~m & below);
+        if (dst >= s0 && dst < s0 + n) A.out_idx[dst] = (int32_t)rid[r];
+    }
+    if (tid == 0) A.child_offsets[2 * v + 1] = (int32_t)(s0 + nl);
+}
+template <typename T, class PS>
+__device__ void psmall_node(const PartArgs& A, const PS& P, int v, int64_t s0, int64_t n, PShared& S) {
+    const int nr = (int)((n + kBlock - 1) / kBlock);
+    if (nr <= 4) psmall_node_r<T, PS, 4>(A, P, v, s0, n, S);
+    else psmall_node_r<T, PS, kPR>(A, P, v, s0, n, S);
+}
+
 template <class PS>
 __global__ __launch_bounds__(kBlock) void k_pplan(PartArgs A, PS P) {
     const int N = nodes_of(A);
     if (blockIdx.x == 0 && threadIdx.x == 0)
         A.child_offsets[2 * N] = (int32_t)clampp(A.node_offsets[N], 0, A.n_samples);
-    for (int v = blockIdx.x * kBlock + threadIdx.x; v < N; v += gridDim.x * kBlock) {
-        int64_t s0, n;
-        prange(A, v, s0, n);
-        A.child_offsets[2 * v] = (int32_t)s0;
+    // the grid covers the nodes in whole waves, so every lane reaches the
+    // wave-wide allocation
+    for (int v0 = blockIdx.x * kBlock; v0 < N; v0 += gridDim.x * kBlock) {
+        const int v = v0 + threadIdx.x;
+        const bool act = v < N;
+        int64_t s0 = 0, n = 0;
+        if (act) {
+            prange(A, v, s0, n);
+            A.child_offsets[2 * v] = (int32_t)s0;
+        }
+        const int nch = act && n > kPartMax ? (int)((n + kPartMax - 1) / kPartMax) : 0;
+        const int ctr[3] = {P_TINY, P_SMALL, P_ITEMS};
+        const int cnt[3] = {act && n <= kPartTiny, act && n > kPartTiny && n <= kPartMax, nch};
+        int o[3];
+        wave_alloc_n<3>(A.hdr, ctr, cnt, o);
+        // the chunk items of the wave's large nodes, written by the whole wave
+        const int lane = lane_id();
+        uint64_t big = __ballot(nch > 0);
+        while (big) {
+            const int src = __builtin_ctzll(big);
+            big &= big - 1;
+            const int bv = __builtin_amdgcn_readlane(v, src);
+            const int bn = __builtin_amdgcn_readlane(nch, src);
+            const int bb = __builtin_amdgcn_readlane(o[2], src);
+            for (int c = lane; c < bn; c += kWave)
+                if (bb + (int64_t)c < A.cap_items) A.big_items[bb + c] = make_int4(bv, c, bn, bb);
+        }
+        if (!act) continue;
         if (n <= kPartTiny) {
             // tiny list fills the node-list region from its far end
-            int o = atomicAdd(&A.hdr[P_TINY], 1);
-            A.big_items[A.cap_items + A.n_nodes - 1 - o] = make_int4(v, 0, 0, 0);
+            A.big_items[A.cap_items + A.n_nodes - 1 - o[0]] = make_int4(v, 0, 0, 0);
         } else if (n <= kPartMax) {
-            int o = atomicAdd(&A.hdr[P_SMALL], 1);
-            A.big_items[A.cap_items + o] = make_int4(v, 0, 0, 0);   // small list lives after the items
-        } else {
-            int nch = (int)((n + kPartMax - 1) / kPartMax);
-            int base = atomicAdd(&A.hdr[P_ITEMS], nch);
-            for (int c = 0; c < nch; ++c)
-                if (base + (int64_t)c < A.cap_items) A.big_items[base + c] = make_int4(v, c, nch, base);
+            A.big_items[A.cap_items + o[1]] = make_int4(v, 0, 0, 0);   // small list lives after the items
         }
     }
 }
@@ -402,11 +472,8 @@ __global__ __launch_bounds__(kBlock) void k_psmall(PartArgs A, PS P) {
             if (v < 0 || v >= N) continue;
             int64_t s0, n;
             prange(A, v, s0, n);
-            predicates<T>(A, P, v, s0, n, S);
-            const int nr = (int)((n + kBlock - 1) / kBlock);
-            const int nl = row_prefix(S, nr);
-            scatter(A, S, s0, n, s0, s0 + nl, s0, s0 + n);
-            if (threadIdx.x == 0) A.child_offsets[2 * v + 1] = (int32_t)(s0 + nl);
+            if (n > kPartMax) n = kPartMax;   // the plan never queues larger nodes here
+            psmall_node<T>(A, P, v, s0, n, S);
         } else {
             const int e = it - nsmall;
             const int4 d = A.big_items[e];
@@ -452,20 +519,15 @@ __global__ __launch_bounds__(kBlock) void k_pscatter(PartArgs A) {
         int64_t cn = n - c0;
         cn = cn < 0 ? 0 : (cn > kPartMax ? kPartMax : cn);
         const int tid = threadIdx.x;
-        // left counts of the node's chunks before this one, and in total
-        if (tid < kWave) {
-            int64_t before = 0, total = 0;
-            for (int c = tid; c < d.z; c += kWave) {
-                int64_t item = (int64_t)d.w + c;
-                int l = item < nitems ? A.chunk_left[item] : 0;
-                total += l;
-                if (c < d.y) before += l;
-            }
-            for (int off = 32; off > 0; off >>= 1) {
-                before += __shfl_xor(before, off);
-                total += __shfl_xor(total, off);
-            }
-            if (tid == 0) { s_base[0] = before; s_base[1] = total; }
+        // left counts of the node's chunks before this one, and in total, from
+        // the exclusive prefix over all chunk items (a node's items are
+        // consecutive, from d.w)
+        if (tid == 0) {
+            const int64_t first = clampp(d.w, 0, nitems);
+            const int64_t last = clampp((int64_t)d.w + d.z, first, nitems);
+            const int64_t pf = A.chunk_pre[first];
+            s_base[0] = A.chunk_pre[clampp(e, first, last)] - pf;
+            s_base[1] = A.chunk_pre[last] - pf;
         }
         if (tid < kWordsPerChunk) {
             uint64_t m = A.pred_bits[(int64_t)e * kWordsPerChunk + tid];
@@ -481,6 +543,48 @@ __global__ __launch_bounds__(kBlock) void k_pscatter(PartArgs A) {
     }
 }
 
+// Exclusive prefix of the chunk items' left counts (pre[0 .. nitems], 64-bit),
+// by one block: tiles of kBlock * 4 items, each thread summing 4 consecutive
+// counts, a block scan of the thread sums, and a carry across tiles.
+__global__ __launch_bounds__(kBlock) void k_pchunkscan(PartArgs A) {
+    __shared__ int64_t wsum[kWavesPerBlock];
+    const int nitems = (int)min((int64_t)A.hdr[P_ITEMS], A.cap_items);
+    const int tid = threadIdx.x, w = tid >> 6, lane = lane_id();
+    int64_t carry = 0;
+    for (int t0 = 0; t0 < nitems; t0 += kBlock * 4) {
+        int64_t c[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int e = t0 + tid * 4 + i;
+            c[i] = e < nitems ? (int64_t)A.chunk_left[e] : 0;
+        }
+        const int64_t mine = c[0] + c[1] + c[2] + c[3];
+        int64_t x = mine;
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+            const int64_t y = __shfl_up(x, off);
+            if (lane >= off) x += y;
+        }
+        if (lane == kWave - 1) wsum[w] = x;
+        __syncthreads();
+        int64_t before = carry, tile = 0;
+        for (int j = 0; j < kWavesPerBlock; ++j) {
+            if (j < w) before += wsum[j];
+            tile += wsum[j];
+        }
+        int64_t run = before + x - mine;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int e = t0 + tid * 4 + i;
+            if (e < nitems) A.chunk_pre[e] = run;
+            run += c[i];
+        }
+        carry += tile;
+        __syncthreads();
+    }
+    if (tid == 0) A.chunk_pre[nitems] = carry;
+}
+
 __global__ void k_preset(int32_t* hdr) {
     for (int i = threadIdx.x; i < P_COUNT; i += blockDim.x) hdr[i] = 0;
 }
@@ -494,6 +598,7 @@ hipError_t launch_part_t(const PartArgs& a, const PS& p, int n_cu, hipStream_t s
     hipLaunchKernelGGL((k_pplan<PS>), dim3(grid_plan), dim3(kBlock), 0, s, a, p);
     hipLaunchKernelGGL((k_ptiny<T, PS>), dim3(n_cu * 4), dim3(kBlock), 0, s, a, p);
     hipLaunchKernelGGL((k_psmall<T, PS>), dim3(n_cu * 4), dim3(kBlock), sizeof(PShared), s, a, p);
+    hipLaunchKernelGGL(k_pchunkscan, dim3(1), dim3(kBlock), 0, s, a);
     hipLaunchKernelGGL(k_pscatter, dim3(n_cu * 4), dim3(kBlock), sizeof(PShared), s, a);
     return hipGetLastError();
 }
@@ -503,7 +608,9 @@ size_t part_workspace(int64_t n_nodes, int64_t n_samples) {
     size_t o = 256;                                                   // header
     o += (size_t)(items + n_nodes + 1) * sizeof(int4);                // items + small list
     o = (o + 255) & ~(size_t)255;
-    o += (size_t)items * sizeof(int32_t);
+    o += (size_t)items * sizeof(int32_t);                             // left count per chunk
+    o = (o + 255) & ~(size_t)255;
+    o += (size_t)(items + 1) * sizeof(int64_t);                       // their exclusive prefix
     o = (o + 255) & ~(size_t)255;
     o += (size_t)items * kWordsPerChunk * sizeof(uint64_t);
     return (o + 255) & ~(size_t)255;
@@ -519,6 +626,9 @@ void part_bind(int64_t n_nodes, int64_t n_samples, void* ws, PartArgs* a) {
     o = (o + 255) & ~(size_t)255;
     a->chunk_left = (int32_t*)(b + o);
     o += (size_t)items * sizeof(int32_t);
+    o = (o + 255) & ~(size_t)255;
+    a->chunk_pre = (int64_t*)(b + o);
+    o += (size_t)(items + 1) * sizeof(int64_t);
     o = (o + 255) & ~(size_t)255;
     a->pred_bits = (uint64_t*)(b + o);
     a->cap_items = items;

@@ -101,14 +101,31 @@ extern "C" int sof_create(int device, sof_ctx** out) {
     c->lds_per_block = (size_t)prop.sharedMemPerBlock;
     const char* chk = getenv("SOF_CHECK");
     c->check = chk && chk[0] == '1';
+    int prev = 0;
+    e = hipGetDevice(&prev);
+    if (e == hipSuccess && prev != device) e = hipSetDevice(device);
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipStreamCreateWithFlags(&c->aux[i], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->fork, hipEventDisableTiming);
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&c->join[i], hipEventDisableTiming);
+    if (prev != device) (void)hipSetDevice(prev);
+    if (e != hipSuccess) {
+        sof_destroy(c);
+        return hip_fail(e, "sof_create: streams and events");
+    }
     *out = c;
     return SOF_OK;
 }
 
 extern "C" int sof_destroy(sof_ctx* ctx) {
-    if (ctx)
+    if (ctx) {
         for (auto& a : ctx->tev)
             for (hipEvent_t e : a) (void)hipEventDestroy(e);
+        for (int i = 0; i < 2; ++i) {
+            if (ctx->aux[i]) (void)hipStreamDestroy(ctx->aux[i]);
+            if (ctx->join[i]) (void)hipEventDestroy(ctx->join[i]);
+        }
+        if (ctx->fork) (void)hipEventDestroy(ctx->fork);
+    }
     delete ctx;
     return SOF_OK;
 }
@@ -125,12 +142,11 @@ extern "C" int sof_timing_read(sof_ctx* ctx, float* ms, int32_t* calls) {
     for (int i = 0; i <= SOF_STAGE_COUNT; ++i) ms[i] = 0.f;
     for (size_t c = 0; c < ctx->tev_used; ++c) {
         auto& e = ctx->tev[c];
-        hipError_t r = hipEventSynchronize(e[SOF_STAGE_COUNT]);
+        hipError_t r = hipEventSynchronize(e[kTimingEvents - 1]);
         if (r != hipSuccess) return hip_fail(r, "hipEventSynchronize");
         for (int i = 0; i <= SOF_STAGE_COUNT; ++i) {
             float t = 0.f;
-            r = i < SOF_STAGE_COUNT ? hipEventElapsedTime(&t, e[i], e[i + 1])
-                                    : hipEventElapsedTime(&t, e[0], e[SOF_STAGE_COUNT]);
+            r = hipEventElapsedTime(&t, e[2 * i], e[2 * i + 1]);
             if (r != hipSuccess) return hip_fail(r, "hipEventElapsedTime");
             ms[i] += t;
         }
@@ -144,7 +160,7 @@ extern "C" int sof_timing_read(sof_ctx* ctx, float* ms, int32_t* calls) {
 static const hipEvent_t* timing_events(sof_ctx* ctx) {
     if (!ctx->timing) return nullptr;
     if (ctx->tev_used == ctx->tev.size()) {
-        std::array<hipEvent_t, SOF_STAGE_COUNT + 1> a;
+        std::array<hipEvent_t, kTimingEvents> a;
         for (auto& e : a)
             if (hipEventCreate(&e) != hipSuccess) return nullptr;
         ctx->tev.push_back(a);
@@ -403,7 +419,10 @@ extern "C" int sof_find_splits(sof_ctx* ctx, const sof_data* data, const sof_fro
     find_bind(L, ws, &a.ws);
     ProjCSR p{proj->proj_offsets, proj->nz_offsets, proj->nz_feature, proj->nz_weight, proj->n_proj,
               proj->n_nz, proj->nz_value};
-    e = launch_find_csr(a, p, cfg, (hipStream_t)stream, timing_events(ctx));
+    {
+        std::lock_guard<std::mutex> g(ctx->launch_mu);
+        e = launch_find_csr(a, p, cfg, find_streams(ctx, (hipStream_t)stream), timing_events(ctx));
+    }
     if (e != hipSuccess) return hip_fail(e, "find_splits launch");
     return SOF_OK;
 }
@@ -445,7 +464,10 @@ extern "C" int sof_find_splits_noalloc(sof_ctx* ctx, const sof_data* data, const
     find_bind(L, ctx->scratch, &a.ws);
     ProjCSR p{proj->proj_offsets, proj->nz_offsets, proj->nz_feature, proj->nz_weight, proj->n_proj,
               proj->n_nz, proj->nz_value};
-    e = launch_find_csr(a, p, cfg, (hipStream_t)stream, nullptr);
+    {
+        std::lock_guard<std::mutex> g(ctx->launch_mu);
+        e = launch_find_csr(a, p, cfg, find_streams(ctx, (hipStream_t)stream), nullptr);
+    }
     if (e != hipSuccess) return hip_fail(e, "find_splits launch");
     return SOF_OK;
 }

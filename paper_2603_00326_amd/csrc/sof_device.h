@@ -76,6 +76,31 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
     return x;
 }
 
+// Wave-aggregated allocation from K counters at once (every lane calls):
+// lane l asks cnt[k] entries of counter hdr[ctr[k]] and gets base[k], the
+// start of its entries; a wave's entries of one counter are contiguous in
+// lane order.  The K atomics are one instruction, issued by lanes 0..K-1, so
+// the wave waits for one round trip instead of K.
+template <int K>
+__device__ __forceinline__ void wave_alloc_n(int32_t* hdr, const int (&ctr)[K], const int (&cnt)[K],
+                                             int (&base)[K]) {
+    static_assert(K <= kWave, "one counter per lane");
+    const int lane = lane_id();
+    uint32_t incl[K];
+    int my_ctr = 0;
+    uint32_t my_tot = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        incl[k] = wave_incl_scan((uint32_t)cnt[k]);
+        const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)incl[k], kWave - 1);
+        if (lane == k) { my_ctr = ctr[k]; my_tot = tot; }
+    }
+    int b = 0;
+    if (lane < K && my_tot) b = atomicAdd(&hdr[my_ctr], (int)my_tot);
+#pragma unroll
+    for (int k = 0; k < K; ++k) base[k] = __builtin_amdgcn_readlane(b, k) + (int)(incl[k] - (uint32_t)cnt[k]);
+}
+
 __device__ __forceinline__ float wave_min(float x) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) x = fminf(x, __shfl_xor(x, off));

@@ -20,10 +20,24 @@ struct sof_ctx {
     std::mutex mu;
     std::map<std::pair<int, int>, sof::LaunchCfg> cfg;   // key (4 * bins + mode, classes)
     bool timing = false;                             // benchmark instrumentation
-    std::vector<std::array<hipEvent_t, SOF_STAGE_COUNT + 1>> tev;  // one event set per recorded call
+    std::vector<std::array<hipEvent_t, sof::kTimingEvents>> tev;  // one event set per recorded call
     size_t tev_used = 0;
     void* scratch = nullptr;   // device address of this device's static scratch array
+    // the find-splits sequence forks its size classes onto two auxiliary
+    // streams (default priority) and joins them back with these events;
+    // launch_mu keeps two host threads from interleaving their forks
+    hipStream_t aux[2] = {nullptr, nullptr};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[2] = {nullptr, nullptr};
+    std::mutex launch_mu;
 };
+
+namespace sof {
+// the context's streams around a launch on the caller's stream s
+inline FindStreams find_streams(sof_ctx* ctx, hipStream_t s) {
+    return FindStreams{s, {ctx->aux[0], ctx->aux[1]}, ctx->fork, {ctx->join[0], ctx->join[1]}};
+}
+}  // namespace sof
 
 namespace sof {
 
@@ -61,6 +75,7 @@ struct PartArgs {
     int32_t* hdr;             // counters
     int4* big_items;          // (node, chunk, chunk count, first item of the node)
     int32_t* chunk_left;      // left count per chunk item
+    int64_t* chunk_pre;       // exclusive prefix of chunk_left over all chunk items
     uint64_t* pred_bits;      // one bit per sample of every chunk item
     int64_t cap_items;
 };

@@ -39,6 +39,10 @@ enum {
     H_Q_SMALL,
     H_Q_SB,
     H_Q_MID2,
+    H_Q_BRANGE = 20,   // dequeue counters of the big-node kernels (blocks of per-wave items)
+    H_Q_BMERGE,
+    H_Q_BHIST,
+    H_Q_BSCAN,
     H_ERR = 32,
     H_COUNT = 64
 };
@@ -139,12 +143,27 @@ struct LaunchCfg {
     size_t smem_main, smem_sort;
 };
 
+// Streams of one find-splits launch sequence: the caller's stream runs the
+// plan; the size classes then run on three streams at once (the caller's and
+// the context's two auxiliary streams, forked with `fork` and joined back with
+// `join`), and the reduction runs on the caller's stream after the join.
+// aux[0] == NULL runs everything on the caller's stream.
+struct FindStreams {
+    hipStream_t main;
+    hipStream_t aux[2];
+    hipEvent_t fork;
+    hipEvent_t join[2];
+};
+
+// Stage timing events (optional): ev[2 s] and ev[2 s + 1] are recorded on the
+// stream of stage s before and after it; ev[2 SOF_STAGE_COUNT] and
+// ev[2 SOF_STAGE_COUNT + 1] around the whole sequence on the caller's stream.
+constexpr int kTimingEvents = 2 * SOF_STAGE_COUNT + 2;
+
 // launchers (return hipError_t)
-// ev (optional, SOF_STAGE_COUNT + 1 events): recorded before the first stage
-// and after every stage of the sequence
-hipError_t launch_find_csr(const FindArgs& a, const ProjCSR& p, const LaunchCfg& cfg, hipStream_t s,
+hipError_t launch_find_csr(const FindArgs& a, const ProjCSR& p, const LaunchCfg& cfg, const FindStreams& st,
                            const hipEvent_t* ev = nullptr);
-hipError_t launch_find_hash(const FindArgs& a, const ProjHash& p, const LaunchCfg& cfg, hipStream_t s,
+hipError_t launch_find_hash(const FindArgs& a, const ProjHash& p, const LaunchCfg& cfg, const FindStreams& st,
                             const hipEvent_t* ev = nullptr);
 size_t find_smem_main(int bins, int classes, bool random_bins, bool entropy);
 size_t find_smem_sort();
