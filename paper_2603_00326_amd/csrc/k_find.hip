@@ -224,7 +224,13 @@ __host__ __device__ constexpr int bins_stride(int bins) { return (bins + 3) & ~3
 // scratch in LDS (the node's class totals).
 constexpr float kScreenKeep = 1.0f - 1.0f / 65536.0f;
 
-__device__ Cand scan_hist_fast(const LdsHistCM& h, int B, int C, int64_t n, float lo, float scale, int32_t* pc) {
+// qfloor (optional): the FP32 score of the caller's incumbent from an earlier
+// scan.  When this scan's best score is below qfloor (1 - 2^-16), its exact
+// best Q is below the incumbent's (both scores are within 20 * 2^-24 of their
+// exact values), so it cannot win or tie and is returned invalid without its
+// exact evaluation.  qmax_out (optional) receives this scan's best score.
+__device__ Cand scan_hist_fast(const LdsHistCM& h, int B, int C, int64_t n, float lo, float scale, int32_t* pc,
+                               float qfloor = -1.f, float* qmax_out = nullptr) {
     const int lane = lane_id();
     const int b0 = lane * 4;
     const float nf = (float)n;
@@ -263,12 +269,14 @@ __device__ Cand scan_hist_fast(const LdsHistCM& h, int B, int C, int64_t n, floa
         qb = fmaxf(qb, q[i]);
     }
     const float qmax = wave_max_f(qb);
+    if (qmax_out) *qmax_out = qmax;
     Cand best;
     cand_invalid(best);
     best.SP = SP;
     best.lo = lo;
     best.scale = scale;
     if (!(qmax >= 0.f)) return best;
+    if (qmax < qfloor * kScreenKeep) return best;
     const float keep = qmax * kScreenKeep;
     wave_sync();   // pc[] and the left counts written above are read by other lanes below
     const uint32_t pcv = lane < C ? (uint32_t)pc[lane] : 0u;
@@ -807,6 +815,7 @@ __device__ void do_small_r(const FindArgs& A, const PS& P, int v, int64_t s0, in
     // fields of the new candidate.
     if (lane == 0) cand_invalid(WS.best);
     wave_sync();
+    float bestq = -1.f;   // the incumbent's FP32 score (Gini histogram scans)
     for (int pb = w; pb < k; pb += kWavesPerBlock * kSmallBatch) {
       if (pb != w) batch_fill(P, batch_range(P, q0, pb, kWavesPerBlock, k), v, pb, kWavesPerBlock, k, A.n_features, WS);
       for (int gi = 0; gi < kSmallBatch; ++gi) {
@@ -846,10 +855,13 @@ __device__ void do_small_r(const FindArgs& A, const PS& P, int v, int64_t s0, in
             wave_sync();
             LdsHistCM h{hist, Bs};
             write_hist_row(A, item_q(P, v, q0, p), h, B);
+            float qm = -1.f;
             if (ENT) c = scan_hist_entropy(h, B, C, n, lo, scale, Flnk{block_flnk(smem, Bm, C, RW), kFlnkLds, nullptr, 0});
-            else c = scan_hist_fast(h, B, C, n, lo, scale, WS.pcs);
+            else c = scan_hist_fast(h, B, C, n, lo, scale, WS.pcs, bestq, &qm);
             if (RW && c.D != 0) c.thr = rw_boundary(A.bin_seed, item_q(P, v, q0, p), B, lo, hi, c.pos);
             wave_sync();
+            // a candidate is only returned valid when it may beat the incumbent
+            if (c.D != 0 && cand_better(c, WS.best)) bestq = qm;
         }
         c.proj = p;
         const bool take = cand_better(c, WS.best);
