@@ -152,7 +152,7 @@ typedef struct {
     int32_t        bins;          /* 2..SOF_MAX_BINS: bin count when node_bins is NULL, else the maximum */
     int32_t        sort_threshold;/* nodes with n < min(T, SOF_SORT_LIMIT + 1) sort; 0 = all histogram */
     int32_t        bin_mode;      /* SOF_BINS_EQUAL or SOF_BINS_RANDOM */
-    int32_t        criterion;     /* SOF_CRIT_GINI, or SOF_CRIT_ENTROPY (histogram path only: sort_threshold 0) */
+    int32_t        criterion;     /* SOF_CRIT_GINI or SOF_CRIT_ENTROPY, on both paths */
     uint64_t       bin_seed;      /* SOF_BINS_RANDOM: seed of the widths */
 } sof_params;
 
@@ -161,9 +161,11 @@ typedef struct {
  * Method section): each boundary's E = sum_c f(l_c) + sum_c f(r_c) - f(n_L)
  * - f(n_R), f(k) = k ln k, in binary64 with a natural log built from IEEE
  * basic operations (reduction to [sqrt(2)/2, sqrt(2)), 12 atanh-series terms),
- * the sums over classes ascending; the largest E wins (lowest projection,
- * then bin, on ties), the gain is ((f(n) - sum_c f(P_c)) + E) / n and the
- * node splits iff it exceeds 1e-12. */
+ * the sums over classes ascending, at every bin boundary (histogram path) or
+ * every boundary between distinct sorted values (sort path); the largest E
+ * wins (lowest projection, then bin or sorted position, on ties), the gain
+ * is ((f(n) - sum_c f(P_c)) + E) / n and the node splits iff it exceeds
+ * 1e-12. */
 
 /* Best split of one node (section 4.3: the projection and its split value). */
 typedef struct {
@@ -208,7 +210,13 @@ typedef struct {
     int32_t        max_depth;     /* 0..64: nodes at this depth become leaves */
     int32_t        sampler;       /* SOF_SAMPLER_FIXED or SOF_SAMPLER_DENSITY */
     int32_t        weights;       /* SOF_WEIGHTS_SIGN or SOF_WEIGHTS_UNIFORM */
+    int32_t        criterion;     /* SOF_CRIT_GINI or SOF_CRIT_ENTROPY */
+    int32_t        bin_mode;      /* SOF_BINS_EQUAL or SOF_BINS_RANDOM */
     int32_t        pad;
+    uint64_t       bin_seed;      /* SOF_BINS_RANDOM: seed of the widths; projection p of the node at
+                                     (tree, level, pos) takes the width stream index
+                                     ((tree * 64 + level) << 24 + pos) << 10 + p in place of the
+                                     projection's index in the call */
 } sof_forest_desc;
 
 /* The sampler (Method: the sparse projection matrix; appendix: Floyd's

@@ -92,7 +92,7 @@ def lib():
         L.or_sample_weight.argtypes = [u64, i32, i32, i32, i32, i32, i32, i32]
         L.or_sample_weight.restype = ctypes.c_float
         L.or_grow_forest.argtypes = [P, ctypes.c_int, i64, i32, P, i32, i32, i32, P, P, i32, i32, i32, i32, u64,
-                                     i32, i32, i32, i32, P, i64, P, P]
+                                     i32, i32, i32, i32, i32, u64, i32, P, i64, P, P]
         L.or_grow_forest.restype = i64
         L.or_leaf_of.argtypes = [P, ctypes.c_int, i64, P, i32, i32]
         L.or_leaf_of.restype = i32
@@ -248,7 +248,8 @@ def sample_weight(seed, sampler, weights, tree, level, pos, proj, rank) -> np.fl
 
 
 def grow_forest(X, y, n_classes, root_offsets, root_idx, *, k, z, seed, bins=256, sort_threshold=0,
-                max_depth=64, threads=0, cap=None, first_tree=0, sampler=SAMPLER_FIXED, weights=WEIGHTS_SIGN):
+                max_depth=64, threads=0, cap=None, first_tree=0, sampler=SAMPLER_FIXED, weights=WEIGHTS_SIGN,
+                criterion=CRIT_GINI, bin_mode=BINS_EQUAL, bin_seed=0):
     """Grow several trees level by level to purity.  Returns (nodes, level_nodes, level_units)."""
     X, dt = _xinfo(X)
     y = _c(y, np.int32)
@@ -264,7 +265,8 @@ def grow_forest(X, y, n_classes, root_offsets, root_idx, *, k, z, seed, bins=256
                              int(first_tree), _p(ro),
                              _p(ri), int(k), int(z), int(sampler), int(weights), seed & (2**64 - 1), int(bins),
                              int(sort_threshold),
-                             int(max_depth), int(threads), _p(nodes), int(cap), _p(ln), _p(lu))
+                             int(max_depth), int(criterion), int(bin_mode), int(bin_seed) & (2**64 - 1),
+                             int(threads), _p(nodes), int(cap), _p(ln), _p(lu))
     if n < 0:
         raise RuntimeError("node capacity too small")
     levels = int(np.count_nonzero(ln))

@@ -398,6 +398,17 @@ static void no_split(or_split* o, int kind, int32_t n)
     o->n_right = 0;
 }
 
+/* bin_keys (optional): the random-width width-stream key of every projection
+ * (forest growth keys a drawn projection by its tree position); NULL keys
+ * projection q by q, its index in the call. */
+static int find_splits_keyed(const void* x, int dtype, int64_t ld, const int32_t* y, int32_t C,
+                             int32_t n_nodes, const int32_t* node_offsets, const int32_t* sample_idx,
+                             const int32_t* proj_offsets, const int32_t* nz_offsets,
+                             const int32_t* nz_feature, const float* nz_weight,
+                             const int32_t* node_bins, int32_t bins, int32_t sort_threshold,
+                             int32_t bin_mode, uint64_t bin_seed, const uint64_t* bin_keys, int32_t criterion,
+                             or_split* out, int32_t* hist_out, int32_t n_threads);
+
 int or_find_splits(const void* x, int dtype, int64_t ld, const int32_t* y, int32_t C,
                    int32_t n_nodes, const int32_t* node_offsets, const int32_t* sample_idx,
                    const int32_t* proj_offsets, const int32_t* nz_offsets,
@@ -405,6 +416,19 @@ int or_find_splits(const void* x, int dtype, int64_t ld, const int32_t* y, int32
                    const int32_t* node_bins, int32_t bins, int32_t sort_threshold,
                    int32_t bin_mode, uint64_t bin_seed, int32_t criterion,
                    or_split* out, int32_t* hist_out, int32_t n_threads)
+{
+    return find_splits_keyed(x, dtype, ld, y, C, n_nodes, node_offsets, sample_idx, proj_offsets, nz_offsets,
+                             nz_feature, nz_weight, node_bins, bins, sort_threshold, bin_mode, bin_seed, NULL,
+                             criterion, out, hist_out, n_threads);
+}
+
+static int find_splits_keyed(const void* x, int dtype, int64_t ld, const int32_t* y, int32_t C,
+                             int32_t n_nodes, const int32_t* node_offsets, const int32_t* sample_idx,
+                             const int32_t* proj_offsets, const int32_t* nz_offsets,
+                             const int32_t* nz_feature, const float* nz_weight,
+                             const int32_t* node_bins, int32_t bins, int32_t sort_threshold,
+                             int32_t bin_mode, uint64_t bin_seed, const uint64_t* bin_keys, int32_t criterion,
+                             or_split* out, int32_t* hist_out, int32_t n_threads)
 {
     int32_t P = proj_offsets[n_nodes];
     int T = effective_threshold(sort_threshold);
@@ -432,8 +456,8 @@ int or_find_splits(const void* x, int dtype, int64_t ld, const int32_t* y, int32
         int32_t j0 = nz_offsets[q], z = nz_offsets[q + 1] - j0;
         int32_t* hrow = (hist_out && !sort_path) ? hist_out + (int64_t)q * bins * C : NULL;
         eval_projection(x, dtype, ld, y, C, sample_idx + s0, n, parent + (int64_t)v * C,
-                        nz_feature + j0, nz_weight + j0, z, B, sort_path, bin_mode, bin_seed, q, criterion,
-                        &cands[q], hrow, bins);
+                        nz_feature + j0, nz_weight + j0, z, B, sort_path, bin_mode, bin_seed,
+                        bin_keys ? (int64_t)bin_keys[q] : (int64_t)q, criterion, &cands[q], hrow, bins);
     }
     for (int32_t v = 0; v < n_nodes; ++v) {
         int32_t n = node_offsets[v + 1] - node_offsets[v];
@@ -721,7 +745,8 @@ int64_t or_grow_forest(const void* x, int dtype, int64_t ld, int32_t d,
                        const int32_t* y, int32_t C, int32_t n_trees, int32_t first_tree,
                        const int64_t* root_offsets, const int32_t* root_idx,
                        int32_t k, int32_t z, int32_t sampler, int32_t weights, uint64_t seed,
-                       int32_t bins, int32_t sort_threshold, int32_t max_depth, int32_t n_threads,
+                       int32_t bins, int32_t sort_threshold, int32_t max_depth,
+                       int32_t criterion, int32_t bin_mode, uint64_t bin_seed, int32_t n_threads,
                        or_tree_node* nodes, int64_t cap,
                        int64_t* level_nodes, int64_t* level_units)
 {
@@ -761,6 +786,9 @@ int64_t or_grow_forest(const void* x, int dtype, int64_t ld, int32_t d,
         int32_t* no = (int32_t*)malloc(sizeof(int32_t) * ((size_t)N * k + 1));
         int32_t* nf = (int32_t*)malloc(sizeof(int32_t) * ((size_t)N * k * 16 + 1));
         float* nw = (float*)malloc(sizeof(float) * ((size_t)N * k * 16 + 1));
+        /* random-width bins of projection p of the node at (tree, level, pos):
+         * the sampler's counter without its draw field */
+        uint64_t* keys = (uint64_t*)malloc(sizeof(uint64_t) * ((size_t)N * k + 1));
         int32_t pos = 0, tot = 0;
         for (int32_t v = 0; v < N; ++v) {
             if (v > 0 && front[v].tree != front[v - 1].tree)
@@ -768,6 +796,7 @@ int64_t or_grow_forest(const void* x, int dtype, int64_t ld, int32_t d,
             po[v] = v * k;
             for (int32_t p = 0; p < k; ++p) {
                 int64_t q = (int64_t)v * k + p;
+                keys[q] = or_counter(front[v].tree, level, pos, p, 0) >> 4;
                 no[q] = tot;
                 tot += or_sample_projection(seed, front[v].tree, level, pos, p, d, sampler, z, weights, nf + tot,
                                             nw + tot);
@@ -779,9 +808,8 @@ int64_t or_grow_forest(const void* x, int dtype, int64_t ld, int32_t d,
         if (level_nodes) level_nodes[level] = N;
         if (level_units) level_units[level] = (int64_t)off[N] * k;
         or_split* sp = (or_split*)malloc(sizeof(or_split) * (size_t)N);
-        or_find_splits(x, dtype, ld, y, C, N, off, sidx, po, no, nf, nw, NULL, bins, sort_threshold, OR_BINS_EQUAL, 0,
-                       OR_CRIT_GINI,
-                       sp, NULL, n_threads);
+        find_splits_keyed(x, dtype, ld, y, C, N, off, sidx, po, no, nf, nw, NULL, bins, sort_threshold, bin_mode,
+                          bin_seed, keys, criterion, sp, NULL, n_threads);
         int32_t* pidx = (int32_t*)malloc(sizeof(int32_t) * (size_t)(off[N] > 0 ? off[N] : 1));
         int32_t* coff = (int32_t*)malloc(sizeof(int32_t) * (size_t)(2 * N + 1));
         or_partition(x, dtype, ld, N, off, sidx, po, no, nf, nw, NULL, bins, sp, pidx, coff);
@@ -836,7 +864,7 @@ int64_t or_grow_forest(const void* x, int dtype, int64_t ld, int32_t d,
         free(front);
         front = next;
         n_front = n_next;
-        free(off); free(sidx); free(po); free(no); free(nf); free(nw); free(sp); free(pidx); free(coff);
+        free(off); free(sidx); free(po); free(no); free(nf); free(nw); free(keys); free(sp); free(pidx); free(coff);
     }
     free(front);
     return n_nodes;

@@ -140,13 +140,17 @@ int32_t or_sample_projection(uint64_t seed, int32_t tree, int32_t level, int32_t
 /* Level-wise growth of several trees to purity (tree ids first_tree ..
  * first_tree + n_trees - 1 key the sampler).  Returns the number of nodes,
  * or -1 if cap is too small.  level_nodes / level_units (optional, length
- * max_depth + 1) receive the frontier size and sum n_v*k per level. */
+ * max_depth + 1) receive the frontier size and sum n_v*k per level.  With
+ * random-width bins, projection p of the node at (tree, level, pos) takes the
+ * width stream key or_counter(tree, level, pos, p, 0) >> 4 in place of its
+ * index in the level's call. */
 int64_t or_grow_forest(const void* x, int dtype, int64_t ld, int32_t n_features,
                        const int32_t* y, int32_t n_classes, int32_t n_trees, int32_t first_tree,
                        const int64_t* root_offsets, const int32_t* root_idx,
                        int32_t k, int32_t z, int32_t sampler, int32_t weights, uint64_t seed,
                        int32_t bins,
-                       int32_t sort_threshold, int32_t max_depth, int32_t n_threads,
+                       int32_t sort_threshold, int32_t max_depth,
+                       int32_t criterion, int32_t bin_mode, uint64_t bin_seed, int32_t n_threads,
                        or_tree_node* nodes, int64_t cap,
                        int64_t* level_nodes, int64_t* level_units);
 

@@ -147,6 +147,15 @@ __device__ __forceinline__ int proj_stage(const ProjHash& P, int v, int p, int d
 // index of node-local projection p in the call, given the node's first (q0)
 __device__ __forceinline__ int item_q(const ProjCSR&, int, int q0, int p) { return q0 + p; }
 __device__ __forceinline__ int item_q(const ProjHash& P, int v, int, int p) { return v * P.k + p; }
+// Key of the random-width bins of node-local projection p: the projection's
+// index in the call for given projections, and for drawn ones the sampler's
+// counter of (tree, level, position, projection) without its draw field, so
+// that a node's bins depend on its tree position only (batched trees equal
+// single-tree runs)
+__device__ __forceinline__ uint64_t bin_key(const ProjCSR&, int, int q0, int p) { return (uint64_t)(q0 + p); }
+__device__ __forceinline__ uint64_t bin_key(const ProjHash& P, int v, int, int p) {
+    return samp_counter(P.tree_of[v], *P.level, P.pos_of[v], p, 0) >> 4;
+}
 
 // ---------------------------------------------------------------------------
 // allocation helpers
@@ -440,12 +449,12 @@ __device__ __forceinline__ int rw_cell(float x, float lo, float sc) {
     const float t = __fmul_rn(__fsub_rn(x, lo), sc);
     return t < (float)kRwCells ? (int)t : kRwCells - 1;
 }
-__device__ __forceinline__ uint32_t rw_width(uint64_t seed, int64_t q, int j) {
+__device__ __forceinline__ uint32_t rw_width(uint64_t seed, uint64_t q, int j) {
     return 1u + (uint32_t)(splitmix_at(seed, (uint64_t)q * 256u + (uint64_t)j) >> 48);
 }
 
 // Build projection q's table (one wave, every lane; lane l owns bins 4l..4l+3).
-__device__ void rw_build(RwTable& T, uint64_t seed, int64_t q, int B, float lo, float hi, float sc) {
+__device__ void rw_build(RwTable& T, uint64_t seed, uint64_t q, int B, float lo, float hi, float sc) {
     const int lane = lane_id();
     uint32_t g[4];
 #pragma unroll
@@ -495,7 +504,7 @@ struct RwBins {
 
 // Boundary b+1 of projection q (the random-width split threshold: bin(v) <= b
 // iff v < it), by one wave with uniform loop bounds.
-__device__ float rw_boundary(uint64_t seed, int64_t q, int B, float lo, float hi, int b) {
+__device__ float rw_boundary(uint64_t seed, uint64_t q, int B, float lo, float hi, int b) {
     const int lane = lane_id();
     uint32_t gb = 0, gt = 0;
     for (int j0 = 0; j0 < 256; j0 += kWave) {
@@ -597,7 +606,12 @@ __device__ __forceinline__ void block_minmax(BlockShared& S, float& lo, float& h
 // (ties by lane), scatters (key, label) to its rank, then per-class inclusive
 // scans over the sorted labels give the left counts at every sorted
 // position.  Boundaries only between distinct values.
-__device__ Cand scan_sort_small(WaveScratch& WS, float val, int lab, int64_t n, int C) {
+// ENT: the entropy criterion at every boundary between distinct values,
+// E = ((sum_c f(l_c) + sum_c f(r_c)) - f(n_L)) - f(n_R) in binary64 with the
+// class sums ascending (f from tab), ordered through key(E) with D = 1 as in
+// the histogram scan; SL, SR, SP carry the bits of the three class sums.
+template <bool ENT>
+__device__ Cand scan_sort_small(WaveScratch& WS, float val, int lab, int64_t n, int C, const Flnk& tab) {
     const int lane = lane_id();
     const bool real = lane < n;
     const uint32_t key = fkey(val);
@@ -620,18 +634,35 @@ __device__ Cand scan_sort_small(WaveScratch& WS, float val, int lab, int64_t n, 
     const uint32_t k0 = WS.sk[0];
     wave_sync();
     uint64_t SL = 0, SR = 0, SP = 0;
+    double FL = 0.0, FR = 0.0, FP = 0.0;
     for (int c = 0; c < C; ++c) {
         const uint32_t l = wave_incl_scan((real && mylab == c) ? 1u : 0u);
         const uint32_t Pc = (uint32_t)WS.pc[c];
         const uint32_t r = Pc - l;
-        SL += (uint64_t)l * l;
-        SR += (uint64_t)r * r;
-        SP += (uint64_t)Pc * Pc;
+        if (ENT) {
+            FL = __dadd_rn(FL, flnk_at(tab, l));
+            FR = __dadd_rn(FR, flnk_at(tab, r));
+            FP = __dadd_rn(FP, flnk_at(tab, Pc));
+        } else {
+            SL += (uint64_t)l * l;
+            SR += (uint64_t)r * r;
+            SP += (uint64_t)Pc * Pc;
+        }
     }
     u128 N = 0;
     uint64_t D = 0;
-    const bool ok = lane + 1 < n && myk < nextk &&
-                    make_q((int64_t)lane + 1, n - (int64_t)lane - 1, SL, SR, N, D);
+    bool ok = lane + 1 < n && myk < nextk;
+    if (ENT) {
+        const double E = __dsub_rn(__dsub_rn(__dadd_rn(FL, FR), flnk_at(tab, lane + 1)),
+                                   flnk_at(tab, n - (int64_t)lane - 1));
+        N = (u128)dkey(E);
+        D = 1;
+        SL = d_bits(FL);
+        SR = d_bits(FR);
+        SP = d_bits(FP);
+    } else {
+        ok = ok && make_q((int64_t)lane + 1, n - (int64_t)lane - 1, SL, SR, N, D);
+    }
     const int win = wave_best_lane(ok, N, D, lane);
     Cand c;
     cand_invalid(c);
@@ -832,7 +863,8 @@ __device__ void do_small_r(const FindArgs& A, const PS& P, int v, int64_t s0, in
         hi = wave_max(hi);
         Cand c;
         if (sortp) {
-            c = scan_sort_small(WS, val[0], lab[0], n, C);
+            c = scan_sort_small<ENT>(WS, val[0], lab[0], n, C,
+                                     Flnk{ENT ? block_flnk(smem, Bm, C, RW) : nullptr, ENT ? kFlnkLds : 0, nullptr, 0});
             write_zero_row(A, item_q(P, v, q0, p));
         } else {
             const float scale = bin_scale(B, lo, hi);
@@ -842,7 +874,7 @@ __device__ void do_small_r(const FindArgs& A, const PS& P, int v, int64_t s0, in
             if (RW) {
                 RwTable& tab = wave_rw(smem, w, Bm, C);
                 const float sc = rw_cell_scale(lo, hi);
-                rw_build(tab, A.bin_seed, item_q(P, v, q0, p), B, lo, hi, sc);
+                rw_build(tab, A.bin_seed, bin_key(P, v, q0, p), B, lo, hi, sc);
                 const RwBins bn{&tab, lo, sc};
 #pragma unroll
                 for (int r = 0; r < R; ++r)
@@ -858,7 +890,7 @@ __device__ void do_small_r(const FindArgs& A, const PS& P, int v, int64_t s0, in
             float qm = -1.f;
             if (ENT) c = scan_hist_entropy(h, B, C, n, lo, scale, Flnk{block_flnk(smem, Bm, C, RW), kFlnkLds, nullptr, 0});
             else c = scan_hist_fast(h, B, C, n, lo, scale, WS.pcs, bestq, &qm);
-            if (RW && c.D != 0) c.thr = rw_boundary(A.bin_seed, item_q(P, v, q0, p), B, lo, hi, c.pos);
+            if (RW && c.D != 0) c.thr = rw_boundary(A.bin_seed, bin_key(P, v, q0, p), B, lo, hi, c.pos);
             wave_sync();
             // a candidate is only returned valid when it may beat the incumbent
             if (c.D != 0 && cand_better(c, WS.best)) bestq = qm;
@@ -1055,7 +1087,7 @@ __device__ void do_mid_r(const FindArgs& A, const PS& P, const MidItem& m, int64
             RwTable& tab = wave_rw(smem, w, Bm, C);
             const float sc = rw_cell_scale(lo, hi);
             wave_sync();   // this wave's lookups of the previous projection are done
-            rw_build(tab, A.bin_seed, item_q(P, v, m.q0, p0 + j), B, lo, hi, sc);
+            rw_build(tab, A.bin_seed, bin_key(P, v, m.q0, p0 + j), B, lo, hi, sc);
             const RwBins bn{&tab, lo, sc};
 #pragma unroll
             for (int r = 0; r < R; ++r)
@@ -1084,7 +1116,7 @@ __device__ void do_mid_r(const FindArgs& A, const PS& P, const MidItem& m, int64
                                          R <= 16 ? Flnk{block_flnk(smem, Bm, C, RW), kFlnkLds, A.ws.flnk, A.ws.cap_flnk}
                                                  : Flnk{nullptr, 0, A.ws.flnk, A.ws.cap_flnk})
                      : scan_hist_fast(h, B, C, n, lo, scale, S.w[w].pcs);
-        if (RW && c.D != 0) c.thr = rw_boundary(A.bin_seed, item_q(P, v, m.q0, p0 + w), B, lo, hi, c.pos);
+        if (RW && c.D != 0) c.thr = rw_boundary(A.bin_seed, bin_key(P, v, m.q0, p0 + w), B, lo, hi, c.pos);
         c.proj = p0 + w;
         if (lane == 0) ((Cand*)A.ws.slots)[m.slot + p0 + w] = c;
     }
@@ -1505,7 +1537,7 @@ __global__ __launch_bounds__(kBlock) void k_bhist(FindArgs A, PS P) {
         if (RW) {
             RwTable& tab = wave_rw(smem, w, Bm, C);
             const float sc = rw_cell_scale(r.x, r.y);
-            rw_build(tab, A.bin_seed, proj_global(P, bd.node, p), B, r.x, r.y, sc);
+            rw_build(tab, A.bin_seed, bin_key(P, bd.node, proj_global(P, bd.node, 0), p), B, r.x, r.y, sc);
             if (vcr) big_chunk_cached(A, bd, ch, vcr, hist, RwBins{&tab, r.x, sc});
             else big_chunk<T, PS, true>(A, P, bd, p, ch, WS, lo, hi, hist, RwBins{&tab, r.x, sc});
         } else {
@@ -1557,7 +1589,7 @@ __global__ __launch_bounds__(kBlock) void k_bscan(FindArgs A, PS P) {
         write_hist_row(A, proj_global(P, bd.node, p), h, B);
         Cand c = ENT ? scan_hist_entropy(h, B, C, n, r.x, scale, Flnk{nullptr, 0, A.ws.flnk, A.ws.cap_flnk})
                      : scan_hist_fast(h, B, C, n, r.x, scale, block_shared(smem).w[w].pcs);
-        if (RW && c.D != 0) c.thr = rw_boundary(A.bin_seed, proj_global(P, bd.node, p), B, r.x, r.y, c.pos);
+        if (RW && c.D != 0) c.thr = rw_boundary(A.bin_seed, bin_key(P, bd.node, proj_global(P, bd.node, 0), p), B, r.x, r.y, c.pos);
         c.proj = p;
         if (lane == 0) ((Cand*)W.slots)[bd.slot + p] = c;
         wave_sync();
@@ -1691,7 +1723,9 @@ __device__ __forceinline__ uint64_t wave_incl_scan64(uint64_t x) {
 // into LDS as (order-preserving key << 32 | label), bitonic sort, then each
 // thread scans a contiguous run of sorted positions with 16-bit packed class
 // counters (four classes per 64-bit word) offset by a block prefix sum.
-template <typename T, class PS>
+// ENT: the entropy criterion (as in scan_sort_small), f(k) from the call's
+// table.
+template <typename T, class PS, bool ENT>
 __device__ void do_sortblock(const FindArgs& A, const PS& P, int4 D, int p, char* smem) {
     SortShared& S = *(SortShared*)smem;
     uint64_t* keys = (uint64_t*)(smem + sizeof(SortShared));
@@ -1764,8 +1798,15 @@ __device__ void do_sortblock(const FindArgs& A, const PS& P, int4 D, int p, char
 #pragma unroll
     for (int q = 0; q < 4; ++q)
         for (int ww = 0; ww < w; ++ww) excl[q] += S.wtot[ww][q];
+    const Flnk tab{nullptr, 0, A.ws.flnk, A.ws.cap_flnk};
     uint64_t SP = 0;
-    for (int c = 0; c < C; ++c) SP += (uint64_t)S.pc[c] * (uint64_t)S.pc[c];
+    if (ENT) {
+        double FP = 0.0;
+        for (int c = 0; c < C; ++c) FP = __dadd_rn(FP, flnk_at(tab, S.pc[c]));
+        SP = d_bits(FP);
+    } else {
+        for (int c = 0; c < C; ++c) SP += (uint64_t)S.pc[c] * (uint64_t)S.pc[c];
+    }
     bool bv = false;
     u128 bN = 0;
     uint64_t bD = 0, bSL = 0, bSR = 0;
@@ -1780,7 +1821,18 @@ __device__ void do_sortblock(const FindArgs& A, const PS& P, int4 D, int p, char
 #pragma unroll
         for (int q = 0; q < 4; ++q)
             if (q == (y >> 2)) cur[q] += one;
-        if (i + 1 < n && (uint32_t)(ki >> 32) < (uint32_t)(keys[i + 1] >> 32)) {
+        if (ENT && i + 1 < n && (uint32_t)(ki >> 32) < (uint32_t)(keys[i + 1] >> 32)) {
+            double FL = 0.0, FR = 0.0;
+            for (int c = 0; c < C; ++c) {
+                const uint32_t l = (uint32_t)((cur[c >> 2] >> (16 * (c & 3))) & 0xffffu);
+                FL = __dadd_rn(FL, flnk_at(tab, l));
+                FR = __dadd_rn(FR, flnk_at(tab, (uint32_t)S.pc[c] - l));
+            }
+            const double Ev = __dsub_rn(__dsub_rn(__dadd_rn(FL, FR), flnk_at(tab, (int64_t)i + 1)),
+                                        flnk_at(tab, n - i - 1));
+            const u128 N = (u128)dkey(Ev);
+            if (!bv || N > bN) { bv = true; bN = N; bD = 1; bpos = i; bSL = d_bits(FL); bSR = d_bits(FR); }
+        } else if (!ENT && i + 1 < n && (uint32_t)(ki >> 32) < (uint32_t)(keys[i + 1] >> 32)) {
             uint64_t SL = 0, SR = 0;
             for (int c = 0; c < C; ++c) {
                 const uint32_t l = (uint32_t)((cur[c >> 2] >> (16 * (c & 3))) & 0xffffu);
@@ -1838,7 +1890,7 @@ __device__ void do_sortblock(const FindArgs& A, const PS& P, int4 D, int p, char
     __syncthreads();
 }
 
-template <typename T, class PS>
+template <typename T, class PS, bool ENT>
 __global__ __launch_bounds__(kBlock) void k_sortblk(FindArgs A, PS P) {
     extern __shared__ __align__(16) char smem[];
     SortShared& S = *(SortShared*)smem;
@@ -1851,7 +1903,7 @@ __global__ __launch_bounds__(kBlock) void k_sortblk(FindArgs A, PS P) {
         int2 e = W.items_sb[it];
         if (e.x >= nd) continue;
         int4 D = W.desc_sb[e.x];
-        if (e.y < D.w) do_sortblock<T>(A, P, D, e.y, smem);
+        if (e.y < D.w) do_sortblock<T, PS, ENT>(A, P, D, e.y, smem);
     }
 }
 
@@ -1917,7 +1969,7 @@ static hipError_t launch_find_t(const FindArgs& a, const PS& p, const LaunchCfg&
     hipLaunchKernelGGL((k_mid<T, PS, true, RW, ENT>), dim3(cfg.grid_mid2), dim3(kBlock), sm, sl, a, p);
     end(SOF_STAGE_MID2, sl);
     beg(SOF_STAGE_SORT, sl);
-    hipLaunchKernelGGL((k_sortblk<T, PS>), dim3(cfg.grid_sort), dim3(kBlock), cfg.smem_sort, sl, a, p);
+    hipLaunchKernelGGL((k_sortblk<T, PS, ENT>), dim3(cfg.grid_sort), dim3(kBlock), cfg.smem_sort, sl, a, p);
     end(SOF_STAGE_SORT, sl);
     beg(SOF_STAGE_MID, s);
     hipLaunchKernelGGL((k_mid<T, PS, false, RW, ENT>), dim3(cfg.grid_mid), dim3(kBlock), sm, s, a, p);
@@ -1959,11 +2011,23 @@ hipError_t launch_find_csr(const FindArgs& a, const ProjCSR& p, const LaunchCfg&
     default: return launch_find_t<float, ProjCSR, false, false>(a, p, cfg, s, ev);
     }
 }
-// forest growth uses equal-width bins
 hipError_t launch_find_hash(const FindArgs& a, const ProjHash& p, const LaunchCfg& cfg, const FindStreams& s,
                             const hipEvent_t* ev) {
-    if (a.dtype == SOF_F16) return launch_find_t<_Float16, ProjHash, false, false>(a, p, cfg, s, ev);
-    return launch_find_t<float, ProjHash, false, false>(a, p, cfg, s, ev);
+    const int mode = (a.bin_mode == SOF_BINS_RANDOM ? 1 : 0) | (a.criterion == SOF_CRIT_ENTROPY ? 2 : 0);
+    if (a.dtype == SOF_F16) {
+        switch (mode) {
+        case 1: return launch_find_t<_Float16, ProjHash, true, false>(a, p, cfg, s, ev);
+        case 2: return launch_find_t<_Float16, ProjHash, false, true>(a, p, cfg, s, ev);
+        case 3: return launch_find_t<_Float16, ProjHash, true, true>(a, p, cfg, s, ev);
+        default: return launch_find_t<_Float16, ProjHash, false, false>(a, p, cfg, s, ev);
+        }
+    }
+    switch (mode) {
+    case 1: return launch_find_t<float, ProjHash, true, false>(a, p, cfg, s, ev);
+    case 2: return launch_find_t<float, ProjHash, false, true>(a, p, cfg, s, ev);
+    case 3: return launch_find_t<float, ProjHash, true, true>(a, p, cfg, s, ev);
+    default: return launch_find_t<float, ProjHash, false, false>(a, p, cfg, s, ev);
+    }
 }
 
 // resident blocks per CU of a kernel (at least 1)
@@ -1988,7 +2052,7 @@ static hipError_t find_occupancy_t(int bins, int classes, int n_cu, LaunchCfg* c
     cfg->grid_mid2 = n_cu * b;
     if ((e = occ((const void*)k_small<float, ProjCSR, RW, ENT>, sm, &b)) != hipSuccess) return e;
     cfg->grid_small = n_cu * b;
-    if ((e = occ((const void*)k_sortblk<float, ProjCSR>, ss, &b)) != hipSuccess) return e;
+    if ((e = occ((const void*)k_sortblk<float, ProjCSR, ENT>, ss, &b)) != hipSuccess) return e;
     cfg->grid_sort = n_cu * b;
     if ((e = occ((const void*)k_brange<float, ProjCSR>, sm, &b)) != hipSuccess) return e;
     cfg->grid_brange = n_cu * b;

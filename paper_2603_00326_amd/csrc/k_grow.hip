@@ -504,6 +504,9 @@ static hipError_t level_launch(sof_forest* f, hipStream_t s) {
     a.node_bins = nullptr;
     a.bins = f->desc.bins;
     a.sort_threshold = clamp_threshold(f->desc.sort_threshold);
+    a.bin_mode = f->desc.bin_mode;
+    a.criterion = f->desc.criterion;
+    a.bin_seed = f->desc.bin_seed;
     a.out = f->b.splits;
     a.hist_out = nullptr;
     find_bind(f->flay, f->b.ws_find, &a.ws);
@@ -579,6 +582,10 @@ extern "C" int sof_forest_create(sof_ctx* ctx, const sof_data* data, const sof_f
     if (desc->bins < 2 || desc->bins > SOF_MAX_BINS) return fail(SOF_ERR_UNSUPPORTED, "bins %d", desc->bins);
     if (desc->sort_threshold < 0) return fail(SOF_ERR_INVALID_ARG, "sort_threshold < 0");
     if (desc->max_depth < 0 || desc->max_depth > 64) return fail(SOF_ERR_INVALID_ARG, "max_depth %d", desc->max_depth);
+    if (desc->criterion != SOF_CRIT_GINI && desc->criterion != SOF_CRIT_ENTROPY)
+        return fail(SOF_ERR_UNSUPPORTED, "criterion %d", desc->criterion);
+    if (desc->bin_mode != SOF_BINS_EQUAL && desc->bin_mode != SOF_BINS_RANDOM)
+        return fail(SOF_ERR_UNSUPPORTED, "bin_mode %d", desc->bin_mode);
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     sof_forest* f = new sof_forest();
@@ -598,10 +605,11 @@ extern "C" int sof_forest_create(sof_ctx* ctx, const sof_data* data, const sof_f
     if (maxroot > SOF_MAX_NODE_SAMPLES) { delete f; return fail(SOF_ERR_OVERFLOW, "root above 2^24 samples"); }
     f->cap_front = f->n_samples / 2 + desc->n_trees + 1;
     f->cap_nodes = 2 * f->n_samples + desc->n_trees + 2;
-    if ((rc = launch_cfg(ctx, desc->bins, data->n_classes, 0, &f->cfg))) { delete f; return rc; }
+    const int mode = (desc->bin_mode == SOF_BINS_RANDOM ? 1 : 0) | (desc->criterion == SOF_CRIT_ENTROPY ? 2 : 0);
+    if ((rc = launch_cfg(ctx, desc->bins, data->n_classes, mode, &f->cfg))) { delete f; return rc; }
     const int C = data->n_classes;
     const int64_t S = f->n_samples > 0 ? f->n_samples : 1, F = f->cap_front;
-    f->flay = find_layout(F, S, F * desc->k, desc->k, desc->bins, C);
+    f->flay = find_layout(F, S, F * desc->k, desc->k, desc->bins, C, flnk_entries(desc->criterion, maxroot));
     GrowBuffers& b = f->b;
     for (int i = 0; i < 2; ++i) {
         if ((rc = falloc(f, (void**)&b.off[i], (F + 1) * 4)) || (rc = falloc(f, (void**)&b.idx[i], S * 4)) ||

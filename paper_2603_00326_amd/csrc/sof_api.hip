@@ -248,8 +248,6 @@ int sof::check_params(const sof_params* q) {
         return fail(SOF_ERR_UNSUPPORTED, "bin_mode %d (expected SOF_BINS_EQUAL or SOF_BINS_RANDOM)", q->bin_mode);
     if (q->criterion != SOF_CRIT_GINI && q->criterion != SOF_CRIT_ENTROPY)
         return fail(SOF_ERR_UNSUPPORTED, "criterion %d (expected SOF_CRIT_GINI or SOF_CRIT_ENTROPY)", q->criterion);
-    if (q->criterion == SOF_CRIT_ENTROPY && q->sort_threshold != 0)
-        return fail(SOF_ERR_UNSUPPORTED, "the entropy criterion runs on the histogram path only (sort_threshold 0)");
     return SOF_OK;
 }
 

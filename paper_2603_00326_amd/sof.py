@@ -73,7 +73,8 @@ class sof_params(ctypes.Structure):
 class sof_forest_desc(ctypes.Structure):
     _fields_ = [("root_offsets", P), ("root_idx", P), ("seed", u64), ("n_trees", i32),
                 ("first_tree", i32), ("k", i32), ("z", i32), ("bins", i32), ("sort_threshold", i32),
-                ("max_depth", i32), ("sampler", i32), ("weights", i32), ("pad", i32)]
+                ("max_depth", i32), ("sampler", i32), ("weights", i32), ("criterion", i32), ("bin_mode", i32),
+                ("pad", i32), ("bin_seed", u64)]
 
 
 class sof_tune(ctypes.Structure):
@@ -410,7 +411,8 @@ class Forest:
 
     def __init__(self, ctx: Context, X, y, n_classes: int, root_offsets, root_idx, *, k: int, z: int,
                  seed: int, bins: int = 256, sort_threshold: int = 0, max_depth: int = 64,
-                 first_tree: int = 0, sampler: int = 0, weights: int = 0):
+                 first_tree: int = 0, sampler: int = 0, weights: int = 0, criterion: int = SOF_CRIT_GINI,
+                 bin_mode: int = SOF_BINS_EQUAL, bin_seed: int = 0):
         self.ctx = ctx
         self._keep = (X, y, root_idx)
         dtype = SOF_F16 if str(X.dtype) == "torch.float16" else SOF_F32
@@ -421,7 +423,8 @@ class Forest:
         self.n_trees = len(ro) - 1
         self.desc = sof_forest_desc(ro.ctypes.data, _ptr(root_idx), int(seed) & (2**64 - 1), self.n_trees,
                                     int(first_tree), int(k), int(z), int(bins), int(sort_threshold),
-                                    int(max_depth), int(sampler), int(weights), 0)
+                                    int(max_depth), int(sampler), int(weights), int(criterion), int(bin_mode), 0,
+                                    int(bin_seed) & (2**64 - 1))
         h = P()
         _check(lib().sof_forest_create(ctx.handle, ctypes.byref(self.data), ctypes.byref(self.desc),
                                        ctypes.byref(h)))

@@ -134,7 +134,6 @@ def test_workspace_size_of_valid_arguments(S, L):
     ("params", dict(bin_mode=2), UNSUPPORTED),
     ("params", dict(bin_mode=-1), UNSUPPORTED),
     ("params", dict(criterion=2), UNSUPPORTED),
-    ("params", dict(criterion=1, sort_threshold=64), UNSUPPORTED),
 ])
 def test_workspace_size_rejects(S, L, part, kw, code):
     args = {"d": None, "f": None, "p": None, "q": None}

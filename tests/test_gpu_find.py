@@ -205,14 +205,26 @@ def test_random_width_bins(ctx, T, C, B, dt):
 @pytest.mark.parametrize("C,B,dt,bm", [(2, 256, np.float32, 0), (3, 7, np.float32, 0), (16, 256, np.float16, 0),
                                         (4, 128, np.float32, 1)])
 def test_entropy_criterion(ctx, C, B, dt, bm):
+    run_entropy_case(C, B, dt, bm, 0)
+
+
+@pytest.mark.parametrize("T,C,dt", [(2**31 - 1, 3, np.float32), (2**31 - 1, 16, np.float16), (300, 2, np.float32),
+                                    (300, 4, np.float16), (64, 3, np.float32)])
+def test_entropy_sort_path(ctx, T, C, dt):
+    """Entropy on the sort path (every size class below T sorts, up to the
+    sort limit) and on mixed frontiers, against the oracle's entropy sort path."""
+    run_entropy_case(C, 256, dt, 0, T)
+
+
+def run_entropy_case(C, B, dt, bm, T):
     import torch
     from paper_2603_00326_amd import sof as S
     wl = W.random_frontier(81 + C, n_rows=90000, d=14, n_classes=C, sizes=EDGE_SIZES, k=5, z=(1, 6),
-                           bins=B, sort_threshold=0, layout="r", dtype=dt)
-    say(f"[gpu] entropy C={C} B={B} dtype={np.dtype(dt).name} bin_mode={bm}")
+                           bins=B, sort_threshold=T, layout="r", dtype=dt)
+    say(f"[gpu] entropy C={C} B={B} dtype={np.dtype(dt).name} bin_mode={bm} T={T}")
     ctx = S.Context(0)   # a fresh workspace, sized for this call alone
     dev = S.to_device(wl)
-    out, H = S.find_splits(ctx, dev, bins=B, sort_threshold=0, hist=True, bin_mode=bm, bin_seed=77,
+    out, H = S.find_splits(ctx, dev, bins=B, sort_threshold=T, hist=True, bin_mode=bm, bin_seed=77,
                            criterion=S.SOF_CRIT_ENTROPY)
     out_idx, coff = S.partition(ctx, dev, out, bins=B)
     torch.cuda.synchronize()

@@ -20,12 +20,13 @@ def ctx():
 
 
 def grow_case(ctx, *, seed, d, n, C, trees, k, z, bins, T, max_depth=64, graph=True, dtype=np.float32,
-              stats=False, sampler=0, weights=0, first_tree=0):
+              stats=False, sampler=0, weights=0, first_tree=0, criterion=0, bin_mode=0, bin_seed=0):
     import torch
     from paper_2603_00326_amd import sof as S
     say(f"[gpu] grow seed={seed} d={d} n={n} C={C} trees={trees} k={k} z={z} B={bins} T={T} "
         f"max_depth={max_depth} graph={graph} dtype={np.dtype(dtype).name} sampler={sampler} weights={weights} "
-        f"first_tree={first_tree}")
+        f"first_tree={first_tree} criterion={criterion} bin_mode={bin_mode}")
+    modes = dict(criterion=criterion, bin_mode=bin_mode, bin_seed=bin_seed)
     rng = np.random.default_rng(seed)
     X = rng.standard_normal((d, n)).astype(np.float32)
     if dtype == np.float16:
@@ -37,11 +38,11 @@ def grow_case(ctx, *, seed, d, n, C, trees, k, z, bins, T, max_depth=64, graph=T
     ri = np.concatenate(roots)
     ref, ref_levels, ref_units = O.grow_forest(X, y, C, ro, ri, k=k, z=z, seed=seed + 7, bins=bins,
                                                sort_threshold=T, max_depth=max_depth, sampler=sampler,
-                                               weights=weights, first_tree=first_tree)
+                                               weights=weights, first_tree=first_tree, **modes)
     Xd = torch.from_numpy(X.astype(dtype)).to("cuda:0")
     f = S.Forest(ctx, Xd, torch.from_numpy(y).to("cuda:0"), C, ro, torch.from_numpy(ri).to("cuda:0"),
                  k=k, z=z, seed=seed + 7, bins=bins, sort_threshold=T, max_depth=max_depth, sampler=sampler,
-                 weights=weights, first_tree=first_tree)
+                 weights=weights, first_tree=first_tree, **modes)
     if stats:
         sizes, units = [], []
         while True:
@@ -177,3 +178,26 @@ def test_full_training_tree0_against_oracle(ctx):
         else:
             bad = np.nonzero(np.any((got[fld] != ref[fld]).reshape(len(ref), -1), axis=1))[0]
             assert bad.size == 0, f"field {fld} differs at node {bad[0]}: {got[bad[0]]} vs {ref[bad[0]]}"
+
+
+# ---------------------------------------------------------------------------
+# growth under the entropy criterion and with random-width bins (keyed by
+# tree position), on every path: sort below T, small/mid histograms, and
+# roots above 8192 samples (big-node passes)
+
+@pytest.mark.parametrize("criterion,bin_mode,T,graph", [(1, 0, 50, True), (1, 0, 0, False), (0, 1, 50, True),
+                                                        (1, 1, 30, False), (1, 0, 2**31 - 1, True)])
+def test_grow_entropy_and_random_width_bins(ctx, criterion, bin_mode, T, graph):
+    grow_case(ctx, seed=57, d=10, n=600, C=3, trees=3, k=6, z=2, bins=64, T=T, graph=graph,
+              criterion=criterion, bin_mode=bin_mode, bin_seed=1234)
+
+
+@pytest.mark.parametrize("criterion,bin_mode,dtype", [(1, 0, np.float32), (0, 1, np.float16), (1, 1, np.float32)])
+def test_grow_entropy_and_random_width_big_roots(ctx, criterion, bin_mode, dtype):
+    grow_case(ctx, seed=58, d=16, n=20000, C=2, trees=2, k=8, z=3, bins=256, T=40, max_depth=4, graph=True,
+              dtype=dtype, criterion=criterion, bin_mode=bin_mode, bin_seed=77)
+
+
+def test_grow_density_sampler_entropy_random_width(ctx):
+    grow_case(ctx, seed=59, d=24, n=800, C=4, trees=2, k=6, z=3, bins=128, T=60, graph=True, sampler=1,
+              weights=1, criterion=1, bin_mode=1, bin_seed=5)

@@ -671,8 +671,16 @@ SAMPLERS = [(O.SAMPLER_FIXED, O.WEIGHTS_SIGN), (O.SAMPLER_DENSITY, O.WEIGHTS_UNI
             (O.SAMPLER_DENSITY, O.WEIGHTS_SIGN)]
 
 
-@pytest.mark.parametrize("sampler,weights", SAMPLERS)
-def test_growth_to_purity_small(sampler, weights):
+# (criterion, bin layout) of growth: Gini or entropy, equal- or random-width bins
+GROW_MODES = [(O.CRIT_GINI, O.BINS_EQUAL), (O.CRIT_ENTROPY, O.BINS_EQUAL), (O.CRIT_GINI, O.BINS_RANDOM),
+              (O.CRIT_ENTROPY, O.BINS_RANDOM)]
+GROW_CASES = [(s, w, O.CRIT_GINI, O.BINS_EQUAL) for s, w in SAMPLERS] + \
+             [(O.SAMPLER_FIXED, O.WEIGHTS_SIGN, c, b) for c, b in GROW_MODES[1:]] + \
+             [(O.SAMPLER_DENSITY, O.WEIGHTS_UNIFORM, O.CRIT_ENTROPY, O.BINS_RANDOM)]
+
+
+@pytest.mark.parametrize("sampler,weights,criterion,bin_mode", GROW_CASES)
+def test_growth_to_purity_small(sampler, weights, criterion, bin_mode):
     rng = np.random.default_rng(51)
     d, n, C = 10, 400, 3
     X = rng.standard_normal((d, n)).astype(np.float32)
@@ -681,8 +689,14 @@ def test_growth_to_purity_small(sampler, weights):
     ro = np.array([0, n, 2 * n, 3 * n], np.int64)
     ri = np.concatenate(roots)
     nodes, ln, lu = O.grow_forest(X, y, C, ro, ri, k=6, z=2, seed=9, bins=64, sort_threshold=50,
-                                  sampler=sampler, weights=weights)
+                                  sampler=sampler, weights=weights, criterion=criterion, bin_mode=bin_mode,
+                                  bin_seed=31)
     assert ln[0] == 3
+    # the split kinds follow the switch and the bin layout: sort below 50
+    # samples, random-width (kind 2) or equal-width (kind 0) histograms above
+    internal_ = nodes[nodes["is_leaf"] == 0]
+    hist_kind = 2 if bin_mode == O.BINS_RANDOM else 0
+    assert np.all(internal_["kind"] == np.where(internal_["n_samples"] < 50, 1, hist_kind))
     for t in range(3):
         for r in roots[t]:
             leaf = _route(nodes, X, int(r), t)
@@ -726,20 +740,56 @@ def renumber_tree(nodes, t):
     return out
 
 
-@pytest.mark.parametrize("sampler,weights", SAMPLERS)
-def test_growth_batched_equals_single_tree(sampler, weights):
+@pytest.mark.parametrize("sampler,weights,criterion,bin_mode", GROW_CASES)
+def test_growth_batched_equals_single_tree(sampler, weights, criterion, bin_mode):
+    # Random-width bins of growth are keyed by tree position, so a node's bins
+    # (and hence every tree) do not depend on the other trees of the batch; a
+    # key taken from the node's place in the batched frontier would fail this.
     rng = np.random.default_rng(52)
     d, n, C = 8, 300, 2
     X = rng.standard_normal((d, n)).astype(np.float32)
     y = rng.integers(0, C, size=n).astype(np.int32)
     roots = [np.sort(np.random.default_rng(100 + t).integers(0, n, n)).astype(np.int32) for t in range(3)]
     ro = np.array([0, n, 2 * n, 3 * n], np.int64)
+    kw = dict(sampler=sampler, weights=weights, criterion=criterion, bin_mode=bin_mode, bin_seed=5)
     nodes, _, _ = O.grow_forest(X, y, C, ro, np.concatenate(roots), k=5, z=2, seed=4, bins=32,
-                                sort_threshold=20, sampler=sampler, weights=weights)
+                                sort_threshold=20, **kw)
     for t in range(3):
         single, _, _ = O.grow_forest(X, y, C, np.array([0, n], np.int64), roots[t], k=5, z=2, seed=4,
-                                     bins=32, sort_threshold=20, first_tree=t, sampler=sampler, weights=weights)
+                                     bins=32, sort_threshold=20, first_tree=t, **kw)
         assert renumber_tree(nodes, t).tobytes() == single.tobytes()
+
+
+def test_growth_random_width_key_is_the_tree_position():
+    """The random-width bins of a grown node come from the width stream keyed
+    by (tree, level, pos, p): rebuilding the root's split from its recorded
+    projection, the keyed boundaries over the root's [lo, hi] and the
+    oracle's one-level search at that key reproduces the recorded threshold."""
+    rng = np.random.default_rng(53)
+    d, n, C = 6, 500, 2
+    X = rng.standard_normal((d, n)).astype(np.float32)
+    y = (X[0] + X[1] > 0).astype(np.int32)
+    ri = np.arange(n, dtype=np.int32)
+    tree = 7
+    nodes, _, _ = O.grow_forest(X, y, C, np.array([0, n], np.int64), ri, k=4, z=2, seed=3, bins=16,
+                                max_depth=1, first_tree=tree, bin_mode=O.BINS_RANDOM, bin_seed=99)
+    root = nodes[0]
+    assert root["is_leaf"] == 0 and root["kind"] == 2
+    z = int(root["nnz"])
+    v = np.array([O.project_value(X, root["feature"][:z], root["weight"][:z], r) for r in range(n)], np.float32)
+    lo, hi = v.min(), v.max()
+    assert np.float32(root["lo"]) == lo
+    # which of the node's 4 projections won is not recorded; one of the keys
+    # (tree, level 0, pos 0, p) must give boundaries containing the threshold
+    # at the recorded bin, and routing by it must give the recorded children
+    hits = []
+    for p in range(4):
+        t = O.rw_boundaries(99, O.counter(tree, 0, 0, p, 0) >> 4, 16, lo, hi)
+        if np.float32(t[root["bin"]]) == np.float32(root["threshold"]):
+            hits.append(p)
+    assert hits, "no keyed boundary matches the recorded threshold"
+    left = int(np.sum(v < root["threshold"]))
+    assert left == nodes[root["left"]]["n_samples"]
 
 
 # --------------------------------------------------------------------------
