@@ -319,7 +319,7 @@ def run_growth(args, S, ctx):
     torch.cuda.synchronize()
     T, tune = args.threshold, None
     if T is None:
-        tune = S.autotune(ctx, C, k, z, bins, dtype=np.float32)
+        tune = S.autotune(ctx, C, k, z, bins, data=(Xd, yd, C))
         T = int(tune["sort_threshold"])
     log(f"[bench] sort threshold T={T}")
     stream = torch.cuda.current_stream()
@@ -444,7 +444,7 @@ def run_accuracy(args, S, ctx):
     ri = np.concatenate([np.sort(np.random.default_rng(1000 + t).integers(0, n, n)) for t in range(trees)])
     rid = torch.from_numpy(ri.astype(np.int32)).to(dev_name)
     ro = np.arange(trees + 1, dtype=np.int64) * n
-    tune = S.autotune(ctx, C, k, z, bins, dtype=np.float32)
+    tune = S.autotune(ctx, C, k, z, bins, data=(Xd, yd, C))
     out = {}
     # dynamic: the threshold this GPU's autotuner picks, and the paper's CPU breakeven (~1200 samples)
     for name, T in (("exact", 2**31 - 1), ("histogram", 0), ("dynamic", int(tune["sort_threshold"])),
@@ -488,6 +488,8 @@ def main():
                     help="config 3: nodes below this size take half the bins (default: the autotuner's "
                          "rule; 0 = full bins everywhere)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--project", type=int, default=1,
+                    help="also time step 1 alone (sof_project) after the timed loop (0 skips it)")
     ap.add_argument("--plain", type=int, default=2,
                     help="steps of the per-node-launch form (0 skips it)")
     ap.add_argument("--cpu-units", type=float, default=3e9,
@@ -537,7 +539,7 @@ def main():
     per_node_bins = args.workload.startswith("c3")   # config 3: 128-256 bins per node
     if T is None or (per_node_bins and args.bins_switch is None):
         tune = S.autotune(ctx, wl.n_classes, int(wl.meta.get("k", 64)), int(wl.meta.get("z", 3)), wl.bins,
-                          dtype=wl.X.dtype)
+                          data=dev)
         if T is None:
             T = int(tune["sort_threshold"])
     if wl.meta.get("criterion", 0):
@@ -580,15 +582,27 @@ def main():
     ctx.timing(False)
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     value = wl.units / (ms_per_step * 1e-3)
+    # Per-kernel figures, after the timed region: a few calls with the size
+    # classes serialised, so that each stage's events bound its own kernels
+    # (in the timed calls the classes share the GPU and a stage's events also
+    # span its wait for compute units).
+    ctx.timing(True, serial=True)
+    ctx.timing_read()
+    for _ in range(5):
+        step()
+    torch.cuda.synchronize()
+    serial_ms, scalls = ctx.timing_read()
+    ctx.timing(False)
 
     splits = S.splits_to_numpy(out)[:wl.n_nodes]
     sb = stage_bytes(wl, T)
     per = {k: v / max(calls, 1) for k, v in stage_ms.items()}
+    sper = {k: v / max(scalls, 1) for k, v in serial_ms.items()}
     data_stages = ("big_range", "big_hist", "mid", "mid2", "small", "sort")
-    dom = max(data_stages, key=lambda s: per[s])
+    dom = max(data_stages, key=lambda s: sper[s])
     kernel_name = {"big_range": "k_brange", "big_hist": "k_bhist", "mid": "k_mid", "mid2": "k_mid_large",
                    "small": "k_small", "sort": "k_sortblk"}[dom]
-    achieved = sb[dom] / (per[dom] * 1e-3) / 1e9 if per[dom] > 0 else 0.0
+    achieved = sb[dom] / (sper[dom] * 1e-3) / 1e9 if sper[dom] > 0 else 0.0
     find_gbs = sb["find"] / (per["total"] * 1e-3) / 1e9 if per["total"] > 0 else 0.0
     # the headline is the whole batched split search (every kernel of one
     # find_splits call, between the events around it); the slowest data
@@ -601,7 +615,8 @@ def main():
             "dominant_kernel": {"kernel": kernel_name, "achieved": round(achieved, 1),
                                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                                 "traffic": measured_traffic(kernel_name, args.workload),
-                                "bytes_per_launch": sb[dom], "ms_per_launch": round(per[dom], 5)}}
+                                "bytes_per_launch": sb[dom], "ms_per_launch": round(sper[dom], 5),
+                                "timing": "5 calls after the timed region with the size classes serialised"}}
     bmin = bmin_bytes(wl, T)
     bmin_gbs = bmin / (per["total"] * 1e-3) / 1e9 if per["total"] > 0 else 0.0
     pb = partition_bytes(wl, splits)
@@ -633,11 +648,38 @@ def main():
                         "bmin_bytes": bmin, "bmin_GBs": round(bmin_gbs, 1),
                         "bmin_frac": round(bmin_gbs / HBM_PEAK_GBS, 4),
                         "stage_ms": {k: round(v, 4) for k, v in per.items()},
+                        "stage_ms_serialised": {k: round(v, 4) for k, v in sper.items()},
                         "stage_bytes": sb},
         "partition": {"algorithmic_bytes": pb},
     }
     if tune:
         result["autotune"] = tune
+
+    if args.project:
+        # step 1 alone through sof_project: every (node, projection, sample)
+        # value written out, [projection][sample] per node
+        n_v = np.diff(wl.node_offsets.astype(np.int64))
+        k_v = np.diff(wl.proj_offsets.astype(np.int64))
+        S.project(ctx, dev)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 5
+        e0.record(stream)
+        for _ in range(reps):
+            S.project(ctx, dev)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        pms = e0.elapsed_time(e1) / reps
+        sx = wl.X.dtype.itemsize
+        zsum = np.add.reduceat(np.diff(wl.nz_offsets.astype(np.int64)), wl.proj_offsets[:-1].astype(np.int64)) \
+            if wl.n_proj else np.zeros(len(n_v), np.int64)
+        pbytes = float((n_v * (4 + np.where(k_v > 0, zsum, 0) * sx + 4 * k_v)).sum())
+        result["project"] = {"ms": round(pms, 4), "units_per_s": wl.units / (pms * 1e-3),
+                             "algorithmic_bytes": pbytes,
+                             "achieved_GBs": round(pbytes / (pms * 1e-3) / 1e9, 1),
+                             "frac": round(pbytes / (pms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                             "note": "sof_project alone: sample ids read once per node, z columns gathered and "
+                                     "one FP32 value written per (node, projection, sample)"}
 
     if args.plain > 0:
         log(f"[bench] plain per-node form: {wl.n_nodes} single-node calls per step")

@@ -368,18 +368,29 @@ int sof_predict(sof_ctx* ctx, const sof_data* data, const sof_tree_node* nodes, 
 
 /* Crossover microbenchmark (section 4.1: run once before training, a search
  * for the node size where histograms overtake sorting): times the sort and
- * histogram paths on synthetic frontiers of equal nodes of growing size, on
- * this device, with the caller's storage type (SOF_F32 or SOF_F16), class
- * count, projections per node (capped at 64 for timing), nonzeros per
- * projection and bin count.  Picks the sort threshold (the smallest measured
- * size from which the histogram path is never slower) and a bin-count switch
- * for small nodes (half the bins below the smallest measured size from which
- * full bins cost at most 10% more than half bins at every larger size; 0 when
- * that holds everywhere).  Allocates its own device buffers, frees
+ * histogram paths on synthetic frontiers (2^16 rows) of equal nodes of
+ * growing size (2 .. 8192), on this device, with the caller's storage type
+ * (SOF_F32 or SOF_F16), class count, projections per node (capped at 64 for
+ * timing), nonzeros per projection and bin count.  Picks the sort threshold
+ * (the smallest measured size from which the histogram path is never slower;
+ * sizes above two consecutive histogram wins are not sorted, their sort_us is
+ * 0) and a bin-count switch for small nodes (half the bins below the smallest
+ * measured size from which full bins cost at most 10% more than half bins at
+ * every larger size, half bins being timed up to 1024 samples; 0 when that
+ * holds everywhere).  Allocates its own device buffers, frees
  * them, and synchronises `stream`.  Errors: SOF_ERR_INVALID_ARG (NULL, k or
  * nnz out of range), SOF_ERR_UNSUPPORTED (dtype, classes, bins), SOF_ERR_HIP. */
 int sof_autotune(sof_ctx* ctx, int32_t dtype, int32_t n_classes, int32_t k, int32_t nnz, int32_t bins,
                  sof_tune* out, void* stream);
+
+/* The same microbenchmark on the caller's own data: the frontiers take rows
+ * 0 .. min(n_rows, 2^16) - 1 of data (its labels and its first min(d, 64)
+ * features, its storage type and class count), so the crossover reflects the
+ * caller's value distribution.  data must stay valid during the call.
+ * Errors: as sof_autotune, and SOF_ERR_INVALID_ARG when data has fewer
+ * features than nnz. */
+int sof_autotune_on(sof_ctx* ctx, const sof_data* data, int32_t k, int32_t nnz, int32_t bins,
+                    sof_tune* out, void* stream);
 
 /* Benchmark instrumentation.  The launch sequence of sof_find_splits runs in
  * these stages, in this order: */
@@ -409,6 +420,9 @@ enum {
  * SOF_STAGE_COUNT + 1 floats), and the number of calls.  Errors:
  * SOF_ERR_INVALID_ARG for NULL arguments, SOF_ERR_HIP if an event query
  * fails. */
+/* enable: 0 off, 1 on, 2 on with the size classes run one after another on
+ * the caller's stream (no fork), so that each stage's events bound its own
+ * kernels alone; for measurement only. */
 int sof_timing_enable(sof_ctx* ctx, int enable);
 int sof_timing_read(sof_ctx* ctx, float* ms, int32_t* calls);
 

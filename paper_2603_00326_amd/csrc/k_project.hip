@@ -1,6 +1,11 @@
 // k_project.hip -- step 1 alone (paper section 4, step 1: the projected
 // feature of every active sample as a sum of weighted columns) and the
 // device-side content checks enabled by SOF_CHECK=1.
+//
+//   k_proj_sizes + k_scan_excl_1blk   output offset of every node (sum n_v k_v)
+//   k_pj_plan    (node, group of 4 projections, 8192-sample chunk) items
+//   k_project    one block per item, one wave per projection, 16 samples per
+//                lane per step with every column's loads issued together
 #include <cstring>
 
 #include "sof_device.h"
@@ -52,51 +57,116 @@ __global__ __launch_bounds__(1024) void k_scan_excl_1blk(int64_t* a, int N) {
     }
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_project(FindArgs A, ProjCSR P, const int64_t* out_off, float* out) {
-    extern __shared__ __align__(16) char smem[];
-    int32_t* lf = (int32_t*)smem;        // staged nonzeros
-    uint32_t* ls = (uint32_t*)(lf + 16);
-    int& s_z = *(int*)(ls + 16);
-    int& s_v = *(&s_z + 1);
+// Work items of the projection: (node, group of kPjGroup projections, chunk
+// of kPjChunk samples), one block each, wave w taking projection
+// kPjGroup * group + w.  The plan writes them with wave-aggregated
+// allocation; a wave writes the items of its nodes together.
+constexpr int kPjGroup = 4;          // projections per item (one per wave)
+constexpr int kPjChunk = 8192;       // samples per item
+constexpr int kPjR = 16;             // samples per lane per step
+
+__global__ __launch_bounds__(256) void k_pj_plan(FindArgs A, ProjCSR P, int32_t* hdr, int4* items,
+                                                 int64_t cap) {
     const int N = A.n_nodes;
-    for (int q = blockIdx.x; q < P.n_proj; q += gridDim.x) {
-        if (threadIdx.x == 0) {
-            // node owning projection q: last v with proj_offsets[v] <= q
-            int lo = 0, hi = N;
-            while (hi - lo > 1) {
-                int mid = (lo + hi) >> 1;
-                if (P.proj_offsets[mid] <= q) lo = mid; else hi = mid;
-            }
-            s_v = lo;
-            int64_t j0 = clampj(P.nz_offsets[q], 0, P.n_nz), j1 = clampj(P.nz_offsets[q + 1], j0, P.n_nz);
-            if (j1 - j0 > SOF_MAX_NNZ) j1 = j0 + SOF_MAX_NNZ;
-            s_z = (int)(j1 - j0);
-            for (int j = 0; j < s_z; ++j) {
-                uint32_t f = (uint32_t)P.nz_feature[j0 + j];
-                lf[j] = f < (uint32_t)A.n_features ? (int)f : 0;
-                ls[j] = csr_weight_bits(P, j0 + j);
-            }
+    const int lane = lane_id();
+    for (int v0 = blockIdx.x * 256; v0 < N; v0 += gridDim.x * 256) {
+        const int v = v0 + threadIdx.x;
+        int cnt = 0, ng = 0, nch = 0;
+        if (v < N) {
+            const int64_t a = clampj(A.node_offsets[v], 0, A.n_samples);
+            const int64_t n = clampj(A.node_offsets[v + 1], a, A.n_samples) - a;
+            const int64_t pa = clampj(P.proj_offsets[v], 0, P.n_proj);
+            const int k = (int)(clampj(P.proj_offsets[v + 1], pa, P.n_proj) - pa);
+            ng = (k + kPjGroup - 1) / kPjGroup;
+            nch = (int)((n + kPjChunk - 1) / kPjChunk);
+            cnt = ng * nch;
         }
+        const int ctr[1] = {0};
+        const int c[1] = {cnt};
+        int o[1];
+        wave_alloc_n<1>(hdr, ctr, c, o);
+        uint64_t m = __ballot(cnt > 0);
+        while (m) {
+            const int src = __builtin_ctzll(m);
+            m &= m - 1;
+            const int bv = __builtin_amdgcn_readlane(v, src);
+            const int bn = __builtin_amdgcn_readlane(cnt, src);
+            const int bch = __builtin_amdgcn_readlane(nch, src);
+            const int bo = __builtin_amdgcn_readlane(o[0], src);
+            for (int t = lane; t < bn; t += kWave)
+                if (bo + (int64_t)t < cap) items[bo + t] = make_int4(bv, t / bch, t % bch, 0);
+        }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_project(FindArgs A, ProjCSR P, const int64_t* out_off, float* out,
+                                                 int32_t* hdr, const int4* items, int64_t cap) {
+    __shared__ int s_item;
+    __shared__ int32_t s_lf[kPjGroup][16];
+    __shared__ uint32_t s_ls[kPjGroup][16];
+    const int w = threadIdx.x >> 6, lane = lane_id();
+    const int ni = (int)(hdr[0] < cap ? hdr[0] : cap);
+    for (;;) {
         __syncthreads();
-        const int v = s_v, z = s_z;
+        if (threadIdx.x == 0) s_item = atomicAdd(&hdr[1], 1);
+        __syncthreads();
+        const int it = s_item;
+        if (it >= ni) break;
+        const int4 e = items[it];
+        const int v = e.x;
+        if (v < 0 || v >= A.n_nodes) continue;
         const int64_t a = clampj(A.node_offsets[v], 0, A.n_samples);
         const int64_t n = clampj(A.node_offsets[v + 1], a, A.n_samples) - a;
-        const int p = q - (int)clampj(P.proj_offsets[v], 0, P.n_proj);
-        const int kv = (int)(clampj(P.proj_offsets[v + 1], 0, P.n_proj) - clampj(P.proj_offsets[v], 0, P.n_proj));
-        if (p < 0 || p >= kv) { __syncthreads(); continue; }
-        float* dst = out + out_off[v] + (int64_t)p * n;
-        for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-            uint32_t r = (uint32_t)A.sample_idx[a + i];
-            const int row = r < (uint32_t)A.n_rows ? (int)r : 0;
-            float acc = 0.f;
-            for (int j = 0; j < z; ++j) {
-                const T* col = (const T*)A.x + (int64_t)lf[j] * A.ld;
-                acc = __fadd_rn(acc, weighted_term(ldx(col, row), ls[j]));
-            }
-            dst[i] = acc;
+        const int64_t pa = clampj(P.proj_offsets[v], 0, P.n_proj);
+        const int k = (int)(clampj(P.proj_offsets[v + 1], pa, P.n_proj) - pa);
+        const int p = e.y * kPjGroup + w;
+        if (p >= k) continue;   // whole wave: no block barrier below
+        // stage the wave's projection (lane j: nonzero j)
+        const int64_t j0 = clampj(P.nz_offsets[pa + p], 0, P.n_nz);
+        int64_t j1 = clampj(P.nz_offsets[pa + p + 1], j0, P.n_nz);
+        if (j1 - j0 > SOF_MAX_NNZ) j1 = j0 + SOF_MAX_NNZ;
+        const int z = __builtin_amdgcn_readfirstlane((int)(j1 - j0));
+        if (lane < z) {
+            const uint32_t f = (uint32_t)P.nz_feature[j0 + lane];
+            s_lf[w][lane] = f < (uint32_t)A.n_features ? (int)f : 0;
+            s_ls[w][lane] = csr_weight_bits(P, j0 + lane);
         }
-        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        const int64_t c0 = (int64_t)e.z * kPjChunk;
+        const int cn = (int)clampj(n - c0, 0, kPjChunk);
+        const int32_t* sidx = A.sample_idx + a + c0;
+        float* dst = out + out_off[v] + (int64_t)p * n + c0;
+        for (int i0 = 0; i0 < cn; i0 += kWave * kPjR) {
+            // slots past the chunk's end repeat its last sample (valid
+            // addresses, every column's loads issued together) and are not stored
+            uint32_t off[kPjR];
+#pragma unroll
+            for (int r = 0; r < kPjR; ++r) {
+                const int i = i0 + r * kWave + lane;
+                const uint32_t row = (uint32_t)sidx[i < cn ? i : cn - 1];
+                off[r] = (row < (uint32_t)A.n_rows ? row : 0u) * (uint32_t)sizeof(T);
+            }
+            float val[kPjR];
+#pragma unroll
+            for (int r = 0; r < kPjR; ++r) val[r] = 0.f;
+            for (int j = 0; j < z; ++j) {
+                const int f = __builtin_amdgcn_readfirstlane(s_lf[w][j]);
+                const uint32_t sg = __builtin_amdgcn_readfirstlane(s_ls[w][j]);
+                const T* col = (const T*)A.x + (int64_t)f * A.ld;
+                float x[kPjR];
+#pragma unroll
+                for (int r = 0; r < kPjR; ++r) x[r] = ldx((const T*)((const char*)col + off[r]), 0);
+#pragma unroll
+                for (int r = 0; r < kPjR; ++r) val[r] = __fadd_rn(val[r], weighted_term(x[r], sg));
+            }
+#pragma unroll
+            for (int r = 0; r < kPjR; ++r) {
+                const int i = i0 + r * kWave + lane;
+                if (i < cn) dst[i] = val[r];
+            }
+        }
     }
 }
 
@@ -158,7 +228,19 @@ __global__ void k_check(sof_data D, sof_frontier F, sof_proj P, sof_params Q, in
     if (bad) atomicOr(flag, bad);
 }
 
-size_t project_workspace(int64_t n_nodes) { return ((size_t)(n_nodes + 1) * sizeof(int64_t) + 255) & ~(size_t)255; }
+// Workspace: the output offsets (N + 1 int64), two counters, the items.  A
+// node has ceil(k/4) ceil(n/8192) items, at most (k + 3)(n + 8191) / 32768;
+// summed over nodes (k <= 1024) that is below S/32 + 3S/32768 + P/4 + N,
+// which the capacity covers.
+static int64_t pj_items_cap(int64_t n_nodes, int64_t n_samples, int64_t n_proj) {
+    return n_proj / 4 + n_nodes + n_samples / kPjChunk + (1024 / kPjGroup + 1) * (n_samples / kPjChunk + 1) + 1;
+}
+size_t project_workspace(int64_t n_nodes, int64_t n_samples, int64_t n_proj) {
+    size_t o = ((size_t)(n_nodes + 1) * sizeof(int64_t) + 255) & ~(size_t)255;
+    o += 256;   // counters
+    o += (size_t)pj_items_cap(n_nodes, n_samples, n_proj) * sizeof(int4);
+    return (o + 255) & ~(size_t)255;
+}
 
 int device_check(sof_ctx* ctx, const sof_data* data, const sof_frontier* fr, const sof_proj* proj,
                  const sof_params* params, hipStream_t s) {
@@ -189,10 +271,18 @@ int device_check(sof_ctx* ctx, const sof_data* data, const sof_frontier* fr, con
     return SOF_OK;
 }
 
+__global__ void k_pj_reset(int32_t* hdr) {
+    if (threadIdx.x < 2) hdr[threadIdx.x] = 0;
+}
+
 hipError_t launch_project(const FindArgs& a, const ProjCSR& p, float* out, void* ws, int n_cu,
                           hipStream_t s) {
     int64_t* off = (int64_t*)ws;
     const int N = a.n_nodes;
+    char* b = (char*)ws + (((size_t)(N + 1) * sizeof(int64_t) + 255) & ~(size_t)255);
+    int32_t* hdr = (int32_t*)b;
+    int4* items = (int4*)(b + 256);
+    const int64_t cap = pj_items_cap(N, a.n_samples, p.n_proj);
     int g = (N + 255) / 256;
     if (g > 4 * n_cu) g = 4 * n_cu;
     if (g < 1) g = 1;
@@ -200,10 +290,14 @@ hipError_t launch_project(const FindArgs& a, const ProjCSR& p, float* out, void*
                        p.n_proj, off);
     hipLaunchKernelGGL(k_scan_excl_1blk, dim3(1), dim3(1024), 17 * sizeof(int64_t), s, off, N);
     if (p.n_proj > 0) {
+        hipLaunchKernelGGL(k_pj_reset, dim3(1), dim3(64), 0, s, hdr);
+        hipLaunchKernelGGL(k_pj_plan, dim3(g), dim3(256), 0, s, a, p, hdr, items, cap);
         if (a.dtype == SOF_F16)
-            hipLaunchKernelGGL(k_project<_Float16>, dim3(n_cu * 8), dim3(256), 256, s, a, p, (const int64_t*)off, out);
+            hipLaunchKernelGGL(k_project<_Float16>, dim3(n_cu * 8), dim3(256), 0, s, a, p, (const int64_t*)off, out,
+                               hdr, (const int4*)items, cap);
         else
-            hipLaunchKernelGGL(k_project<float>, dim3(n_cu * 8), dim3(256), 256, s, a, p, (const int64_t*)off, out);
+            hipLaunchKernelGGL(k_project<float>, dim3(n_cu * 8), dim3(256), 0, s, a, p, (const int64_t*)off, out,
+                               hdr, (const int4*)items, cap);
     }
     return hipGetLastError();
 }
@@ -218,7 +312,7 @@ extern "C" int sof_project(sof_ctx* ctx, const sof_data* data, const sof_frontie
     int rc;
     if ((rc = check_data(data)) || (rc = check_frontier(fr)) || (rc = check_proj(proj, data))) return rc;
     if (proj->n_proj > 0 && fr->n_samples > 0 && !out) return fail(SOF_ERR_INVALID_ARG, "out is NULL");
-    if ((rc = check_ws_public(ws, ws_bytes, project_workspace(fr->n_nodes)))) return rc;
+    if ((rc = check_ws_public(ws, ws_bytes, project_workspace(fr->n_nodes, fr->n_samples, proj->n_proj)))) return rc;
     if (fr->n_nodes == 0) return SOF_OK;
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");

@@ -133,6 +133,7 @@ extern "C" int sof_destroy(sof_ctx* ctx) {
 extern "C" int sof_timing_enable(sof_ctx* ctx, int enable) {
     if (!ctx) return fail(SOF_ERR_INVALID_ARG, "ctx is NULL");
     ctx->timing = enable != 0;
+    ctx->timing_serial = enable == 2;
     ctx->tev_used = 0;
     return SOF_OK;
 }
@@ -343,7 +344,7 @@ extern "C" int sof_workspace_size(const sof_ctx* ctx, const sof_data* data, cons
     size_t need = L.total;
     size_t part = part_workspace(fr->n_nodes, fr->n_samples);
     if (part > need) need = part;
-    size_t pj = project_workspace(fr->n_nodes);
+    size_t pj = project_workspace(fr->n_nodes, fr->n_samples, proj->n_proj);
     if (pj > need) need = pj;
     *bytes = need;
     return SOF_OK;

@@ -20,6 +20,7 @@ struct sof_ctx {
     std::mutex mu;
     std::map<std::pair<int, int>, sof::LaunchCfg> cfg;   // key (4 * bins + mode, classes)
     bool timing = false;                             // benchmark instrumentation
+    bool timing_serial = false;                      // ... with the size classes serialised
     std::vector<std::array<hipEvent_t, sof::kTimingEvents>> tev;  // one event set per recorded call
     size_t tev_used = 0;
     void* scratch = nullptr;   // device address of this device's static scratch array
@@ -35,6 +36,7 @@ struct sof_ctx {
 namespace sof {
 // the context's streams around a launch on the caller's stream s
 inline FindStreams find_streams(sof_ctx* ctx, hipStream_t s) {
+    if (ctx->timing && ctx->timing_serial) return FindStreams{s, {nullptr, nullptr}, nullptr, {nullptr, nullptr}};
     return FindStreams{s, {ctx->aux[0], ctx->aux[1]}, ctx->fork, {ctx->join[0], ctx->join[1]}};
 }
 }  // namespace sof
@@ -85,7 +87,7 @@ hipError_t launch_partition_csr(const PartArgs& a, const ProjCSR& p, int n_cu, h
 hipError_t launch_partition_hash(const PartArgs& a, const ProjHash& p, int n_cu, hipStream_t s);
 
 // projection only
-size_t project_workspace(int64_t n_nodes);
+size_t project_workspace(int64_t n_nodes, int64_t n_samples, int64_t n_proj);
 hipError_t launch_project(const FindArgs& a, const ProjCSR& p, float* out, void* ws, int n_cu,
                           hipStream_t s);
 

@@ -2,12 +2,15 @@
 // 4.1: histograms win on large nodes and sorting on small ones, and the
 // crossover is measured once before training).
 //
-// For a ladder of node sizes s, a synthetic frontier of equal nodes of s
-// contiguous rows (about 2^18 samples in all, k projections of nnz features)
-// is searched twice through sof_find_splits: all nodes on the sort path
-// (T = INT32_MAX) and all on the histogram path (T = 0).  The chosen T is the
-// smallest measured size from which the histogram path is never slower.  The
-// same frontiers, searched with half the bins, give the bin-count switch for
+// For a ladder of node sizes s (2 .. 8192), a frontier of equal nodes of s
+// contiguous rows (2^16 samples in all, k projections of nnz features; the
+// rows are synthetic, or the caller's own with sof_autotune_on) is searched
+// through sof_find_splits with all nodes on the sort path (T = INT32_MAX) and
+// all on the histogram path (T = 0).  The chosen T is the smallest measured
+// size from which the histogram path is never slower; sorting only loses
+// ground as nodes grow (n log n against n), so once histograms have won at two
+// consecutive sizes the larger sizes are not sorted.  The same frontiers
+// searched with half the bins (sizes up to 1024) give the bin-count switch for
 // small nodes: below the first size where full bins cost at most 10% more
 // than half bins, nodes use half the bins.
 #include <hip/hip_runtime.h>
@@ -90,8 +93,8 @@ struct TuneBufs {
 
 }  // namespace
 
-extern "C" int sof_autotune(sof_ctx* ctx, int32_t dtype, int32_t n_classes, int32_t k, int32_t nnz,
-                            int32_t bins, sof_tune* out, void* stream) {
+static int autotune_impl(sof_ctx* ctx, const sof_data* user, int32_t dtype, int32_t n_classes, int32_t k,
+                         int32_t nnz, int32_t bins, sof_tune* out, void* stream) {
     if (!ctx || !out) return fail(SOF_ERR_INVALID_ARG, "sof_autotune: NULL argument");
     if (dtype != SOF_F32 && dtype != SOF_F16) return fail(SOF_ERR_UNSUPPORTED, "sof_autotune: dtype %d", dtype);
     if (n_classes < 2 || n_classes > SOF_MAX_CLASSES)
@@ -99,49 +102,61 @@ extern "C" int sof_autotune(sof_ctx* ctx, int32_t dtype, int32_t n_classes, int3
     if (k < 1 || k > 1024) return fail(SOF_ERR_INVALID_ARG, "sof_autotune: k %d outside [1, 1024]", k);
     if (nnz < 1 || nnz > SOF_MAX_NNZ) return fail(SOF_ERR_INVALID_ARG, "sof_autotune: nnz %d", nnz);
     if (bins < SOF_MIN_BINS || bins > SOF_MAX_BINS) return fail(SOF_ERR_UNSUPPORTED, "sof_autotune: bins %d", bins);
+    if (user && user->n_features < nnz)
+        return fail(SOF_ERR_INVALID_ARG, "sof_autotune_on: %d features, fewer than nnz %d", user->n_features, nnz);
     auto wall0 = std::chrono::steady_clock::now();
     memset(out, 0, sizeof(*out));
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
 
-    static const int kSizes[] = {4, 8, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048,
-                                 3072, 4096, 6144, 8192};
+    static const int kSizes[] = {2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024,
+                                 1536, 2048, 3072, 4096, 6144, 8192};
     const int n_sizes = (int)(sizeof(kSizes) / sizeof(kSizes[0]));
-    const int n_rows = 1 << 18;
-    const int d = 64;
+    static_assert(sizeof(kSizes) / sizeof(kSizes[0]) <= 32, "sof_tune holds 32 points");
+    // the caller's rows (at most 2^16 of them, its first 64 features) or 2^16
+    // synthetic rows
+    const int n_rows = user ? (user->n_rows < (1 << 16) ? user->n_rows : (1 << 16)) : (1 << 16);
+    const int d = user ? (user->n_features < 64 ? user->n_features : 64) : 64;
     const int kk = k > 64 ? 64 : k;   // per node-projection cost is what is compared
     int maxN = 0;
     for (int i = 0; i < n_sizes; ++i) maxN = n_rows / kSizes[i] > maxN ? n_rows / kSizes[i] : maxN;
     const int64_t maxP = (int64_t)maxN * kk;
 
     TuneBufs B;
-    float* x;
-    _Float16* xh;
-    int32_t *y, *no, *idx, *po, *zo, *zf, *node_bins;
+    float* x = nullptr;
+    _Float16* xh = nullptr;
+    int32_t *y = nullptr, *no, *idx, *po, *zo, *zf, *node_bins;
     int8_t* zw;
     sof_split* sp;
-    if ((e = B.get(&x, (size_t)n_rows * d)) || (e = B.get(&xh, (size_t)n_rows * d)) || (e = B.get(&y, n_rows)) ||
+    if ((!user && ((e = B.get(&x, (size_t)n_rows * d)) || (e = B.get(&xh, (size_t)n_rows * d)) ||
+                   (e = B.get(&y, n_rows)))) ||
         (e = B.get(&no, maxN + 1)) || (e = B.get(&idx, n_rows)) || (e = B.get(&po, maxN + 1)) ||
         (e = B.get(&zo, maxP + 1)) || (e = B.get(&zf, maxP * nnz)) || (e = B.get(&zw, maxP * nnz)) ||
         (e = B.get(&sp, maxN)) || (e = B.get(&node_bins, maxN)))
         return hip_fail(e, "sof_autotune: hipMalloc");
-    hipLaunchKernelGGL(k_tune_data, dim3(1024), dim3(256), 0, s, x, xh, y, n_rows, d, n_classes);
+    if (!user) hipLaunchKernelGGL(k_tune_data, dim3(1024), dim3(256), 0, s, x, xh, y, n_rows, d, n_classes);
 
     sof_data data;
     memset(&data, 0, sizeof(data));
-    data.x = dtype == SOF_F16 ? (const void*)xh : (const void*)x;
-    data.y = y;
-    data.ld = n_rows;
-    data.n_rows = n_rows;
-    data.n_features = d;
-    data.n_classes = n_classes;
-    data.dtype = dtype;
+    if (user) {
+        data = *user;
+        data.n_rows = n_rows;   // the frontiers use rows 0 .. n_rows-1 only
+    } else {
+        data.x = dtype == SOF_F16 ? (const void*)xh : (const void*)x;
+        data.y = y;
+        data.ld = n_rows;
+        data.n_rows = n_rows;
+        data.n_features = d;
+        data.n_classes = n_classes;
+        data.dtype = dtype;
+    }
 
     // workspace for the largest frontier
     size_t ws_bytes = 0;
     for (int i = 0; i < n_sizes; ++i) {
         const int N = n_rows / kSizes[i];
+        if (N < 1) continue;
         sof_frontier fr{no, idx, (int64_t)N * kSizes[i], N, kSizes[i]};
         sof_proj pj{po, zo, zf, zw, (int64_t)N * kk * nnz, N * kk, kk};
         sof_params q{nullptr, bins, 0};
@@ -161,16 +176,23 @@ extern "C" int sof_autotune(sof_ctx* ctx, int32_t dtype, int32_t n_classes, int3
     float* half_us = out->half_us;
     int rc = SOF_OK;
     const int half_bins = bins / 2 >= SOF_MIN_BINS ? bins / 2 : SOF_MIN_BINS;
+    bool warm[3] = {false, false, false};
+    int hist_wins = 0;   // consecutive sizes at which histograms were not slower
+    int np = 0;
     for (int i = 0; i < n_sizes && rc == SOF_OK; ++i) {
         const int sz = kSizes[i], N = n_rows / sz;
+        if (N < 1) break;
         hipLaunchKernelGGL(k_tune_frontier, dim3(512), dim3(256), 0, s, no, idx, po, zo, zf, zw, N, sz, kk, nnz, d);
         sof_frontier fr{no, idx, (int64_t)N * sz, N, sz};
         sof_proj pj{po, zo, zf, zw, (int64_t)N * kk * nnz, N * kk, kk};
         float best[3] = {1e30f, 1e30f, 1e30f};
+        const bool need_sort = hist_wins < 2, need_half = sz <= 1024;
         for (int path = 0; path < 3 && rc == SOF_OK; ++path) {
             // 0: sort path, 1: histogram path, 2: histogram path with half the bins
+            if ((path == 0 && !need_sort) || (path == 2 && !need_half)) continue;
             sof_params q{nullptr, path == 2 ? half_bins : bins, path == 0 ? 0x7fffffff : 0};
-            for (int rep = 0; rep < 3 && rc == SOF_OK; ++rep) {
+            // the first call of each path warms it up; then two timed calls
+            for (int rep = warm[path] ? 1 : 0; rep < 3 && rc == SOF_OK; ++rep) {
                 (void)hipEventRecord(ev0, s);
                 rc = sof_find_splits(ctx, &data, &fr, &pj, &q, sp, nullptr, ws, ws_bytes, stream);
                 (void)hipEventRecord(ev1, s);
@@ -181,38 +203,56 @@ extern "C" int sof_autotune(sof_ctx* ctx, int32_t dtype, int32_t n_classes, int3
                 }
                 float ms = 0.f;
                 (void)hipEventElapsedTime(&ms, ev0, ev1);
-                if (rep > 0 && ms < best[path]) best[path] = ms;   // first run warms up
+                if (rep > 0 && ms < best[path]) best[path] = ms;
             }
+            warm[path] = true;
         }
         const float per = 1e3f / (float)((int64_t)N * kk);   // ms per call -> us per node-projection
         out->sizes[i] = sz;
-        out->sort_us[i] = best[0] * per;
         out->hist_us[i] = best[1] * per;
-        half_us[i] = best[2] * per;
+        // not sorted: histograms had won at two smaller sizes (recorded as 0)
+        out->sort_us[i] = need_sort ? best[0] * per : 0.f;
+        // above 1024 samples half bins are not measured: recorded as full bins
+        half_us[i] = need_half ? best[2] * per : out->hist_us[i];
+        if (need_sort) hist_wins = out->hist_us[i] <= out->sort_us[i] ? hist_wins + 1 : 0;
+        np = i + 1;
     }
     (void)hipEventDestroy(ev0);
     (void)hipEventDestroy(ev1);
     if (rc) return rc;
-    out->n_points = n_sizes;
-    // T: smallest size from which the histogram path is never slower
+    out->n_points = np;
+    // T: smallest size from which the histogram path is never slower (sizes
+    // not sorted count as histogram wins)
     int T = SOF_SORT_LIMIT + 1;
-    for (int i = n_sizes - 1; i >= 0; --i) {
-        if (out->hist_us[i] <= out->sort_us[i]) T = kSizes[i];
+    for (int i = np - 1; i >= 0; --i) {
+        if (out->sort_us[i] == 0.f || out->hist_us[i] <= out->sort_us[i]) T = kSizes[i];
         else break;
     }
     out->sort_threshold = T;
     // bins switch: smallest size from which full bins cost at most 10% more than
     // half bins at every larger measured size (half bins below it); if the
     // largest size already fails, every measured size takes half bins
-    int sw = kSizes[n_sizes - 1] + 1;
-    for (int i = n_sizes - 1; i >= 0; --i) {
+    int sw = np > 0 ? kSizes[np - 1] + 1 : 0;
+    for (int i = np - 1; i >= 0; --i) {
         if (out->hist_us[i] <= 1.1f * half_us[i]) sw = kSizes[i];
         else break;
     }
-    if (sw == kSizes[0]) sw = 0;
+    if (np > 0 && sw == kSizes[0]) sw = 0;
     out->bins_small = half_bins;
     out->bins_switch = sw;
     out->elapsed_ms =
         std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - wall0).count();
     return SOF_OK;
+}
+
+extern "C" int sof_autotune(sof_ctx* ctx, int32_t dtype, int32_t n_classes, int32_t k, int32_t nnz,
+                            int32_t bins, sof_tune* out, void* stream) {
+    return autotune_impl(ctx, nullptr, dtype, n_classes, k, nnz, bins, out, stream);
+}
+
+extern "C" int sof_autotune_on(sof_ctx* ctx, const sof_data* data, int32_t k, int32_t nnz, int32_t bins,
+                               sof_tune* out, void* stream) {
+    int rc;
+    if ((rc = check_data(data))) return rc;
+    return autotune_impl(ctx, data, data->dtype, data->n_classes, k, nnz, bins, out, stream);
 }

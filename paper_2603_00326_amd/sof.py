@@ -36,7 +36,7 @@ EXPORTED = [
     "sof_project", "sof_find_splits", "sof_partition", "sof_forest_create", "sof_forest_destroy",
     "sof_grow_level", "sof_forest_frontier_size", "sof_forest_frontier_stats", "sof_forest_export",
     "sof_autotune", "sof_predict",
-    "sof_timing_enable", "sof_timing_read", "sof_find_splits_noalloc",
+    "sof_timing_enable", "sof_timing_read", "sof_find_splits_noalloc", "sof_autotune_on",
 ]
 
 
@@ -136,8 +136,8 @@ def lib():
         L.sof_timing_enable.argtypes = [P, ctypes.c_int]
         L.sof_timing_read.argtypes = [P, P, ctypes.POINTER(i32)]
         L.sof_predict.argtypes = [P, ctypes.POINTER(sof_data), P, i64, P, i32, P, P, P]
-        if hasattr(L, "sof_autotune"):
-            L.sof_autotune.argtypes = [P, i32, i32, i32, i32, i32, ctypes.POINTER(sof_tune), P]
+        L.sof_autotune.argtypes = [P, i32, i32, i32, i32, i32, ctypes.POINTER(sof_tune), P]
+        L.sof_autotune_on.argtypes = [P, ctypes.POINTER(sof_data), i32, i32, i32, ctypes.POINTER(sof_tune), P]
         _lib = L
     return _lib
 
@@ -183,9 +183,11 @@ class Context:
         except Exception:
             pass
 
-    def timing(self, enable: bool):
-        """Benchmark instrumentation: HIP events around each find_splits call."""
-        _check(lib().sof_timing_enable(self.handle, int(bool(enable))))
+    def timing(self, enable, serial: bool = False):
+        """Benchmark instrumentation: HIP events around each find_splits call
+        and its stages; serial runs the size classes one after another so that
+        each stage's events bound its own kernels."""
+        _check(lib().sof_timing_enable(self.handle, 0 if not enable else (2 if serial else 1)))
 
     STAGES = ("plan", "big_range", "big_merge", "big_hist", "big_scan", "mid", "mid2", "small", "sort",
               "reduce")
@@ -366,14 +368,28 @@ def splits_from_numpy(rec: np.ndarray, device="cuda:0"):
     return torch.from_numpy(out.view(np.int32).reshape(-1, 10).copy()).to(device)
 
 
+def data_struct(X, y, n_classes: int) -> sof_data:
+    """sof_data over device tensors X ((d, n) FP32/FP16) and y (n int32)."""
+    dtype = SOF_F16 if str(X.dtype) == "torch.float16" else SOF_F32
+    return sof_data(_ptr(X), _ptr(y), int(X.stride(0)), int(X.shape[1]), int(X.shape[0]), int(n_classes), dtype)
+
+
 def autotune(ctx: Context, n_classes: int, k: int, z: int, bins: int = 256, *, dtype=np.float32,
-             stream=None) -> dict:
-    """Run the library's crossover microbenchmark (sof_autotune) and return
-    its choice: sort threshold, small-node bin rule and the measured curve."""
+             stream=None, data=None) -> dict:
+    """Run the library's crossover microbenchmark and return its choice: sort
+    threshold, small-node bin rule and the measured curve.  With data (a
+    DeviceFrontier, or a tuple (X, y, n_classes) of device tensors) it runs
+    sof_autotune_on over that matrix and labels, else sof_autotune on
+    synthetic rows of the given storage type."""
     t = sof_tune()
-    code = SOF_F16 if np.dtype(dtype) == np.float16 else SOF_F32
-    _check(lib().sof_autotune(ctx.handle, code, int(n_classes), int(k), int(z), int(bins), ctypes.byref(t),
-                              _stream(stream)))
+    if data is not None:
+        d = data.structs()[0] if isinstance(data, DeviceFrontier) else data_struct(*data)
+        _check(lib().sof_autotune_on(ctx.handle, ctypes.byref(d), int(k), int(z), int(bins), ctypes.byref(t),
+                                     _stream(stream)))
+    else:
+        code = SOF_F16 if np.dtype(dtype) == np.float16 else SOF_F32
+        _check(lib().sof_autotune(ctx.handle, code, int(n_classes), int(k), int(z), int(bins), ctypes.byref(t),
+                                  _stream(stream)))
     n = int(t.n_points)
     return {"sort_threshold": int(t.sort_threshold), "bins_small": int(t.bins_small),
             "bins_switch": int(t.bins_switch), "ms": float(t.elapsed_ms),

@@ -147,7 +147,7 @@ def test_project_matches_oracle(ctx):
     import paper_2603_00326_amd as S
     import torch
     for dt in (np.float32, np.float16):
-        wl = W.random_frontier(41, n_rows=30000, d=20, n_classes=2, sizes=[0, 1, 77, 5000, 20000], k=5,
+        wl = W.random_frontier(41, n_rows=30000, d=20, n_classes=2, sizes=[0, 1, 77, 5000, 8192, 8193, 20000], k=9,
                                z=(1, 16), layout="r", dtype=dt)
         say(f"[gpu] project {dt.__name__}")
         dev = S.to_device(wl)
@@ -259,3 +259,45 @@ def test_fp32_weights_all_paths(ctx, T, dt):
     want = O.project(wl.X, wl.node_offsets, wl.sample_idx, wl.proj_offsets, wl.nz_offsets, wl.nz_feature,
                      wl.nz_weight)
     assert np.array_equal(pj.cpu().numpy().view(np.uint32), want.view(np.uint32))
+
+
+# --------------------------------------------------------------------------
+# crossover microbenchmark (sof_autotune, sof_autotune_on)
+
+TUNE_SIZES = [2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048, 3072,
+              4096, 6144, 8192]
+
+
+def check_tune(t, bins):
+    assert t["sizes"] == TUNE_SIZES[:len(t["sizes"])] and len(t["sizes"]) == len(TUNE_SIZES)
+    T = t["sort_threshold"]
+    assert T in TUNE_SIZES or T == 8193
+    i = TUNE_SIZES.index(T) if T in TUNE_SIZES else len(TUNE_SIZES)
+    # the choice follows the measured curve: histograms never slower from T on
+    # (sizes not sorted record 0), and slower at the size just below T
+    for j in range(i, len(TUNE_SIZES)):
+        assert t["sort_us"][j] == 0 or t["hist_us"][j] <= t["sort_us"][j]
+    if 0 < i:
+        assert t["hist_us"][i - 1] > t["sort_us"][i - 1] > 0
+    assert all(h > 0 for h in t["hist_us"])
+    assert t["bins_small"] == max(bins // 2, 2)
+
+
+@pytest.mark.parametrize("dt", [np.float32, np.float16])
+def test_autotune_synthetic_and_on_caller_data(ctx, dt):
+    from paper_2603_00326_amd import sof as S
+    t = S.autotune(ctx, 3, 64, 4, 256, dtype=dt)
+    say(f"[gpu] autotune synthetic {np.dtype(dt).name}: T={t['sort_threshold']} in {t['ms']:.1f} ms")
+    check_tune(t, 256)
+    wl = W.random_frontier(95, n_rows=200000, d=40, n_classes=3, sizes=[10], k=4, z=3, dtype=dt)
+    t2 = S.autotune(ctx, 3, 64, 4, 256, data=S.to_device(wl))
+    say(f"[gpu] autotune on data {np.dtype(dt).name}: T={t2['sort_threshold']} in {t2['ms']:.1f} ms")
+    check_tune(t2, 256)
+
+
+def test_autotune_on_rejects_fewer_features_than_nonzeros(ctx):
+    from paper_2603_00326_amd import sof as S
+    wl = W.random_frontier(96, n_rows=1000, d=3, n_classes=2, sizes=[10], k=2, z=2)
+    with pytest.raises(S.SofError) as e:
+        S.autotune(ctx, 2, 8, 4, 64, data=S.to_device(wl))
+    assert e.value.code == S.SOF_ERR_INVALID_ARG

@@ -23,9 +23,11 @@ def ctx():
 
 
 def tune(ctx, wl):
+    """The benchmark's tuning: the crossover microbenchmark on the workload's
+    own matrix and labels."""
     from paper_2603_00326_amd import sof as S
     return S.autotune(ctx, wl.n_classes, int(wl.meta.get("k", 64)), int(wl.meta.get("z", 3)), wl.bins,
-                      dtype=wl.X.dtype)
+                      data=S.to_device(wl))
 
 
 def tuned_threshold(ctx, wl):
@@ -167,3 +169,31 @@ def test_root_at_the_maximum_node_size(ctx, criterion):
     want_idx, want_coff = O.partition(wl.X, wl.node_offsets, wl.sample_idx, wl.proj_offsets, wl.nz_offsets,
                                       wl.nz_feature, wl.nz_weight, ref, bins=wl.bins)
     assert np.array_equal(coff, want_coff) and np.array_equal(out_idx, want_idx)
+
+
+def test_project_full_frontier_sampled_nodes(ctx):
+    """sof_project over the whole 4096-node frontier (the launch the benchmark
+    times, 2.6e8 values): the blocks of 64 nodes drawn from every size class,
+    including the largest, equal the oracle's projection bit for bit."""
+    import torch
+    from paper_2603_00326_amd import sof as S
+    wl = W.config3("a")
+    say(f"[gpu] project full frontier nodes={wl.n_nodes} units={wl.units}")
+    dev = S.to_device(wl)
+    got = S.project(ctx, dev)
+    torch.cuda.synchronize()
+    n = np.diff(wl.node_offsets.astype(np.int64))
+    k = np.diff(wl.proj_offsets.astype(np.int64))
+    off = np.concatenate([[0], np.cumsum(n * k)])
+    rng = np.random.default_rng(5)
+    order = np.argsort(n)
+    pick = sorted(set(rng.choice(wl.n_nodes, 56, replace=False).tolist()) | set(order[-8:].tolist()))
+    sub = W.sub_frontier(wl, pick)
+    want = O.project(sub.X, sub.node_offsets, sub.sample_idx, sub.proj_offsets, sub.nz_offsets, sub.nz_feature,
+                     sub.nz_weight)
+    g = got.cpu().numpy()
+    pos = 0
+    for v in pick:
+        m = int(n[v] * k[v])
+        assert np.array_equal(g[off[v]:off[v] + m].view(np.uint32), want[pos:pos + m].view(np.uint32)), f"node {v}"
+        pos += m

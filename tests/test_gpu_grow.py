@@ -156,10 +156,11 @@ def test_full_training_tree0_against_oracle(ctx):
     from paper_2603_00326_amd import workloads as W
     X, y, C, ro, ri = W.config4_data()
     k, z, bins, seed, depth = 128, 3, 256, 4, 20
-    T = int(S.autotune(ctx, C, k, z, bins, dtype=X.dtype)["sort_threshold"])
-    say(f"[gpu] full training 8 trees x {X.shape[1]} rows, d={X.shape[0]}, k={k}, T={T}, depth {depth}")
     Xd = torch.from_numpy(X).to("cuda:0")
-    f = S.Forest(ctx, Xd, torch.from_numpy(y).to("cuda:0"), C, ro, torch.from_numpy(ri).to("cuda:0"),
+    yd = torch.from_numpy(y).to("cuda:0")
+    T = int(S.autotune(ctx, C, k, z, bins, data=(Xd, yd, C))["sort_threshold"])
+    say(f"[gpu] full training 8 trees x {X.shape[1]} rows, d={X.shape[0]}, k={k}, T={T}, depth {depth}")
+    f = S.Forest(ctx, Xd, yd, C, ro, torch.from_numpy(ri).to("cuda:0"),
                  k=k, z=z, seed=seed, bins=bins, sort_threshold=T, max_depth=depth)
     f.grow(use_graph=True)
     got = tree_nodes(f.export(), 0)
