@@ -1339,20 +1339,23 @@ __global__ __launch_bounds__(kBlock) void k_plan(FindArgs A, PS P) {
 }
 
 constexpr int kMaxProj = 1024;   // projections per node (the boundary's limit)
+constexpr int kExpandSlices = 16;   // blocks sharing the item writes of one big node
 
 template <class PS>
 __global__ __launch_bounds__(kBlock) void k_expand(FindArgs A, PS P) {
     __shared__ int zcnt[SOF_MAX_NNZ + 1], zbase[SOF_MAX_NNZ + 1];
     __shared__ int perm[kMaxProj];
+    __shared__ uint8_t zof[kMaxProj];
     const FindWs& W = A.ws;
     const int tid = threadIdx.x;
     const int nmid = count_of(A, H_DMID, W.cap_dmid);
     const int nsb = count_of(A, H_DSB, W.cap_dsb);
     const int nbig = count_of(A, H_DBIG, W.cap_dbig);
     const int nmid2 = count_of(A, H_DMID2, W.cap_dmid2);
-    for (int d = blockIdx.x; d < nmid + nsb + nbig + nmid2; d += gridDim.x) {
-        if (d >= nmid + nsb + nbig) {
-            const int e = d - nmid - nsb - nbig;
+    // a big descriptor is written by kExpandSlices blocks, each a slice of its items
+    for (int d = blockIdx.x; d < nmid + nsb + nbig * kExpandSlices + nmid2; d += gridDim.x) {
+        if (d >= nmid + nsb + nbig * kExpandSlices) {
+            const int e = d - nmid - nsb - nbig * kExpandSlices;
             const int4 D = W.desc_mid2[e];
             const int ng = (D.w + kMidGroup - 1) / kMidGroup;
             int64_t s0 = 0, n = 0;
@@ -1388,18 +1391,25 @@ __global__ __launch_bounds__(kBlock) void k_expand(FindArgs A, PS P) {
             // t' = p * nchunk + ch (stored), wherever it sits; the range and
             // histogram results are indexed by t' and merged order-free, so
             // the order changes no result.
-            int e = d - nmid - nsb;
+            const int e = (d - nmid - nsb) / kExpandSlices, slice = (d - nmid - nsb) % kExpandSlices;
             BigDesc bd = big_desc(A, e);
             const int k = bd.k < kMaxProj ? bd.k : kMaxProj;
             const int na = k * bd.nchunk;
+            const int t0 = (int)((int64_t)na * slice / kExpandSlices);
+            const int t1 = (int)((int64_t)na * (slice + 1) / kExpandSlices);
+            // The order is a function of the counts alone (equal counts by
+            // projection index), so every slice block builds the same one.
             if (tid <= SOF_MAX_NNZ) zcnt[tid] = 0;
             __syncthreads();
-            int zr[kMaxProj / kBlock], slot[kMaxProj / kBlock];
+            int zr[kMaxProj / kBlock];
 #pragma unroll
             for (int i = 0; i < kMaxProj / kBlock; ++i) {
                 const int p = tid + i * kBlock;
                 zr[i] = p < k ? proj_nnz(P, bd.node, p, A.n_features) : 0;
-                slot[i] = p < k ? atomicAdd(&zcnt[zr[i]], 1) : 0;
+                if (p < k) {
+                    zof[p] = (uint8_t)zr[i];
+                    atomicAdd(&zcnt[zr[i]], 1);
+                }
             }
             __syncthreads();
             if (tid == 0) {
@@ -1410,16 +1420,21 @@ __global__ __launch_bounds__(kBlock) void k_expand(FindArgs A, PS P) {
 #pragma unroll
             for (int i = 0; i < kMaxProj / kBlock; ++i) {
                 const int p = tid + i * kBlock;
-                if (p < k) perm[zbase[zr[i]] + slot[i]] = p;
+                if (p < k) {
+                    int before = 0;   // projections below p with the same count
+                    for (int q = 0; q < p; ++q) before += zof[q] == zr[i] ? 1 : 0;
+                    perm[zbase[zr[i]] + before] = p;
+                }
             }
             __syncthreads();
-            for (int t = tid; t < na; t += kBlock) {
+            for (int t = t0 + tid; t < t1; t += kBlock) {
                 const int pos = t / bd.nchunk, ch = t - pos * bd.nchunk;
                 if (bd.item_a + (int64_t)t < W.cap_ibiga)
                     W.items_biga[bd.item_a + t] = make_int2(e, perm[pos] * bd.nchunk + ch);
             }
-            for (int p = tid; p < bd.k; p += kBlock)
-                if (bd.item_c + (int64_t)p < W.cap_ibigc) W.items_bigc[bd.item_c + p] = make_int2(e, p);
+            if (slice == 0)
+                for (int p = tid; p < bd.k; p += kBlock)
+                    if (bd.item_c + (int64_t)p < W.cap_ibigc) W.items_bigc[bd.item_c + p] = make_int2(e, p);
             __syncthreads();   // zcnt and perm are reused by the block's next descriptor
         }
     }
@@ -1430,13 +1445,19 @@ __global__ __launch_bounds__(kBlock) void k_expand(FindArgs A, PS P) {
 // dynamically, kWavesPerBlock consecutive items per block claim (one atomic,
 // wave w takes the w-th), so waves whose items cost more (more nonzeros) or
 // that became resident late (the size classes share the GPU) take fewer of
-// the tail.  body(it) runs on whole waves and contains no block barrier.
+// the tail; with at most kStaticRounds rounds every item is taken statically.
+// body(it) runs on whole waves and contains no block barrier.
 constexpr int kDynRounds = 1;
+constexpr int kStaticRounds = 2;   // up to this many rounds: static grid stride only
 template <class F>
 __device__ __forceinline__ void for_wave_items(int n, int32_t* ctr, int* s_item, F&& body) {
     const int w = threadIdx.x >> 6;
     const int gw = (int)((blockIdx.x * kBlock + threadIdx.x) >> 6);
     const int nw = (int)(gridDim.x * kWavesPerBlock);
+    if (n <= kStaticRounds * nw) {   // few rounds (cheap, even items): no claims at all
+        for (int it = gw; it < n; it += nw) body(it);
+        return;
+    }
     const int fixed = n / nw - kDynRounds;
     for (int r = 0; r < fixed; ++r) body(gw + r * nw);
     const int base = (fixed > 0 ? fixed : 0) * nw;
