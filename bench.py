@@ -162,7 +162,7 @@ def partition_bytes(wl, splits):
 def measured_traffic(kernel: str, workload: str):
     import hashlib
     src = os.path.join(ROOT, "paper_2603_00326_amd", "csrc", "k_find.hip")
-    prof = os.path.join(ROOT, "profiles", f"find_{workload}_hbm_traffic.md")
+    prof = os.path.join(ROOT, "profiles", f"find_{workload}_profile.md")
     if not os.path.exists(prof) or not os.path.exists(src):
         return None
     md5 = hashlib.md5(open(src, "rb").read()).hexdigest()
