@@ -476,6 +476,39 @@ def run_accuracy(args, S, ctx):
 
 # ---------------------------------------------------------------------------
 
+def graph_leg(step, out, steps):
+    """The same step captured once into a HIP graph (the find's and the
+    partition's forks onto the context's streams become graph branches) and
+    replayed: every replay's split records and partition are checked against
+    an eager step's, then `steps` replays are timed."""
+    import torch
+    idx_e, coff_e = step()
+    torch.cuda.synchronize()
+    ref = (out.clone(), idx_e.clone(), coff_e.clone())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        idx_g, coff_g = step()
+    torch.cuda.synchronize()
+    checked = 0
+    for _ in range(3):
+        out.fill_(-7)
+        g.replay()
+        torch.cuda.synchronize()
+        for a, b in zip((out, idx_g, coff_g), ref):
+            if not torch.equal(a, b):
+                raise RuntimeError("graph replay differs from the eager step")
+        checked += 1
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.replay()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    del g
+    return {"ms_per_step": round(ms, 4), "steps": steps, "replays_checked": checked,
+            "note": "find_splits + partition captured once into one HIP graph and replayed"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -488,6 +521,8 @@ def main():
                     help="config 3: nodes below this size take half the bins (default: the autotuner's "
                          "rule; 0 = full bins everywhere)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--graph", type=int, default=1,
+                    help="also time the step captured into one HIP graph and replayed")
     ap.add_argument("--project", type=int, default=1,
                     help="also time step 1 alone (sof_project) after the timed loop (0 skips it)")
     ap.add_argument("--plain", type=int, default=2,
@@ -565,7 +600,7 @@ def main():
     def step():
         S.find_splits(ctx, dev, bins=wl.bins, sort_threshold=T, out=out, bin_mode=bin_mode, bin_seed=bin_seed,
                       criterion=criterion)
-        S.partition(ctx, dev, out, bins=wl.bins)
+        return S.partition(ctx, dev, out, bins=wl.bins)
 
     for _ in range(args.warmup):
         step()
@@ -654,6 +689,9 @@ def main():
     }
     if tune:
         result["autotune"] = tune
+
+    if args.graph:
+        result["graph_step"] = graph_leg(step, out, args.steps)
 
     if args.project:
         # step 1 alone through sof_project: every (node, projection, sample)

@@ -232,12 +232,23 @@ __host__ __device__ constexpr int bins_stride(int bins) { return (bins + 3) & ~3
 // can never win under that tie rule and is skipped.  pc: 16 ints of wave
 // scratch in LDS (the node's class totals).
 constexpr float kScreenKeep = 1.0f - 1.0f / 65536.0f;
+// When more than kSerialContenders boundaries pass that screen (a flat score
+// curve: many samples and a projection that separates the classes little),
+// they are screened again in binary64, one lane per boundary: with the class
+// left counts exact, S_L, S_R < 2^48 and n_L, n_R are exact in binary64, and
+// Q64 = S_L / n_L + S_R / n_R (two correctly rounded divisions, one sum) lies
+// within 2 * 2^-53 Q of Q.  Every boundary whose exact Q is the largest then
+// scores at least max Q64 (1 - 2^-48); only those reach the exact comparison.
+// PRE = false leaves this stage out (the small-node kernel with random-width
+// bins, whose register budget it would overflow).
+constexpr int kSerialContenders = 4;
 
 // qfloor (optional): the FP32 score of the caller's incumbent from an earlier
 // scan.  When this scan's best score is below qfloor (1 - 2^-16), its exact
 // best Q is below the incumbent's (both scores are within 20 * 2^-24 of their
 // exact values), so it cannot win or tie and is returned invalid without its
 // exact evaluation.  qmax_out (optional) receives this scan's best score.
+template <bool PRE = true>
 __device__ Cand scan_hist_fast(const LdsHistCM& h, int B, int C, int64_t n, float lo, float scale, int32_t* pc,
                                float qfloor = -1.f, float* qmax_out = nullptr) {
     const int lane = lane_id();
@@ -289,6 +300,35 @@ __device__ Cand scan_hist_fast(const LdsHistCM& h, int B, int C, int64_t n, floa
     const float keep = qmax * kScreenKeep;
     wave_sync();   // pc[] and the left counts written above are read by other lanes below
     const uint32_t pcv = lane < C ? (uint32_t)pc[lane] : 0u;
+    uint32_t cm = 0;   // this lane's contenders (bit i: boundary after bin b0 + i)
+    int ncont = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        if (q[i] >= 0.f && q[i] >= keep) cm |= 1u << i;
+        ncont += __popcll(__ballot((cm >> i) & 1u));
+    }
+    if (PRE && ncont > kSerialContenders) {
+        // Q64 of the lane's boundary b0 + i, recomputed in the second pass
+        // (the same operations, so the same value) rather than kept
+        auto q64 = [&](int i) -> double {
+            uint64_t nLx = 0, SLx = 0, SRx = 0;
+            for (int c = 0; c < C; ++c) {
+                const uint64_t lc = h(b0 + i, c);
+                const uint64_t rc = (uint64_t)(uint32_t)pc[c] - lc;
+                nLx += lc;
+                SLx += lc * lc;
+                SRx += rc * rc;
+            }
+            return (double)SLx / (double)nLx + (double)SRx / (double)((uint64_t)n - nLx);
+        };
+        double qdb = -1.0;
+        for (uint32_t t = cm; t; t &= t - 1) qdb = fmax(qdb, q64(__builtin_ctz(t)));
+        const double keepd = wave_max_d(qdb) * (1.0 - 0x1p-48);
+        for (uint32_t t = cm; t; t &= t - 1) {
+            const int i = __builtin_ctz(t);
+            if (q64(i) < keepd) cm &= ~(1u << i);
+        }
+    }
     bool have = false;
     u128 bN = 0;
     uint64_t bD = 0, bSL = 0, bSR = 0;
@@ -296,7 +336,7 @@ __device__ Cand scan_hist_fast(const LdsHistCM& h, int B, int C, int64_t n, floa
     uint32_t bnL = 0;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        uint64_t m = __ballot(q[i] >= 0.f && q[i] >= keep);
+        uint64_t m = __ballot((cm >> i) & 1u);
         while (m) {
             const int ln = __builtin_ctzll(m);
             m &= m - 1;
@@ -889,7 +929,7 @@ __device__ void do_small_r(const FindArgs& A, const PS& P, int v, int64_t s0, in
             write_hist_row(A, item_q(P, v, q0, p), h, B);
             float qm = -1.f;
             if (ENT) c = scan_hist_entropy(h, B, C, n, lo, scale, Flnk{block_flnk(smem, Bm, C, RW), kFlnkLds, nullptr, 0});
-            else c = scan_hist_fast(h, B, C, n, lo, scale, WS.pcs, bestq, &qm);
+            else c = scan_hist_fast<!RW>(h, B, C, n, lo, scale, WS.pcs, bestq, &qm);
             if (RW && c.D != 0) c.thr = rw_boundary(A.bin_seed, bin_key(P, v, q0, p), B, lo, hi, c.pos);
             wave_sync();
             // a candidate is only returned valid when it may beat the incumbent

@@ -532,7 +532,7 @@ static hipError_t level_launch(sof_forest* f, hipStream_t s) {
     pa.out_idx = f->b.part_idx;
     pa.child_offsets = f->b.child_off;
     part_bind(f->cap_front, f->n_samples, f->b.ws_part, &pa);
-    e = launch_partition_hash(pa, ph, f->ctx->n_cu, s);
+    e = launch_partition_hash(pa, ph, f->ctx->n_cu, find_streams(f->ctx, s));
     if (e != hipSuccess) return e;
     const int grid = f->ctx->n_cu * 4;
     const int nb_scan = (int)((f->cap_front + 1 + kScanBlock - 1) / kScanBlock);

@@ -10,11 +10,15 @@
 //   k_pplan     per node: child offsets, tiny/small-node queues or chunk items
 //   k_ptiny     nodes <= 1024 samples: one wave per node, all in registers
 //   k_psmall    nodes <= 2048 samples: one block per node, 8 samples per
-//               thread, scattered from registers; chunk items (2048 samples)
-//               of larger nodes: predicate bits and left counts (first pass)
+//               thread, scattered from registers
+//   k_ppred     chunk items (2048 samples) of larger nodes: predicate bits
+//               and left counts (first pass)
 //   k_pchunkscan  one block: exclusive prefix of the chunk items' left counts
 //   k_pscatter  chunk items: left counts of the node's earlier chunks from
 //               that prefix, scatter
+// The three node classes are independent: after the plan, k_ptiny and the
+// chunk chain (k_ppred, k_pchunkscan, k_pscatter) run on the context's two
+// auxiliary streams beside k_psmall on the caller's, and join it at the end.
 // Every gather requests all (up to 4) columns of the split's projection in
 // one round trip.
 #include <cstring>
@@ -459,42 +463,52 @@ __global__ __launch_bounds__(kBlock) void k_psmall(PartArgs A, PS P) {
     extern __shared__ __align__(16) char smem[];
     PShared& S = *(PShared*)smem;
     const int nsmall = A.hdr[P_SMALL];
-    const int nitems = (int)min((int64_t)A.hdr[P_ITEMS], A.cap_items);
     const int N = nodes_of(A);
     for (;;) {
         __syncthreads();
         if (threadIdx.x == 0) S.item = atomicAdd(&A.hdr[P_Q_SMALL], 1);
         __syncthreads();
         const int it = S.item;
-        if (it >= nsmall + nitems) break;
-        if (it < nsmall) {
-            const int v = A.big_items[A.cap_items + it].x;
-            if (v < 0 || v >= N) continue;
-            int64_t s0, n;
-            prange(A, v, s0, n);
-            if (n > kPartMax) n = kPartMax;   // the plan never queues larger nodes here
-            psmall_node<T>(A, P, v, s0, n, S);
-        } else {
-            const int e = it - nsmall;
-            const int4 d = A.big_items[e];
-            if (d.x < 0 || d.x >= N) continue;
-            int64_t s0, n;
-            prange(A, d.x, s0, n);
-            const int64_t c0 = (int64_t)d.y * kPartMax;
-            int64_t cn = n - c0;
-            cn = cn < 0 ? 0 : (cn > kPartMax ? kPartMax : cn);
-            predicates<T>(A, P, d.x, s0 + c0, cn, S);
-            const int tid = threadIdx.x;
-            if (tid < kWordsPerChunk) {
-                A.pred_bits[(int64_t)e * kWordsPerChunk + tid] = S.mask[tid >> 2][tid & 3];
-            }
-            if (tid == 0) {
-                int s = 0;
-                const int nr = (int)((cn + kBlock - 1) / kBlock);
-                for (int r = 0; r < nr; ++r)
-                    for (int w = 0; w < kWavesPerBlock; ++w) s += S.cnt[r][w];
-                A.chunk_left[e] = s;
-            }
+        if (it >= nsmall) break;
+        const int v = A.big_items[A.cap_items + it].x;
+        if (v < 0 || v >= N) continue;
+        int64_t s0, n;
+        prange(A, v, s0, n);
+        if (n > kPartMax) n = kPartMax;   // the plan never queues larger nodes here
+        psmall_node<T>(A, P, v, s0, n, S);
+    }
+}
+
+template <typename T, class PS>
+__global__ __launch_bounds__(kBlock) void k_ppred(PartArgs A, PS P) {
+    extern __shared__ __align__(16) char smem[];
+    PShared& S = *(PShared*)smem;
+    const int nitems = (int)min((int64_t)A.hdr[P_ITEMS], A.cap_items);
+    const int N = nodes_of(A);
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) S.item = atomicAdd(&A.hdr[P_Q_A], 1);
+        __syncthreads();
+        const int e = S.item;
+        if (e >= nitems) break;
+        const int4 d = A.big_items[e];
+        if (d.x < 0 || d.x >= N) continue;
+        int64_t s0, n;
+        prange(A, d.x, s0, n);
+        const int64_t c0 = (int64_t)d.y * kPartMax;
+        int64_t cn = n - c0;
+        cn = cn < 0 ? 0 : (cn > kPartMax ? kPartMax : cn);
+        predicates<T>(A, P, d.x, s0 + c0, cn, S);
+        const int tid = threadIdx.x;
+        if (tid < kWordsPerChunk) {
+            A.pred_bits[(int64_t)e * kWordsPerChunk + tid] = S.mask[tid >> 2][tid & 3];
+        }
+        if (tid == 0) {
+            int s = 0;
+            const int nr = (int)((cn + kBlock - 1) / kBlock);
+            for (int r = 0; r < nr; ++r)
+                for (int w = 0; w < kWavesPerBlock; ++w) s += S.cnt[r][w];
+            A.chunk_left[e] = s;
         }
     }
 }
@@ -590,17 +604,36 @@ __global__ void k_preset(int32_t* hdr) {
 }
 
 template <typename T, class PS>
-hipError_t launch_part_t(const PartArgs& a, const PS& p, int n_cu, hipStream_t s) {
+hipError_t launch_part_t(const PartArgs& a, const PS& p, int n_cu, const FindStreams& st) {
+    const hipStream_t s = st.main;
+    const bool fork = st.aux[0] && st.aux[1];
+    const hipStream_t st_tiny = fork ? st.aux[0] : s;
+    const hipStream_t st_chunk = fork ? st.aux[1] : s;
     const int Nc = a.n_nodes > 0 ? a.n_nodes : 1;
     int grid_plan = (Nc + kBlock - 1) / kBlock;
     if (grid_plan > 4 * n_cu) grid_plan = 4 * n_cu;
     hipLaunchKernelGGL(k_preset, dim3(1), dim3(64), 0, s, a.hdr);
     hipLaunchKernelGGL((k_pplan<PS>), dim3(grid_plan), dim3(kBlock), 0, s, a, p);
-    hipLaunchKernelGGL((k_ptiny<T, PS>), dim3(n_cu * 4), dim3(kBlock), 0, s, a, p);
+    hipError_t e = hipGetLastError();
+    if (fork && e == hipSuccess) {
+        e = hipEventRecord(st.fork, s);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st_tiny, st.fork, 0);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st_chunk, st.fork, 0);
+    }
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_ptiny<T, PS>), dim3(n_cu * 4), dim3(kBlock), 0, st_tiny, a, p);
+    hipLaunchKernelGGL((k_ppred<T, PS>), dim3(n_cu * 4), dim3(kBlock), sizeof(PShared), st_chunk, a, p);
+    hipLaunchKernelGGL(k_pchunkscan, dim3(1), dim3(kBlock), 0, st_chunk, a);
+    hipLaunchKernelGGL(k_pscatter, dim3(n_cu * 4), dim3(kBlock), sizeof(PShared), st_chunk, a);
     hipLaunchKernelGGL((k_psmall<T, PS>), dim3(n_cu * 4), dim3(kBlock), sizeof(PShared), s, a, p);
-    hipLaunchKernelGGL(k_pchunkscan, dim3(1), dim3(kBlock), 0, s, a);
-    hipLaunchKernelGGL(k_pscatter, dim3(n_cu * 4), dim3(kBlock), sizeof(PShared), s, a);
-    return hipGetLastError();
+    e = hipGetLastError();
+    if (fork && e == hipSuccess) {
+        e = hipEventRecord(st.join[0], st_tiny);
+        if (e == hipSuccess) e = hipEventRecord(st.join[1], st_chunk);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, st.join[0], 0);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, st.join[1], 0);
+    }
+    return e;
 }
 
 size_t part_workspace(int64_t n_nodes, int64_t n_samples) {
@@ -634,13 +667,13 @@ void part_bind(int64_t n_nodes, int64_t n_samples, void* ws, PartArgs* a) {
     a->cap_items = items;
 }
 
-hipError_t launch_partition_csr(const PartArgs& a, const ProjCSR& p, int n_cu, hipStream_t s) {
-    if (a.dtype == SOF_F16) return launch_part_t<_Float16>(a, p, n_cu, s);
-    return launch_part_t<float>(a, p, n_cu, s);
+hipError_t launch_partition_csr(const PartArgs& a, const ProjCSR& p, int n_cu, const FindStreams& st) {
+    if (a.dtype == SOF_F16) return launch_part_t<_Float16>(a, p, n_cu, st);
+    return launch_part_t<float>(a, p, n_cu, st);
 }
-hipError_t launch_partition_hash(const PartArgs& a, const ProjHash& p, int n_cu, hipStream_t s) {
-    if (a.dtype == SOF_F16) return launch_part_t<_Float16>(a, p, n_cu, s);
-    return launch_part_t<float>(a, p, n_cu, s);
+hipError_t launch_partition_hash(const PartArgs& a, const ProjHash& p, int n_cu, const FindStreams& st) {
+    if (a.dtype == SOF_F16) return launch_part_t<_Float16>(a, p, n_cu, st);
+    return launch_part_t<float>(a, p, n_cu, st);
 }
 
 }  // namespace sof
@@ -687,7 +720,10 @@ extern "C" int sof_partition(sof_ctx* ctx, const sof_data* data, const sof_front
     part_bind(fr->n_nodes, fr->n_samples, ws, &a);
     ProjCSR p{proj->proj_offsets, proj->nz_offsets, proj->nz_feature, proj->nz_weight, proj->n_proj,
               proj->n_nz, proj->nz_value};
-    e = launch_partition_csr(a, p, ctx->n_cu, (hipStream_t)stream);
+    {
+        std::lock_guard<std::mutex> g(ctx->launch_mu);
+        e = launch_partition_csr(a, p, ctx->n_cu, find_streams(ctx, (hipStream_t)stream));
+    }
     if (e != hipSuccess) return hip_fail(e, "partition launch");
     return SOF_OK;
 }

@@ -24,8 +24,9 @@ struct sof_ctx {
     std::vector<std::array<hipEvent_t, sof::kTimingEvents>> tev;  // one event set per recorded call
     size_t tev_used = 0;
     void* scratch = nullptr;   // device address of this device's static scratch array
-    // the find-splits sequence forks its size classes onto two auxiliary
-    // streams (default priority) and joins them back with these events;
+    // the find-splits and partition sequences fork their size classes onto
+    // two auxiliary streams (default priority) and join them back with these
+    // events;
     // launch_mu keeps two host threads from interleaving their forks
     hipStream_t aux[2] = {nullptr, nullptr};
     hipEvent_t fork = nullptr;
@@ -83,8 +84,8 @@ struct PartArgs {
 };
 size_t part_workspace(int64_t n_nodes, int64_t n_samples);
 void part_bind(int64_t n_nodes, int64_t n_samples, void* ws, PartArgs* a);
-hipError_t launch_partition_csr(const PartArgs& a, const ProjCSR& p, int n_cu, hipStream_t s);
-hipError_t launch_partition_hash(const PartArgs& a, const ProjHash& p, int n_cu, hipStream_t s);
+hipError_t launch_partition_csr(const PartArgs& a, const ProjCSR& p, int n_cu, const FindStreams& st);
+hipError_t launch_partition_hash(const PartArgs& a, const ProjHash& p, int n_cu, const FindStreams& st);
 
 // projection only
 size_t project_workspace(int64_t n_nodes, int64_t n_samples, int64_t n_proj);
