@@ -1169,6 +1169,15 @@ __device__ void do_mid_r(const FindArgs& A, const PS& P, const MidItem& m, int64
 // item_a + p * nchunk + ch, and every per-item partial (range, histogram) is
 // stored at that number.
 
+// Item slots of a big node: k * nch, or in the XCD-local layout (nodes of
+// kXcdChunks chunks or more) whole quads of projections times whole groups of
+// kXcds chunks, plus room to start the region on a multiple of 4 * kXcds.
+__host__ __device__ __forceinline__ bool big_xcd(int nch) { return nch >= kXcdChunks; }
+__host__ __device__ __forceinline__ int big_slots(int k, int nch) {
+    if (!big_xcd(nch)) return k * nch;
+    return ((k + 3) / 4) * 4 * (((nch + kXcds - 1) / kXcds) * kXcds) + 4 * kXcds - 1;
+}
+
 struct BigDesc {
     int node, slot, item_a, item_c, bigslot, k, nchunk, vc;   // vc: value-cache base in kVcUnit units, or -1
 };
@@ -1326,7 +1335,7 @@ __global__ __launch_bounds__(kBlock) void k_plan(FindArgs A, PS P) {
                              H_DBIG, H_IBIGA, H_IBIGC, H_SLOTS, H_BIGSLOTS, H_VCACHE};
         const int cnt[13] = {cat == CAT_SMALL, cat == CAT_MID, cat == CAT_MID ? gmid : 0,
                              cat == CAT_MID2, cat == CAT_MID2 ? gmid : 0, cat == CAT_SB, cat == CAT_SB ? k : 0,
-                             cat == CAT_BIG, cat == CAT_BIG ? k * nch : 0, cat == CAT_BIG ? k : 0,
+                             cat == CAT_BIG, cat == CAT_BIG ? big_slots(k, nch) : 0, cat == CAT_BIG ? k : 0,
                              slot_node ? k : 0, cat == CAT_BIG ? k : 0, vunits};
         int ob[13];
         wave_alloc_n<13>(W.hdr, ctr, cnt, ob);
@@ -1339,7 +1348,7 @@ __global__ __launch_bounds__(kBlock) void k_plan(FindArgs A, PS P) {
         if (cat == CAT_MID && (o_dmid >= W.cap_dmid || o_imid + (int64_t)gmid > W.cap_imid)) over = true;
         if (cat == CAT_MID2 && (o_dmid2 >= W.cap_dmid2 || o_imid2 + (int64_t)gmid > W.cap_imid2)) over = true;
         if (cat == CAT_SB && (o_dsb >= W.cap_dsb || o_isb + (int64_t)k > W.cap_isb)) over = true;
-        if (cat == CAT_BIG && (o_dbig >= W.cap_dbig || o_ia + (int64_t)k * nch > W.cap_ibiga ||
+        if (cat == CAT_BIG && (o_dbig >= W.cap_dbig || o_ia + (int64_t)big_slots(k, nch) > W.cap_ibiga ||
                                o_ic + (int64_t)k > W.cap_ibigc || o_bslot + (int64_t)k > W.cap_bigslots))
             over = true;
         if (over) {
@@ -1434,7 +1443,7 @@ __global__ __launch_bounds__(kBlock) void k_expand(FindArgs A, PS P) {
             const int e = (d - nmid - nsb) / kExpandSlices, slice = (d - nmid - nsb) % kExpandSlices;
             BigDesc bd = big_desc(A, e);
             const int k = bd.k < kMaxProj ? bd.k : kMaxProj;
-            const int na = k * bd.nchunk;
+            const int na = big_slots(bd.k, bd.nchunk);
             const int t0 = (int)((int64_t)na * slice / kExpandSlices);
             const int t1 = (int)((int64_t)na * (slice + 1) / kExpandSlices);
             // The order is a function of the counts alone (equal counts by
@@ -1467,14 +1476,53 @@ __global__ __launch_bounds__(kBlock) void k_expand(FindArgs A, PS P) {
                 }
             }
             __syncthreads();
-            for (int t = t0 + tid; t < t1; t += kBlock) {
-                const int pos = t / bd.nchunk, ch = t - pos * bd.nchunk;
-                if (bd.item_a + (int64_t)t < W.cap_ibiga)
-                    W.items_biga[bd.item_a + t] = make_int2(e, perm[pos] * bd.nchunk + ch);
+            if (!big_xcd(bd.nchunk)) {
+                for (int t = t0 + tid; t < t1; t += kBlock) {
+                    const int pos = t / bd.nchunk, ch = t - pos * bd.nchunk;
+                    if (bd.item_a + (int64_t)t < W.cap_ibiga)
+                        W.items_biga[bd.item_a + t] = make_int2(e, perm[pos] * bd.nchunk + ch);
+                }
+            } else {
+                // XCD-local layout: in the static rounds slot s of the items
+                // array goes to a wave of block s / 4 (mod the grid, a multiple
+                // of kXcds blocks), which runs on XCD (s / 4) mod kXcds.  The
+                // region starts on a multiple of 4 kXcds, and its slot
+                // a = 4 kXcds q + 4 x + j holds chunk kXcds g + x and projection
+                // position 4 pq + j, q = g Q4 + pq: every projection of a chunk
+                // runs on one XCD at about the same time, so the chunk's columns
+                // are read from HBM about once and then from that XCD's L2.
+                // Slots past the node's chunks or projections hold no item.
+                const int Q4 = (bd.k + 3) / 4;
+                const int nreg = Q4 * 4 * (((bd.nchunk + kXcds - 1) / kXcds) * kXcds);
+                const int base = ((bd.item_a + 4 * kXcds - 1) & ~(4 * kXcds - 1)) - bd.item_a;
+                for (int t = t0 + tid; t < t1; t += kBlock) {
+                    int2 item = make_int2(-1, 0);
+                    const int a = t - base;
+                    if (a >= 0 && a < nreg) {
+                        const int q = a / (4 * kXcds), x = (a >> 2) % kXcds, j = a & 3;
+                        const int g = q / Q4, pq = q - g * Q4;
+                        const int ch = g * kXcds + x, pos = pq * 4 + j;
+                        if (ch < bd.nchunk && pos < k) item = make_int2(e, perm[pos] * bd.nchunk + ch);
+                    }
+                    if (bd.item_a + (int64_t)t < W.cap_ibiga) W.items_biga[bd.item_a + t] = item;
+                }
             }
-            if (slice == 0)
+            if (slice == 0) {
                 for (int p = tid; p < bd.k; p += kBlock)
                     if (bd.item_c + (int64_t)p < W.cap_ibigc) W.items_bigc[bd.item_c + p] = make_int2(e, p);
+                // In the XCD-local layout, FP32 values whose node reads at most
+                // 8 bytes of distinct columns per value (min(d, sum z) columns
+                // over k projections) re-gather from L2 in the histogram pass
+                // instead of writing and reading the value cache (8 bytes of
+                // HBM per value).  FP16 gathers (128 bytes per wave
+                // instruction) stay bound by their issue, so they keep it.
+                int zs = 0;
+                for (int z = 1; z <= SOF_MAX_NNZ; ++z) zs += z * zcnt[z];
+                const int64_t m = zs < A.n_features ? zs : A.n_features;
+                if (tid == 0 && bd.vc >= 0 && big_xcd(bd.nchunk) && A.dtype != SOF_F16 &&
+                    m * 4 <= 8 * (int64_t)bd.k)
+                    ((int*)&W.desc_big[2 * e + 1])[3] = -1;
+            }
             __syncthreads();   // zcnt and perm are reused by the block's next descriptor
         }
     }

@@ -274,7 +274,9 @@ FindLayout sof::find_layout(int64_t N, int64_t S, int64_t P, int64_t K, int bins
     c.cap_dsb = nsb + 1;
     c.cap_isb = mn(P, K * nsb) + 1;
     c.cap_dbig = nbig + 1;
-    c.cap_ibiga = K * (S / kChunk + nbig) + 1;
+    // the XCD-local layout pads a node's items to whole quads of projections
+    // times whole groups of kXcds chunks, plus alignment
+    c.cap_ibiga = (K + 3) * (S / kChunk + 2 * kXcds * nbig) + 4 * kXcds * nbig + 1;
     c.cap_ibigc = mn(P, K * nbig) + 1;
     c.cap_slots = mn(P, K * nsb) + 1;
     c.cap_bigslots = mn(P, K * nbig) + 1;

@@ -17,6 +17,8 @@ constexpr int kSmallMax = 512;       // histogram nodes up to here: one block pe
 constexpr int kMidSplit = 4096;      // mid nodes up to here: at most 16 samples per thread
 constexpr int kMidMax = 8192;        // histogram nodes up to here: one block per (node, projection group)
 constexpr int kChunk = 8192;         // larger nodes: (node, projection, sample chunk) items
+constexpr int kXcdChunks = 16;       // big nodes of this many chunks or more: XCD-local item layout
+constexpr int kXcds = 8;             // XCDs of the device (workgroups are dealt to them round-robin)
 constexpr int kSortMax = SOF_SORT_LIMIT;
 constexpr int kVcUnit = 256;         // allocation unit of the big-node value cache (floats)
 
