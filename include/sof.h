@@ -422,7 +422,9 @@ enum {
  * fails. */
 /* enable: 0 off, 1 on, 2 on with the size classes run one after another on
  * the caller's stream (no fork), so that each stage's events bound its own
- * kernels alone; for measurement only. */
+ * kernels alone, 3 on with only the events around the whole sequence (the
+ * stage figures read 0; the least added work per call); for measurement
+ * only. */
 int sof_timing_enable(sof_ctx* ctx, int enable);
 int sof_timing_read(sof_ctx* ctx, float* ms, int32_t* calls);
 

@@ -2038,7 +2038,7 @@ static hipError_t launch_find_t(const FindArgs& a, const PS& p, const LaunchCfg&
     const hipStream_t sl = fork ? st.aux[1] : s;   // large mid nodes, then sort blocks
     hipError_t e = hipSuccess;
     auto rec = [&](int i, hipStream_t q) {
-        if (ev && e == hipSuccess) e = hipEventRecord(ev[i], q);
+        if (ev && ev[i] && e == hipSuccess) e = hipEventRecord(ev[i], q);
     };
     auto beg = [&](int stage, hipStream_t q) { rec(2 * stage, q); };
     auto end = [&](int stage, hipStream_t q) { rec(2 * stage + 1, q); };

@@ -118,8 +118,10 @@ extern "C" int sof_create(int device, sof_ctx** out) {
 
 extern "C" int sof_destroy(sof_ctx* ctx) {
     if (ctx) {
-        for (auto& a : ctx->tev)
-            for (hipEvent_t e : a) (void)hipEventDestroy(e);
+        for (auto* pool : {&ctx->tev, &ctx->tev_whole})
+            for (auto& a : *pool)
+                for (hipEvent_t e : a)
+                    if (e) (void)hipEventDestroy(e);
         for (int i = 0; i < 2; ++i) {
             if (ctx->aux[i]) (void)hipStreamDestroy(ctx->aux[i]);
             if (ctx->join[i]) (void)hipEventDestroy(ctx->join[i]);
@@ -134,6 +136,7 @@ extern "C" int sof_timing_enable(sof_ctx* ctx, int enable) {
     if (!ctx) return fail(SOF_ERR_INVALID_ARG, "ctx is NULL");
     ctx->timing = enable != 0;
     ctx->timing_serial = enable == 2;
+    ctx->timing_whole = enable == 3;
     ctx->tev_used = 0;
     return SOF_OK;
 }
@@ -141,11 +144,13 @@ extern "C" int sof_timing_enable(sof_ctx* ctx, int enable) {
 extern "C" int sof_timing_read(sof_ctx* ctx, float* ms, int32_t* calls) {
     if (!ctx || !ms || !calls) return fail(SOF_ERR_INVALID_ARG, "NULL argument");
     for (int i = 0; i <= SOF_STAGE_COUNT; ++i) ms[i] = 0.f;
-    for (size_t c = 0; c < ctx->tev_used; ++c) {
-        auto& e = ctx->tev[c];
+    auto& pool = ctx->timing_whole ? ctx->tev_whole : ctx->tev;
+    for (size_t c = 0; c < ctx->tev_used && c < pool.size(); ++c) {
+        auto& e = pool[c];
         hipError_t r = hipEventSynchronize(e[kTimingEvents - 1]);
         if (r != hipSuccess) return hip_fail(r, "hipEventSynchronize");
         for (int i = 0; i <= SOF_STAGE_COUNT; ++i) {
+            if (!e[2 * i] || !e[2 * i + 1]) continue;
             float t = 0.f;
             r = hipEventElapsedTime(&t, e[2 * i], e[2 * i + 1]);
             if (r != hipSuccess) return hip_fail(r, "hipEventElapsedTime");
@@ -160,13 +165,21 @@ extern "C" int sof_timing_read(sof_ctx* ctx, float* ms, int32_t* calls) {
 // next event set for an instrumented call (allocates events on first use)
 static const hipEvent_t* timing_events(sof_ctx* ctx) {
     if (!ctx->timing) return nullptr;
-    if (ctx->tev_used == ctx->tev.size()) {
+    auto& pool = ctx->timing_whole ? ctx->tev_whole : ctx->tev;
+    if (ctx->tev_used == pool.size()) {
         std::array<hipEvent_t, kTimingEvents> a;
-        for (auto& e : a)
-            if (hipEventCreate(&e) != hipSuccess) return nullptr;
-        ctx->tev.push_back(a);
+        for (int i = 0; i < kTimingEvents; ++i) {
+            a[i] = nullptr;
+            if (ctx->timing_whole && i < 2 * SOF_STAGE_COUNT) continue;
+            if (hipEventCreate(&a[i]) != hipSuccess) {
+                for (int j = 0; j < i; ++j)
+                    if (a[j]) (void)hipEventDestroy(a[j]);
+                return nullptr;
+            }
+        }
+        pool.push_back(a);
     }
-    return ctx->tev[ctx->tev_used++].data();
+    return pool[ctx->tev_used++].data();
 }
 
 int sof::launch_cfg(sof_ctx* ctx, int bins, int classes, int mode, LaunchCfg* cfg) {

@@ -21,7 +21,10 @@ struct sof_ctx {
     std::map<std::pair<int, int>, sof::LaunchCfg> cfg;   // key (4 * bins + mode, classes)
     bool timing = false;                             // benchmark instrumentation
     bool timing_serial = false;                      // ... with the size classes serialised
-    std::vector<std::array<hipEvent_t, sof::kTimingEvents>> tev;  // one event set per recorded call
+    bool timing_whole = false;                       // ... around the whole call only
+    // one event set per recorded call; in tev_whole only the whole call's
+    // pair exists (the stage entries are null)
+    std::vector<std::array<hipEvent_t, sof::kTimingEvents>> tev, tev_whole;
     size_t tev_used = 0;
     void* scratch = nullptr;   // device address of this device's static scratch array
     // the find-splits and partition sequences fork their size classes onto

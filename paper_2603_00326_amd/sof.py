@@ -183,11 +183,12 @@ class Context:
         except Exception:
             pass
 
-    def timing(self, enable, serial: bool = False):
+    def timing(self, enable, serial: bool = False, whole: bool = False):
         """Benchmark instrumentation: HIP events around each find_splits call
         and its stages; serial runs the size classes one after another so that
-        each stage's events bound its own kernels."""
-        _check(lib().sof_timing_enable(self.handle, 0 if not enable else (2 if serial else 1)))
+        each stage's events bound its own kernels; whole records only the
+        events around the call."""
+        _check(lib().sof_timing_enable(self.handle, 0 if not enable else (2 if serial else (3 if whole else 1))))
 
     STAGES = ("plan", "big_range", "big_merge", "big_hist", "big_scan", "mid", "mid2", "small", "sort",
               "reduce")

@@ -168,6 +168,34 @@ def test_repeat_runs_identical(ctx):
         assert a.tobytes() == b.tobytes() and np.array_equal(Ha, Hb)
 
 
+def test_timing_modes(ctx):
+    """The instrumentation's three modes leave the records unchanged: stage
+    events (every stage that has work reads > 0), the size classes serialised,
+    and the whole call only (stage figures 0, the whole call > 0)."""
+    import paper_2603_00326_amd as S
+    import torch
+    wl = W.random_frontier(52, n_rows=60000, d=16, n_classes=3, sizes=[10, 300, 2000, 6000, 20000], k=4, z=3,
+                           bins=256, sort_threshold=0, layout="r")
+    say("[gpu] timing modes")
+    _, ref, _ = run_gpu(ctx, wl, hist=False)
+    dev = S.to_device(wl)
+    for mode in ("stages", "serial", "whole"):
+        ctx.timing(True, serial=mode == "serial", whole=mode == "whole")
+        ctx.timing_read()
+        out, _ = S.find_splits(ctx, dev, bins=wl.bins, sort_threshold=0)
+        out, _ = S.find_splits(ctx, dev, bins=wl.bins, sort_threshold=0, out=out)
+        torch.cuda.synchronize()
+        ms, calls = ctx.timing_read()
+        ctx.timing(False)
+        assert calls == 2 and ms["total"] > 0, (mode, ms, calls)
+        stages = [ms[k] for k in ("plan", "big_range", "big_hist", "mid", "mid2", "small", "reduce")]
+        if mode == "whole":
+            assert all(t == 0 for t in stages), ms
+        else:
+            assert all(t > 0 for t in stages), (mode, ms)
+        assert S.splits_to_numpy(out)[:wl.n_nodes].tobytes() == ref.tobytes(), mode
+
+
 # --------------------------------------------------------------------------
 # random-width bins: every size class, histograms, records and partition
 
