@@ -1287,14 +1287,19 @@ __device__ __forceinline__ void big_chunk_cached(const FindArgs& A, const BigDes
 
 // The value cache pays when re-gathering a projection costs more than
 // reading its stored value back (z elements of s_x bytes against 4).
+// vc >= 0: the cache's base; vc <= -2: base -2 - vc, and projections of at
+// most 4 nonzeros re-gather (set by the expansion for XCD-local FP32 nodes
+// whose distinct columns come to at most 8 bytes per value); -1: no cache.
+__device__ __forceinline__ int vc_base(const BigDesc& bd) { return bd.vc >= 0 ? bd.vc : -2 - bd.vc; }
 template <typename T>
 __device__ __forceinline__ bool use_vcache(const BigDesc& bd, int z) {
-    return bd.vc >= 0 && z * (int)sizeof(T) > 8;
+    if (bd.vc == -1 || z * (int)sizeof(T) <= 8) return false;
+    return bd.vc >= 0 || z > 4;
 }
 __device__ __forceinline__ float* vcache_at(const FindArgs& A, const BigDesc& bd, int p, int ch) {
     int64_t s0, n;
     node_range(A, bd.node, s0, n);
-    return A.ws.vcache + (int64_t)bd.vc * kVcUnit + (int64_t)p * n + (int64_t)ch * kChunk;
+    return A.ws.vcache + (int64_t)vc_base(bd) * kVcUnit + (int64_t)p * n + (int64_t)ch * kChunk;
 }
 
 // ---------------------------------------------------------------------------
@@ -1510,18 +1515,19 @@ __global__ __launch_bounds__(kBlock) void k_expand(FindArgs A, PS P) {
             if (slice == 0) {
                 for (int p = tid; p < bd.k; p += kBlock)
                     if (bd.item_c + (int64_t)p < W.cap_ibigc) W.items_bigc[bd.item_c + p] = make_int2(e, p);
-                // In the XCD-local layout, FP32 values whose node reads at most
-                // 8 bytes of distinct columns per value (min(d, sum z) columns
-                // over k projections) re-gather from L2 in the histogram pass
-                // instead of writing and reading the value cache (8 bytes of
-                // HBM per value).  FP16 gathers (128 bytes per wave
-                // instruction) stay bound by their issue, so they keep it.
+                // In the XCD-local layout, FP32 projections of at most 4
+                // nonzeros whose node reads at most 8 bytes of distinct
+                // columns per value (min(d, sum z) columns over k projections)
+                // re-gather from L2 in the histogram pass instead of writing
+                // and reading the value cache (8 bytes of HBM per value).
+                // Projections of more nonzeros, and FP16 gathers (128 bytes
+                // per wave instruction), are bound by their issue and keep it.
                 int zs = 0;
                 for (int z = 1; z <= SOF_MAX_NNZ; ++z) zs += z * zcnt[z];
                 const int64_t m = zs < A.n_features ? zs : A.n_features;
                 if (tid == 0 && bd.vc >= 0 && big_xcd(bd.nchunk) && A.dtype != SOF_F16 &&
                     m * 4 <= 8 * (int64_t)bd.k)
-                    ((int*)&W.desc_big[2 * e + 1])[3] = -1;
+                    ((int*)&W.desc_big[2 * e + 1])[3] = -2 - bd.vc;
             }
             __syncthreads();   // zcnt and perm are reused by the block's next descriptor
         }
