@@ -168,6 +168,35 @@ def test_repeat_runs_identical(ctx):
         assert a.tobytes() == b.tobytes() and np.array_equal(Ha, Hb)
 
 
+# Nodes of 16 or more 8192-sample chunks take the XCD-local item order (their
+# projections and chunks padded to whole quads and groups of 8); FP32 nodes
+# with few distinct columns re-gather projections of up to 4 nonzeros instead
+# of caching them.  Random labels keep the score curves flat (the binary64
+# screen of many near-tied boundaries runs too).
+@pytest.mark.parametrize("k,z,d,bm,crit,dt", [(6, (1, 8), 8, 0, 0, np.float32), (5, 3, 40, 1, 0, np.float32),
+                                             (7, (1, 6), 16, 0, 1, np.float16), (8, 4, 300, 1, 1, np.float32)])
+def test_xcd_layout_nodes(ctx, k, z, d, bm, crit, dt):
+    import torch
+    from paper_2603_00326_amd import sof as S
+    wl = W.random_frontier(97 + k, n_rows=450000, d=d, n_classes=3, sizes=[140000, 9000, 270001, 600, 131073], k=k,
+                           z=z, bins=256, sort_threshold=0, layout="b", dtype=dt)
+    say(f"[gpu] XCD-local big nodes k={k} z={z} d={d} bin_mode={bm} criterion={crit} dtype={np.dtype(dt).name}")
+    modes = dict(bin_mode=bm, bin_seed=31, criterion=crit)
+    dev = S.to_device(wl)
+    out, H = S.find_splits(ctx, dev, bins=wl.bins, sort_threshold=0, hist=True, **modes)
+    out_idx, coff = S.partition(ctx, dev, out, bins=wl.bins)
+    torch.cuda.synchronize()
+    got = S.splits_to_numpy(out)[:wl.n_nodes]
+    ref, Href = O.find_splits_w(wl, hist=True, **modes)
+    assert_splits_match(got, ref, "XCD-local")
+    bad = np.argwhere(H.cpu().numpy() != Href)
+    assert bad.size == 0, f"histogram differs at {bad[:5].tolist()}"
+    want_idx, want_coff = O.partition(wl.X, wl.node_offsets, wl.sample_idx, wl.proj_offsets, wl.nz_offsets,
+                                      wl.nz_feature, wl.nz_weight, ref, bins=wl.bins)
+    assert np.array_equal(coff.cpu().numpy(), want_coff)
+    assert np.array_equal(out_idx.cpu().numpy(), want_idx)
+
+
 def test_timing_modes(ctx):
     """The instrumentation's three modes leave the records unchanged: stage
     events (every stage that has work reads > 0), the size classes serialised,
