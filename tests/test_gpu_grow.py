@@ -202,3 +202,12 @@ def test_grow_entropy_and_random_width_big_roots(ctx, criterion, bin_mode, dtype
 def test_grow_density_sampler_entropy_random_width(ctx):
     grow_case(ctx, seed=59, d=24, n=800, C=4, trees=2, k=6, z=3, bins=128, T=60, graph=True, sampler=1,
               weights=1, criterion=1, bin_mode=1, bin_seed=5)
+
+
+# Roots of 140000 samples (18 chunks): the XCD-local item order of the
+# big-node passes under drawn projections, with entropy, random-width bins
+# and FP16 storage.
+@pytest.mark.parametrize("criterion,bin_mode,dtype", [(1, 0, np.float32), (0, 1, np.float32), (0, 0, np.float16)])
+def test_grow_xcd_layout_roots(ctx, criterion, bin_mode, dtype):
+    grow_case(ctx, seed=60, d=12, n=140000, C=3, trees=2, k=6, z=3, bins=256, T=40, max_depth=3, graph=True,
+              dtype=dtype, criterion=criterion, bin_mode=bin_mode, bin_seed=9)
