@@ -521,6 +521,10 @@ def main():
                     help="config 3: nodes below this size take half the bins (default: the autotuner's "
                          "rule; 0 = full bins everywhere)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--small-max", type=int, default=None,
+                    help="wave tile edge: nodes up to this size take a wave per projection (256..512; default tuned)")
+    ap.add_argument("--mid-split", type=int, default=None,
+                    help="wave tile edge: 16 samples per thread up to this size (2048..4096; default tuned)")
     ap.add_argument("--graph", type=int, default=1,
                     help="also time the step captured into one HIP graph and replayed")
     ap.add_argument("--project", type=int, default=1,
@@ -593,13 +597,20 @@ def main():
     stream = torch.cuda.current_stream()
     out = torch.empty((max(wl.n_nodes, 1), 10), dtype=torch.int32, device=dev_name)
 
+    # the wave tile edges the autotuner chose (0: the library's defaults)
+    small_max = int(tune["small_max"]) if tune else 0
+    mid_split = int(tune["mid_split"]) if tune else 0
+    if args.small_max is not None:
+        small_max = args.small_max
+    if args.mid_split is not None:
+        mid_split = args.mid_split
     bin_mode = int(wl.meta.get("bin_mode", 0))
     bin_seed = int(wl.meta.get("bin_seed", 0))
     criterion = int(wl.meta.get("criterion", 0))
 
     def step():
         S.find_splits(ctx, dev, bins=wl.bins, sort_threshold=T, out=out, bin_mode=bin_mode, bin_seed=bin_seed,
-                      criterion=criterion)
+                      criterion=criterion, small_max=small_max, mid_split=mid_split)
         return S.partition(ctx, dev, out, bins=wl.bins)
 
     for _ in range(args.warmup):
@@ -684,6 +695,7 @@ def main():
                    "sort_threshold": T, "bins": wl.bins,
                    "bins_small": int(bins_small) if bins_switch > 0 else None,
                    "bins_switch": int(bins_switch),
+                   "wave_tile": {"small_max": small_max or 512, "mid_split": mid_split or 4096},
                    "bin_layout": "random width" if bin_mode else "equal width",
                    "criterion": "entropy" if criterion else "gini",
                    "step": "find_splits + partition"},

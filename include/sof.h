@@ -154,6 +154,14 @@ typedef struct {
     int32_t        bin_mode;      /* SOF_BINS_EQUAL or SOF_BINS_RANDOM */
     int32_t        criterion;     /* SOF_CRIT_GINI or SOF_CRIT_ENTROPY, on both paths */
     uint64_t       bin_seed;      /* SOF_BINS_RANDOM: seed of the widths */
+    /* Wave tile of the histogram path (the results do not depend on it):
+     * nodes of up to small_max samples take one wave per projection, larger
+     * ones up to mid_split one block per 4 projections with up to 16 samples
+     * per thread, larger ones up to 8192 the same with 32 per thread.
+     * small_max in [256, 512], mid_split in [2048, 4096]; 0 picks 512 and
+     * 4096 (sof_autotune measures both choices). */
+    int32_t        small_max;
+    int32_t        mid_split;
 } sof_params;
 
 /* Criteria.  SOF_CRIT_GINI: Gini decrease, argmax by exact 128-bit integer
@@ -247,6 +255,15 @@ typedef struct {
     int32_t sizes[32];
     float   elapsed_ms;       /* wall time of the whole tuning run */
     float   half_us[32];      /* per measured size: histogram path with bins_small bins (us) */
+    int32_t small_max;        /* chosen wave tile (sof_params.small_max, mid_split) */
+    int32_t mid_split;
+    /* per measured size in 257..512 (2049..4096), on a frontier of at least 4
+     * nodes per compute unit: the histogram path with the default tile and
+     * with the block tile (32 samples per thread) (us); 0 elsewhere.  An edge
+     * moves below a size when the other tile is more than 5% faster there
+     * and at every larger size of its range. */
+    float   tile_base_us[32];
+    float   tile_us[32];
 } sof_tune;
 
 /* ---------------------------------------------------------------------- */

@@ -1326,9 +1326,9 @@ __global__ __launch_bounds__(kBlock) void k_plan(FindArgs A, PS P) {
         int cat = CAT_NONE;
         if (act) {
             if (k == 0) cat = CAT_NOSPLIT;
-            else if (sortp ? n <= kSortWaveMax : n <= kSmallMax) cat = CAT_SMALL;
+            else if (sortp ? n <= kSortWaveMax : n <= A.small_max) cat = CAT_SMALL;
             else if (sortp) cat = CAT_SB;
-            else if (n <= kMidSplit) cat = CAT_MID;
+            else if (n <= A.mid_split) cat = CAT_MID;
             else if (n <= kMidMax) cat = CAT_MID2;
             else cat = CAT_BIG;
         }

@@ -504,6 +504,8 @@ static hipError_t level_launch(sof_forest* f, hipStream_t s) {
     a.node_bins = nullptr;
     a.bins = f->desc.bins;
     a.sort_threshold = clamp_threshold(f->desc.sort_threshold);
+    a.small_max = kSmallMax;
+    a.mid_split = kMidSplit;
     a.bin_mode = f->desc.bin_mode;
     a.criterion = f->desc.criterion;
     a.bin_seed = f->desc.bin_seed;

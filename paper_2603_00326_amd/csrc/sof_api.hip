@@ -262,6 +262,12 @@ int sof::check_params(const sof_params* q) {
         return fail(SOF_ERR_UNSUPPORTED, "bin_mode %d (expected SOF_BINS_EQUAL or SOF_BINS_RANDOM)", q->bin_mode);
     if (q->criterion != SOF_CRIT_GINI && q->criterion != SOF_CRIT_ENTROPY)
         return fail(SOF_ERR_UNSUPPORTED, "criterion %d (expected SOF_CRIT_GINI or SOF_CRIT_ENTROPY)", q->criterion);
+    if (q->small_max != 0 && (q->small_max < kSmallMaxMin || q->small_max > kSmallMax))
+        return fail(SOF_ERR_INVALID_ARG, "small_max %d outside [%d, %d] (0: %d)", q->small_max, kSmallMaxMin,
+                    kSmallMax, kSmallMax);
+    if (q->mid_split != 0 && (q->mid_split < kMidSplitMin || q->mid_split > kMidSplit))
+        return fail(SOF_ERR_INVALID_ARG, "mid_split %d outside [%d, %d] (0: %d)", q->mid_split, kMidSplitMin,
+                    kMidSplit, kMidSplit);
     return SOF_OK;
 }
 
@@ -278,7 +284,7 @@ FindLayout sof::find_layout(int64_t N, int64_t S, int64_t P, int64_t K, int bins
     FindLayout L;
     memset(&L, 0, sizeof(L));
     FindWs& c = L.caps;
-    const int64_t nmid = mn(N, S / (kSmallMax + 1));
+    const int64_t nmid = mn(N, S / (kSmallMaxMin + 1));
     const int64_t nsb = mn(N, S / (kSortWaveMax + 1));
     const int64_t nbig = mn(N, S / (kMidMax + 1));
     c.cap_small = N + 1;
@@ -293,7 +299,7 @@ FindLayout sof::find_layout(int64_t N, int64_t S, int64_t P, int64_t K, int bins
     c.cap_ibigc = mn(P, K * nbig) + 1;
     c.cap_slots = mn(P, K * nsb) + 1;
     c.cap_bigslots = mn(P, K * nbig) + 1;
-    const int64_t nmid2 = mn(N, S / (kMidSplit + 1));
+    const int64_t nmid2 = mn(N, S / (kMidSplitMin + 1));
     c.cap_dmid2 = nmid2 + 1;
     c.cap_imid2 = mn(P, K * nmid2) + 1;
     // every big node's n * k values, each node rounded up to whole units; off
@@ -398,6 +404,8 @@ int sof::fill_find_args(const sof_data* data, const sof_frontier* fr, const sof_
     a->node_bins = params->node_bins;
     a->bins = params->bins;
     a->sort_threshold = clamp_threshold(params->sort_threshold);
+    a->small_max = params->small_max ? params->small_max : kSmallMax;
+    a->mid_split = params->mid_split ? params->mid_split : kMidSplit;
     a->bin_mode = params->bin_mode;
     a->criterion = params->criterion;
     a->bin_seed = params->bin_seed;

@@ -16,6 +16,9 @@ constexpr int kSortWaveMax = 64;     // sort nodes up to here: sorted in registe
 constexpr int kSmallMax = 512;       // histogram nodes up to here: one block per node (8 samples per lane)
 constexpr int kMidSplit = 4096;      // mid nodes up to here: at most 16 samples per thread
 constexpr int kMidMax = 8192;        // histogram nodes up to here: one block per (node, projection group)
+// ranges of the run-time wave tile edges (sof_params.small_max, mid_split)
+constexpr int kSmallMaxMin = 256;
+constexpr int kMidSplitMin = 2048;
 constexpr int kChunk = 8192;         // larger nodes: (node, projection, sample chunk) items
 constexpr int kXcdChunks = 16;       // big nodes of this many chunks or more: XCD-local item layout
 constexpr int kXcds = 8;             // XCDs of the device (workgroups are dealt to them round-robin)
@@ -110,6 +113,7 @@ struct FindArgs {
     const int32_t* n_nodes_dev; // device count (forest growth), or NULL
     const int32_t* node_bins;
     int32_t bins, sort_threshold;  // sort_threshold already clamped
+    int32_t small_max, mid_split;  // wave tile edges (sof_params; 0 there means kSmallMax, kMidSplit)
     int32_t bin_mode;           // SOF_BINS_EQUAL or SOF_BINS_RANDOM
     int32_t criterion;          // SOF_CRIT_GINI or SOF_CRIT_ENTROPY
     uint64_t bin_seed;

@@ -47,17 +47,18 @@ __global__ void k_tune_data(float* x, _Float16* xh, int32_t* y, int n_rows, int 
     }
 }
 
-// frontier of N nodes of s contiguous rows; k projections per node, nnz
-// distinct features each (consecutive from a hashed start), signs hashed
+// frontier of N nodes of s contiguous rows (row i mod n_rows for sample i);
+// k projections per node, nnz distinct features each (consecutive from a
+// hashed start), signs hashed
 __global__ void k_tune_frontier(int32_t* node_off, int32_t* idx, int32_t* proj_off, int32_t* nz_off,
-                                int32_t* nz_f, int8_t* nz_w, int N, int s, int k, int nnz, int d) {
+                                int32_t* nz_f, int8_t* nz_w, int N, int s, int k, int nnz, int d, int n_rows) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     for (int64_t v = t0; v <= N; v += stride) {
         node_off[v] = (int32_t)(v * s);
         proj_off[v] = (int32_t)(v * k);
     }
-    for (int64_t i = t0; i < (int64_t)N * s; i += stride) idx[i] = (int32_t)i;
+    for (int64_t i = t0; i < (int64_t)N * s; i += stride) idx[i] = (int32_t)(i % n_rows);
     const int64_t P = (int64_t)N * k;
     for (int64_t q = t0; q <= P; q += stride) nz_off[q] = (int32_t)(q * nnz);
     for (int64_t q = t0; q < P; q += stride) {
@@ -121,7 +122,14 @@ static int autotune_impl(sof_ctx* ctx, const sof_data* user, int32_t dtype, int3
     const int kk = k > 64 ? 64 : k;   // per node-projection cost is what is compared
     int maxN = 0;
     for (int i = 0; i < n_sizes; ++i) maxN = n_rows / kSizes[i] > maxN ? n_rows / kSizes[i] : maxN;
+    // The two wave tiles are compared on frontiers that fill the GPU (4
+    // nodes per compute unit; rows repeat): with only 2^16 rows the larger
+    // sizes have too few nodes for the wave-per-projection tile's one block
+    // per node, and the block tile would win for that reason alone.
+    const int n_tile = 4 * ctx->n_cu;
+    if (n_tile > maxN) maxN = n_tile;
     const int64_t maxP = (int64_t)maxN * kk;
+    const int64_t max_idx = (int64_t)n_tile * kMidSplit > n_rows ? (int64_t)n_tile * kMidSplit : n_rows;
 
     TuneBufs B;
     float* x = nullptr;
@@ -131,7 +139,7 @@ static int autotune_impl(sof_ctx* ctx, const sof_data* user, int32_t dtype, int3
     sof_split* sp;
     if ((!user && ((e = B.get(&x, (size_t)n_rows * d)) || (e = B.get(&xh, (size_t)n_rows * d)) ||
                    (e = B.get(&y, n_rows)))) ||
-        (e = B.get(&no, maxN + 1)) || (e = B.get(&idx, n_rows)) || (e = B.get(&po, maxN + 1)) ||
+        (e = B.get(&no, maxN + 1)) || (e = B.get(&idx, (size_t)max_idx)) || (e = B.get(&po, maxN + 1)) ||
         (e = B.get(&zo, maxP + 1)) || (e = B.get(&zf, maxP * nnz)) || (e = B.get(&zw, maxP * nnz)) ||
         (e = B.get(&sp, maxN)) || (e = B.get(&node_bins, maxN)))
         return hip_fail(e, "sof_autotune: hipMalloc");
@@ -155,8 +163,9 @@ static int autotune_impl(sof_ctx* ctx, const sof_data* user, int32_t dtype, int3
     // workspace for the largest frontier
     size_t ws_bytes = 0;
     for (int i = 0; i < n_sizes; ++i) {
-        const int N = n_rows / kSizes[i];
+        int N = n_rows / kSizes[i];
         if (N < 1) continue;
+        if (kSizes[i] > kSmallMaxMin && kSizes[i] <= kMidSplit && N < n_tile) N = n_tile;
         sof_frontier fr{no, idx, (int64_t)N * kSizes[i], N, kSizes[i]};
         sof_proj pj{po, zo, zf, zw, (int64_t)N * kk * nnz, N * kk, kk};
         sof_params q{nullptr, bins, 0};
@@ -176,25 +185,29 @@ static int autotune_impl(sof_ctx* ctx, const sof_data* user, int32_t dtype, int3
     float* half_us = out->half_us;
     int rc = SOF_OK;
     const int half_bins = bins / 2 >= SOF_MIN_BINS ? bins / 2 : SOF_MIN_BINS;
-    bool warm[3] = {false, false, false};
+    bool warm[4] = {false, false, false, false};
     int hist_wins = 0;   // consecutive sizes at which histograms were not slower
     int np = 0;
     for (int i = 0; i < n_sizes && rc == SOF_OK; ++i) {
         const int sz = kSizes[i], N = n_rows / sz;
         if (N < 1) break;
-        hipLaunchKernelGGL(k_tune_frontier, dim3(512), dim3(256), 0, s, no, idx, po, zo, zf, zw, N, sz, kk, nnz, d);
+        hipLaunchKernelGGL(k_tune_frontier, dim3(512), dim3(256), 0, s, no, idx, po, zo, zf, zw, N, sz, kk, nnz, d,
+                           n_rows);
         sof_frontier fr{no, idx, (int64_t)N * sz, N, sz};
         sof_proj pj{po, zo, zf, zw, (int64_t)N * kk * nnz, N * kk, kk};
-        float best[3] = {1e30f, 1e30f, 1e30f};
+        float best[4] = {1e30f, 1e30f, 1e30f, 1e30f};
         const bool need_sort = hist_wins < 2, need_half = sz <= 1024;
-        for (int path = 0; path < 3 && rc == SOF_OK; ++path) {
-            // 0: sort path, 1: histogram path, 2: histogram path with half the bins
-            if ((path == 0 && !need_sort) || (path == 2 && !need_half)) continue;
-            sof_params q{nullptr, path == 2 ? half_bins : bins, path == 0 ? 0x7fffffff : 0};
-            // the first call of each path warms it up; then two timed calls
-            for (int rep = warm[path] ? 1 : 0; rep < 3 && rc == SOF_OK; ++rep) {
+        // the other wave tile of this size: a block per 4 projections instead
+        // of a wave per projection (257..512), or 32 samples per thread
+        // instead of 16 (2049..4096)
+        const bool tile_small = sz > kSmallMaxMin && sz <= kSmallMax;
+        const bool tile_mid = sz > kMidSplitMin && sz <= kMidSplit;
+        // best of two timed calls (after a warm-up call when warm is false)
+        auto time_calls = [&](const sof_frontier& f, const sof_proj& pp, const sof_params& q, bool warm) {
+            float b = 1e30f;
+            for (int rep = warm ? 1 : 0; rep < 3 && rc == SOF_OK; ++rep) {
                 (void)hipEventRecord(ev0, s);
-                rc = sof_find_splits(ctx, &data, &fr, &pj, &q, sp, nullptr, ws, ws_bytes, stream);
+                rc = sof_find_splits(ctx, &data, &f, &pp, &q, sp, nullptr, ws, ws_bytes, stream);
                 (void)hipEventRecord(ev1, s);
                 if (rc) break;
                 if ((e = hipEventSynchronize(ev1)) != hipSuccess) {
@@ -203,8 +216,15 @@ static int autotune_impl(sof_ctx* ctx, const sof_data* user, int32_t dtype, int3
                 }
                 float ms = 0.f;
                 (void)hipEventElapsedTime(&ms, ev0, ev1);
-                if (rep > 0 && ms < best[path]) best[path] = ms;
+                if (rep > 0 && ms < b) b = ms;
             }
+            return b;
+        };
+        for (int path = 0; path < 3 && rc == SOF_OK; ++path) {
+            // 0: sort path, 1: histogram path, 2: histogram path with half the bins
+            if ((path == 0 && !need_sort) || (path == 2 && !need_half)) continue;
+            sof_params q{nullptr, path == 2 ? half_bins : bins, path == 0 ? 0x7fffffff : 0};
+            best[path] = time_calls(fr, pj, q, warm[path]);
             warm[path] = true;
         }
         const float per = 1e3f / (float)((int64_t)N * kk);   // ms per call -> us per node-projection
@@ -214,6 +234,23 @@ static int autotune_impl(sof_ctx* ctx, const sof_data* user, int32_t dtype, int3
         out->sort_us[i] = need_sort ? best[0] * per : 0.f;
         // above 1024 samples half bins are not measured: recorded as full bins
         half_us[i] = need_half ? best[2] * per : out->hist_us[i];
+        if ((tile_small || tile_mid) && rc == SOF_OK) {
+            // both wave tiles on a frontier of at least n_tile nodes
+            const int Nt = N > n_tile ? N : n_tile;
+            hipLaunchKernelGGL(k_tune_frontier, dim3(512), dim3(256), 0, s, no, idx, po, zo, zf, zw, Nt, sz, kk,
+                               nnz, d, n_rows);
+            sof_frontier ft{no, idx, (int64_t)Nt * sz, Nt, sz};
+            sof_proj pt{po, zo, zf, zw, (int64_t)Nt * kk * nnz, Nt * kk, kk};
+            sof_params q{nullptr, bins, 0};
+            const float base = time_calls(ft, pt, q, warm[3]);
+            q.small_max = tile_small ? kSmallMaxMin : 0;
+            q.mid_split = tile_mid ? kMidSplitMin : 0;
+            best[3] = time_calls(ft, pt, q, warm[3]);
+            warm[3] = true;
+            const float pt_us = 1e3f / (float)((int64_t)Nt * kk);
+            out->tile_base_us[i] = base * pt_us;
+            out->tile_us[i] = best[3] * pt_us;
+        }
         if (need_sort) hist_wins = out->hist_us[i] <= out->sort_us[i] ? hist_wins + 1 : 0;
         np = i + 1;
     }
@@ -240,6 +277,20 @@ static int autotune_impl(sof_ctx* ctx, const sof_data* user, int32_t dtype, int3
     if (np > 0 && sw == kSizes[0]) sw = 0;
     out->bins_small = half_bins;
     out->bins_switch = sw;
+    // wave tile edges: from the largest measured size of each range down, a
+    // size whose other tile is more than 5% faster moves the edge below it
+    int small_max = kSmallMax, mid_split = kMidSplit;
+    for (int i = np - 1; i >= 0; --i) {
+        const int sz = kSizes[i];
+        if (sz > kSmallMaxMin && sz <= kSmallMax && sz == small_max && out->tile_us[i] > 0.f &&
+            out->tile_us[i] * 1.05f < out->tile_base_us[i])
+            small_max = i > 0 && kSizes[i - 1] >= kSmallMaxMin ? kSizes[i - 1] : kSmallMaxMin;
+        if (sz > kMidSplitMin && sz <= kMidSplit && sz == mid_split && out->tile_us[i] > 0.f &&
+            out->tile_us[i] * 1.05f < out->tile_base_us[i])
+            mid_split = i > 0 && kSizes[i - 1] >= kMidSplitMin ? kSizes[i - 1] : kMidSplitMin;
+    }
+    out->small_max = small_max;
+    out->mid_split = mid_split;
     out->elapsed_ms =
         std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - wall0).count();
     return SOF_OK;

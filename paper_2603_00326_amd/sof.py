@@ -67,7 +67,7 @@ class sof_proj(ctypes.Structure):
 
 class sof_params(ctypes.Structure):
     _fields_ = [("node_bins", P), ("bins", i32), ("sort_threshold", i32), ("bin_mode", i32), ("criterion", i32),
-                ("bin_seed", u64)]
+                ("bin_seed", u64), ("small_max", i32), ("mid_split", i32)]
 
 
 class sof_forest_desc(ctypes.Structure):
@@ -80,7 +80,9 @@ class sof_forest_desc(ctypes.Structure):
 class sof_tune(ctypes.Structure):
     _fields_ = [("sort_threshold", i32), ("bins_small", i32), ("bins_switch", i32), ("n_points", i32),
                 ("sort_us", ctypes.c_float * 32), ("hist_us", ctypes.c_float * 32),
-                ("sizes", i32 * 32), ("elapsed_ms", ctypes.c_float), ("half_us", ctypes.c_float * 32)]
+                ("sizes", i32 * 32), ("elapsed_ms", ctypes.c_float), ("half_us", ctypes.c_float * 32),
+                ("small_max", i32), ("mid_split", i32), ("tile_base_us", ctypes.c_float * 32),
+                ("tile_us", ctypes.c_float * 32)]
 
 
 SPLIT_DTYPE = np.dtype([
@@ -106,6 +108,13 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2603_00326_amd.build.build()")
+        # PyTorch first: its wheel ships its own HIP runtime under the same
+        # soname as the system one libsof.so links, so whichever loads first
+        # serves both; loaded the other way round, torch finds no GPU
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         L.sof_version.restype = ctypes.c_char_p
         L.sof_last_error.restype = ctypes.c_char_p
@@ -271,9 +280,9 @@ def to_device(wl, device="cuda:0", X=None) -> DeviceFrontier:
 
 
 def _params(dev: DeviceFrontier, bins: int, sort_threshold: int, bin_mode: int = SOF_BINS_EQUAL,
-            bin_seed: int = 0, criterion: int = SOF_CRIT_GINI) -> sof_params:
+            bin_seed: int = 0, criterion: int = SOF_CRIT_GINI, small_max: int = 0, mid_split: int = 0) -> sof_params:
     return sof_params(_ptr(dev.node_bins), int(bins), int(sort_threshold), int(bin_mode), int(criterion),
-                      int(bin_seed) & (2**64 - 1))
+                      int(bin_seed) & (2**64 - 1), int(small_max), int(mid_split))
 
 
 def workspace_size(dev: DeviceFrontier, bins: int = 256, sort_threshold: int = 0, ctx=None,
@@ -287,12 +296,14 @@ def workspace_size(dev: DeviceFrontier, bins: int = 256, sort_threshold: int = 0
 
 
 def find_splits(ctx: Context, dev: DeviceFrontier, *, bins=256, sort_threshold=0, hist=False,
-                out=None, stream=None, bin_mode=SOF_BINS_EQUAL, bin_seed=0, criterion=SOF_CRIT_GINI):
+                out=None, stream=None, bin_mode=SOF_BINS_EQUAL, bin_seed=0, criterion=SOF_CRIT_GINI,
+                small_max=0, mid_split=0):
     """Best split per node.  Returns (splits int32 tensor (N, 10) in sof_split
-    layout, hist int32 tensor (P, bins, C) or None)."""
+    layout, hist int32 tensor (P, bins, C) or None).  small_max / mid_split:
+    the wave tile edges (0: the library's defaults)."""
     import torch
     d, f, p = dev.structs()
-    q = _params(dev, bins, sort_threshold, bin_mode, bin_seed, criterion)
+    q = _params(dev, bins, sort_threshold, bin_mode, bin_seed, criterion, small_max, mid_split)
     ws, wsb = ctx.workspace(workspace_size(dev, bins, sort_threshold, ctx, criterion))
     N = dev.n_nodes
     if out is None:
@@ -393,11 +404,14 @@ def autotune(ctx: Context, n_classes: int, k: int, z: int, bins: int = 256, *, d
                                   _stream(stream)))
     n = int(t.n_points)
     return {"sort_threshold": int(t.sort_threshold), "bins_small": int(t.bins_small),
-            "bins_switch": int(t.bins_switch), "ms": float(t.elapsed_ms),
+            "bins_switch": int(t.bins_switch), "small_max": int(t.small_max), "mid_split": int(t.mid_split),
+            "ms": float(t.elapsed_ms),
             "sizes": [int(t.sizes[i]) for i in range(n)],
             "sort_us": [round(float(t.sort_us[i]), 5) for i in range(n)],
             "hist_us": [round(float(t.hist_us[i]), 5) for i in range(n)],
-            "half_us": [round(float(t.half_us[i]), 5) for i in range(n)]}
+            "half_us": [round(float(t.half_us[i]), 5) for i in range(n)],
+            "tile_base_us": [round(float(t.tile_base_us[i]), 5) for i in range(n)],
+            "tile_us": [round(float(t.tile_us[i]), 5) for i in range(n)]}
 
 
 def nodes_to_device(nodes: np.ndarray, device="cuda:0"):

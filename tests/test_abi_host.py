@@ -80,10 +80,11 @@ def proj(S, **kw):
 
 
 def params(S, **kw):
-    q = dict(node_bins=None, bins=256, sort_threshold=64, bin_mode=0, bin_seed=0, criterion=0)
+    q = dict(node_bins=None, bins=256, sort_threshold=64, bin_mode=0, bin_seed=0, criterion=0, small_max=0,
+             mid_split=0)
     q.update(kw)
     return S.sof_params(q["node_bins"], q["bins"], q["sort_threshold"], q["bin_mode"], q["criterion"],
-                        q["bin_seed"])
+                        q["bin_seed"], q["small_max"], q["mid_split"])
 
 
 def ws_size(S, L, d=None, f=None, p=None, q=None):
@@ -96,6 +97,10 @@ def ws_size(S, L, d=None, f=None, p=None, q=None):
 def test_workspace_size_of_valid_arguments(S, L):
     rc, n = ws_size(S, L)
     assert rc == OK and n > 0
+    # every wave tile in range is accepted and sized alike
+    for sm, ms in ((256, 2048), (384, 3072), (512, 4096)):
+        rc_t, n_t = ws_size(S, L, q=params(S, small_max=sm, mid_split=ms))
+        assert rc_t == OK and n_t == n
     # larger frontiers never need less workspace
     rc2, n2 = ws_size(S, L, f=frontier(S, n_nodes=40, n_samples=100000, max_node_samples=4000),
                       d=data(S, n_rows=100000, ld=100000))
@@ -134,6 +139,10 @@ def test_workspace_size_of_valid_arguments(S, L):
     ("params", dict(bin_mode=2), UNSUPPORTED),
     ("params", dict(bin_mode=-1), UNSUPPORTED),
     ("params", dict(criterion=2), UNSUPPORTED),
+    ("params", dict(small_max=255), INVALID),
+    ("params", dict(small_max=513), INVALID),
+    ("params", dict(mid_split=2047), INVALID),
+    ("params", dict(mid_split=4097), INVALID),
 ])
 def test_workspace_size_rejects(S, L, part, kw, code):
     args = {"d": None, "f": None, "p": None, "q": None}

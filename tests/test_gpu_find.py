@@ -197,6 +197,27 @@ def test_xcd_layout_nodes(ctx, k, z, d, bm, crit, dt):
     assert np.array_equal(out_idx.cpu().numpy(), want_idx)
 
 
+# The wave tile edges change which kernel takes a node, never its split.
+@pytest.mark.parametrize("small_max,mid_split,crit,bm", [(256, 2048, 0, 0), (384, 3072, 1, 0), (256, 2048, 0, 1)])
+def test_wave_tile_edges(ctx, small_max, mid_split, crit, bm):
+    import torch
+    from paper_2603_00326_amd import sof as S
+    sizes = EDGE_SIZES + [300, 384, 385, 400, 2500, 3072, 3073, 3500]
+    wl = W.random_frontier(98, n_rows=120000, d=16, n_classes=3, sizes=sizes, k=5, z=(1, 6), bins=256,
+                           sort_threshold=40, layout="r")
+    say(f"[gpu] wave tile small_max={small_max} mid_split={mid_split} criterion={crit} bin_mode={bm}")
+    modes = dict(bin_mode=bm, bin_seed=5, criterion=crit)
+    dev = S.to_device(wl)
+    out, H = S.find_splits(ctx, dev, bins=256, sort_threshold=40, hist=True, small_max=small_max,
+                           mid_split=mid_split, **modes)
+    torch.cuda.synchronize()
+    got = S.splits_to_numpy(out)[:wl.n_nodes]
+    ref, Href = O.find_splits_w(wl, hist=True, **modes)
+    assert_splits_match(got, ref, "wave tile")
+    bad = np.argwhere(H.cpu().numpy() != Href)
+    assert bad.size == 0, f"histogram differs at {bad[:5].tolist()}"
+
+
 def test_timing_modes(ctx):
     """The instrumentation's three modes leave the records unchanged: stage
     events (every stage that has work reads > 0), the size classes serialised,
@@ -338,6 +359,19 @@ def check_tune(t, bins):
         assert t["hist_us"][i - 1] > t["sort_us"][i - 1] > 0
     assert all(h > 0 for h in t["hist_us"])
     assert t["bins_small"] == max(bins // 2, 2)
+    # the wave tile: the other tile measured exactly at 384, 512, 3072, 4096,
+    # and each edge moved below a size only where that tile was > 5% faster
+    tiled = {384, 512, 3072, 4096}
+    for j, sz in enumerate(TUNE_SIZES):
+        assert (t["tile_us"][j] > 0) == (sz in tiled)
+    for edge, (lo, mid, hi) in (("small_max", (256, 384, 512)), ("mid_split", (2048, 3072, 4096))):
+        def faster(sz):
+            j = TUNE_SIZES.index(sz)
+            return t["tile_us"][j] * 1.05 < t["tile_base_us"][j]
+        want = hi
+        if faster(hi):
+            want = lo if faster(mid) else mid
+        assert t[edge] == want, (edge, t[edge], want)
 
 
 @pytest.mark.parametrize("dt", [np.float32, np.float16])

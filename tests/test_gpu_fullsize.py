@@ -36,7 +36,8 @@ def tuned_threshold(ctx, wl):
 
 def tuned_config3(ctx, wl):
     """The benchmark's configuration of a config-3 frontier: the autotuned
-    switch, and half the bins below the autotuned size (128-256 bins)."""
+    switch, half the bins below the autotuned size (128-256 bins), and the
+    autotuned wave tile (passed on by run_full)."""
     t = tune(ctx, wl)
     if t["bins_switch"] > 0:
         n = np.diff(wl.node_offsets.astype(np.int64))
@@ -44,12 +45,13 @@ def tuned_config3(ctx, wl):
     return int(t["sort_threshold"]), t
 
 
-def run_full(ctx, wl, T, bin_mode=0, bin_seed=0, criterion=0):
+def run_full(ctx, wl, T, bin_mode=0, bin_seed=0, criterion=0, tune=None):
     import torch
     from paper_2603_00326_amd import sof as S
     dev = S.to_device(wl)
+    tiles = dict(small_max=tune["small_max"], mid_split=tune["mid_split"]) if tune else {}
     out, _ = S.find_splits(ctx, dev, bins=wl.bins, sort_threshold=T, bin_mode=bin_mode, bin_seed=bin_seed,
-                           criterion=criterion)
+                           criterion=criterion, **tiles)
     out_idx, coff = S.partition(ctx, dev, out, bins=wl.bins)
     torch.cuda.synchronize()
     got = S.splits_to_numpy(out)[:wl.n_nodes]
@@ -94,8 +96,8 @@ def test_frontier_4096_lognormal_nodes(ctx, layout):
     T0, t = tuned_config3(ctx, wl)
     for T in sorted({T0, 48}):
         say(f"[gpu] full frontier layout={layout} nodes={wl.n_nodes} samples={wl.n_samples} T={T} "
-            f"bins {t['bins_small']} below n={t['bins_switch']}")
-        got, out_idx, coff = run_full(ctx, wl, T)
+            f"bins {t['bins_small']} below n={t['bins_switch']}, wave tile {t['small_max']}/{t['mid_split']}")
+        got, out_idx, coff = run_full(ctx, wl, T, tune=t)
         check_partition_properties(wl, got, out_idx, coff)
         check_all(wl, T, got, out_idx, coff, f"c3{layout} T={T}")
 
@@ -135,19 +137,19 @@ def test_root_4096_rows_both_paths(ctx, T):
 
 def test_frontier_4096_nodes_random_width_bins(ctx):
     wl = W.config3("a")
-    T, _ = tuned_config3(ctx, wl)
+    T, t = tuned_config3(ctx, wl)
     seed = 20260302
     say(f"[gpu] full frontier random-width bins nodes={wl.n_nodes} samples={wl.n_samples} T={T}")
-    got, out_idx, coff = run_full(ctx, wl, T, bin_mode=1, bin_seed=seed)
+    got, out_idx, coff = run_full(ctx, wl, T, bin_mode=1, bin_seed=seed, tune=t)
     check_partition_properties(wl, got, out_idx, coff)
     check_all(wl, T, got, out_idx, coff, "c3a random-width", bin_mode=1, bin_seed=seed)
 
 
 def test_frontier_4096_nodes_entropy(ctx):
     wl = W.config3("a")
-    tuned_config3(ctx, wl)
+    _, t = tuned_config3(ctx, wl)
     say(f"[gpu] full frontier entropy criterion nodes={wl.n_nodes} samples={wl.n_samples} T=0")
-    got, out_idx, coff = run_full(ctx, wl, 0, criterion=1)
+    got, out_idx, coff = run_full(ctx, wl, 0, criterion=1, tune=t)
     check_partition_properties(wl, got, out_idx, coff)
     check_all(wl, 0, got, out_idx, coff, "c3a entropy", criterion=1)
 
