@@ -57,6 +57,43 @@ def test_noalloc_fp16_random_bins():
     _run_both(S, ctx, wl, bin_mode=S.SOF_BINS_RANDOM, bin_seed=99)
 
 
+def test_noalloc_under_graph_capture():
+    """The callers it is for capture it: sof_find_splits_noalloc recorded in a
+    HIP graph and replayed three times, with eager calls on another frontier
+    (which reuse the same static scratch) between the replays, gives the
+    workspace call's records and histograms every time."""
+    import torch
+    from paper_2603_00326_amd import sof as S
+    ctx = S.Context(0)
+    wl = W.random_frontier(24, n_rows=60000, d=16, n_classes=3, sizes=[5, 300, 2000, 9000, 20000], k=6, z=3,
+                           bins=256, sort_threshold=64, layout="b")
+    other = W.random_frontier(25, n_rows=20000, d=16, n_classes=3, sizes=[40, 3000, 12000], k=4, z=2,
+                              bins=128, sort_threshold=64, layout="a")
+    say("[noalloc] graph capture")
+    dev, odev = S.to_device(wl, "cuda:0"), S.to_device(other, "cuda:0")
+    ref, Href = S.find_splits(ctx, dev, bins=wl.bins, sort_threshold=64, hist=True)
+    torch.cuda.synchronize()
+    out = torch.empty_like(ref)
+    H = torch.empty_like(Href)
+    oout = torch.empty((other.n_nodes, 10), dtype=torch.int32, device="cuda:0")
+    S.find_splits_noalloc(ctx, dev, bins=wl.bins, sort_threshold=64, hist=H, out=out)   # warm-up, eager
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        S.find_splits_noalloc(ctx, dev, bins=wl.bins, sort_threshold=64, hist=H, out=out)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        out.fill_(-7)
+        H.fill_(-7)
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out[:wl.n_nodes], ref[:wl.n_nodes]), f"replay {rep}: records"
+        assert torch.equal(H, Href), f"replay {rep}: histograms"
+        S.find_splits_noalloc(ctx, odev, bins=other.bins, sort_threshold=64, out=oout)
+        torch.cuda.synchronize()
+    del g
+
+
 def test_noalloc_rejects_sizes_above_the_scratch():
     from paper_2603_00326_amd import sof as S
     from paper_2603_00326_amd import sof
